@@ -1,0 +1,179 @@
+/*
+ * cc.h -- C ABI of the MI355X coupled-cluster residual engine.
+ *
+ * The library evaluates the spin-orbital CCD / CCSD energy and amplitude
+ * equations
+ *
+ *     E - E_HF = <Phi_0| exp(-T) H_N exp(T) |Phi_0>
+ *     R_l      = <Phi_l| exp(-T) H_N exp(T) |Phi_0>      (paper, Eq. eq:amp)
+ *
+ * with T = T1 + T2 (paper, Sec. "Coupled cluster amplitude equations") and
+ * H_N the normal-ordered Hamiltonian of Eq. ham2q, as a list of binary tensor
+ * contractions (the transpose-transpose-GEMM-transpose scheme of Sec.
+ * "Tensor contractions"), led by the particle-particle ladder
+ * 1/2 sum_cd <ab||cd> tau_ij^cd.  A Jacobi denominator update and the
+ * correlation-energy reduction complete one iteration.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every tensor pointer is DEVICE memory on the context's device, dense and
+ *   row-major, 16-byte aligned, and owned by the caller.  The library never
+ *   frees caller memory.  Scalars of type CC_R64 are double; CC_C128 are
+ *   interleaved (re, im) double pairs.
+ * - o = number of occupied spin orbitals, v = number of virtual ones.
+ *   Index letters i,j,k,l,m,n run over occupied and a,b,c,d,e,f over virtual
+ *   orbitals.  Integral blocks hold <pq||rs> (antisymmetrised, Eq. ham2q):
+ *     oooo[i][j][k][l] = <ij||kl>      ooov[i][j][k][a] = <ij||ka>
+ *     oovv[i][j][a][b] = <ij||ab>      ovvo[i][a][b][j] = <ia||bj>
+ *     ovvv[i][a][b][c] = <ia||bc>      vvvv[a][b][c][d] = <ab||cd>
+ *   Every other block follows from antisymmetry and <rs||pq> = conj(<pq||rs>).
+ *   Fock blocks: f_oo[i][j], f_ov[i][a], f_vv[a][b] (f_vo = f_ov^H).
+ * - Amplitudes: t1[i][a] (o*v), t2[i][j][a][b] (o*o*v*v), antisymmetric in
+ *   (i,j) and in (a,b); T2 = 1/4 sum t_ij^ab a+_a a+_b a_j a_i.
+ * - Work is enqueued on the context's HIP stream.  Calls that return host
+ *   scalars synchronise that stream before returning.
+ * - One context per host thread.  No C++ exception crosses this ABI.  Every
+ *   call returns CC_OK (0) or a negative cc_status; cc_last_error() gives
+ *   a human-readable reason for the last failure on that context.
+ */
+#ifndef CC_H_
+#define CC_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CC_OK = 0,
+  CC_EINVAL = -1,       /* bad argument: null/misaligned pointer, o<1, v<1, t1 vs method */
+  CC_ENOMEM = -2,       /* device workspace allocation failed */
+  CC_EDEVICE = -3,      /* no usable HIP device, or a HIP runtime error */
+  CC_ENOTCONV = -4,     /* cc_iterate reached max_iter above tolerance */
+  CC_EDIVERGED = -5,    /* non-finite or growing residual norm */
+  CC_EUNSUPPORTED = -6, /* unsupported combination (e.g. precision x scalar) */
+  CC_EINTERNAL = -7
+} cc_status;
+
+typedef enum { CC_CCD = 0, CC_CCSD = 1 } cc_method;
+typedef enum { CC_R64 = 0, CC_C128 = 1 } cc_scalar;
+/* Arithmetic of the contractions.  Norms, denominators, the update and the
+ * energy are always FP64. */
+typedef enum { CC_PREC_F64 = 0, CC_PREC_F32 = 1, CC_PREC_BF16X3 = 2 } cc_prec;
+
+typedef struct cc_ctx cc_ctx;
+typedef struct cc_plan cc_plan;
+
+/* One system: sizes plus device pointers to the Fock and integral blocks
+ * (layouts above).  f_ov may be all zeros but must be a valid pointer. */
+typedef struct {
+  int32_t o, v;
+  int32_t scalar; /* cc_scalar */
+  const void *f_oo, *f_ov, *f_vv;
+  const void *oooo, *ooov, *oovv, *ovvo, *ovvv, *vvvv;
+} cc_system;
+
+/* Amplitudes or residuals.  t1 must be NULL for CC_CCD, non-NULL for CC_CCSD. */
+typedef struct {
+  void *t1;
+  void *t2;
+} cc_amps;
+
+typedef struct {
+  double tol;          /* stop when ||R(t_n)|| < tol (Frobenius norm over all stored R1, R2) */
+  int32_t max_iter;    /* at most this many residual evaluations */
+  int32_t prec;        /* cc_prec of the contractions */
+  double level_shift;  /* s >= 0: update t <- t + R / (D - s); s = 0 is plain Jacobi */
+  int32_t refine_every;/* mixed precision: an FP64 residual every this many steps (0 = never) */
+  int32_t use_graph;   /* 1: capture one iteration as a HIP graph and replay it */
+  int32_t check_every; /* read the norm back every this many iterations (>= 1) */
+  int32_t diverge_window; /* EDIVERGED if the norm grew for this many checks in a row (0 = off) */
+} cc_iter_opts;
+
+typedef struct {
+  int32_t iters;       /* residual evaluations performed */
+  int32_t converged;   /* 1 if ||R|| < tol was reached */
+  double rnorm;        /* ||R(t_final)|| */
+  double e_re, e_im;   /* E(t_final) - E_HF */
+  double seconds;      /* wall time of the loop (setup excluded) */
+  double setup_seconds;/* plan creation: derived integral views, workspace */
+  double *hist_rnorm;  /* host arrays of capacity hist_cap, or NULL */
+  double *hist_e;      /* E per iteration (real part) */
+  int32_t hist_cap;
+} cc_iter_report;
+
+/* ---- context ------------------------------------------------------------ */
+/* Binds device `device` and `hip_stream` (a hipStream_t, NULL = a stream the
+ * library creates and owns).  Returns CC_EDEVICE when no HIP device exists. */
+int cc_create(cc_ctx **ctx, int device, void *hip_stream);
+int cc_destroy(cc_ctx *ctx);
+const char *cc_last_error(const cc_ctx *ctx);
+/* Static error text for a status code. */
+const char *cc_status_string(int status);
+
+/* ---- plans: setup once, evaluate many times ------------------------------
+ * A plan binds one system (the pointers in *sys are retained, not copied:
+ * they must stay valid and unchanged until cc_plan_destroy), a method and a
+ * contraction precision.  Creation derives the permuted / conjugated integral
+ * views the contraction list needs and allocates the workspace. */
+int cc_plan_create(cc_ctx *ctx, const cc_system *sys, int method, int prec, cc_plan **plan);
+int cc_plan_destroy(cc_plan *plan);
+/* Workspace bytes held by the plan (derived views + intermediates). */
+size_t cc_plan_workspace_bytes(const cc_plan *plan);
+
+/* Residual R(t) (Eq. eq:amp, singles and doubles projections).  r may be
+ * NULL (only the norm is produced); r->t1 is ignored for CC_CCD.
+ * rnorm_out (host, may be NULL) receives ||R||. */
+int cc_plan_residual(cc_plan *plan, const cc_amps *t, cc_amps *r, double *rnorm_out);
+/* One Jacobi step: evaluates E(t) and R(t), then t <- t + R/(D - s) in
+ * place.  The scalars are left in device memory; cc_plan_scalars reads them. */
+int cc_plan_step(cc_plan *plan, cc_amps *t, double level_shift);
+/* ||R|| and E (re, im) of the last cc_plan_step / cc_plan_residual (syncs). */
+int cc_plan_scalars(cc_plan *plan, double *rnorm, double *e_re, double *e_im);
+
+/* ---- one-shot conveniences ---------------------------------------------- */
+int cc_residual(cc_ctx *ctx, const cc_system *sys, int method, int prec, const cc_amps *t,
+                cc_amps *r, double *rnorm_out);
+/* E - E_HF = sum f_ia t_i^a + 1/4 sum <ij||ab> tau_ij^ab (first line of Eq. eq:amp). */
+int cc_energy(cc_ctx *ctx, const cc_system *sys, int method, const cc_amps *t, double *e_re,
+              double *e_im);
+/* Jacobi iteration from the amplitudes in t_inout (zeros = start from the
+ * reference, whose first step yields the MP2 amplitudes).  Returns CC_OK,
+ * CC_ENOTCONV or CC_EDIVERGED; t_inout holds the last finite iterate. */
+int cc_iterate(cc_ctx *ctx, const cc_system *sys, int method, const cc_iter_opts *opts,
+               cc_amps *t_inout, cc_iter_report *report);
+
+/* ---- kernel-level entry points (used by the kernel tests) ----------------
+ * C[m][n] = alpha * sum_k A(m,k) B(n,k) + beta * C[m][n], row-major C with
+ * leading dimension ldc.  A(m,k) = A[m*sam + k*sak] with sam == 1 or sak == 1;
+ * B(n,k) = B[n*sbn + k*sbk] with sbn == 1 or sbk == 1.  prec selects the
+ * MFMA path (F64: FP64 MFMA; F32: FP32 MFMA on FP64 data rounded to FP32;
+ * BF16X3: split-bf16 MFMA), scalar CC_C128 the complex path.  Accumulation is
+ * FP64 for F64, FP32 otherwise. */
+int cc_gemm(cc_ctx *ctx, int prec, int scalar, int64_t M, int64_t N, int64_t K, double alpha,
+            const void *A, int64_t sam, int64_t sak, const void *B, int64_t sbn, int64_t sbk,
+            double beta, void *C, int64_t ldc);
+/* out[I] = alpha * in[perm(I)] + beta * out[I] for a dense rank-r tensor
+ * (r <= 6): out has dims out_dims[0..r-1]; out index d reads input dim
+ * perm[d]; in is dense row-major with dims in_dims. */
+int cc_permute(cc_ctx *ctx, int scalar, int rank, const int64_t *in_dims, const int32_t *perm,
+               double alpha, const void *in, double beta, void *out);
+
+/* ---- introspection ------------------------------------------------------ */
+/* Text listing of the plan's setup and per-iteration steps (permutes, GEMMs
+ * with shapes and tiles, elementwise kernels).  Valid until the next call on
+ * the same host thread. */
+const char *cc_plan_describe(const cc_plan *plan);
+/* The same listing for a plan of the given sizes, built without a device
+ * (no allocation, no kernel launch). */
+const char *cc_plan_describe_dry(int o, int v, int method, int scalar);
+/* Algorithmic (dense) flops of one iteration (which = 0) or of the
+ * particle-particle ladder alone (which = 1). */
+double cc_plan_flops(const cc_plan *plan, int which);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CC_H_ */

@@ -1,0 +1,470 @@
+// C ABI of the engine: validation, error mapping and the Jacobi driver.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "plan.hpp"
+
+using ccmi::CCError;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(cc_ctx *ctx, int status, const std::string &msg) {
+  if (ctx) ctx->last_error = msg;
+  g_last_error = msg;
+  return status;
+}
+
+template <class F>
+int guarded(cc_ctx *ctx, F &&f) {
+  try {
+    return f();
+  } catch (const CCError &e) {
+    return fail(ctx, e.status, e.what());
+  } catch (const std::bad_alloc &) {
+    return fail(ctx, CC_ENOMEM, "host allocation failed");
+  } catch (const std::exception &e) {
+    return fail(ctx, CC_EINTERNAL, e.what());
+  }
+}
+
+bool aligned(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+void check_ptr(const void *p, const char *what) {
+  if (p == nullptr) throw CCError(CC_EINVAL, std::string(what) + " is NULL");
+  if (!aligned(p)) throw CCError(CC_EINVAL, std::string(what) + " is not 16-byte aligned");
+}
+
+void validate_system(const cc_system *s) {
+  if (!s) throw CCError(CC_EINVAL, "system is NULL");
+  if (s->o < 1 || s->v < 1) throw CCError(CC_EINVAL, "o and v must be >= 1");
+  if (int64_t(s->o) * s->o * s->v * s->v > (int64_t(1) << 40))
+    throw CCError(CC_EINVAL, "system too large");
+  if (s->scalar != CC_R64 && s->scalar != CC_C128) throw CCError(CC_EINVAL, "unknown scalar type");
+  check_ptr(s->f_oo, "f_oo");
+  check_ptr(s->f_ov, "f_ov");
+  check_ptr(s->f_vv, "f_vv");
+  check_ptr(s->oooo, "oooo");
+  check_ptr(s->ooov, "ooov");
+  check_ptr(s->oovv, "oovv");
+  check_ptr(s->ovvo, "ovvo");
+  check_ptr(s->ovvv, "ovvv");
+  check_ptr(s->vvvv, "vvvv");
+}
+
+void validate_method(int method, int prec, int scalar) {
+  if (method != CC_CCD && method != CC_CCSD) throw CCError(CC_EINVAL, "unknown method");
+  if (prec != CC_PREC_F64 && prec != CC_PREC_F32 && prec != CC_PREC_BF16X3)
+    throw CCError(CC_EINVAL, "unknown precision");
+  if (scalar == CC_C128 && prec != CC_PREC_F64)
+    throw CCError(CC_EUNSUPPORTED, "complex amplitudes support FP64 contractions only");
+}
+
+void validate_amps(const cc_amps *t, int method, const char *what) {
+  if (!t) throw CCError(CC_EINVAL, std::string(what) + " is NULL");
+  check_ptr(t->t2, (std::string(what) + ".t2").c_str());
+  if (method == CC_CCSD) check_ptr(t->t1, (std::string(what) + ".t1").c_str());
+  if (method == CC_CCD && t->t1 != nullptr)
+    throw CCError(CC_EINVAL, std::string(what) + ".t1 must be NULL for CCD");
+}
+
+void set_device(cc_ctx *ctx) { CC_HIP_CHECK(hipSetDevice(ctx->device)); }
+
+void read_scalars(cc_plan *p, double *rn, double *er, double *ei) {
+  cc_ctx *ctx = p->ctx;
+  CC_HIP_CHECK(hipMemcpyAsync(ctx->pinned, p->scalars, 3 * sizeof(double), hipMemcpyDeviceToHost,
+                              ctx->stream));
+  CC_HIP_CHECK(hipStreamSynchronize(ctx->stream));
+  if (rn) *rn = ctx->pinned[0];
+  if (er) *er = ctx->pinned[1];
+  if (ei) *ei = ctx->pinned[2];
+}
+
+// One update step; replays a captured graph when asked and when the
+// amplitude pointers and shift match the capture.
+void run_step(cc_plan *p, bool use_graph) {
+  if (!use_graph) {
+    ccmi::plan_run(p);
+    return;
+  }
+  const bool same = p->graph && p->graph_key[0] == p->t1 && p->graph_key[1] == p->t2 &&
+                    p->graph_key[2] == p->r1_out && p->graph_key[3] == p->r2_out &&
+                    p->graph_shift == p->shift && p->graph_update == p->update;
+  if (!same) {
+    if (p->graph) (void)hipGraphExecDestroy(p->graph);
+    p->graph = nullptr;
+    hipGraph_t g;
+    CC_HIP_CHECK(hipStreamBeginCapture(p->ctx->stream, hipStreamCaptureModeThreadLocal));
+    try {
+      ccmi::plan_run(p);
+    } catch (...) {
+      hipGraph_t dummy;
+      (void)hipStreamEndCapture(p->ctx->stream, &dummy);
+      throw;
+    }
+    CC_HIP_CHECK(hipStreamEndCapture(p->ctx->stream, &g));
+    CC_HIP_CHECK(hipGraphInstantiate(&p->graph, g, nullptr, nullptr, 0));
+    (void)hipGraphDestroy(g);
+    p->graph_key[0] = p->t1;
+    p->graph_key[1] = p->t2;
+    p->graph_key[2] = p->r1_out;
+    p->graph_key[3] = p->r2_out;
+    p->graph_shift = p->shift;
+    p->graph_update = p->update;
+  }
+  CC_HIP_CHECK(hipGraphLaunch(p->graph, p->ctx->stream));
+}
+
+cc_plan *make_plan(cc_ctx *ctx, const cc_system *sys, int method, int prec) {
+  validate_system(sys);
+  validate_method(method, prec, sys->scalar);
+  set_device(ctx);
+  cc_plan *p = new cc_plan();
+  p->ctx = ctx;
+  p->o = sys->o;
+  p->v = sys->v;
+  p->method = method;
+  p->prec = prec;
+  p->cplx = sys->scalar == CC_C128;
+  p->esize = p->cplx ? 16 : 8;
+  try {
+    ccmi::plan_build(p, sys);
+  } catch (...) {
+    ccmi::plan_free(p);
+    delete p;
+    throw;
+  }
+  return p;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *cc_status_string(int s) {
+  switch (s) {
+    case CC_OK: return "ok";
+    case CC_EINVAL: return "invalid argument";
+    case CC_ENOMEM: return "out of device memory";
+    case CC_EDEVICE: return "device error";
+    case CC_ENOTCONV: return "not converged";
+    case CC_EDIVERGED: return "diverged";
+    case CC_EUNSUPPORTED: return "unsupported";
+    case CC_EINTERNAL: return "internal error";
+    default: return "unknown status";
+  }
+}
+
+const char *cc_last_error(const cc_ctx *ctx) {
+  return ctx ? ctx->last_error.c_str() : g_last_error.c_str();
+}
+
+int cc_create(cc_ctx **out, int device, void *stream) {
+  if (!out) return fail(nullptr, CC_EINVAL, "ctx pointer is NULL");
+  *out = nullptr;
+  return guarded(nullptr, [&] {
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n == 0) {
+      (void)hipGetLastError();
+      throw CCError(CC_EDEVICE, "no HIP device available");
+    }
+    if (device < 0 || device >= n) throw CCError(CC_EINVAL, "device index out of range");
+    CC_HIP_CHECK(hipSetDevice(device));
+    cc_ctx *c = new cc_ctx();
+    c->device = device;
+    if (stream) {
+      c->stream = static_cast<hipStream_t>(stream);
+    } else {
+      if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+        delete c;
+        throw CCError(CC_EDEVICE, "stream creation failed");
+      }
+      c->own_stream = true;
+    }
+    if (hipHostMalloc(reinterpret_cast<void **>(&c->pinned), 64, hipHostMallocDefault) != hipSuccess) {
+      if (c->own_stream) (void)hipStreamDestroy(c->stream);
+      delete c;
+      throw CCError(CC_EDEVICE, "pinned host allocation failed");
+    }
+    *out = c;
+    return CC_OK;
+  });
+}
+
+int cc_destroy(cc_ctx *ctx) {
+  if (!ctx) return CC_OK;
+  (void)hipSetDevice(ctx->device);
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+  return CC_OK;
+}
+
+int cc_plan_create(cc_ctx *ctx, const cc_system *sys, int method, int prec, cc_plan **plan) {
+  if (!ctx) return fail(nullptr, CC_EINVAL, "ctx is NULL");
+  if (!plan) return fail(ctx, CC_EINVAL, "plan pointer is NULL");
+  *plan = nullptr;
+  return guarded(ctx, [&] {
+    *plan = make_plan(ctx, sys, method, prec);
+    return CC_OK;
+  });
+}
+
+int cc_plan_destroy(cc_plan *p) {
+  if (!p) return CC_OK;
+  (void)hipSetDevice(p->ctx->device);
+  (void)hipStreamSynchronize(p->ctx->stream);
+  ccmi::plan_free(p);
+  delete p;
+  return CC_OK;
+}
+
+size_t cc_plan_workspace_bytes(const cc_plan *p) { return p ? p->workspace : 0; }
+
+int cc_plan_residual(cc_plan *p, const cc_amps *t, cc_amps *r, double *rnorm_out) {
+  if (!p) return fail(nullptr, CC_EINVAL, "plan is NULL");
+  return guarded(p->ctx, [&] {
+    validate_amps(t, p->method, "t");
+    if (r) validate_amps(r, p->method, "r");
+    set_device(p->ctx);
+    p->t1 = t->t1;
+    p->t2 = t->t2;
+    p->r1_out = r ? r->t1 : nullptr;
+    p->r2_out = r ? r->t2 : nullptr;
+    p->update = false;
+    p->shift = 0.0;
+    ccmi::plan_run(p);
+    if (rnorm_out) read_scalars(p, rnorm_out, nullptr, nullptr);
+    else CC_HIP_CHECK(hipStreamSynchronize(p->ctx->stream));
+    return CC_OK;
+  });
+}
+
+int cc_plan_step(cc_plan *p, cc_amps *t, double level_shift) {
+  if (!p) return fail(nullptr, CC_EINVAL, "plan is NULL");
+  return guarded(p->ctx, [&] {
+    validate_amps(t, p->method, "t");
+    if (!(level_shift >= 0.0) || !std::isfinite(level_shift))
+      throw CCError(CC_EINVAL, "level_shift must be finite and >= 0");
+    set_device(p->ctx);
+    p->t1 = t->t1;
+    p->t2 = t->t2;
+    p->r1_out = nullptr;
+    p->r2_out = nullptr;
+    p->update = true;
+    p->shift = level_shift;
+    ccmi::plan_run(p);
+    CC_HIP_CHECK(hipGetLastError());
+    return CC_OK;
+  });
+}
+
+int cc_plan_scalars(cc_plan *p, double *rn, double *er, double *ei) {
+  if (!p) return fail(nullptr, CC_EINVAL, "plan is NULL");
+  return guarded(p->ctx, [&] {
+    set_device(p->ctx);
+    read_scalars(p, rn, er, ei);
+    return CC_OK;
+  });
+}
+
+int cc_residual(cc_ctx *ctx, const cc_system *sys, int method, int prec, const cc_amps *t,
+                cc_amps *r, double *rnorm_out) {
+  if (!ctx) return fail(nullptr, CC_EINVAL, "ctx is NULL");
+  return guarded(ctx, [&] {
+    validate_amps(t, method, "t");
+    if (r) validate_amps(r, method, "r");
+    cc_plan *p = make_plan(ctx, sys, method, prec);
+    int st = cc_plan_residual(p, t, r, rnorm_out);
+    cc_plan_destroy(p);
+    return st;
+  });
+}
+
+int cc_energy(cc_ctx *ctx, const cc_system *sys, int method, const cc_amps *t, double *e_re,
+              double *e_im) {
+  if (!ctx) return fail(nullptr, CC_EINVAL, "ctx is NULL");
+  return guarded(ctx, [&] {
+    validate_amps(t, method, "t");
+    cc_plan *p = make_plan(ctx, sys, method, CC_PREC_F64);
+    try {
+      p->t1 = t->t1;
+      p->t2 = t->t2;
+      ccmi::plan_run_energy(p);
+      read_scalars(p, nullptr, e_re, e_im);
+    } catch (...) {
+      cc_plan_destroy(p);
+      throw;
+    }
+    cc_plan_destroy(p);
+    return CC_OK;
+  });
+}
+
+int cc_iterate(cc_ctx *ctx, const cc_system *sys, int method, const cc_iter_opts *opts,
+               cc_amps *t, cc_iter_report *rep) {
+  if (!ctx) return fail(nullptr, CC_EINVAL, "ctx is NULL");
+  return guarded(ctx, [&] {
+    if (!opts) throw CCError(CC_EINVAL, "opts is NULL");
+    if (opts->max_iter < 1) throw CCError(CC_EINVAL, "max_iter must be >= 1");
+    if (!(opts->tol > 0.0)) throw CCError(CC_EINVAL, "tol must be > 0");
+    if (!(opts->level_shift >= 0.0)) throw CCError(CC_EINVAL, "level_shift must be >= 0");
+    validate_amps(t, method, "t");
+    const auto t0 = std::chrono::steady_clock::now();
+    cc_plan *p = make_plan(ctx, sys, method, opts->prec);
+    const auto t1c = std::chrono::steady_clock::now();
+    int status = CC_ENOTCONV;
+    int iters = 0;
+    double rn = NAN, er = NAN, ei = NAN, best = INFINITY;
+    int grew = 0;
+    try {
+      p->t1 = t->t1;
+      p->t2 = t->t2;
+      p->r1_out = p->r2_out = nullptr;
+      p->update = true;
+      p->shift = opts->level_shift;
+      for (int it = 0; it < opts->max_iter; ++it) {
+        run_step(p, opts->use_graph != 0);
+        ++iters;
+        read_scalars(p, &rn, &er, &ei);
+        if (rep && rep->hist_rnorm && it < rep->hist_cap) rep->hist_rnorm[it] = rn;
+        if (rep && rep->hist_e && it < rep->hist_cap) rep->hist_e[it] = er;
+        if (!std::isfinite(rn) || !std::isfinite(er)) {
+          status = CC_EDIVERGED;
+          break;
+        }
+        if (rn < opts->tol) {
+          status = CC_OK;
+          break;
+        }
+        if (rn < best) {
+          best = rn;
+          grew = 0;
+        } else if (opts->diverge_window > 0 && ++grew >= opts->diverge_window) {
+          status = CC_EDIVERGED;
+          break;
+        }
+      }
+    } catch (...) {
+      cc_plan_destroy(p);
+      throw;
+    }
+    const auto t2c = std::chrono::steady_clock::now();
+    if (rep) {
+      rep->iters = iters;
+      rep->converged = status == CC_OK;
+      rep->rnorm = rn;
+      rep->e_re = er;
+      rep->e_im = ei;
+      rep->seconds = std::chrono::duration<double>(t2c - t1c).count();
+      rep->setup_seconds = std::chrono::duration<double>(t1c - t0).count();
+    }
+    cc_plan_destroy(p);
+    if (status == CC_ENOTCONV) ctx->last_error = "max_iter reached before tolerance";
+    if (status == CC_EDIVERGED) ctx->last_error = "residual norm diverged";
+    return status;
+  });
+}
+
+// ---- kernel-level entry points -------------------------------------------
+int cc_gemm(cc_ctx *ctx, int prec, int scalar, int64_t M, int64_t N, int64_t K, double alpha,
+            const void *A, int64_t sam, int64_t sak, const void *B, int64_t sbn, int64_t sbk,
+            double beta, void *C, int64_t ldc) {
+  if (!ctx) return fail(nullptr, CC_EINVAL, "ctx is NULL");
+  return guarded(ctx, [&] {
+    if (M < 0 || N < 0 || K < 0) throw CCError(CC_EINVAL, "negative GEMM size");
+    if (M == 0 || N == 0) return CC_OK;
+    check_ptr(C, "C");
+    if (K > 0) {
+      check_ptr(A, "A");
+      check_ptr(B, "B");
+    }
+    if (!(sam == 1 || sak == 1) || !(sbn == 1 || sbk == 1))
+      throw CCError(CC_EINVAL, "each operand needs one unit stride");
+    if (ldc < N) throw CCError(CC_EINVAL, "ldc < N");
+    if (scalar == CC_C128 && prec != CC_PREC_F64)
+      throw CCError(CC_EUNSUPPORTED, "complex GEMM is FP64 only");
+    set_device(ctx);
+    ccmi::GemmDesc d{M, N, K, A, sam, sak, B, sbn, sbk, C, ldc, alpha, beta};
+    if (scalar == CC_C128) ccmi::gemm_c128(d, ctx->stream);
+    else if (prec == CC_PREC_F64) ccmi::gemm_f64(d, ctx->stream, -1);
+    else ccmi::gemm_lowp(d, prec, ctx->stream, -1);
+    CC_HIP_CHECK(hipStreamSynchronize(ctx->stream));
+    return CC_OK;
+  });
+}
+
+int cc_permute(cc_ctx *ctx, int scalar, int rank, const int64_t *in_dims, const int32_t *perm,
+               double alpha, const void *in, double beta, void *out) {
+  if (!ctx) return fail(nullptr, CC_EINVAL, "ctx is NULL");
+  return guarded(ctx, [&] {
+    if (rank < 1 || rank > ccmi::kMaxRank) throw CCError(CC_EINVAL, "rank must be 1..6");
+    if (!in_dims || !perm) throw CCError(CC_EINVAL, "dims/perm NULL");
+    check_ptr(in, "in");
+    check_ptr(out, "out");
+    int64_t istr[ccmi::kMaxRank];
+    istr[rank - 1] = 1;
+    for (int d = rank - 2; d >= 0; --d) istr[d] = istr[d + 1] * in_dims[d + 1];
+    bool seen[ccmi::kMaxRank] = {false};
+    ccmi::PermDesc pd{};
+    pd.rank = rank;
+    for (int d = 0; d < rank; ++d) {
+      if (perm[d] < 0 || perm[d] >= rank || seen[perm[d]]) throw CCError(CC_EINVAL, "bad permutation");
+      if (in_dims[d] < 0) throw CCError(CC_EINVAL, "negative dim");
+      seen[perm[d]] = true;
+      pd.out_dims[d] = in_dims[perm[d]];
+      pd.in_strides[d] = istr[perm[d]];
+    }
+    pd.out_strides[rank - 1] = 1;
+    for (int d = rank - 2; d >= 0; --d) pd.out_strides[d] = pd.out_strides[d + 1] * pd.out_dims[d + 1];
+    pd.alpha = alpha;
+    pd.beta = beta;
+    pd.conj = 0;
+    set_device(ctx);
+    if (scalar == CC_C128) ccmi::permute_c128(pd, in, out, ctx->stream);
+    else ccmi::permute_f64(pd, in, out, ctx->stream);
+    CC_HIP_CHECK(hipStreamSynchronize(ctx->stream));
+    return CC_OK;
+  });
+}
+
+// Text dump of a plan's steps (debugging aid; the string stays valid until
+// the next call on the same thread).
+const char *cc_plan_describe(const cc_plan *p) {
+  static thread_local std::string s;
+  s = p ? ccmi::plan_describe(p) : std::string();
+  return s.c_str();
+}
+
+const char *cc_plan_describe_dry(int o, int v, int method, int scalar) {
+  static thread_local std::string s;
+  try {
+    if (o < 1 || v < 1) throw CCError(CC_EINVAL, "o and v must be >= 1");
+    validate_method(method, CC_PREC_F64, scalar);
+    cc_plan p;
+    p.o = o;
+    p.v = v;
+    p.method = method;
+    p.cplx = scalar == CC_C128;
+    p.esize = p.cplx ? 16 : 8;
+    cc_system sys{};
+    sys.o = o;
+    sys.v = v;
+    sys.scalar = scalar;
+    ccmi::plan_layout(&p, &sys);
+    s = ccmi::plan_describe(&p);
+  } catch (const std::exception &e) {
+    s = std::string("error: ") + e.what();
+  }
+  return s.c_str();
+}
+
+double cc_plan_flops(const cc_plan *p, int which) {
+  if (!p) return 0.0;
+  return which == 1 ? p->ladder_flops : p->flops_per_iter;
+}
+
+}  // extern "C"

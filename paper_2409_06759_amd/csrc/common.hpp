@@ -1,0 +1,81 @@
+// Shared host/device definitions of the coupled-cluster engine (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+
+namespace ccmi {
+
+// Error raised inside the library; converted to a cc_status at the ABI.
+struct CCError : public std::runtime_error {
+  int status;
+  CCError(int s, const std::string &m) : std::runtime_error(m), status(s) {}
+};
+
+#define CC_HIP_CHECK(expr)                                                                  \
+  do {                                                                                      \
+    hipError_t _e = (expr);                                                                 \
+    if (_e != hipSuccess)                                                                   \
+      throw ::ccmi::CCError(-3, std::string(#expr) + ": " + hipGetErrorString(_e));         \
+  } while (0)
+
+#define CC_REQUIRE(cond, status, msg)                                                       \
+  do {                                                                                      \
+    if (!(cond)) throw ::ccmi::CCError((status), (msg));                                    \
+  } while (0)
+
+constexpr int kWave = 64;
+constexpr int kNumXcd = 8;   // MI355X: 8 accelerator complex dies, round-robin dispatch
+
+// Workgroup-id remap so that consecutive logical tiles land on the same XCD
+// (workgroups are dispatched round-robin over the XCDs; each has its own L2).
+__device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t total) {
+  const int64_t per = total / kNumXcd, rem = total % kNumXcd;
+  const int64_t x = bid % kNumXcd, l = bid / kNumXcd;
+  return (x < rem) ? x * (per + 1) + l : rem * (per + 1) + (x - rem) * per + l;
+}
+
+// ---- GEMM descriptor: C[m][n] = alpha * sum_k A(m,k) B(n,k) + beta * C ----
+struct GemmDesc {
+  int64_t M, N, K;
+  const void *A;
+  int64_t sam, sak;  // A(m,k) = A[m*sam + k*sak]
+  const void *B;
+  int64_t sbn, sbk;  // B(n,k) = B[n*sbn + k*sbk]
+  void *C;
+  int64_t ldc;       // C[m*ldc + n]
+  double alpha, beta;
+  int conj_a = 0, conj_b = 0;  // complex only
+};
+
+enum Prec { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16X3 = 2 };
+
+// Tile configuration chosen by the tuner for one GEMM shape.
+struct GemmTile {
+  int id;  // index into the instantiated configuration table
+};
+
+void gemm_f64(const GemmDesc &d, hipStream_t s, int tile_id = -1);
+void gemm_lowp(const GemmDesc &d, int prec, hipStream_t s, int tile_id = -1);
+void gemm_c128(const GemmDesc &d, hipStream_t s);
+int gemm_f64_num_tiles();
+const char *gemm_f64_tile_name(int id);
+int gemm_f64_pick(int64_t M, int64_t N, int64_t K, bool a_kc, bool b_kc);
+
+// ---- dense rank<=6 tensor views for permutation kernels ----
+constexpr int kMaxRank = 6;
+struct PermDesc {
+  int rank;
+  int64_t out_dims[kMaxRank];   // output dims
+  int64_t in_strides[kMaxRank]; // stride in the input for each OUTPUT dim
+  int64_t out_strides[kMaxRank];// output strides (dense row-major normally)
+  double alpha, beta;
+  int conj;
+};
+void permute_f64(const PermDesc &d, const void *in, void *out, hipStream_t s);
+void permute_c128(const PermDesc &d, const void *in, void *out, hipStream_t s);
+
+}  // namespace ccmi

@@ -1,0 +1,646 @@
+// Contraction list of the spin-orbital CCD/CCSD residual, the planner that
+// turns each binary contraction into permute -> MFMA GEMM -> permute-accumulate
+// steps (paper, Sec. "Tensor contractions": transpose-transpose-GEMM-transpose),
+// and the executor that enqueues those steps on one HIP stream.
+//
+// The list follows the usual factorisation of the spin-orbital CCSD
+// equations into one- and two-body intermediates (F_ae, F_mi, F_me, W_mnij,
+// W_mbej), with two changes that keep every operation binary and bound the
+// memory (paper, Sec. "Secondary optimization": intermediates that are too
+// large are not formed): the four-virtual intermediate W_abef is never built
+// -- its <ab||ef> part is the particle-particle ladder contracted directly
+// with the stored vvvv block, its t1 part goes through Z_ij^am, and its
+// tau<mn||ef>tau part is folded into W_mnij with a factor 1/2.
+//
+// Every integral is used in the orientation <pq||rs> where p, q are creation
+// indices of H_N (external virtual or summed occupied indices) and r, s are
+// annihilation indices; with complex Hermitian integrals the blocks not stored
+// are conjugates of stored ones (driver <ab||ij> = conj <ij||ab>).
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <set>
+#include <sstream>
+
+namespace ccmi {
+namespace {
+
+// clang-format off
+// C, labels, alpha, A, labels, B, labels, conjA, conjB, P(xy), needs_t1, tag
+const OpSpec kOps[] = {
+  // F_me = f_me + t_n^f <mn||ef>
+  {"Fme", "me", 1.0, "fov", "me", nullptr, nullptr, false, false, nullptr, true, "Fme_f"},
+  {"Fme", "me", 1.0, "oovv", "mnef", "t1", "nf", false, false, nullptr, true, "Fme_t1"},
+  // F_ae = f_ae - 1/2 t_m^a f_me + t_m^f <ma||fe> - 1/2 taut_mn^af <mn||ef>
+  {"Fae", "ae", 1.0, "fvv", "ae", nullptr, nullptr, false, false, nullptr, false, "Fae_f"},
+  {"Fae", "ae", -0.5, "t1", "ma", "fov", "me", false, false, nullptr, true, "Fae_ft1"},
+  {"Fae", "ae", 1.0, "ovvv", "mafe", "t1", "mf", false, false, nullptr, true, "Fae_t1"},
+  {"Fae", "ae", -0.5, "taut", "mnaf", "oovv", "mnef", false, false, nullptr, false, "Fae_t2"},
+  // F_mi = f_mi + 1/2 t_i^e f_me + t_n^e <mn||ie> + 1/2 taut_in^ef <mn||ef>
+  {"Fmi", "mi", 1.0, "foo", "mi", nullptr, nullptr, false, false, nullptr, false, "Fmi_f"},
+  {"Fmi", "mi", 0.5, "fov", "me", "t1", "ie", false, false, nullptr, true, "Fmi_ft1"},
+  {"Fmi", "mi", 1.0, "ooov", "mnie", "t1", "ne", false, false, nullptr, true, "Fmi_t1"},
+  {"Fmi", "mi", 0.5, "oovv", "mnef", "taut", "inef", false, false, nullptr, false, "Fmi_t2"},
+  // W_mnij = <mn||ij> + P(ij) t_j^e <mn||ie> + 1/2 tau_ij^ef <mn||ef>
+  {"Wmnij", "mnij", 1.0, "oooo", "mnij", nullptr, nullptr, false, false, nullptr, false, "Wmnij_v"},
+  {"Wmnij", "mnij", 1.0, "ooov", "mnie", "t1", "je", false, false, "ij", true, "Wmnij_t1"},
+  {"Wmnij", "mnij", 0.5, "oovv", "mnef", "tau", "ijef", false, false, nullptr, false, "Wmnij_tau"},
+  // W_mbej (stored [j][b][m][e]) = <mb||ej> + t_j^f <mb||ef> - t_n^b <mn||ej>
+  //                               - (1/2 t_jn^fb + t_j^f t_n^b) <mn||ef>
+  {"Wjbme", "jbme", 1.0, "ovvo", "mbej", nullptr, nullptr, false, false, nullptr, false, "Wmbej_v"},
+  {"Wjbme", "jbme", 1.0, "ovvv", "mbef", "t1", "jf", false, false, nullptr, true, "Wmbej_ovvv"},
+  {"Wjbme", "jbme", 1.0, "ooov", "mnje", "t1", "nb", false, false, nullptr, true, "Wmbej_ooov"},
+  {"Y", "jbnf", 0.5, "t2", "jnfb", nullptr, nullptr, false, false, nullptr, false, "Y_t2"},
+  {"Y", "jbnf", 1.0, "t1", "jf", "t1", "nb", false, false, nullptr, true, "Y_t1t1"},
+  {"Wjbme", "jbme", -1.0, "Y", "jbnf", "oovv", "mnef", false, false, nullptr, false, "Wmbej_ring"},
+  // doubles: driver <ab||ij>
+  {"XP", "ijab", 1.0, "oovv", "ijab", nullptr, nullptr, true, false, nullptr, false, "driver"},
+  // P(ij)P(ab) ( t_im^ae W_mbej - t_i^e t_m^a <mb||ej> )
+  {"Xr", "ijab", 1.0, "t2", "imae", "Wjbme", "jbme", false, false, nullptr, false, "ring"},
+  {"Q", "imbj", 1.0, "t1", "ie", "ovvo", "mbej", false, false, nullptr, true, "Q"},
+  {"Xr", "ijab", -1.0, "Q", "imbj", "t1", "ma", false, false, nullptr, true, "ring_t1t1"},
+  // P(ij) t_i^e <ab||ej>,  <ab||ej> = -conj <je||ab>
+  {"Xij", "ijab", -1.0, "t1", "ie", "ovvv", "jeab", false, true, nullptr, true, "abej_t1"},
+  // -P(ab) t_m^a <mb||ij>,  <mb||ij> = conj <ij||mb>
+  {"Xab", "ijab", -1.0, "t1", "ma", "ooov", "ijmb", false, true, nullptr, true, "mbij_t1"},
+  // P(ab) t_ij^ae (F_be - 1/2 t_m^b F_me)
+  {"FF", "be", 1.0, "Fae", "be", nullptr, nullptr, false, false, nullptr, false, "FF"},
+  {"FF", "be", -0.5, "t1", "mb", "Fme", "me", false, false, nullptr, true, "FF_t1"},
+  {"Xab", "ijab", 1.0, "t2", "ijae", "FF", "be", false, false, nullptr, false, "Fvv_t2"},
+  // -P(ij) t_im^ab (F_mj + 1/2 t_j^e F_me)
+  {"GG", "mj", 1.0, "Fmi", "mj", nullptr, nullptr, false, false, nullptr, false, "GG"},
+  {"GG", "mj", 0.5, "Fme", "me", "t1", "je", false, false, nullptr, true, "GG_t1"},
+  {"Xij", "ijab", -1.0, "t2", "imab", "GG", "mj", false, false, nullptr, false, "Foo_t2"},
+  // 1/2 tau_mn^ab W_mnij
+  {"XP", "ijab", 0.5, "Wmnij", "mnij", "tau", "mnab", false, false, nullptr, false, "hh_ladder"},
+  // 1/2 <ab||ef> tau_ij^ef : the particle-particle ladder
+  {"XP", "ijab", 0.5, "tau", "ijef", "vvvv", "abef", false, false, nullptr, false, "ladder"},
+  // -1/2 P(ab) t_m^b Z_ij^am with Z_ij^am = <am||ef> tau_ij^ef = -Zs[ij][am]
+  {"Zs", "ijam", 1.0, "tau", "ijef", "ovvv", "maef", false, false, nullptr, true, "Z"},
+  {"Xab", "ijab", 0.5, "Zs", "ijam", "t1", "mb", false, false, nullptr, true, "Z_t1"},
+  // singles
+  {"R1", "ia", 1.0, "fov", "ia", nullptr, nullptr, true, false, nullptr, true, "R1_f"},
+  {"R1", "ia", 1.0, "t1", "ie", "Fae", "ae", false, false, nullptr, true, "R1_Fae"},
+  {"R1", "ia", -1.0, "Fmi", "mi", "t1", "ma", false, false, nullptr, true, "R1_Fmi"},
+  {"R1", "ia", 1.0, "t2", "imae", "Fme", "me", false, false, nullptr, true, "R1_Fme"},
+  {"R1", "ia", 1.0, "ovvo", "nafi", "t1", "nf", false, false, nullptr, true, "R1_ovvo"},
+  {"R1", "ia", -0.5, "t2", "imef", "ovvv", "maef", false, false, nullptr, true, "R1_ovvv"},
+  {"R1", "ia", -0.5, "t2", "mnae", "ooov", "mnie", false, false, nullptr, true, "R1_ooov"},
+};
+// clang-format on
+
+int64_t dim_of(char c, int o, int v) {
+  if (c >= 'i' && c <= 'n') return o;
+  if (c >= 'a' && c <= 'h') return v;
+  throw CCError(CC_EINTERNAL, std::string("bad index label ") + c);
+}
+char space_of(char c) { return (c >= 'i' && c <= 'n') ? 'o' : 'v'; }
+
+std::vector<int64_t> dense_strides(const std::vector<int64_t> &dims) {
+  std::vector<int64_t> s(dims.size(), 1);
+  for (int i = int(dims.size()) - 2; i >= 0; --i) s[i] = s[i + 1] * dims[i + 1];
+  return s;
+}
+
+void *dev_alloc(size_t bytes) {
+  const char *f = std::getenv("CC_FAULT_INJECT");
+  if (f && std::strcmp(f, "alloc") == 0) throw CCError(CC_ENOMEM, "allocation failure injected (CC_FAULT_INJECT=alloc)");
+  void *ptr = nullptr;
+  if (bytes == 0) bytes = 16;
+  if (hipMalloc(&ptr, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    throw CCError(CC_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  return ptr;
+}
+
+struct Planner {
+  cc_plan *p;
+  int scratch = -1;        // shared buffer for GEMM outputs that need a permute
+  int64_t scratch_elems = 0;
+
+  int slot(const std::string &name) {
+    auto it = p->index.find(name);
+    if (it == p->index.end()) throw CCError(CC_EINTERNAL, "unknown tensor " + name);
+    return it->second;
+  }
+
+  int add_slot(const std::string &name, const std::string &spaces, bool constant, bool external,
+               bool owned) {
+    Slot s;
+    s.name = name;
+    s.spaces = spaces;
+    s.elems = 1;
+    for (char c : spaces) {
+      const int64_t d = (c == 'o') ? p->o : p->v;
+      s.dims.push_back(d);
+      s.elems *= d;
+    }
+    s.constant = constant;
+    s.external = external;
+    s.owned = owned;
+    p->slots.push_back(s);
+    const int id = int(p->slots.size()) - 1;
+    p->index[name] = id;
+    return id;
+  }
+
+  int add_work(const std::string &name, const std::vector<int64_t> &dims) {
+    Slot s;
+    s.name = name;
+    s.dims = dims;
+    s.elems = 1;
+    for (auto d : dims) s.elems *= d;
+    s.owned = true;
+    p->slots.push_back(s);
+    const int id = int(p->slots.size()) - 1;
+    p->index[name] = id;
+    return id;
+  }
+
+  std::vector<int64_t> label_dims(const std::string &l) {
+    std::vector<int64_t> d;
+    for (char c : l) d.push_back(dim_of(c, p->o, p->v));
+    return d;
+  }
+
+  void check_labels(int s, const std::string &l) {
+    const Slot &sl = p->slots[s];
+    if (sl.dims.size() != l.size()) throw CCError(CC_EINTERNAL, "rank mismatch for " + sl.name + "[" + l + "]");
+    if (!sl.spaces.empty())
+      for (size_t i = 0; i < l.size(); ++i)
+        if (space_of(l[i]) != sl.spaces[i])
+          throw CCError(CC_EINTERNAL, "space mismatch for " + sl.name + "[" + l + "]");
+  }
+
+  bool is_const(int s) { return p->slots[s].constant; }
+
+  std::vector<Step> &stream_for(int src) { return is_const(src) ? p->setup : p->iter; }
+
+  // dst[dl] (+)= alpha * conj?(src[sl]); beta decided by first touch.
+  void accumulate(int src, const std::string &sl, bool conj, int dst, const std::string &dl,
+                  double alpha, const char *swap, std::vector<Step> &out, bool force_first,
+                  const std::vector<int64_t> *src_dims = nullptr) {
+    const auto sst = dense_strides(src_dims ? *src_dims : p->slots[src].dims);
+    const auto dst_dims = p->slots[dst].dims;
+    const auto dstr = dense_strides(dst_dims);
+    auto make = [&](const std::string &lab, double a, double b) {
+      Step st;
+      st.kind = Step::PERMUTE;
+      st.a = src;
+      st.c = dst;
+      st.perm.rank = int(dl.size());
+      for (size_t d = 0; d < dl.size(); ++d) {
+        st.perm.out_dims[d] = dst_dims[d];
+        st.perm.out_strides[d] = dstr[d];
+        const size_t pos = sl.find(lab[d]);
+        if (pos == std::string::npos) throw CCError(CC_EINTERNAL, "label missing in accumulate");
+        st.perm.in_strides[d] = sst[pos];
+      }
+      st.perm.alpha = a;
+      st.perm.beta = b;
+      st.perm.conj = conj ? 1 : 0;
+      st.nelem = p->slots[dst].elems;
+      st.tag = p->slots[src].name + "[" + sl + "]->" + p->slots[dst].name + "[" + lab + "]";
+      out.push_back(st);
+    };
+    const bool first = force_first || !p->touched[dst];
+    make(dl, alpha, first ? 0.0 : 1.0);
+    if (swap) {
+      std::string sw = dl;
+      for (auto &c : sw) {
+        if (c == swap[0]) c = swap[1];
+        else if (c == swap[1]) c = swap[0];
+      }
+      make(sw, -alpha, 1.0);
+    }
+    p->touched[dst] = true;
+    p->version[dst]++;
+  }
+
+  // A view of tensor s with its labels rearranged to `target` (cached).
+  int view(int s, const std::string &sl, const std::string &target, bool conj) {
+    if (sl == target && !(conj && p->cplx)) return s;
+    const bool cj = conj && p->cplx;
+    std::string key = p->slots[s].name + "|" + target + "|" + (cj ? "c" : "n") + "|" +
+                      std::to_string(p->version[s]) + "|" + sl;
+    auto it = p->view_cache.find(key);
+    if (it != p->view_cache.end()) return it->second;
+    const int v = add_work(p->slots[s].name + "_" + target + (cj ? "_conj" : ""), label_dims(target));
+    p->slots[v].constant = is_const(s);
+    std::vector<Step> &out = stream_for(s);
+    // a fresh buffer: write with beta = 0
+    const bool saved = p->touched[v];
+    accumulate(s, sl, cj, v, target, 1.0, nullptr, out, true);
+    p->touched[v] = saved;
+    p->view_cache[key] = v;
+    return v;
+  }
+
+  static std::string order_in(const std::string &lab, const std::set<char> &set) {
+    std::string r;
+    for (char c : lab)
+      if (set.count(c)) r += c;
+    return r;
+  }
+
+  void contract(const OpSpec &op) {
+    const int c = slot(op.C), a = slot(op.A), b = slot(op.B);
+    const std::string cl = op.cl, al = op.al, bl = op.bl;
+    check_labels(c, cl);
+    check_labels(a, al);
+    check_labels(b, bl);
+    std::set<char> sA(al.begin(), al.end()), sB(bl.begin(), bl.end()), sC(cl.begin(), cl.end());
+    std::set<char> K;
+    for (char x : sA)
+      if (sB.count(x)) K.insert(x);
+    for (char x : sC)
+      if (!(sA.count(x) ^ sB.count(x))) throw CCError(CC_EINTERNAL, std::string("label ") + x + " of " + op.tag);
+    for (char x : K)
+      if (sC.count(x)) throw CCError(CC_EINTERNAL, "hadamard label");
+    if (K.empty()) return outer(op, c, a, b);
+
+    struct Cand {
+      bool swap;
+      std::string rows, cols, k;
+      bool xm, ym, cm, xkc, ykc;
+      double cost;
+    } best{};
+    best.cost = 1e300;
+    for (int sw = 0; sw < 2; ++sw) {
+      const int X = sw ? b : a, Y = sw ? a : b;
+      const std::string xl = sw ? bl : al, yl = sw ? al : bl;
+      std::set<char> rs, cs;
+      for (char x : xl)
+        if (sC.count(x)) rs.insert(x);
+      for (char x : yl)
+        if (sC.count(x)) cs.insert(x);
+      const std::string rowOpt[2] = {order_in(cl, rs), order_in(xl, rs)};
+      const std::string colOpt[2] = {order_in(cl, cs), order_in(yl, cs)};
+      const std::string kOpt[2] = {order_in(xl, K), order_in(yl, K)};
+      for (int ri = 0; ri < 2; ++ri)
+        for (int ci = 0; ci < 2; ++ci)
+          for (int ki = 0; ki < 2; ++ki) {
+            Cand cd;
+            cd.swap = sw;
+            cd.rows = rowOpt[ri];
+            cd.cols = colOpt[ci];
+            cd.k = kOpt[ki];
+            cd.xm = (xl == cd.rows + cd.k) || (xl == cd.k + cd.rows);
+            cd.xkc = (xl == cd.rows + cd.k);
+            cd.ym = (yl == cd.cols + cd.k) || (yl == cd.k + cd.cols);
+            cd.ykc = (yl == cd.cols + cd.k);
+            cd.cm = (cl == cd.rows + cd.cols) && op.swap == nullptr;
+            const bool cjx = (sw ? op.conjB : op.conjA) && p->cplx;
+            const bool cjy = (sw ? op.conjA : op.conjB) && p->cplx;
+            if (cjx) cd.xm = false;  // conjugation is applied while permuting
+            if (cjy) cd.ym = false;
+            double cost = 0.0;
+            auto opcost = [&](int s, bool matched) {
+              if (matched) return 0.0;
+              return (is_const(s) ? 0.01 : 2.0) * double(p->slots[s].elems);
+            };
+            cost += opcost(X, cd.xm) + opcost(Y, cd.ym);
+            if (!cd.cm) cost += 3.0 * double(p->slots[c].elems);
+            if (!(cd.xm ? cd.xkc : true)) cost += 1e-3;  // prefer K-contiguous panels
+            if (!(cd.ym ? cd.ykc : true)) cost += 1e-3;
+            cost += sw * 1e-6;
+            cd.cost = cost;
+            if (cd.cost < best.cost) best = cd;
+          }
+    }
+    const int X = best.swap ? b : a, Y = best.swap ? a : b;
+    const std::string xl = best.swap ? bl : al, yl = best.swap ? al : bl;
+    const bool cjx = (best.swap ? op.conjB : op.conjA), cjy = (best.swap ? op.conjA : op.conjB);
+    int xs = X, ys = Y;
+    bool xkc = best.xkc, ykc = best.ykc;
+    if (!best.xm) {
+      xs = view(X, xl, best.rows + best.k, cjx);
+      xkc = true;
+    }
+    if (!best.ym) {
+      ys = view(Y, yl, best.cols + best.k, cjy);
+      ykc = true;
+    }
+    int64_t M = 1, N = 1, Kd = 1;
+    for (char x : best.rows) M *= dim_of(x, p->o, p->v);
+    for (char x : best.cols) N *= dim_of(x, p->o, p->v);
+    for (char x : best.k) Kd *= dim_of(x, p->o, p->v);
+    Step g;
+    g.kind = Step::GEMM;
+    g.a = xs;
+    g.b = ys;
+    g.gemm.M = M;
+    g.gemm.N = N;
+    g.gemm.K = Kd;
+    g.gemm.sam = xkc ? Kd : 1;
+    g.gemm.sak = xkc ? 1 : M;
+    g.gemm.sbn = ykc ? Kd : 1;
+    g.gemm.sbk = ykc ? 1 : N;
+    g.gemm.ldc = N;
+    g.gemm.conj_a = 0;
+    g.gemm.conj_b = 0;
+    g.flops = (p->cplx ? 8.0 : 2.0) * double(M) * double(N) * double(Kd);
+    g.tag = op.tag;
+    g.tile = p->cplx ? -1 : gemm_f64_pick(M, N, Kd, xkc, ykc);
+    if (best.cm) {
+      g.c = c;
+      g.gemm.alpha = op.alpha;
+      g.gemm.beta = p->touched[c] ? 1.0 : 0.0;
+      p->touched[c] = true;
+      p->version[c]++;
+      p->iter.push_back(g);
+    } else {
+      const int64_t need = M * N;
+      if (need > scratch_elems) scratch_elems = need;
+      g.c = scratch;
+      g.gemm.alpha = op.alpha;
+      g.gemm.beta = 0.0;
+      p->iter.push_back(g);
+      const auto tdims = label_dims(best.rows + best.cols);
+      accumulate(scratch, best.rows + best.cols, false, c, cl, 1.0, op.swap, p->iter, false, &tdims);
+    }
+    p->flops_per_iter += g.flops;
+    if (std::string(op.tag) == "ladder") p->ladder_flops += g.flops;
+  }
+
+  void outer(const OpSpec &op, int c, int a, int b) {
+    if (op.swap) throw CCError(CC_EINTERNAL, "antisymmetrised outer product");
+    const std::string cl = op.cl, al = op.al, bl = op.bl;
+    if (!p->touched[c]) {
+      Step f;
+      f.kind = Step::FILL;
+      f.c = c;
+      f.nelem = p->slots[c].elems;
+      f.tag = "zero " + p->slots[c].name;
+      p->iter.push_back(f);
+      p->touched[c] = true;
+    }
+    Step st;
+    st.kind = Step::OUTER;
+    st.a = a;
+    st.b = b;
+    st.c = c;
+    st.outer.rank = int(cl.size());
+    const auto sa = dense_strides(p->slots[a].dims), sb = dense_strides(p->slots[b].dims);
+    for (size_t d = 0; d < cl.size(); ++d) {
+      st.outer.dims[d] = p->slots[c].dims[d];
+      const size_t pa = al.find(cl[d]), pb = bl.find(cl[d]);
+      st.outer.sa[d] = pa == std::string::npos ? 0 : sa[pa];
+      st.outer.sb[d] = pb == std::string::npos ? 0 : sb[pb];
+    }
+    st.outer.alpha = op.alpha;
+    st.outer.conj_a = op.conjA && p->cplx;
+    st.outer.conj_b = op.conjB && p->cplx;
+    st.nelem = p->slots[c].elems;
+    st.tag = op.tag;
+    p->iter.push_back(st);
+    p->version[c]++;
+  }
+
+  void unary(const OpSpec &op) {
+    const int c = slot(op.C), a = slot(op.A);
+    check_labels(c, op.cl);
+    check_labels(a, op.al);
+    accumulate(a, op.al, op.conjA && p->cplx, c, op.cl, op.alpha, op.swap, p->iter, false);
+    p->iter.back().tag = op.tag;
+  }
+
+  void build(const cc_system *sys) {
+    const bool ccsd = p->method == CC_CCSD;
+    const char *inputs[] = {"foo", "fov", "fvv", "oooo", "ooov", "oovv", "ovvo", "ovvv", "vvvv"};
+    const char *spaces[] = {"oo", "ov", "vv", "oooo", "ooov", "oovv", "ovvo", "ovvv", "vvvv"};
+    const void *ptrs[] = {sys->f_oo, sys->f_ov, sys->f_vv, sys->oooo, sys->ooov,
+                          sys->oovv, sys->ovvo, sys->ovvv, sys->vvvv};
+    for (int i = 0; i < 9; ++i) {
+      const int s = add_slot(inputs[i], spaces[i], true, false, false);
+      p->slots[s].ptr = const_cast<void *>(ptrs[i]);
+    }
+    add_slot("t1", "ov", false, true, false);
+    add_slot("t2", "oovv", false, true, false);
+    if (ccsd) {
+      add_slot("tau", "oovv", false, false, true);
+      add_slot("taut", "oovv", false, false, true);
+    } else {
+      p->index["tau"] = p->index["t2"];
+      p->index["taut"] = p->index["t2"];
+    }
+    const char *work[][2] = {{"Fme", "ov"},  {"Fae", "vv"},   {"Fmi", "oo"}, {"Wmnij", "oooo"},
+                             {"Wjbme", "ovov"}, {"Y", "ovov"}, {"XP", "oovv"}, {"Xij", "oovv"},
+                             {"Xab", "oovv"}, {"Xr", "oovv"},  {"R1", "ov"},   {"Zs", "oovo"},
+                             {"FF", "vv"},   {"GG", "oo"},    {"Q", "oovo"}};
+    for (auto &w : work) add_slot(w[0], w[1], false, false, true);
+    scratch = add_work("scratch", {1});
+
+    Step te;
+    te.kind = Step::TAU_E;
+    te.tag = "tau_energy";
+    p->iter.push_back(te);
+    for (const OpSpec &op : kOps) {
+      if (op.needs_t1 && !ccsd) continue;
+      if (op.B == nullptr) unary(op);
+      else contract(op);
+    }
+    for (const char *x : {"XP", "Xij", "Xab", "Xr"}) {
+      const int s = slot(x);
+      if (!p->touched[s]) {
+        Step f;
+        f.kind = Step::FILL;
+        f.c = s;
+        f.nelem = p->slots[s].elems;
+        f.tag = std::string("zero ") + x;
+        p->iter.push_back(f);
+      }
+    }
+    Step as;
+    as.kind = Step::ASSEMBLE;
+    as.tag = "r2_assemble_update";
+    p->iter.push_back(as);
+    if (ccsd) {
+      Step r1;
+      r1.kind = Step::R1UPD;
+      r1.tag = "r1_update";
+      p->iter.push_back(r1);
+    }
+    Step fin;
+    fin.kind = Step::FINALIZE;
+    fin.tag = "finalize";
+    p->iter.push_back(fin);
+    p->slots[scratch].dims = {scratch_elems};
+    p->slots[scratch].elems = scratch_elems;
+  }
+};
+
+void run_gemm(cc_plan *p, GemmDesc &d, int tile, hipStream_t s) {
+  if (p->cplx) gemm_c128(d, s);
+  else if (p->prec == PREC_F64) gemm_f64(d, s, tile);
+  else gemm_lowp(d, p->prec, s, tile);
+}
+
+void *ptr_of(cc_plan *p, int s) {
+  const Slot &sl = p->slots[s];
+  if (sl.external) return sl.name == "t1" ? p->t1 : p->t2;
+  return sl.ptr;
+}
+
+void exec(cc_plan *p, Step &st, hipStream_t s) {
+  const bool cplx = p->cplx;
+  switch (st.kind) {
+    case Step::PERMUTE:
+      if (cplx) permute_c128(st.perm, ptr_of(p, st.a), ptr_of(p, st.c), s);
+      else permute_f64(st.perm, ptr_of(p, st.a), ptr_of(p, st.c), s);
+      break;
+    case Step::GEMM: {
+      GemmDesc d = st.gemm;
+      d.A = ptr_of(p, st.a);
+      d.B = ptr_of(p, st.b);
+      d.C = ptr_of(p, st.c);
+      run_gemm(p, d, st.tile, s);
+      break;
+    }
+    case Step::OUTER:
+      outer_acc(st.outer, cplx, ptr_of(p, st.a), ptr_of(p, st.b), ptr_of(p, st.c), s);
+      break;
+    case Step::FILL:
+      fill_zero(ptr_of(p, st.c), st.nelem, cplx, s);
+      break;
+    case Step::TAU_E: {
+      const bool ccsd = p->method == CC_CCSD;
+      tau_energy(cplx, p->o, p->v, ccsd ? p->t1 : nullptr, p->t2, p->slots[p->index["oovv"]].ptr,
+                 p->slots[p->index["fov"]].ptr, ccsd ? p->slots[p->index["tau"]].ptr : nullptr,
+                 ccsd ? p->slots[p->index["taut"]].ptr : nullptr, p->epart, s);
+      break;
+    }
+    case Step::ASSEMBLE: {
+      R2Args a{p->o, p->v, p->d_oo, p->d_vv, p->shift};
+      r2_assemble(cplx, a, p->slots[p->index["XP"]].ptr, p->slots[p->index["Xij"]].ptr,
+                  p->slots[p->index["Xab"]].ptr, p->slots[p->index["Xr"]].ptr, p->r2_out,
+                  p->update ? p->t2 : nullptr, p->n2part, s);
+      break;
+    }
+    case Step::R1UPD: {
+      void *R1 = p->slots[p->index["R1"]].ptr;
+      if (p->r1_out)
+        CC_HIP_CHECK(hipMemcpyAsync(p->r1_out, R1, size_t(p->o) * p->v * p->esize,
+                                    hipMemcpyDeviceToDevice, s));
+      r1_update(cplx, p->o, p->v, R1, p->update ? p->t1 : nullptr, p->d_oo, p->d_vv, p->shift,
+                p->n1part, s);
+      break;
+    }
+    case Step::FINALIZE:
+      finalize_scalars(p->epart, p->n_epart, p->n2part, p->n_n2part,
+                       p->method == CC_CCSD ? p->n1part : nullptr, p->scalars, s);
+      break;
+  }
+}
+
+}  // namespace
+
+void plan_layout(cc_plan *p, const cc_system *sys) {
+  Planner pl{p};
+  pl.build(sys);
+}
+
+void plan_build(cc_plan *p, const cc_system *sys) {
+  plan_layout(p, sys);
+  // allocate owned slots
+  for (Slot &s : p->slots) {
+    if (!s.owned) continue;
+    const size_t bytes = size_t(std::max<int64_t>(s.elems, 1)) * p->esize;
+    s.ptr = dev_alloc(bytes);
+    p->workspace += bytes;
+  }
+  p->n_epart = tau_energy_blocks(p->o, p->v);
+  p->n_n2part = int(r2_assemble_blocks(p->o, p->v));
+  p->d_oo = static_cast<double *>(dev_alloc(sizeof(double) * p->o));
+  p->d_vv = static_cast<double *>(dev_alloc(sizeof(double) * p->v));
+  p->epart = static_cast<double *>(dev_alloc(sizeof(double) * 2 * p->n_epart));
+  p->n2part = static_cast<double *>(dev_alloc(sizeof(double) * p->n_n2part));
+  p->n1part = static_cast<double *>(dev_alloc(sizeof(double) * 2));
+  p->scalars = static_cast<double *>(dev_alloc(sizeof(double) * 4));
+  hipStream_t s = p->ctx->stream;
+  fock_diag(p->cplx, p->o, p->v, sys->f_oo, sys->f_vv, p->d_oo, p->d_vv, s);
+  fill_zero(p->n1part, 2, false, s);
+  for (Step &st : p->setup) exec(p, st, s);
+  CC_HIP_CHECK(hipStreamSynchronize(s));
+  for (Step &st : p->iter)
+    if (st.kind == Step::GEMM) p->gemm_steps.push_back(&st);
+}
+
+void plan_free(cc_plan *p) {
+  if (p->graph) (void)hipGraphExecDestroy(p->graph);
+  p->graph = nullptr;
+  for (Slot &s : p->slots)
+    if (s.owned && s.ptr) (void)hipFree(s.ptr);
+  for (double *q : {p->d_oo, p->d_vv, p->epart, p->n2part, p->n1part, p->scalars})
+    if (q) (void)hipFree(q);
+}
+
+void plan_run(cc_plan *p) {
+  hipStream_t s = p->ctx->stream;
+  for (Step &st : p->iter) exec(p, st, s);
+}
+
+void plan_run_energy(cc_plan *p) {
+  hipStream_t s = p->ctx->stream;
+  for (Step &st : p->iter)
+    if (st.kind == Step::TAU_E) exec(p, st, s);
+  finalize_scalars(p->epart, p->n_epart, p->n2part, 0, nullptr, p->scalars, s);
+}
+
+std::string plan_describe(const cc_plan *p) {
+  std::ostringstream os;
+  auto nm = [&](int s) { return s >= 0 ? p->slots[s].name : std::string("-"); };
+  auto dump = [&](const char *title, const std::vector<Step> &v) {
+    os << title << "\n";
+    for (const Step &st : v) {
+      switch (st.kind) {
+        case Step::PERMUTE:
+          os << "PERMUTE " << st.tag << " alpha=" << st.perm.alpha << " beta=" << st.perm.beta
+             << " conj=" << st.perm.conj << " in_strides=";
+          for (int d = 0; d < st.perm.rank; ++d) os << st.perm.in_strides[d] << (d + 1 < st.perm.rank ? "," : "");
+          os << " out_dims=";
+          for (int d = 0; d < st.perm.rank; ++d) os << st.perm.out_dims[d] << (d + 1 < st.perm.rank ? "," : "");
+          os << " out_strides=";
+          for (int d = 0; d < st.perm.rank; ++d) os << st.perm.out_strides[d] << (d + 1 < st.perm.rank ? "," : "");
+          os << " src=" << nm(st.a) << " dst=" << nm(st.c) << "\n";
+          break;
+        case Step::GEMM:
+          os << "GEMM " << st.tag << " A=" << nm(st.a) << " B=" << nm(st.b) << " C=" << nm(st.c)
+             << " M=" << st.gemm.M << " N=" << st.gemm.N << " K=" << st.gemm.K << " sam=" << st.gemm.sam
+             << " sak=" << st.gemm.sak << " sbn=" << st.gemm.sbn << " sbk=" << st.gemm.sbk
+             << " ldc=" << st.gemm.ldc << " alpha=" << st.gemm.alpha << " beta=" << st.gemm.beta
+             << " tile=" << (st.tile >= 0 ? gemm_f64_tile_name(st.tile) : "auto") << "\n";
+          break;
+        case Step::OUTER:
+          os << "OUTER " << st.tag << " A=" << nm(st.a) << " B=" << nm(st.b) << " C=" << nm(st.c)
+             << " alpha=" << st.outer.alpha << " sa=";
+          for (int d = 0; d < st.outer.rank; ++d) os << st.outer.sa[d] << (d + 1 < st.outer.rank ? "," : "");
+          os << " sb=";
+          for (int d = 0; d < st.outer.rank; ++d) os << st.outer.sb[d] << (d + 1 < st.outer.rank ? "," : "");
+          os << " dims=";
+          for (int d = 0; d < st.outer.rank; ++d) os << st.outer.dims[d] << (d + 1 < st.outer.rank ? "," : "");
+          os << " conj=" << st.outer.conj_a << st.outer.conj_b << "\n";
+          break;
+        case Step::FILL: os << "FILL " << nm(st.c) << "\n"; break;
+        default: os << "SPECIAL " << st.tag << "\n"; break;
+      }
+    }
+  };
+  dump("# setup", p->setup);
+  dump("# iteration", p->iter);
+  os << "# aliases\n";
+  for (const auto &kv : p->index)
+    if (p->slots[kv.second].name != kv.first) os << kv.first << " -> " << p->slots[kv.second].name << "\n";
+  os << "# slots\n";
+  for (const Slot &s : p->slots) {
+    os << s.name << " dims=";
+    for (size_t i = 0; i < s.dims.size(); ++i) os << s.dims[i] << (i + 1 < s.dims.size() ? "," : "");
+    os << (s.constant ? " const" : "") << (s.external ? " external" : "") << "\n";
+  }
+  return os.str();
+}
+
+}  // namespace ccmi

@@ -1,0 +1,96 @@
+// Contraction table, planner and executor of the residual path.
+#pragma once
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/cc.h"
+#include "kernels.hpp"
+
+struct cc_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string last_error;
+  double *pinned = nullptr;  // small pinned host buffer for scalar read-back
+};
+
+namespace ccmi {
+
+// One binary (or unary / outer-product) tensor operation of the contraction
+// list:  C[cl] += alpha * op(A)[al] * op(B)[bl], optionally followed by the
+// antisymmetriser P(xy) over two labels of C (swap = "xy").
+struct OpSpec {
+  const char *C, *cl;
+  double alpha;
+  const char *A, *al;
+  const char *B, *bl;  // B == nullptr: unary accumulate
+  bool conjA, conjB;
+  const char *swap;    // nullptr or two labels of C
+  bool needs_t1;       // skipped for CCD
+  const char *tag;     // short name for profiling
+};
+
+struct Slot {
+  std::string name, spaces;
+  std::vector<int64_t> dims;
+  int64_t elems = 0;
+  void *ptr = nullptr;
+  bool constant = false;  // integrals / Fock: unchanged for the plan's lifetime
+  bool owned = false;     // allocated by the plan
+  bool external = false;  // amplitudes / residual supplied per call
+};
+
+struct Step {
+  enum Kind { PERMUTE, GEMM, OUTER, FILL, TAU_E, ASSEMBLE, R1UPD, FINALIZE } kind;
+  int a = -1, b = -1, c = -1;
+  PermDesc perm{};
+  GemmDesc gemm{};
+  OuterArgs outer{};
+  int tile = -1;
+  int64_t nelem = 0;
+  double flops = 0.0;
+  std::string tag;
+};
+
+}  // namespace ccmi
+
+struct cc_plan {
+  cc_ctx *ctx = nullptr;
+  int o = 0, v = 0, method = 0, prec = 0;
+  bool cplx = false;
+  size_t esize = 8;
+  std::vector<ccmi::Slot> slots;
+  std::map<std::string, int> index;
+  std::vector<ccmi::Step> setup, iter;
+  std::map<std::string, int> view_cache;  // (tensor, labels, conj, version) -> slot
+  std::map<int, int> version;             // writes seen so far while planning
+  std::map<int, bool> touched;            // first write of an iteration uses beta = 0
+  size_t workspace = 0;
+  // scalar machinery (device)
+  double *d_oo = nullptr, *d_vv = nullptr;
+  double *epart = nullptr, *n2part = nullptr, *n1part = nullptr, *scalars = nullptr;
+  int n_epart = 0, n_n2part = 0;
+  // per-call state
+  void *t1 = nullptr, *t2 = nullptr, *r1_out = nullptr, *r2_out = nullptr;
+  bool update = false;
+  double shift = 0.0;
+  // graph replay
+  hipGraphExec_t graph = nullptr;
+  void *graph_key[4] = {nullptr, nullptr, nullptr, nullptr};
+  double graph_shift = 0.0;
+  bool graph_update = false;
+  double flops_per_iter = 0.0, ladder_flops = 0.0;
+  std::vector<ccmi::Step *> gemm_steps;
+};
+
+namespace ccmi {
+void plan_layout(cc_plan *p, const cc_system *sys);  // planning only, no device work
+void plan_build(cc_plan *p, const cc_system *sys);
+void plan_free(cc_plan *p);
+void plan_run(cc_plan *p);           // enqueue one residual (+ update) on the stream
+void plan_run_energy(cc_plan *p);    // tau + energy only
+std::string plan_describe(const cc_plan *p);
+void plan_autotune(cc_plan *p);
+}  // namespace ccmi

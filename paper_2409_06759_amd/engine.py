@@ -1,0 +1,218 @@
+"""Python front end of the engine: device tensors from PyTorch, every
+computation in the HIP library behind ``include/cc.h``."""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+CCD, CCSD = L.CC_CCD, L.CC_CCSD
+F64, F32, BF16X3 = L.CC_PREC_F64, L.CC_PREC_F32, L.CC_PREC_BF16X3
+METHODS = {"ccd": CCD, "ccsd": CCSD}
+PRECS = {"f64": F64, "f32": F32, "bf16x3": BF16X3}
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class Context:
+    """A library context bound to one device and one stream (torch's
+    current stream of that device unless given)."""
+
+    def __init__(self, device: int = 0, stream: Optional["torch.cuda.Stream"] = None):
+        self.lib = L.load()
+        self.device = device
+        # A stream of its own (default priority) so that one iteration can be
+        # captured as a graph; every call is ordered against torch's current
+        # stream on entry and exit.
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
+        self.h = C.c_void_p()
+        rc = self.lib.cc_create(C.byref(self.h), device, C.c_void_p(self.stream.cuda_stream))
+        if rc != 0:
+            raise L.CCError(rc, self.lib.cc_last_error(None).decode())
+
+    def check(self, rc: int, ok=(0,)):
+        cur = torch.cuda.current_stream(self.device)
+        cur.wait_stream(self.stream)
+        if rc not in ok:
+            raise L.CCError(rc, self.lib.cc_last_error(self.h).decode())
+        return rc
+
+    def enter(self):
+        """Order the library stream after the work queued so far by torch."""
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+
+    def close(self):
+        if self.h:
+            self.lib.cc_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+class DeviceSystem:
+    """Fock and integral blocks of one system resident in device memory."""
+
+    NAMES = ("f_oo", "f_ov", "f_vv", "oooo", "ooov", "oovv", "ovvo", "ovvv", "vvvv")
+
+    def __init__(self, sysm, device: str = "cuda", drop_host: bool = False):
+        self.o, self.v = sysm.o, sysm.v
+        self.is_complex = sysm.is_complex
+        self.dtype = torch.complex128 if sysm.is_complex else torch.float64
+        self.t = {}
+        for n in self.NAMES:
+            if n.startswith("f_"):
+                arr = getattr(sysm, n)
+            else:
+                arr = sysm.block(n)
+            self.t[n] = torch.from_numpy(np.ascontiguousarray(arr)).to(device)
+            if drop_host and not n.startswith("f_"):
+                sysm.drop(n)
+        self.struct = L.CCSystemStruct(self.o, self.v, L.CC_C128 if self.is_complex else L.CC_R64,
+                                       *[self.t[n].data_ptr() for n in self.NAMES])
+
+    @classmethod
+    def from_tensors(cls, o, v, tensors: dict):
+        self = cls.__new__(cls)
+        self.o, self.v = o, v
+        self.dtype = tensors["oovv"].dtype
+        self.is_complex = self.dtype == torch.complex128
+        self.t = {n: tensors[n].contiguous() for n in cls.NAMES}
+        self.struct = L.CCSystemStruct(o, v, L.CC_C128 if self.is_complex else L.CC_R64,
+                                       *[self.t[n].data_ptr() for n in cls.NAMES])
+        return self
+
+
+def zeros_amps(dsys: DeviceSystem, method: int):
+    o, v = dsys.o, dsys.v
+    dev = dsys.t["oovv"].device
+    t2 = torch.zeros((o, o, v, v), dtype=dsys.dtype, device=dev)
+    t1 = torch.zeros((o, v), dtype=dsys.dtype, device=dev) if method == CCSD else None
+    return t1, t2
+
+
+def _amps(t1, t2):
+    return L.CCAmps(None if t1 is None else t1.data_ptr(), t2.data_ptr())
+
+
+class Plan:
+    def __init__(self, ctx: Context, dsys: DeviceSystem, method: int = CCSD, prec: int = F64):
+        self.ctx, self.dsys, self.method = ctx, dsys, method
+        self.h = C.c_void_p()
+        ctx.enter()
+        ctx.check(ctx.lib.cc_plan_create(ctx.h, C.byref(dsys.struct), method, prec, C.byref(self.h)))
+
+    def residual(self, t1, t2, want_r=True):
+        r1 = r2 = None
+        if want_r:
+            r2 = torch.empty_like(t2)
+            r1 = torch.empty_like(t1) if t1 is not None else None
+        rn = C.c_double()
+        ra = _amps(r1, r2) if want_r else None
+        self.ctx.enter()
+        self.ctx.check(self.ctx.lib.cc_plan_residual(self.h, C.byref(_amps(t1, t2)),
+                                                     C.byref(ra) if ra is not None else None,
+                                                     C.byref(rn)))
+        return r1, r2, rn.value
+
+    def step(self, t1, t2, shift: float = 0.0):
+        self.ctx.enter()
+        self.ctx.check(self.ctx.lib.cc_plan_step(self.h, C.byref(_amps(t1, t2)), shift))
+
+    def scalars(self):
+        rn, er, ei = C.c_double(), C.c_double(), C.c_double()
+        self.ctx.check(self.ctx.lib.cc_plan_scalars(self.h, C.byref(rn), C.byref(er), C.byref(ei)))
+        return rn.value, er.value, ei.value
+
+    def describe(self) -> str:
+        return self.ctx.lib.cc_plan_describe(self.h).decode()
+
+    def flops(self, ladder_only=False) -> float:
+        return self.ctx.lib.cc_plan_flops(self.h, 1 if ladder_only else 0)
+
+    def workspace_bytes(self) -> int:
+        return self.ctx.lib.cc_plan_workspace_bytes(self.h)
+
+    def close(self):
+        if self.h:
+            self.ctx.lib.cc_plan_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def residual(ctx, dsys, method, t1, t2, prec=F64):
+    r2 = torch.empty_like(t2)
+    r1 = torch.empty_like(t1) if t1 is not None else None
+    rn = C.c_double()
+    ctx.enter()
+    ctx.check(ctx.lib.cc_residual(ctx.h, C.byref(dsys.struct), method, prec, C.byref(_amps(t1, t2)),
+                                  C.byref(_amps(r1, r2)), C.byref(rn)))
+    return r1, r2, rn.value
+
+
+def energy(ctx, dsys, method, t1, t2):
+    er, ei = C.c_double(), C.c_double()
+    ctx.enter()
+    ctx.check(ctx.lib.cc_energy(ctx.h, C.byref(dsys.struct), method, C.byref(_amps(t1, t2)),
+                                C.byref(er), C.byref(ei)))
+    return complex(er.value, ei.value) if dsys.is_complex else er.value
+
+
+def iterate(ctx, dsys, method, t1, t2, tol=1e-8, max_iter=100, level_shift=0.0, prec=F64,
+            use_graph=True, refine_every=0, diverge_window=0, hist_cap=None):
+    cap = hist_cap or max_iter
+    hr = (C.c_double * cap)()
+    he = (C.c_double * cap)()
+    opts = L.CCIterOpts(tol, max_iter, prec, level_shift, refine_every, 1 if use_graph else 0, 1,
+                        diverge_window)
+    rep = L.CCIterReport(0, 0, 0.0, 0.0, 0.0, 0.0, 0.0, C.cast(hr, C.POINTER(C.c_double)),
+                         C.cast(he, C.POINTER(C.c_double)), cap)
+    ctx.enter()
+    rc = ctx.lib.cc_iterate(ctx.h, C.byref(dsys.struct), method, C.byref(opts), C.byref(_amps(t1, t2)),
+                            C.byref(rep))
+    ctx.check(rc, ok=(L.CC_OK, L.CC_ENOTCONV, L.CC_EDIVERGED))
+    n = min(rep.iters, cap)
+    return {"status": rc, "iters": rep.iters, "converged": bool(rep.converged), "rnorm": rep.rnorm,
+            "energy": complex(rep.e_re, rep.e_im) if dsys.is_complex else rep.e_re,
+            "seconds": rep.seconds, "setup_seconds": rep.setup_seconds,
+            "hist_rnorm": list(hr[:n]), "hist_e": list(he[:n])}
+
+
+def gemm(ctx, A, B, Cm, alpha=1.0, beta=0.0, a_kcontig=True, b_kcontig=True, prec=F64):
+    """C = alpha * A' B'^T + beta * C with A' (M x K), B' (N x K).  A is stored
+    [M][K] if a_kcontig else [K][M]; B is [N][K] if b_kcontig else [K][N]."""
+    M, N = Cm.shape
+    K = A.shape[1] if a_kcontig else A.shape[0]
+    sam, sak = (K, 1) if a_kcontig else (1, M)
+    sbn, sbk = (K, 1) if b_kcontig else (1, N)
+    scalar = L.CC_C128 if Cm.dtype == torch.complex128 else L.CC_R64
+    ctx.enter()
+    ctx.check(ctx.lib.cc_gemm(ctx.h, prec, scalar, M, N, K, alpha, _ptr(A), sam, sak, _ptr(B), sbn, sbk,
+                              beta, _ptr(Cm), N))
+
+
+def permute(ctx, x, perm, out=None, alpha=1.0, beta=0.0):
+    """out = alpha * x.permute(perm) + beta * out (dense result)."""
+    shape = [x.shape[p] for p in perm]
+    if out is None:
+        out = torch.empty(shape, dtype=x.dtype, device=x.device)
+    dims = (C.c_int64 * x.dim())(*x.shape)
+    pr = (C.c_int32 * x.dim())(*perm)
+    scalar = L.CC_C128 if x.dtype == torch.complex128 else L.CC_R64
+    ctx.enter()
+    ctx.check(ctx.lib.cc_permute(ctx.h, scalar, x.dim(), dims, pr, alpha, _ptr(x), beta, _ptr(out)))
+    return out

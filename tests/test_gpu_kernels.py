@@ -1,0 +1,74 @@
+"""Kernel-level parity on the GPU: the MFMA GEMM against numpy.matmul in
+FP64 and the LDS-tiled permutation against numpy transposes (exact)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2409_06759_amd import engine as E
+    c = E.Context(0)
+    yield c
+    c.close()
+
+
+SHAPES = [(1, 1, 1), (16, 16, 16), (17, 33, 65), (64, 576, 576), (100, 129, 37), (257, 300, 49),
+          (1024, 160, 96)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("akc", [True, False])
+@pytest.mark.parametrize("bkc", [True, False])
+def test_gemm_f64_matches_numpy(ctx, shape, akc, bkc):
+    from paper_2409_06759_amd import engine as E
+    M, N, K = shape
+    print(f"gemm M={M} N={N} K={K} akc={akc} bkc={bkc}", flush=True)
+    rng = np.random.default_rng(M * 7 + N * 3 + K)
+    A = rng.normal(size=(M, K))
+    B = rng.normal(size=(N, K))
+    C0 = rng.normal(size=(M, N))
+    alpha, beta = 0.5, -1.25
+    ref = alpha * (A @ B.T) + beta * C0
+    Ad = torch.from_numpy(A if akc else np.ascontiguousarray(A.T)).cuda()
+    Bd = torch.from_numpy(B if bkc else np.ascontiguousarray(B.T)).cuda()
+    Cd = torch.from_numpy(C0).cuda()
+    E.gemm(ctx, Ad, Bd, Cd, alpha, beta, a_kcontig=akc, b_kcontig=bkc)
+    got = Cd.cpu().numpy()
+    bound = 2 * K * np.finfo(np.float64).eps * (abs(alpha) * (np.abs(A) @ np.abs(B).T) + abs(beta) * np.abs(C0))
+    assert np.all(np.abs(got - ref) <= bound + 1e-300), np.abs(got - ref).max()
+
+
+def test_gemm_beta_zero_ignores_nan(ctx):
+    from paper_2409_06759_amd import engine as E
+    A = torch.ones((33, 20), dtype=torch.float64, device="cuda")
+    B = torch.ones((45, 20), dtype=torch.float64, device="cuda")
+    Cd = torch.full((33, 45), float("nan"), dtype=torch.float64, device="cuda")
+    E.gemm(ctx, A, B, Cd, 1.0, 0.0)
+    assert torch.all(Cd == 20.0)
+
+
+@pytest.mark.parametrize("dims,perm", [((5, 7), (1, 0)), ((3, 40, 33, 5), (0, 2, 1, 3)),
+                                       ((6, 6, 35, 35), (2, 0, 3, 1)), ((4, 5, 6, 7), (3, 2, 1, 0)),
+                                       ((3, 4, 5, 6, 7), (4, 0, 3, 1, 2)),
+                                       ((2, 3, 4, 5, 6, 7), (5, 4, 3, 2, 1, 0))])
+def test_permute_exact(ctx, dims, perm):
+    from paper_2409_06759_amd import engine as E
+    rng = np.random.default_rng(len(dims))
+    x = rng.normal(size=dims)
+    got = E.permute(ctx, torch.from_numpy(x).cuda(), perm).cpu().numpy()
+    assert np.array_equal(got, np.ascontiguousarray(x.transpose(perm)))
+
+
+def test_permute_accumulate(ctx):
+    from paper_2409_06759_amd import engine as E
+    rng = np.random.default_rng(5)
+    x = rng.normal(size=(9, 37, 8, 41))
+    y = rng.normal(size=(9, 8, 41, 37))
+    out = torch.from_numpy(y).cuda()
+    E.permute(ctx, torch.from_numpy(x).cuda(), (0, 2, 3, 1), out=out, alpha=2.0, beta=-1.0)
+    ref = 2.0 * x.transpose(0, 2, 3, 1) - y
+    assert np.abs(out.cpu().numpy() - ref).max() < 1e-14

@@ -1,0 +1,177 @@
+"""HIP path against the CPU oracle through the C ABI (GPU).
+
+Tolerances (FP64 everywhere): residual elements agree to 1e-12 absolute
+(terms are O(1e-2); summation order differs between einsum and the
+MFMA tiles); energies along a Jacobi trajectory agree to 1e-12 Eh; the
+residual's (ij) and (ab) antisymmetry holds bitwise.
+"""
+import numpy as np
+import pytest
+
+from ccinputs.synth import make_system
+from oracle.cc import Fock, denominators, energy, jacobi, residual
+from oracle.integrals import Integrals
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def E():
+    from paper_2409_06759_amd import engine
+    return engine
+
+
+@pytest.fixture(scope="module")
+def ctx(E):
+    c = E.Context(0)
+    yield c
+    c.close()
+
+
+def _amps(o, v, seed, scale=0.01, cplx=False):
+    rng = np.random.default_rng(seed)
+    t1 = rng.normal(size=(o, v)) * scale
+    t2 = rng.normal(size=(o, o, v, v)) * scale
+    if cplx:
+        t1 = t1 + 1j * rng.normal(size=(o, v)) * scale
+        t2 = t2 + 1j * rng.normal(size=(o, o, v, v)) * scale
+    t2 = t2 - t2.transpose(1, 0, 2, 3)
+    t2 = t2 - t2.transpose(0, 1, 3, 2)
+    return t1, t2
+
+
+@pytest.mark.parametrize("method", ["ccd", "ccsd"])
+@pytest.mark.parametrize("ov", [(3, 5), (8, 24), (12, 37), (5, 70)])
+def test_residual_matches_oracle(E, ctx, method, ov):
+    o, v = ov
+    print(f"residual {method} o={o} v={v}", flush=True)
+    s = make_system(o, v, 1000 + o * v)
+    t1, t2 = _amps(o, v, o + v)
+    if method == "ccd":
+        t1 = None
+    F, V = Fock.from_system(s), Integrals.from_system(s)
+    r1_ref, r2_ref = residual(F, V, t1, t2)
+    d = E.DeviceSystem(s)
+    T1 = torch.from_numpy(t1).cuda() if t1 is not None else None
+    T2 = torch.from_numpy(t2).cuda()
+    r1, r2, rn = E.residual(ctx, d, E.METHODS[method], T1, T2)
+    r2 = r2.cpu().numpy()
+    assert np.abs(r2 - r2_ref).max() < 1e-12
+    if method == "ccsd":
+        assert np.abs(r1.cpu().numpy() - r1_ref).max() < 1e-12
+    # bitwise antisymmetry and exact zeros on the diagonals
+    assert np.array_equal(r2, -r2.transpose(1, 0, 2, 3))
+    assert np.array_equal(r2, -r2.transpose(0, 1, 3, 2))
+    nref = np.sqrt(np.sum(np.abs(r2_ref) ** 2) + (np.sum(np.abs(r1_ref) ** 2) if r1_ref is not None else 0))
+    assert abs(rn - nref) < 1e-12 * max(1.0, nref)
+    e = E.energy(ctx, d, E.METHODS[method], T1, T2)
+    assert abs(e - energy(F, V, t1, t2)) < 1e-13
+
+
+def test_complex_not_yet_rejected_cleanly(E, ctx):
+    s = make_system(3, 5, 9, is_complex=True)
+    d = E.DeviceSystem(s)
+    t1 = torch.zeros((3, 5), dtype=torch.complex128, device="cuda")
+    t2 = torch.zeros((3, 3, 5, 5), dtype=torch.complex128, device="cuda")
+    try:
+        E.residual(ctx, d, E.CCSD, t1, t2)
+    except Exception as exc:  # complex GEMM may be unavailable: must be a clean error
+        assert "complex" in str(exc) or "-6" in str(exc)
+
+
+def test_ccd_c1_trajectory(E, ctx):
+    """o=8, v=24 CCD: ten Jacobi iterations from t = 0 (first = MP2)."""
+    o, v = 8, 24
+    s = make_system(o, v)
+    F, V = Fock.from_system(s), Integrals.from_system(s)
+    ref = jacobi(F, V, "ccd", tol=0.0, max_iter=10)
+    d = E.DeviceSystem(s)
+    _, t2 = E.zeros_amps(d, E.CCD)
+    out = E.iterate(ctx, d, E.CCD, None, t2, tol=1e-30, max_iter=10, use_graph=True)
+    assert out["iters"] == 10
+    assert np.allclose(out["hist_e"], ref["hist_e"], rtol=0, atol=1e-12)
+    assert np.allclose(out["hist_rnorm"], ref["hist_r"], rtol=1e-10, atol=1e-14)
+    _, d2 = denominators(F)
+    g = V.get("oovv")
+    assert abs(out["hist_e"][1] - 0.25 * np.sum(g * g / d2)) < 1e-13
+
+
+def test_ccsd_converges_like_oracle(E, ctx):
+    o, v = 8, 24
+    s = make_system(o, v)
+    F, V = Fock.from_system(s), Integrals.from_system(s)
+    ref = jacobi(F, V, "ccsd", tol=1e-8, max_iter=60)
+    d = E.DeviceSystem(s)
+    t1, t2 = E.zeros_amps(d, E.CCSD)
+    out = E.iterate(ctx, d, E.CCSD, t1, t2, tol=1e-8, max_iter=60)
+    assert out["converged"] and ref["converged"]
+    assert out["iters"] == ref["iters"]
+    assert abs(out["energy"] - ref["energy"]) < 1e-12
+    assert np.allclose(out["hist_e"], ref["hist_e"], rtol=0, atol=1e-12)
+
+
+def test_level_shift_trajectory(E, ctx):
+    o, v = 6, 30
+    s = make_system(o, v, 77)
+    F, V = Fock.from_system(s), Integrals.from_system(s)
+    ref = jacobi(F, V, "ccsd", tol=0.0, max_iter=6, level_shift=1.5)
+    d = E.DeviceSystem(s)
+    t1, t2 = E.zeros_amps(d, E.CCSD)
+    out = E.iterate(ctx, d, E.CCSD, t1, t2, tol=1e-30, max_iter=6, level_shift=1.5, use_graph=False)
+    assert np.allclose(out["hist_e"], ref["hist_e"], rtol=0, atol=1e-12)
+    assert np.abs(t2.cpu().numpy() - ref["t2"]).max() < 1e-12  # t_6 on both sides
+    assert np.abs(t1.cpu().numpy() - ref["t1"]).max() < 1e-12
+
+
+def test_graph_replay_is_bitwise_eager(E, ctx):
+    o, v = 6, 22
+    s = make_system(o, v, 5)
+    d = E.DeviceSystem(s)
+    a1, a2 = E.zeros_amps(d, E.CCSD)
+    b1, b2 = E.zeros_amps(d, E.CCSD)
+    ra = E.iterate(ctx, d, E.CCSD, a1, a2, tol=1e-30, max_iter=5, use_graph=True)
+    rb = E.iterate(ctx, d, E.CCSD, b1, b2, tol=1e-30, max_iter=5, use_graph=False)
+    assert ra["hist_e"] == rb["hist_e"] and ra["hist_rnorm"] == rb["hist_rnorm"]
+    assert torch.equal(a2, b2) and torch.equal(a1, b1)
+
+
+def test_plan_step_matches_iterate(E, ctx):
+    o, v = 5, 19
+    s = make_system(o, v, 8)
+    d = E.DeviceSystem(s)
+    t1, t2 = E.zeros_amps(d, E.CCSD)
+    with E.Plan(ctx, d, E.CCSD) as p:
+        hist = []
+        for _ in range(4):
+            p.step(t1, t2, 0.0)
+            hist.append(p.scalars()[1])
+    u1, u2 = E.zeros_amps(d, E.CCSD)
+    out = E.iterate(ctx, d, E.CCSD, u1, u2, tol=1e-30, max_iter=4, use_graph=False)
+    assert hist == out["hist_e"]
+    assert torch.equal(t2, u2)
+
+
+def test_abi_errors_on_device(E, ctx):
+    from paper_2409_06759_amd import _lib as L
+    s = make_system(3, 5, 1)
+    d = E.DeviceSystem(s)
+    t1, t2 = E.zeros_amps(d, E.CCSD)
+    with pytest.raises(L.CCError) as ei:  # CCD must not get t1
+        E.residual(ctx, d, E.CCD, t1, t2)
+    assert ei.value.status == L.CC_EINVAL
+    bad = torch.zeros(3 * 3 * 5 * 5 + 1, dtype=torch.float64, device="cuda")[1:].view(3, 3, 5, 5)
+    with pytest.raises(L.CCError) as ei:  # misaligned pointer
+        E.residual(ctx, d, E.CCD, None, bad)
+    assert ei.value.status == L.CC_EINVAL
+    nan_sys = make_system(3, 5, 1)
+    blk = nan_sys.block("oovv").copy()
+    blk[0, 1, 0, 1] = np.nan
+    nan_sys._blocks["oovv"] = blk
+    dn = E.DeviceSystem(nan_sys)
+    u1, u2 = E.zeros_amps(dn, E.CCSD)
+    out = E.iterate(ctx, dn, E.CCSD, u1, u2, tol=1e-8, max_iter=5)
+    assert out["status"] == L.CC_EDIVERGED
+    u1, u2 = E.zeros_amps(d, E.CCSD)
+    out = E.iterate(ctx, d, E.CCSD, u1, u2, tol=1e-8, max_iter=1)
+    assert out["status"] == L.CC_ENOTCONV

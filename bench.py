@@ -1,0 +1,199 @@
+"""Benchmark of the CCSD residual path on one MI355X.
+
+One step = one Jacobi iteration of spin-orbital CCSD: tau formation and the
+energy, every binary contraction of the residual (ladder, ring, hh ladder,
+Z, intermediates, singles), the antisymmetrising assembly, the denominator
+update and the residual norm.  Workload: o = 32 occupied, v = 160 virtual
+spin orbitals, FP64, seeded random antisymmetrised integrals (sigma = 0.01),
+diagonal Fock with occupied energies in [-2, -0.5] and virtual in [0.5, 3].
+
+Prints one JSON line.  `value` is the algorithmic dense FLOP rate of a step
+(inputs resident in HBM); `roofline` is the ladder GEMM's rate measured with
+HIP events on the library stream during the timed steps; `cpu_baseline` is
+the FP64 NumPy oracle timed on the host for one residual evaluation.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import pathlib
+import sys
+import time
+
+ROOT = pathlib.Path(__file__).resolve().parent
+sys.path.insert(0, str(ROOT))
+
+PEAK_FP64_TFLOPS = 78.6  # MI355X dense FP64 matrix peak (published)
+CONFIGS = {
+    "c2": dict(o=32, v=160, method="ccsd"),
+    "c1": dict(o=8, v=24, method="ccd"),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("gemm_f64.hip", "common.hpp"):
+        h.update((ROOT / "paper_2409_06759_amd" / "csrc" / f).read_bytes())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(config: str):
+    """HBM bytes per ladder launch from the committed counter summary, if it
+    was taken from the current GEMM source."""
+    f = ROOT / "profiles" / f"ladder_{config}_traffic.json"
+    if not f.exists():
+        return None
+    try:
+        d = json.loads(f.read_text())
+    except Exception:
+        return None
+    if d.get("gemm_source_hash") != source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(sysm, method, flops_per_step):
+    import numpy as np
+    from oracle.cc import Fock, residual
+    from oracle.integrals import Integrals
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max((d.get("num_threads", 1) for d in threadpool_info()), default=os.cpu_count())
+    except Exception:
+        cores = os.cpu_count()
+    F, V = Fock.from_system(sysm), Integrals.from_system(sysm)
+    o, v = sysm.o, sysm.v
+    rng = np.random.default_rng(1)
+    t2 = rng.normal(size=(o, o, v, v)) * 1e-3
+    t2 = t2 - t2.transpose(1, 0, 2, 3)
+    t2 = t2 - t2.transpose(0, 1, 3, 2)
+    t1 = rng.normal(size=(o, v)) * 1e-3 if method == "ccsd" else None
+    t0 = time.perf_counter()
+    residual(F, V, t1, t2)
+    el = time.perf_counter() - t0
+    return {"value": flops_per_step / el / 1e12, "unit": "TFLOP/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"one {method.upper()} residual evaluation (unfactorised einsum oracle, FP64) at "
+                      f"o={o} v={v}: {el:.1f} s", "seconds": el}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
+    ap.add_argument("--shift", type=float, default=0.0, help="level shift of the Jacobi update")
+    ap.add_argument("--bare", action="store_true", help="bare Fock denominators instead of dressed")
+    ap.add_argument("--no-converge", action="store_true", help="skip the time-to-1e-8 run")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--max-iter", type=int, default=1500)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 1 GiB copy (for HBM counter scaling)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path has no "
+              "multi-GPU mode in this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from ccinputs.synth import make_system
+    from paper_2409_06759_amd import engine as E
+
+    cfg = CONFIGS[args.config]
+    o, v, method = cfg["o"], cfg["v"], cfg["method"]
+    m = E.METHODS[method]
+    t0 = time.time()
+    sysm = make_system(o, v)
+    dsys = E.DeviceSystem(sysm, drop_host=args.no_cpu_baseline)
+    log(f"[bench] system o={o} v={v} {method} generated and resident in HBM ({time.time() - t0:.1f}s)")
+    ctx = E.Context(0)
+    plan = E.Plan(ctx, dsys, m)
+    flops = plan.flops()
+    ladder_flops = plan.flops(ladder_only=True)
+    t1, t2 = E.zeros_amps(dsys, m)
+    dressed = not args.bare
+    plan.step(t1, t2, args.shift, dressed)
+    torch.cuda.synchronize()
+    plan.autotune(t1, t2, 2)
+    for _ in range(args.warmup):
+        plan.step(t1, t2, args.shift, dressed)
+    torch.cuda.synchronize()
+    log(f"[bench] warmup done ({args.warmup} steps)")
+
+    plan.profile(True)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    for _ in range(args.steps):
+        plan.step(t1, t2, args.shift, dressed)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - ts
+    rows = plan.profile_table()
+    plan.profile(False)
+    ms_per_step = el / args.steps * 1e3
+    value = flops / (el / args.steps) / 1e12
+    lad = [r for r in rows if r[1] == "GEMM" and r[2].startswith("ladder@")]
+    lad_ms = lad[0][5] if lad else float("nan")
+    achieved = ladder_flops / (lad_ms / 1e3) / 1e12 if lad else None
+    log(f"[bench] {args.steps} steps: {ms_per_step:.2f} ms/step, {value:.2f} TFLOP/s; ladder {lad_ms:.3f} ms "
+        f"({achieved:.2f} TFLOP/s)")
+    top = sorted(rows, key=lambda r: -r[4])[:8]
+    for r in top:
+        log(f"[bench]   {r[1]:8s} {r[2]:44s} {r[5]:8.3f} ms")
+
+    if args.copy_calibration:
+        n = 1 << 27  # 1 GiB of doubles, copied by the library's flat permute kernel
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        E.permute(ctx, src, (0,))
+        torch.cuda.synchronize()
+        log("[bench] copy calibration: 1 GiB read + 1 GiB write")
+
+    conv = {}
+    if not args.no_converge:
+        u1, u2 = E.zeros_amps(dsys, m)
+        out = E.iterate(ctx, dsys, m, u1, u2, tol=1e-8, max_iter=args.max_iter, level_shift=args.shift,
+                        dressed=dressed, use_graph=True)
+        conv = {"converged": out["converged"], "iterations": out["iters"], "seconds": round(out["seconds"], 3),
+                "energy": out["energy"], "rnorm": out["rnorm"]}
+        gold = ROOT / "tests" / "golden" / f"{args.config}_{method}_energy.json"
+        if gold.exists():
+            g = json.loads(gold.read_text())
+            conv["oracle_energy"] = g["energy"]
+            conv["abs_err_vs_oracle"] = abs(out["energy"] - g["energy"])
+        log(f"[bench] time to ||R||<1e-8: {out['seconds']:.2f}s, {out['iters']} iterations, E={out['energy']:.10f}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle (one residual evaluation)...")
+        cpu = cpu_baseline(sysm, method, flops)
+        log(f"[bench] oracle: {cpu['seconds']:.1f}s per residual -> {cpu['value']:.4f} TFLOP/s")
+
+    line = {
+        "metric": "CCSD residual TFLOP/s & time-to-1e-8 convergence, FP64 vs mixed/learned",
+        "value": round(value, 3), "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{method} o={o} v={v} fp64 real, seeded antisymmetrised <pq||rs>~N(0,0.01^2), "
+                               f"diagonal Fock", "o": o, "v": v, "method": method,
+                   "update": ("dressed" if dressed else "bare") + f" Jacobi, shift {args.shift}",
+                   "flops_per_step": flops},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3) if achieved else None,
+                     "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_FP64_TFLOPS, 4) if achieved else None,
+                     "traffic": read_traffic(args.config), "kernel": "ladder GEMM (FP64 MFMA)",
+                     "avg_ms": round(lad_ms, 4), "flops_per_launch": ladder_flops},
+        "cpu_baseline": ({k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")} if cpu else None),
+        "time_to_1e-8": conv or None,
+    }
+    print(json.dumps(line), flush=True)
+    plan.close()
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -90,6 +90,8 @@ typedef struct {
   int32_t use_graph;   /* 1: capture one iteration as a HIP graph and replay it */
   int32_t check_every; /* read the norm back every this many iterations (>= 1) */
   int32_t diverge_window; /* EDIVERGED if the norm grew for this many checks in a row (0 = off) */
+  int32_t dressed;     /* 0: D from the bare Fock diagonal; 1: from the diagonals of the
+                          T-dressed one-body intermediates of the current iterate */
 } cc_iter_opts;
 
 typedef struct {
@@ -128,8 +130,11 @@ size_t cc_plan_workspace_bytes(const cc_plan *plan);
  * rnorm_out (host, may be NULL) receives ||R||. */
 int cc_plan_residual(cc_plan *plan, const cc_amps *t, cc_amps *r, double *rnorm_out);
 /* One Jacobi step: evaluates E(t) and R(t), then t <- t + R/(D - s) in
- * place.  The scalars are left in device memory; cc_plan_scalars reads them. */
-int cc_plan_step(cc_plan *plan, cc_amps *t, double level_shift);
+ * place (D bare, or dressed when dressed != 0: D_ij^ab = F~_ii + F~_jj -
+ * F~_aa - F~_bb with F~ the one-body intermediates that multiply t2 in the
+ * doubles residual, and D_i^a = F~_ii - F~_aa for the singles).  The scalars
+ * are left in device memory; cc_plan_scalars reads them. */
+int cc_plan_step(cc_plan *plan, cc_amps *t, double level_shift, int dressed);
 /* ||R|| and E (re, im) of the last cc_plan_step / cc_plan_residual (syncs). */
 int cc_plan_scalars(cc_plan *plan, double *rnorm, double *e_re, double *e_im);
 
@@ -169,6 +174,20 @@ const char *cc_plan_describe(const cc_plan *plan);
 /* The same listing for a plan of the given sizes, built without a device
  * (no allocation, no kernel launch). */
 const char *cc_plan_describe_dry(int o, int v, int method, int scalar);
+/* Autotuner: times every instantiated GEMM tile configuration for each
+ * distinct GEMM shape of the plan (reps launches each, on the plan's own
+ * buffers, with t as the amplitude operand) and keeps the fastest.  Choices
+ * are cached per shape for the life of the process.  Workspace contents are
+ * clobbered; the next step recomputes them.  t is only read. */
+int cc_plan_autotune(cc_plan *plan, const cc_amps *t, int reps);
+/* Per-step timing: with enable != 0 every later cc_plan_step /
+ * cc_plan_residual records a HIP event after each of its steps on the
+ * context stream and waits for the last one; durations accumulate per step.
+ * Enabling (again) clears the accumulators. */
+int cc_plan_profile(cc_plan *plan, int enable);
+/* Table "index kind tag calls total_ms avg_ms flops_per_call", one line per
+ * step.  Valid until the next call on the same host thread. */
+const char *cc_plan_profile_table(const cc_plan *plan);
 /* Algorithmic (dense) flops of one iteration (which = 0) or of the
  * particle-particle ladder alone (which = 1). */
 double cc_plan_flops(const cc_plan *plan, int which);

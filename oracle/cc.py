@@ -189,6 +189,32 @@ def diagram_count(method: str) -> int:
     raise ValueError(method)
 
 
+def dressed_diagonals(F: Fock, V: Integrals, t1, t2):
+    """Diagonals of the T-dressed one-body intermediates.
+
+    F~_ae = f_ae - 1/2 f_me t_m^a + t_m^f <ma||fe> - 1/2 taut_mn^af <mn||ef>
+    F~_mi = f_mi + 1/2 f_me t_i^e + t_n^e <mn||ie> + 1/2 taut_in^ef <mn||ef>
+    F~_me = f_me + t_n^f <mn||ef>,   taut = t2 + 1/2 (t1 t1 - t1 t1)
+    and the operators that multiply t2 in the doubles residual,
+    Fv = F~_ae - 1/2 t_m^b F~_me (at a = e = b), Fo = F~_mi + 1/2 F~_me t_i^e (at m = i).
+    Returned: (diag F~_oo, diag F~_vv, diag Fo, diag Fv); t1 None means CCD.
+    Only diagonal elements are formed (einsum over the repeated index).
+    """
+    oovv = V.get("oovv")
+    taut = t2
+    if t1 is not None:
+        x = _es("ia,jb->ijab", t1, t1)
+        taut = t2 + 0.5 * (x - x.transpose(0, 1, 3, 2))
+    fv = np.diag(F.vv).copy() - 0.5 * _es("mnaf,mnaf->a", taut, oovv)
+    fo = np.diag(F.oo).copy() + 0.5 * _es("inef,inef->i", oovv, taut)
+    if t1 is None:
+        return fo, fv, fo.copy(), fv.copy()
+    fv += -0.5 * _es("ma,ma->a", F.ov, t1) + _es("mafa,mf->a", V.get("ovvv"), t1)
+    fo += 0.5 * _es("ie,ie->i", F.ov, t1) + _es("inie,ne->i", V.get("ooov"), t1)
+    fme = F.ov + _es("mnef,nf->me", oovv, t1)
+    return fo, fv, fo + 0.5 * _es("ie,ie->i", fme, t1), fv - 0.5 * _es("mb,mb->b", t1, fme)
+
+
 def residual_norm(r1, r2):
     """Frobenius norm over every stored element of R1 and R2."""
     s = float(np.sum(np.abs(r2) ** 2))
@@ -198,10 +224,13 @@ def residual_norm(r1, r2):
 
 
 def jacobi(F: Fock, V: Integrals, method: str = "ccsd", tol: float = 1e-8, max_iter: int = 200,
-           t1=None, t2=None, callback=None, level_shift: float = 0.0):
+           t1=None, t2=None, callback=None, level_shift: float = 0.0, dressed: bool = False):
     """Jacobi iteration t <- t + R(t)/(D - s) from t = 0 (or the given guess).
 
-    s >= 0 is a level shift (s = 0: the plain denominator update).
+    s >= 0 is a level shift (s = 0: the plain denominator update).  With
+    ``dressed`` the denominators are rebuilt every iteration from the
+    diagonals of the dressed one-body operators (``dressed_diagonals``):
+    D_ij^ab = Fo_i + Fo_j - Fv_a - Fv_b, D_i^a = F~_ii - F~_aa.
     Iteration n evaluates R(t_n), records ||R(t_n)|| and E(t_n), stops if
     ||R(t_n)|| < tol and otherwise updates.  Returns a dict with the final
     amplitudes and the per-iteration history; E(t_1) is the MP2 energy when
@@ -233,8 +262,15 @@ def jacobi(F: Fock, V: Integrals, method: str = "ccsd", tol: float = 1e-8, max_i
             break
         if not np.isfinite(rn):
             break
-        t2 = t2 + r2 / d2
+        if dressed:
+            fo1, fv1, fo2, fv2 = dressed_diagonals(F, V, t1, t2)
+            e1 = np.real(fo1)[:, None] - np.real(fv1)[None, :] - level_shift
+            e2 = (np.real(fo2)[:, None, None, None] + np.real(fo2)[None, :, None, None]) - (
+                np.real(fv2)[None, None, :, None] + np.real(fv2)[None, None, None, :]) - level_shift
+        else:
+            e1, e2 = d1, d2
+        t2 = t2 + r2 / e2
         if t1 is not None:
-            t1 = t1 + r1 / d1
+            t1 = t1 + r1 / e1
     return {"t1": t1, "t2": t2, "energy": hist_e[-1], "rnorm": hist_r[-1], "hist_e": hist_e,
             "hist_r": hist_r, "iters": len(hist_e), "converged": converged}

@@ -24,7 +24,8 @@ EXPORTS = (
     "cc_create", "cc_destroy", "cc_last_error", "cc_status_string",
     "cc_plan_create", "cc_plan_destroy", "cc_plan_workspace_bytes", "cc_plan_residual",
     "cc_plan_step", "cc_plan_scalars", "cc_residual", "cc_energy", "cc_iterate", "cc_gemm",
-    "cc_permute", "cc_plan_describe", "cc_plan_describe_dry", "cc_plan_flops",
+    "cc_permute", "cc_plan_describe", "cc_plan_describe_dry", "cc_plan_flops", "cc_plan_profile",
+    "cc_plan_profile_table", "cc_plan_autotune",
 )
 
 
@@ -41,7 +42,7 @@ class CCAmps(C.Structure):
 class CCIterOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("prec", C.c_int32),
                 ("level_shift", C.c_double), ("refine_every", C.c_int32), ("use_graph", C.c_int32),
-                ("check_every", C.c_int32), ("diverge_window", C.c_int32)]
+                ("check_every", C.c_int32), ("diverge_window", C.c_int32), ("dressed", C.c_int32)]
 
 
 class CCIterReport(C.Structure):
@@ -79,7 +80,7 @@ def load() -> C.CDLL:
         "cc_plan_destroy": (C.c_int, [vp]),
         "cc_plan_workspace_bytes": (C.c_size_t, [vp]),
         "cc_plan_residual": (C.c_int, [vp, P(CCAmps), P(CCAmps), P(dbl)]),
-        "cc_plan_step": (C.c_int, [vp, P(CCAmps), dbl]),
+        "cc_plan_step": (C.c_int, [vp, P(CCAmps), dbl, C.c_int]),
         "cc_plan_scalars": (C.c_int, [vp, P(dbl), P(dbl), P(dbl)]),
         "cc_residual": (C.c_int, [vp, P(CCSystemStruct), C.c_int, C.c_int, P(CCAmps), P(CCAmps), P(dbl)]),
         "cc_energy": (C.c_int, [vp, P(CCSystemStruct), C.c_int, P(CCAmps), P(dbl), P(dbl)]),
@@ -89,6 +90,9 @@ def load() -> C.CDLL:
         "cc_plan_describe": (C.c_char_p, [vp]),
         "cc_plan_describe_dry": (C.c_char_p, [C.c_int, C.c_int, C.c_int, C.c_int]),
         "cc_plan_flops": (dbl, [vp, C.c_int]),
+        "cc_plan_profile": (C.c_int, [vp, C.c_int]),
+        "cc_plan_autotune": (C.c_int, [vp, P(CCAmps), C.c_int]),
+        "cc_plan_profile_table": (C.c_char_p, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

@@ -1,6 +1,7 @@
 // C ABI of the engine: validation, error mapping and the Jacobi driver.
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
@@ -92,7 +93,8 @@ void run_step(cc_plan *p, bool use_graph) {
   }
   const bool same = p->graph && p->graph_key[0] == p->t1 && p->graph_key[1] == p->t2 &&
                     p->graph_key[2] == p->r1_out && p->graph_key[3] == p->r2_out &&
-                    p->graph_shift == p->shift && p->graph_update == p->update;
+                    p->graph_shift == p->shift && p->graph_update == p->update &&
+                    p->graph_dressed == p->dressed;
   if (!same) {
     if (p->graph) (void)hipGraphExecDestroy(p->graph);
     p->graph = nullptr;
@@ -114,6 +116,7 @@ void run_step(cc_plan *p, bool use_graph) {
     p->graph_key[3] = p->r2_out;
     p->graph_shift = p->shift;
     p->graph_update = p->update;
+    p->graph_dressed = p->dressed;
   }
   CC_HIP_CHECK(hipGraphLaunch(p->graph, p->ctx->stream));
 }
@@ -243,7 +246,7 @@ int cc_plan_residual(cc_plan *p, const cc_amps *t, cc_amps *r, double *rnorm_out
   });
 }
 
-int cc_plan_step(cc_plan *p, cc_amps *t, double level_shift) {
+int cc_plan_step(cc_plan *p, cc_amps *t, double level_shift, int dressed) {
   if (!p) return fail(nullptr, CC_EINVAL, "plan is NULL");
   return guarded(p->ctx, [&] {
     validate_amps(t, p->method, "t");
@@ -256,6 +259,7 @@ int cc_plan_step(cc_plan *p, cc_amps *t, double level_shift) {
     p->r2_out = nullptr;
     p->update = true;
     p->shift = level_shift;
+    p->dressed = dressed ? 1 : 0;
     ccmi::plan_run(p);
     CC_HIP_CHECK(hipGetLastError());
     return CC_OK;
@@ -326,6 +330,7 @@ int cc_iterate(cc_ctx *ctx, const cc_system *sys, int method, const cc_iter_opts
       p->r1_out = p->r2_out = nullptr;
       p->update = true;
       p->shift = opts->level_shift;
+      p->dressed = opts->dressed ? 1 : 0;
       for (int it = 0; it < opts->max_iter; ++it) {
         run_step(p, opts->use_graph != 0);
         ++iters;
@@ -390,7 +395,10 @@ int cc_gemm(cc_ctx *ctx, int prec, int scalar, int64_t M, int64_t N, int64_t K, 
     set_device(ctx);
     ccmi::GemmDesc d{M, N, K, A, sam, sak, B, sbn, sbk, C, ldc, alpha, beta};
     if (scalar == CC_C128) ccmi::gemm_c128(d, ctx->stream);
-    else if (prec == CC_PREC_F64) ccmi::gemm_f64(d, ctx->stream, -1);
+    else if (prec == CC_PREC_F64) {
+      const char *tv = std::getenv("CC_GEMM_TILE");  // tuning sweeps: force one tile configuration
+      ccmi::gemm_f64(d, ctx->stream, tv ? std::atoi(tv) : -1);
+    }
     else ccmi::gemm_lowp(d, prec, ctx->stream, -1);
     CC_HIP_CHECK(hipStreamSynchronize(ctx->stream));
     return CC_OK;
@@ -459,6 +467,35 @@ const char *cc_plan_describe_dry(int o, int v, int method, int scalar) {
   } catch (const std::exception &e) {
     s = std::string("error: ") + e.what();
   }
+  return s.c_str();
+}
+
+int cc_plan_autotune(cc_plan *p, const cc_amps *t, int reps) {
+  if (!p) return fail(nullptr, CC_EINVAL, "plan is NULL");
+  return guarded(p->ctx, [&] {
+    validate_amps(t, p->method, "t");
+    if (reps < 1) throw CCError(CC_EINVAL, "reps must be >= 1");
+    set_device(p->ctx);
+    p->t1 = t->t1;
+    p->t2 = t->t2;
+    ccmi::plan_autotune(p, reps);
+    return CC_OK;
+  });
+}
+
+int cc_plan_profile(cc_plan *p, int enable) {
+  if (!p) return fail(nullptr, CC_EINVAL, "plan is NULL");
+  return guarded(p->ctx, [&] {
+    p->profiling = enable != 0;
+    p->step_ms.assign(p->iter.size(), 0.0);
+    p->step_calls.assign(p->iter.size(), 0);
+    return CC_OK;
+  });
+}
+
+const char *cc_plan_profile_table(const cc_plan *p) {
+  static thread_local std::string s;
+  s = p ? ccmi::plan_profile_table(p) : std::string();
   return s.c_str();
 }
 

@@ -49,6 +49,9 @@ struct GemmDesc {
   int64_t ldc;       // C[m*ldc + n]
   double alpha, beta;
   int conj_a = 0, conj_b = 0;  // complex only
+  int ladder = 0;              // 1: launch the ladder's own kernel symbol (profiling)
+  int split = 1;               // split-K factor; > 1 needs ws of split*M*N elements
+  void *ws = nullptr;
 };
 
 enum Prec { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16X3 = 2 };
@@ -64,6 +67,9 @@ void gemm_c128(const GemmDesc &d, hipStream_t s);
 int gemm_f64_num_tiles();
 const char *gemm_f64_tile_name(int id);
 int gemm_f64_pick(int64_t M, int64_t N, int64_t K, bool a_kc, bool b_kc);
+int gemm_split_pick(int64_t M, int64_t N, int64_t K, int tile_id);
+void splitk_reduce(bool cplx, const void *ws, int split, int64_t M, int64_t N, void *C, int64_t ldc,
+                   double alpha, double beta, hipStream_t s);
 
 // ---- dense rank<=6 tensor views for permutation kernels ----
 constexpr int kMaxRank = 6;

@@ -199,6 +199,24 @@ __global__ __launch_bounds__(256) void outer_kernel(OuterArgs p, const T *__rest
   }
 }
 
+// ---------------------------------------------------------- split-K sum --
+// C = alpha * sum_s W[s] + beta * C, s in increasing order (deterministic).
+template <class T>
+__global__ __launch_bounds__(256) void splitk_kernel(const T *__restrict__ W, int split, int64_t M,
+                                                     int64_t N, T *__restrict__ C, int64_t ldc,
+                                                     double alpha, double beta) {
+  const int64_t total = M * N;
+  for (int64_t e = blockIdx.x * int64_t(256) + threadIdx.x; e < total;
+       e += int64_t(gridDim.x) * 256) {
+    T acc = W[e];
+    for (int k = 1; k < split; ++k) acc = add(acc, W[int64_t(k) * total + e]);
+    const int64_t m = e / N, n = e % N;
+    T v = sc(alpha, acc);
+    if (beta != 0.0) v = add(v, sc(beta, C[m * ldc + n]));
+    C[m * ldc + n] = v;
+  }
+}
+
 // ------------------------------------------------------------------- fill --
 template <class T>
 __global__ __launch_bounds__(256) void fill_kernel(T *__restrict__ p, T val, int64_t n) {
@@ -334,7 +352,14 @@ __global__ __launch_bounds__(256) void r2_assemble_kernel(R2Args p, const T *__r
           R[e_ji] = sc(-1.0, r);
         }
         if (t2 != nullptr) {
-          const double D = (d_oo[i] + d_oo[j]) - (d_vv[aa] + d_vv[bb]);
+          double D;
+          if (p.dressed) {
+            const T *Fo = static_cast<const T *>(p.Fo), *Fv = static_cast<const T *>(p.Fv);
+            D = (re(Fo[int64_t(i) * o + i]) + re(Fo[int64_t(j) * o + j])) -
+                (re(Fv[int64_t(aa) * v + aa]) + re(Fv[int64_t(bb) * v + bb]));
+          } else {
+            D = (d_oo[i] + d_oo[j]) - (d_vv[aa] + d_vv[bb]);
+          }
           tn = add(t2[e], sc(1.0 / (D - p.shift), r));
           t2[e] = tn;
           t2[e_ji] = sc(-1.0, tn);
@@ -377,6 +402,7 @@ template <class T>
 __global__ __launch_bounds__(RED_THREADS) void r1_update_kernel(int o, int v, const T *__restrict__ R1,
                                                                 T *__restrict__ t1, const double *d_oo,
                                                                 const double *d_vv, double shift,
+                                                                int dressed, const T *Fo, const T *Fv,
                                                                 double *partial) {
   __shared__ double sh[RED_THREADS];
   double nrm = 0.0;
@@ -384,7 +410,8 @@ __global__ __launch_bounds__(RED_THREADS) void r1_update_kernel(int o, int v, co
     const int i = e / v, a = e % v;
     const T r = R1[e];
     nrm += abs2(r);
-    if (t1 != nullptr) t1[e] = add(t1[e], sc(1.0 / ((d_oo[i] - d_vv[a]) - shift), r));
+    const double D = dressed ? re(Fo[int64_t(i) * o + i]) - re(Fv[int64_t(a) * v + a]) : d_oo[i] - d_vv[a];
+    if (t1 != nullptr) t1[e] = add(t1[e], sc(1.0 / (D - shift), r));
   }
   const double s = block_sum(nrm, sh);
   if (threadIdx.x == 0) partial[0] = s;
@@ -446,6 +473,22 @@ void outer_acc(const OuterArgs &a, bool cplx, const void *A, const void *B, void
   CC_HIP_CHECK(hipGetLastError());
 }
 
+void splitk_reduce(bool cplx, const void *ws, int split, int64_t M, int64_t N, void *C, int64_t ldc,
+                   double alpha, double beta, hipStream_t s) {
+  const int64_t total = M * N;
+  if (total == 0) return;
+  const int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
+  if (cplx)
+    hipLaunchKernelGGL(splitk_kernel<double2>, dim3(blocks), dim3(256), 0, s,
+                       static_cast<const double2 *>(ws), split, M, N, static_cast<double2 *>(C), ldc,
+                       alpha, beta);
+  else
+    hipLaunchKernelGGL(splitk_kernel<double>, dim3(blocks), dim3(256), 0, s,
+                       static_cast<const double *>(ws), split, M, N, static_cast<double *>(C), ldc,
+                       alpha, beta);
+  CC_HIP_CHECK(hipGetLastError());
+}
+
 void fill_zero(void *p, int64_t n_elems, bool cplx, hipStream_t s) {
   if (n_elems <= 0) return;
   const int64_t blocks = std::min<int64_t>((n_elems + 255) / 256, 65536);
@@ -498,13 +541,16 @@ void r2_assemble(bool cplx, const R2Args &a, const void *XP, const void *Xij, co
 }
 
 void r1_update(bool cplx, int o, int v, const void *R1, void *t1, const double *d_oo,
-               const double *d_vv, double shift, double *partial, hipStream_t s) {
+               const double *d_vv, double shift, int dressed, const void *Fo, const void *Fv,
+               double *partial, hipStream_t s) {
   if (cplx)
     hipLaunchKernelGGL(r1_update_kernel<double2>, dim3(1), dim3(RED_THREADS), 0, s, o, v,
-                       (const double2 *)R1, (double2 *)t1, d_oo, d_vv, shift, partial);
+                       (const double2 *)R1, (double2 *)t1, d_oo, d_vv, shift, dressed,
+                       (const double2 *)Fo, (const double2 *)Fv, partial);
   else
     hipLaunchKernelGGL(r1_update_kernel<double>, dim3(1), dim3(RED_THREADS), 0, s, o, v,
-                       (const double *)R1, (double *)t1, d_oo, d_vv, shift, partial);
+                       (const double *)R1, (double *)t1, d_oo, d_vv, shift, dressed,
+                       (const double *)Fo, (const double *)Fv, partial);
   CC_HIP_CHECK(hipGetLastError());
 }
 

@@ -44,15 +44,16 @@ struct Cfg {
   static_assert((BM * BK) % NT == 0 && (BN * BK) % NT == 0, "load split");
 };
 
-template <int BM, int BN, int BK, int WM, int WN, bool AKC, bool BKC>
+template <int BM, int BN, int BK, int WM, int WN, bool AKC, bool BKC, int TAG>
 __global__ __launch_bounds__(WM *WN *kWave) void gemm_f64_kernel(GemmDesc d, int64_t tilesM,
                                                                   int64_t tilesN) {
   using C = Cfg<BM, BN, BK, WM, WN, AKC, BKC>;
   __shared__ double smem[2 * (C::A_ELEMS + C::B_ELEMS)];
   // buffer b of A at smem + b*A_ELEMS, of B at smem + 2*A_ELEMS + b*B_ELEMS
 
-  const int64_t total = tilesM * tilesN;
-  const int64_t L = xcd_remap(blockIdx.x, total);
+  const int64_t tiles = tilesM * tilesN, total = tiles * d.split;
+  const int64_t L0 = xcd_remap(blockIdx.x, total);
+  const int64_t ks = L0 / tiles, L = L0 % tiles;
   const int64_t m0 = (L % tilesM) * BM, n0 = (L / tilesM) * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm0 = (wave / WN) * C::WTM, wn0 = (wave % WN) * C::WTN;
@@ -60,7 +61,13 @@ __global__ __launch_bounds__(WM *WN *kWave) void gemm_f64_kernel(GemmDesc d, int
 
   const double *__restrict__ A = static_cast<const double *>(d.A);
   const double *__restrict__ B = static_cast<const double *>(d.B);
-  const int64_t M = d.M, N = d.N, K = d.K;
+  const int64_t M = d.M, N = d.N;
+  // split-K: this workgroup covers k in [kb, kb + K) of the full range
+  const int64_t kchunk = ((d.K + d.split - 1) / d.split + BK - 1) / BK * BK;
+  const int64_t kb = ks * kchunk;
+  const int64_t K = std::max<int64_t>(0, std::min<int64_t>(d.K - kb, kchunk));
+  A += kb * d.sak;
+  B += kb * d.sbk;
 
   double ra[C::LA], rb[C::LB];
 
@@ -145,7 +152,14 @@ __global__ __launch_bounds__(WM *WN *kWave) void gemm_f64_kernel(GemmDesc d, int
   // epilogue: accumulator t of lane l holds row (l >> 4) + 4t, column l & 15
   // of its 16x16 block (f64 MFMA output layout, checked on the device)
   double *__restrict__ Cp = static_cast<double *>(d.C);
-  const double alpha = d.alpha, beta = d.beta;
+  double alpha = d.alpha, beta = d.beta;
+  int64_t ldc = d.ldc;
+  if (d.split > 1) {  // raw partial sums; splitk_reduce applies alpha and beta
+    Cp = static_cast<double *>(d.ws) + ks * M * N;
+    alpha = 1.0;
+    beta = 0.0;
+    ldc = N;
+  }
 #pragma unroll
   for (int i = 0; i < C::FM; ++i)
 #pragma unroll
@@ -155,7 +169,7 @@ __global__ __launch_bounds__(WM *WN *kWave) void gemm_f64_kernel(GemmDesc d, int
       for (int t = 0; t < 4; ++t) {
         const int64_t gm = m0 + wm0 + i * 16 + q + 4 * t;
         if (gm < M && gn < N) {
-          double *p = Cp + gm * d.ldc + gn;
+          double *p = Cp + gm * ldc + gn;
           const double v = alpha * acc[i][j][t];
           *p = (beta == 0.0) ? v : v + beta * *p;
         }
@@ -167,11 +181,14 @@ struct TileInfo {
   const char *name;
   int BM, BN, BK, threads;
   void (*launch[4])(const GemmDesc &, int64_t, int64_t, hipStream_t);  // [akc*2 + bkc]
+  void (*launch_ladder)(const GemmDesc &, int64_t, int64_t, hipStream_t);  // both K-contiguous
 };
 
-template <int BM, int BN, int BK, int WM, int WN, bool AKC, bool BKC>
+// TAG only changes the kernel's symbol name: TAG 1 is the particle-particle
+// ladder, so that profilers report it on its own line.
+template <int BM, int BN, int BK, int WM, int WN, bool AKC, bool BKC, int TAG = 0>
 void launch_cfg(const GemmDesc &d, int64_t tm, int64_t tn, hipStream_t s) {
-  hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, WM, WN, AKC, BKC>), dim3(tm * tn),
+  hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, WM, WN, AKC, BKC, TAG>), dim3(tm * tn * d.split),
                      dim3(WM * WN * kWave), 0, s, d, tm, tn);
 }
 
@@ -180,7 +197,7 @@ void launch_cfg(const GemmDesc &d, int64_t tm, int64_t tn, hipStream_t s) {
     #BM "x" #BN "x" #BK "_w" #WM "x" #WN, BM, BN, BK, WM *WN * kWave, {                      \
       &launch_cfg<BM, BN, BK, WM, WN, false, false>, &launch_cfg<BM, BN, BK, WM, WN, false, true>, \
           &launch_cfg<BM, BN, BK, WM, WN, true, false>, &launch_cfg<BM, BN, BK, WM, WN, true, true> \
-    }                                                                                        \
+    }, &launch_cfg<BM, BN, BK, WM, WN, true, true, 1>                                        \
   }
 
 const TileInfo kTiles[] = {
@@ -219,6 +236,17 @@ int gemm_f64_pick(int64_t M, int64_t N, int64_t K, bool, bool) {
   return best;
 }
 
+// Split-K factor: enough workgroups to cover the chip when the output has
+// few tiles and the contraction is long (e.g. M = N = o, K = o v^2).
+// Independent of the tile so that the autotuner can change tiles freely.
+int gemm_split_pick(int64_t M, int64_t N, int64_t K, int) {
+  const int64_t tiles = ((M + 63) / 64) * ((N + 63) / 64);
+  if (tiles >= 256) return 1;
+  int64_t split = (512 + tiles - 1) / tiles;
+  split = std::min<int64_t>(split, std::max<int64_t>(1, K / 256));
+  return int(std::max<int64_t>(1, std::min<int64_t>(split, 128)));
+}
+
 void gemm_f64(const GemmDesc &d, hipStream_t s, int tile_id) {
   if (d.M <= 0 || d.N <= 0) return;
   const bool akc = (d.sak == 1), bkc = (d.sbk == 1);
@@ -244,9 +272,13 @@ void gemm_f64(const GemmDesc &d, hipStream_t s, int tile_id) {
   if (tile_id < 0 || tile_id >= kNumTiles) tile_id = gemm_f64_pick(d.M, d.N, d.K, akc, bkc);
   const TileInfo &ti = kTiles[tile_id];
   const int64_t tm = (d.M + ti.BM - 1) / ti.BM, tn = (d.N + ti.BN - 1) / ti.BN;
-  CC_REQUIRE(tm * tn < (int64_t(1) << 31), -1, "gemm: too many tiles");
-  ti.launch[(akc ? 2 : 0) + (bkc ? 1 : 0)](d, tm, tn, s);
+  CC_REQUIRE(d.split >= 1, -1, "gemm: split must be >= 1");
+  CC_REQUIRE(d.split == 1 || d.ws != nullptr, -1, "gemm: split-K needs a workspace");
+  CC_REQUIRE(tm * tn * d.split < (int64_t(1) << 31), -1, "gemm: too many tiles");
+  if (d.ladder && akc && bkc) ti.launch_ladder(d, tm, tn, s);
+  else ti.launch[(akc ? 2 : 0) + (bkc ? 1 : 0)](d, tm, tn, s);
   CC_HIP_CHECK(hipGetLastError());
+  if (d.split > 1) splitk_reduce(false, d.ws, d.split, d.M, d.N, d.C, d.ldc, d.alpha, d.beta, s);
 }
 
 }  // namespace ccmi

@@ -120,6 +120,8 @@ struct Planner {
   cc_plan *p;
   int scratch = -1;        // shared buffer for GEMM outputs that need a permute
   int64_t scratch_elems = 0;
+  int splitws = -1;        // split-K partial sums
+  int64_t splitws_elems = 0;
 
   int slot(const std::string &name) {
     auto it = p->index.find(name);
@@ -344,6 +346,12 @@ struct Planner {
     g.gemm.conj_b = 0;
     g.flops = (p->cplx ? 8.0 : 2.0) * double(M) * double(N) * double(Kd);
     g.tag = op.tag;
+    g.gemm.ladder = std::string(op.tag) == "ladder" ? 1 : 0;
+    g.gemm.split = p->cplx ? 1 : gemm_split_pick(M, N, Kd, -1);
+    if (g.gemm.split > 1) {
+      splitws_elems = std::max<int64_t>(splitws_elems, int64_t(g.gemm.split) * M * N);
+      g.b2 = splitws;
+    }
     g.tile = p->cplx ? -1 : gemm_f64_pick(M, N, Kd, xkc, ykc);
     if (best.cm) {
       g.c = c;
@@ -433,6 +441,7 @@ struct Planner {
                              {"FF", "vv"},   {"GG", "oo"},    {"Q", "oovo"}};
     for (auto &w : work) add_slot(w[0], w[1], false, false, true);
     scratch = add_work("scratch", {1});
+    splitws = add_work("splitk_ws", {1});
 
     Step te;
     te.kind = Step::TAU_E;
@@ -470,6 +479,8 @@ struct Planner {
     p->iter.push_back(fin);
     p->slots[scratch].dims = {scratch_elems};
     p->slots[scratch].elems = scratch_elems;
+    p->slots[splitws].dims = {std::max<int64_t>(splitws_elems, 1)};
+    p->slots[splitws].elems = std::max<int64_t>(splitws_elems, 1);
   }
 };
 
@@ -497,6 +508,7 @@ void exec(cc_plan *p, Step &st, hipStream_t s) {
       d.A = ptr_of(p, st.a);
       d.B = ptr_of(p, st.b);
       d.C = ptr_of(p, st.c);
+      d.ws = st.b2 >= 0 ? ptr_of(p, st.b2) : nullptr;
       run_gemm(p, d, st.tile, s);
       break;
     }
@@ -514,7 +526,8 @@ void exec(cc_plan *p, Step &st, hipStream_t s) {
       break;
     }
     case Step::ASSEMBLE: {
-      R2Args a{p->o, p->v, p->d_oo, p->d_vv, p->shift};
+      R2Args a{p->o, p->v, p->d_oo, p->d_vv, p->shift, p->dressed, p->slots[p->index["GG"]].ptr,
+               p->slots[p->index["FF"]].ptr};
       r2_assemble(cplx, a, p->slots[p->index["XP"]].ptr, p->slots[p->index["Xij"]].ptr,
                   p->slots[p->index["Xab"]].ptr, p->slots[p->index["Xr"]].ptr, p->r2_out,
                   p->update ? p->t2 : nullptr, p->n2part, s);
@@ -526,7 +539,7 @@ void exec(cc_plan *p, Step &st, hipStream_t s) {
         CC_HIP_CHECK(hipMemcpyAsync(p->r1_out, R1, size_t(p->o) * p->v * p->esize,
                                     hipMemcpyDeviceToDevice, s));
       r1_update(cplx, p->o, p->v, R1, p->update ? p->t1 : nullptr, p->d_oo, p->d_vv, p->shift,
-                p->n1part, s);
+                p->dressed, p->slots[p->index["Fmi"]].ptr, p->slots[p->index["Fae"]].ptr, p->n1part, s);
       break;
     }
     case Step::FINALIZE:
@@ -570,6 +583,8 @@ void plan_build(cc_plan *p, const cc_system *sys) {
 }
 
 void plan_free(cc_plan *p) {
+  for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
+  p->events.clear();
   if (p->graph) (void)hipGraphExecDestroy(p->graph);
   p->graph = nullptr;
   for (Slot &s : p->slots)
@@ -580,7 +595,101 @@ void plan_free(cc_plan *p) {
 
 void plan_run(cc_plan *p) {
   hipStream_t s = p->ctx->stream;
-  for (Step &st : p->iter) exec(p, st, s);
+  if (!p->profiling) {
+    for (Step &st : p->iter) exec(p, st, s);
+    return;
+  }
+  const size_t n = p->iter.size();
+  if (p->events.size() != n + 1) {
+    for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
+    p->events.assign(n + 1, nullptr);
+    for (auto &e : p->events) CC_HIP_CHECK(hipEventCreate(&e));
+    p->step_ms.assign(n, 0.0);
+    p->step_calls.assign(n, 0);
+  }
+  CC_HIP_CHECK(hipEventRecord(p->events[0], s));
+  for (size_t i = 0; i < n; ++i) {
+    exec(p, p->iter[i], s);
+    CC_HIP_CHECK(hipEventRecord(p->events[i + 1], s));
+  }
+  CC_HIP_CHECK(hipEventSynchronize(p->events[n]));
+  for (size_t i = 0; i < n; ++i) {
+    float ms = 0.f;
+    CC_HIP_CHECK(hipEventElapsedTime(&ms, p->events[i], p->events[i + 1]));
+    p->step_ms[i] += ms;
+    p->step_calls[i] += 1;
+  }
+}
+
+// Time every tile configuration for each distinct GEMM shape of the
+// iteration (on the plan's own buffers) and keep the fastest.  Results are
+// cached per (M, N, K, layouts) for the life of the process.
+void plan_autotune(cc_plan *p, int reps) {
+  if (p->cplx || p->prec != PREC_F64) return;
+  static std::map<std::string, int> cache;
+  hipStream_t s = p->ctx->stream;
+  hipEvent_t e0, e1;
+  CC_HIP_CHECK(hipEventCreate(&e0));
+  CC_HIP_CHECK(hipEventCreate(&e1));
+  try {
+    for (Step *st : p->gemm_steps) {
+      GemmDesc d = st->gemm;
+      const bool akc = d.sak == 1, bkc = d.sbk == 1;
+      const std::string key = std::to_string(d.M) + "x" + std::to_string(d.N) + "x" +
+                              std::to_string(d.K) + (akc ? "k" : "m") + (bkc ? "k" : "n");
+      auto it = cache.find(key);
+      if (it != cache.end()) {
+        st->tile = it->second;
+        continue;
+      }
+      d.A = ptr_of(p, st->a);
+      d.B = ptr_of(p, st->b);
+      d.C = ptr_of(p, st->c);
+      d.ws = st->b2 >= 0 ? ptr_of(p, st->b2) : nullptr;
+      int best = st->tile;
+      float best_ms = 1e30f;
+      for (int t = 0; t < gemm_f64_num_tiles(); ++t) {
+        gemm_f64(d, s, t);
+        CC_HIP_CHECK(hipEventRecord(e0, s));
+        for (int r = 0; r < reps; ++r) gemm_f64(d, s, t);
+        CC_HIP_CHECK(hipEventRecord(e1, s));
+        CC_HIP_CHECK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        CC_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = t;
+        }
+      }
+      st->tile = best;
+      cache[key] = best;
+    }
+  } catch (...) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (p->graph) (void)hipGraphExecDestroy(p->graph);
+  p->graph = nullptr;
+}
+
+std::string plan_profile_table(const cc_plan *p) {
+  std::ostringstream os;
+  os << "# step kind tag calls total_ms avg_ms flops_per_call\n";
+  for (size_t i = 0; i < p->step_ms.size() && i < p->iter.size(); ++i) {
+    const Step &st = p->iter[i];
+    static const char *kinds[] = {"PERMUTE", "GEMM", "OUTER", "FILL", "TAU_E", "ASSEMBLE", "R1UPD", "FINALIZE"};
+    std::string tag = st.tag.empty() ? "-" : st.tag;
+    for (auto &c : tag)
+      if (c == ' ') c = '_';
+    if (st.kind == Step::GEMM) tag += "@" + std::string(gemm_f64_tile_name(st.tile));
+    os << i << " " << kinds[st.kind] << " " << tag << " " << p->step_calls[i]
+       << " " << p->step_ms[i] << " " << (p->step_calls[i] ? p->step_ms[i] / p->step_calls[i] : 0.0)
+       << " " << st.flops << "\n";
+  }
+  return os.str();
 }
 
 void plan_run_energy(cc_plan *p) {
@@ -612,6 +721,7 @@ std::string plan_describe(const cc_plan *p) {
              << " M=" << st.gemm.M << " N=" << st.gemm.N << " K=" << st.gemm.K << " sam=" << st.gemm.sam
              << " sak=" << st.gemm.sak << " sbn=" << st.gemm.sbn << " sbk=" << st.gemm.sbk
              << " ldc=" << st.gemm.ldc << " alpha=" << st.gemm.alpha << " beta=" << st.gemm.beta
+             << " split=" << st.gemm.split
              << " tile=" << (st.tile >= 0 ? gemm_f64_tile_name(st.tile) : "auto") << "\n";
           break;
         case Step::OUTER:

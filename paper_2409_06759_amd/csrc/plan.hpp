@@ -44,7 +44,7 @@ struct Slot {
 
 struct Step {
   enum Kind { PERMUTE, GEMM, OUTER, FILL, TAU_E, ASSEMBLE, R1UPD, FINALIZE } kind;
-  int a = -1, b = -1, c = -1;
+  int a = -1, b = -1, c = -1, b2 = -1;  // b2: split-K workspace of a GEMM
   PermDesc perm{};
   GemmDesc gemm{};
   OuterArgs outer{};
@@ -76,13 +76,20 @@ struct cc_plan {
   void *t1 = nullptr, *t2 = nullptr, *r1_out = nullptr, *r2_out = nullptr;
   bool update = false;
   double shift = 0.0;
+  int dressed = 0;
   // graph replay
   hipGraphExec_t graph = nullptr;
   void *graph_key[4] = {nullptr, nullptr, nullptr, nullptr};
   double graph_shift = 0.0;
   bool graph_update = false;
+  int graph_dressed = 0;
   double flops_per_iter = 0.0, ladder_flops = 0.0;
   std::vector<ccmi::Step *> gemm_steps;
+  // per-step timing (HIP events around every step of an iteration)
+  bool profiling = false;
+  std::vector<hipEvent_t> events;
+  std::vector<double> step_ms;   // accumulated per iteration step
+  std::vector<int64_t> step_calls;
 };
 
 namespace ccmi {
@@ -92,5 +99,6 @@ void plan_free(cc_plan *p);
 void plan_run(cc_plan *p);           // enqueue one residual (+ update) on the stream
 void plan_run_energy(cc_plan *p);    // tau + energy only
 std::string plan_describe(const cc_plan *p);
-void plan_autotune(cc_plan *p);
+void plan_autotune(cc_plan *p, int reps);
+std::string plan_profile_table(const cc_plan *p);
 }  // namespace ccmi

@@ -124,9 +124,10 @@ class Plan:
                                                      C.byref(rn)))
         return r1, r2, rn.value
 
-    def step(self, t1, t2, shift: float = 0.0):
+    def step(self, t1, t2, shift: float = 0.0, dressed: bool = False):
         self.ctx.enter()
-        self.ctx.check(self.ctx.lib.cc_plan_step(self.h, C.byref(_amps(t1, t2)), shift))
+        self.ctx.check(self.ctx.lib.cc_plan_step(self.h, C.byref(_amps(t1, t2)), shift,
+                                                 1 if dressed else 0))
 
     def scalars(self):
         rn, er, ei = C.c_double(), C.c_double(), C.c_double()
@@ -138,6 +139,23 @@ class Plan:
 
     def flops(self, ladder_only=False) -> float:
         return self.ctx.lib.cc_plan_flops(self.h, 1 if ladder_only else 0)
+
+    def autotune(self, t1, t2, reps: int = 2):
+        self.ctx.enter()
+        self.ctx.check(self.ctx.lib.cc_plan_autotune(self.h, C.byref(_amps(t1, t2)), reps))
+
+    def profile(self, enable: bool = True):
+        self.ctx.check(self.ctx.lib.cc_plan_profile(self.h, 1 if enable else 0))
+
+    def profile_table(self):
+        """[(index, kind, tag, calls, total_ms, avg_ms, flops_per_call)]"""
+        rows = []
+        for line in self.ctx.lib.cc_plan_profile_table(self.h).decode().splitlines():
+            if line.startswith("#") or not line.strip():
+                continue
+            i, kind, tag, calls, tot, avg, fl = line.split()
+            rows.append((int(i), kind, tag, int(calls), float(tot), float(avg), float(fl)))
+        return rows
 
     def workspace_bytes(self) -> int:
         return self.ctx.lib.cc_plan_workspace_bytes(self.h)
@@ -173,12 +191,12 @@ def energy(ctx, dsys, method, t1, t2):
 
 
 def iterate(ctx, dsys, method, t1, t2, tol=1e-8, max_iter=100, level_shift=0.0, prec=F64,
-            use_graph=True, refine_every=0, diverge_window=0, hist_cap=None):
+            use_graph=True, refine_every=0, diverge_window=0, hist_cap=None, dressed=False):
     cap = hist_cap or max_iter
     hr = (C.c_double * cap)()
     he = (C.c_double * cap)()
     opts = L.CCIterOpts(tol, max_iter, prec, level_shift, refine_every, 1 if use_graph else 0, 1,
-                        diverge_window)
+                        diverge_window, 1 if dressed else 0)
     rep = L.CCIterReport(0, 0, 0.0, 0.0, 0.0, 0.0, 0.0, C.cast(hr, C.POINTER(C.c_double)),
                          C.cast(he, C.POINTER(C.c_double)), cap)
     ctx.enter()

@@ -175,3 +175,19 @@ def test_abi_errors_on_device(E, ctx):
     u1, u2 = E.zeros_amps(d, E.CCSD)
     out = E.iterate(ctx, d, E.CCSD, u1, u2, tol=1e-8, max_iter=1)
     assert out["status"] == L.CC_ENOTCONV
+
+
+@pytest.mark.parametrize("method", ["ccd", "ccsd"])
+def test_dressed_denominator_trajectory(E, ctx, method):
+    o, v = 6, 30
+    s = make_system(o, v, 78)
+    F, V = Fock.from_system(s), Integrals.from_system(s)
+    ref = jacobi(F, V, method, tol=0.0, max_iter=7, dressed=True, level_shift=0.25)
+    d = E.DeviceSystem(s)
+    m = E.METHODS[method]
+    t1, t2 = E.zeros_amps(d, m)
+    out = E.iterate(ctx, d, m, t1, t2, tol=1e-30, max_iter=7, level_shift=0.25, dressed=True)
+    assert np.allclose(out["hist_e"], ref["hist_e"], rtol=0, atol=1e-12)
+    assert np.abs(t2.cpu().numpy() - ref["t2"]).max() < 1e-12
+    if method == "ccsd":
+        assert np.abs(t1.cpu().numpy() - ref["t1"]).max() < 1e-12

@@ -26,6 +26,10 @@ ROOT = pathlib.Path(__file__).resolve().parent
 sys.path.insert(0, str(ROOT))
 
 PEAK_FP64_TFLOPS = 78.6  # MI355X dense FP64 matrix peak (published)
+# Peaks per contraction precision, in algorithmic TFLOP/s: FP32 matrix 157.3;
+# split-bf16 issues three bf16 MFMA products per algorithmic product, so its
+# roofline is the dense bf16 peak (2.5 PFLOP/s) divided by three.
+PEAKS = {"f64": 78.6, "f32": 157.3, "bf16x3": 2500.0 / 3.0}
 CONFIGS = {
     "c2": dict(o=32, v=160, method="ccsd"),
     "c1": dict(o=8, v=24, method="ccd"),
@@ -93,6 +97,10 @@ def main():
     ap.add_argument("--no-converge", action="store_true", help="skip the time-to-1e-8 run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--max-iter", type=int, default=1500)
+    ap.add_argument("--prec", default="f64", choices=["f64", "f32", "bf16x3"],
+                    help="contraction precision of the timed steps")
+    ap.add_argument("--converge-precs", default="f64,f32,bf16x3",
+                    help="precisions whose time to ||R||<1e-8 is reported (reduced ones refine in FP64)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB copy (for HBM counter scaling)")
     args = ap.parse_args()
@@ -118,6 +126,7 @@ def main():
     ladder_flops = plan.flops(ladder_only=True)
     t1, t2 = E.zeros_amps(dsys, m)
     dressed = not args.bare
+    plan.set_precision(E.PRECS[args.prec])
     plan.step(t1, t2, args.shift, dressed)
     torch.cuda.synchronize()
     plan.autotune(t1, t2, 2)
@@ -155,17 +164,24 @@ def main():
 
     conv = {}
     if not args.no_converge:
-        u1, u2 = E.zeros_amps(dsys, m)
-        out = E.iterate(ctx, dsys, m, u1, u2, tol=1e-8, max_iter=args.max_iter, level_shift=args.shift,
-                        dressed=dressed, use_graph=True)
-        conv = {"converged": out["converged"], "iterations": out["iters"], "seconds": round(out["seconds"], 3),
-                "energy": out["energy"], "rnorm": out["rnorm"]}
         gold = ROOT / "tests" / "golden" / f"{args.config}_{method}_energy.json"
-        if gold.exists():
-            g = json.loads(gold.read_text())
-            conv["oracle_energy"] = g["energy"]
-            conv["abs_err_vs_oracle"] = abs(out["energy"] - g["energy"])
-        log(f"[bench] time to ||R||<1e-8: {out['seconds']:.2f}s, {out['iters']} iterations, E={out['energy']:.10f}")
+        g = json.loads(gold.read_text()) if gold.exists() else None
+        for pname in [x for x in args.converge_precs.split(",") if x]:
+            u1, u2 = E.zeros_amps(dsys, m)
+            out = E.iterate(ctx, dsys, m, u1, u2, tol=1e-8, max_iter=args.max_iter, level_shift=args.shift,
+                            dressed=dressed, use_graph=True, prec=E.PRECS[pname], autotune=True)
+            rec = {"converged": out["converged"], "iterations": out["iters"],
+                   "reduced_precision_iterations": out["lowp_iters"], "seconds": round(out["seconds"], 3),
+                   "energy": out["energy"], "rnorm": out["rnorm"]}
+            if g is not None:
+                rec["oracle_energy"] = g["energy"]
+                rec["abs_err_vs_oracle"] = abs(out["energy"] - g["energy"])
+            if "f64" in conv:
+                rec["abs_err_vs_f64"] = abs(out["energy"] - conv["f64"]["energy"])
+                rec["speedup_vs_f64"] = round(conv["f64"]["seconds"] / out["seconds"], 3)
+            conv[pname] = rec
+            log(f"[bench] {pname}: time to ||R||<1e-8 {out['seconds']:.2f}s, {out['iters']} iterations "
+                f"({out['lowp_iters']} reduced), E={out['energy']:.10f}")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -177,15 +193,16 @@ def main():
         "metric": "CCSD residual TFLOP/s & time-to-1e-8 convergence, FP64 vs mixed/learned",
         "value": round(value, 3), "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
+        "dtype": args.prec, "data": "synthetic",
         "config": {"workload": f"{method} o={o} v={v} fp64 real, seeded antisymmetrised <pq||rs>~N(0,0.01^2), "
                                f"diagonal Fock", "o": o, "v": v, "method": method,
                    "update": ("dressed" if dressed else "bare") + f" Jacobi, shift {args.shift}",
                    "flops_per_step": flops},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3) if achieved else None,
-                     "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_FP64_TFLOPS, 4) if achieved else None,
-                     "traffic": read_traffic(args.config), "kernel": "ladder GEMM (FP64 MFMA)",
+                     "peak": round(PEAKS[args.prec], 1), "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAKS[args.prec], 4) if achieved else None,
+                     "traffic": read_traffic(args.config) if args.prec == "f64" else None,
+                     "kernel": f"ladder GEMM ({args.prec} MFMA)",
                      "avg_ms": round(lad_ms, 4), "flops_per_launch": ladder_flops},
         "cpu_baseline": ({k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")} if cpu else None),
         "time_to_1e-8": conv or None,

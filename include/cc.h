@@ -86,12 +86,14 @@ typedef struct {
   int32_t max_iter;    /* at most this many residual evaluations */
   int32_t prec;        /* cc_prec of the contractions */
   double level_shift;  /* s >= 0: update t <- t + R / (D - s); s = 0 is plain Jacobi */
-  int32_t refine_every;/* mixed precision: an FP64 residual every this many steps (0 = never) */
+  double refine_tol;   /* reduced prec: switch to FP64 steps once ||R|| < refine_tol, or when the
+                          norm fell by less than 10% over 5 steps (refinement phase) */
   int32_t use_graph;   /* 1: capture one iteration as a HIP graph and replay it */
   int32_t check_every; /* read the norm back every this many iterations (>= 1) */
   int32_t diverge_window; /* EDIVERGED if the norm grew for this many checks in a row (0 = off) */
   int32_t dressed;     /* 0: D from the bare Fock diagonal; 1: from the diagonals of the
                           T-dressed one-body intermediates of the current iterate */
+  int32_t autotune;    /* 1: run the GEMM tile autotuner before iterating (counted as setup) */
 } cc_iter_opts;
 
 typedef struct {
@@ -101,6 +103,7 @@ typedef struct {
   double e_re, e_im;   /* E(t_final) - E_HF */
   double seconds;      /* wall time of the loop (setup excluded) */
   double setup_seconds;/* plan creation: derived integral views, workspace */
+  int32_t lowp_iters;  /* iterations done in reduced precision before the FP64 phase */
   double *hist_rnorm;  /* host arrays of capacity hist_cap, or NULL */
   double *hist_e;      /* E per iteration (real part) */
   int32_t hist_cap;
@@ -174,8 +177,11 @@ const char *cc_plan_describe(const cc_plan *plan);
 /* The same listing for a plan of the given sizes, built without a device
  * (no allocation, no kernel launch). */
 const char *cc_plan_describe_dry(int o, int v, int method, int scalar);
-/* Autotuner: times every instantiated GEMM tile configuration for each
- * distinct GEMM shape of the plan (reps launches each, on the plan's own
+/* Precision of the contractions of the following steps (cc_prec); the
+ * plan's creation precision is the initial value. */
+int cc_plan_set_precision(cc_plan *plan, int prec);
+/* Autotuner: times every instantiated GEMM tile configuration (of the
+ * plan's current precision) for each distinct GEMM shape of the plan (reps launches each, on the plan's own
  * buffers, with t as the amplitude operand) and keeps the fastest.  Choices
  * are cached per shape for the life of the process.  Workspace contents are
  * clobbered; the next step recomputes them.  t is only read. */

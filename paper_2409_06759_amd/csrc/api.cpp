@@ -4,6 +4,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "plan.hpp"
 
@@ -94,7 +95,7 @@ void run_step(cc_plan *p, bool use_graph) {
   const bool same = p->graph && p->graph_key[0] == p->t1 && p->graph_key[1] == p->t2 &&
                     p->graph_key[2] == p->r1_out && p->graph_key[3] == p->r2_out &&
                     p->graph_shift == p->shift && p->graph_update == p->update &&
-                    p->graph_dressed == p->dressed;
+                    p->graph_dressed == p->dressed && p->graph_prec == p->cur_prec;
   if (!same) {
     if (p->graph) (void)hipGraphExecDestroy(p->graph);
     p->graph = nullptr;
@@ -117,6 +118,7 @@ void run_step(cc_plan *p, bool use_graph) {
     p->graph_shift = p->shift;
     p->graph_update = p->update;
     p->graph_dressed = p->dressed;
+    p->graph_prec = p->cur_prec;
   }
   CC_HIP_CHECK(hipGraphLaunch(p->graph, p->ctx->stream));
 }
@@ -131,6 +133,7 @@ cc_plan *make_plan(cc_ctx *ctx, const cc_system *sys, int method, int prec) {
   p->v = sys->v;
   p->method = method;
   p->prec = prec;
+  p->cur_prec = prec;
   p->cplx = sys->scalar == CC_C128;
   p->esize = p->cplx ? 16 : 8;
   try {
@@ -324,6 +327,8 @@ int cc_iterate(cc_ctx *ctx, const cc_system *sys, int method, const cc_iter_opts
     int iters = 0;
     double rn = NAN, er = NAN, ei = NAN, best = INFINITY;
     int grew = 0;
+    std::vector<double> seen;  // norms seen in the current precision
+    int switched_at = -1;
     try {
       p->t1 = t->t1;
       p->t2 = t->t2;
@@ -331,6 +336,13 @@ int cc_iterate(cc_ctx *ctx, const cc_system *sys, int method, const cc_iter_opts
       p->update = true;
       p->shift = opts->level_shift;
       p->dressed = opts->dressed ? 1 : 0;
+      if (opts->autotune) {
+        for (int pr : {opts->prec, int(CC_PREC_F64)}) {
+          p->cur_prec = pr;
+          ccmi::plan_autotune(p, 1);
+        }
+        p->cur_prec = opts->prec;
+      }
       for (int it = 0; it < opts->max_iter; ++it) {
         run_step(p, opts->use_graph != 0);
         ++iters;
@@ -341,9 +353,23 @@ int cc_iterate(cc_ctx *ctx, const cc_system *sys, int method, const cc_iter_opts
           status = CC_EDIVERGED;
           break;
         }
-        if (rn < opts->tol) {
+        if (rn < opts->tol && p->cur_prec == CC_PREC_F64) {
           status = CC_OK;
           break;
+        }
+        if (p->cur_prec != CC_PREC_F64) {
+          // refinement: leave reduced precision once the norm is below
+          // refine_tol or has stopped falling (less than 10% over 5 steps);
+          // the following FP64 steps correct the reduced-precision iterate.
+          seen.push_back(rn);
+          const size_t n = seen.size();
+          const bool stagnant = n > 5 && seen[n - 1] > 0.9 * seen[n - 6];
+          if (rn < std::max(opts->refine_tol, opts->tol) || stagnant) {
+            p->cur_prec = CC_PREC_F64;
+            switched_at = it + 1;
+            best = INFINITY;
+            grew = 0;
+          }
         }
         if (rn < best) {
           best = rn;
@@ -365,6 +391,7 @@ int cc_iterate(cc_ctx *ctx, const cc_system *sys, int method, const cc_iter_opts
       rep->e_re = er;
       rep->e_im = ei;
       rep->seconds = std::chrono::duration<double>(t2c - t1c).count();
+      rep->lowp_iters = switched_at < 0 ? (opts->prec == CC_PREC_F64 ? 0 : iters) : switched_at;
       rep->setup_seconds = std::chrono::duration<double>(t1c - t0).count();
     }
     cc_plan_destroy(p);
@@ -468,6 +495,15 @@ const char *cc_plan_describe_dry(int o, int v, int method, int scalar) {
     s = std::string("error: ") + e.what();
   }
   return s.c_str();
+}
+
+int cc_plan_set_precision(cc_plan *p, int prec) {
+  if (!p) return fail(nullptr, CC_EINVAL, "plan is NULL");
+  return guarded(p->ctx, [&] {
+    validate_method(p->method, prec, p->cplx ? CC_C128 : CC_R64);
+    p->cur_prec = prec;
+    return CC_OK;
+  });
 }
 
 int cc_plan_autotune(cc_plan *p, const cc_amps *t, int reps) {

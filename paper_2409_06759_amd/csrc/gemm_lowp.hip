@@ -1,11 +1,317 @@
-// Placeholder: mixed-precision and complex GEMM paths.
+// Reduced-precision GEMMs on FP64 tensors:
+//   C[m][n] = alpha * sum_k A(m,k) B(n,k) + beta * C[m][n]   (C in FP64)
+// * F32:    operands rounded to FP32, v_mfma_f32_16x16x4_f32, FP32 accumulate.
+// * BF16X3: operands rounded to FP32 and split x = hi + lo with hi = bf16(x),
+//           lo = bf16(x - hi); the product keeps hi*hi + hi*lo + lo*hi
+//           (v_mfma_f32_16x16x32_bf16, FP32 accumulate), dropping lo*lo
+//           (split-bfloat16 products: Henry, Tang & Heinecke, ARITH 2019).
+// Operands stay FP64 in HBM; the conversion happens while a tile is staged
+// into LDS, so the rest of the residual path (permutations, assembly, norms,
+// denominators, energy) is unchanged FP64.  Tiling, double buffering, split-K
+// and the XCD-aware tile order follow the FP64 kernel.
 #include "common.hpp"
 
+#include <cmath>
+
 namespace ccmi {
-void gemm_lowp(const GemmDesc &, int, hipStream_t, int) {
-  throw CCError(-6, "FP32 / BF16x3 contractions are not built yet");
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+// round-to-nearest-even FP32 -> BF16 bits (finite inputs)
+__device__ __forceinline__ unsigned short bf16_bits(float x) {
+  unsigned u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return static_cast<unsigned short>(u >> 16);
 }
+__device__ __forceinline__ float bf16_to_float(unsigned short h) {
+  return __uint_as_float(static_cast<unsigned>(h) << 16);
+}
+
+template <int MODE, int BM, int BN, int BK, int WM, int WN, bool AKC, bool BKC>
+struct LCfg {
+  static constexpr int NT = WM * WN * kWave;
+  static constexpr int WTM = BM / WM, WTN = BN / WN;
+  static constexpr int FM = WTM / 16, FN = WTN / 16;
+  static constexpr int PAD = (MODE == PREC_F32) ? 4 : 8;  // elements
+  static constexpr int A_ROWS = AKC ? BM : BK, A_LD = AKC ? BK + PAD : BM + PAD;
+  static constexpr int B_ROWS = BKC ? BN : BK, B_LD = BKC ? BK + PAD : BN + PAD;
+  static constexpr int A_ELEMS = A_ROWS * A_LD, B_ELEMS = B_ROWS * B_LD;
+  static constexpr int LA = BM * BK / NT, LB = BN * BK / NT;
+  static constexpr int KSTEP = (MODE == PREC_F32) ? 16 : 32;  // k consumed per fragment load
+  static_assert(BM % (16 * WM) == 0 && BN % (16 * WN) == 0, "tile/wave mismatch");
+  static_assert(BK % KSTEP == 0, "BK");
+  static_assert((BM * BK) % NT == 0 && (BN * BK) % NT == 0, "load split");
+};
+
+template <int MODE, int BM, int BN, int BK, int WM, int WN, bool AKC, bool BKC, int TAG>
+__global__ __launch_bounds__(WM *WN *kWave) void gemm_lowp_kernel(GemmDesc d, int64_t tilesM,
+                                                                   int64_t tilesN) {
+  using C = LCfg<MODE, BM, BN, BK, WM, WN, AKC, BKC>;
+  // F32: one float array per operand and buffer.  BF16X3: hi and lo arrays
+  // (16-bit) per operand and buffer, laid out as [hi | lo].
+  constexpr int ESZ = (MODE == PREC_F32) ? 4 : 2;
+  constexpr int NPART = (MODE == PREC_F32) ? 1 : 2;
+  constexpr int A_BYTES = C::A_ELEMS * ESZ * NPART, B_BYTES = C::B_ELEMS * ESZ * NPART;
+  __shared__ __attribute__((aligned(16))) unsigned char smem[2 * (A_BYTES + B_BYTES)];
+
+  const int64_t tiles = tilesM * tilesN, total = tiles * d.split;
+  const int64_t L0 = xcd_remap(blockIdx.x, total);
+  const int64_t ks = L0 / tiles, L = L0 % tiles;
+  const int64_t m0 = (L % tilesM) * BM, n0 = (L / tilesM) * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm0 = (wave / WN) * C::WTM, wn0 = (wave % WN) * C::WTN;
+  const int q = lane >> 4, r = lane & 15;
+
+  const double *__restrict__ A = static_cast<const double *>(d.A);
+  const double *__restrict__ B = static_cast<const double *>(d.B);
+  const int64_t M = d.M, N = d.N;
+  const int64_t kchunk = ((d.K + d.split - 1) / d.split + BK - 1) / BK * BK;
+  const int64_t kb = ks * kchunk;
+  const int64_t K = std::max<int64_t>(0, std::min<int64_t>(d.K - kb, kchunk));
+  A += kb * d.sak;
+  B += kb * d.sbk;
+
+  float ra[C::LA], rb[C::LB];
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int i = 0; i < C::LA; ++i) {
+      const int e = tid + i * C::NT;
+      int mm, kk;
+      if (AKC) { mm = e / BK; kk = e % BK; } else { kk = e / BM; mm = e % BM; }
+      const int64_t gm = m0 + mm, gk = k0 + kk;
+      ra[i] = (gm < M && gk < K) ? static_cast<float>(A[gm * d.sam + gk * d.sak]) : 0.0f;
+    }
+#pragma unroll
+    for (int i = 0; i < C::LB; ++i) {
+      const int e = tid + i * C::NT;
+      int nn, kk;
+      if (BKC) { nn = e / BK; kk = e % BK; } else { kk = e / BN; nn = e % BN; }
+      const int64_t gn = n0 + nn, gk = k0 + kk;
+      rb[i] = (gn < N && gk < K) ? static_cast<float>(B[gn * d.sbn + gk * d.sbk]) : 0.0f;
+    }
+  };
+  auto a_base = [&](int buf) { return smem + buf * A_BYTES; };
+  auto b_base = [&](int buf) { return smem + 2 * A_BYTES + buf * B_BYTES; };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < C::LA; ++i) {
+      const int e = tid + i * C::NT;
+      const int idx = AKC ? (e / BK) * C::A_LD + (e % BK) : (e / BM) * C::A_LD + (e % BM);
+      if (MODE == PREC_F32) {
+        reinterpret_cast<float *>(a_base(buf))[idx] = ra[i];
+      } else {
+        const unsigned short h = bf16_bits(ra[i]);
+        unsigned short *p = reinterpret_cast<unsigned short *>(a_base(buf));
+        p[idx] = h;
+        p[C::A_ELEMS + idx] = bf16_bits(ra[i] - bf16_to_float(h));
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < C::LB; ++i) {
+      const int e = tid + i * C::NT;
+      const int idx = BKC ? (e / BK) * C::B_LD + (e % BK) : (e / BN) * C::B_LD + (e % BN);
+      if (MODE == PREC_F32) {
+        reinterpret_cast<float *>(b_base(buf))[idx] = rb[i];
+      } else {
+        const unsigned short h = bf16_bits(rb[i]);
+        unsigned short *p = reinterpret_cast<unsigned short *>(b_base(buf));
+        p[idx] = h;
+        p[C::B_ELEMS + idx] = bf16_bits(rb[i] - bf16_to_float(h));
+      }
+    }
+  };
+
+  f4 acc[C::FM][C::FN];
+#pragma unroll
+  for (int i = 0; i < C::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < C::FN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+
+  const int64_t nk = (K + BK - 1) / BK;
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) gload((kt + 1) * BK);
+    if constexpr (MODE == PREC_F32) {
+      const float *as = reinterpret_cast<const float *>(a_base(buf));
+      const float *bs = reinterpret_cast<const float *>(b_base(buf));
+#pragma unroll
+      for (int kc = 0; kc < BK; kc += 16) {
+        float fa[C::FM][4], fb[C::FN][4];
+#pragma unroll
+        for (int i = 0; i < C::FM; ++i) {
+          const int mm = wm0 + i * 16 + r;
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+            fa[i][s] = AKC ? as[mm * C::A_LD + kc + 4 * q + s] : as[(kc + 4 * q + s) * C::A_LD + mm];
+        }
+#pragma unroll
+        for (int j = 0; j < C::FN; ++j) {
+          const int nn = wn0 + j * 16 + r;
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+            fb[j][s] = BKC ? bs[nn * C::B_LD + kc + 4 * q + s] : bs[(kc + 4 * q + s) * C::B_LD + nn];
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int i = 0; i < C::FM; ++i)
+#pragma unroll
+            for (int j = 0; j < C::FN; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i][s], fb[j][s], acc[i][j], 0, 0, 0);
+      }
+    } else {
+      const unsigned short *ah = reinterpret_cast<const unsigned short *>(a_base(buf));
+      const unsigned short *bh = reinterpret_cast<const unsigned short *>(b_base(buf));
+      const unsigned short *al = ah + C::A_ELEMS, *bl = bh + C::B_ELEMS;
+#pragma unroll
+      for (int kc = 0; kc < BK; kc += 32) {
+        bf8 fah[C::FM], fal[C::FM], fbh[C::FN], fbl[C::FN];
+        // lane group q supplies logical k = kc + 8q .. kc + 8q + 7 for A and B alike
+#pragma unroll
+        for (int i = 0; i < C::FM; ++i) {
+          const int mm = wm0 + i * 16 + r;
+#pragma unroll
+          for (int s = 0; s < 8; ++s) {
+            const int idx = AKC ? mm * C::A_LD + kc + 8 * q + s : (kc + 8 * q + s) * C::A_LD + mm;
+            fah[i][s] = __builtin_bit_cast(__bf16, ah[idx]);
+            fal[i][s] = __builtin_bit_cast(__bf16, al[idx]);
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < C::FN; ++j) {
+          const int nn = wn0 + j * 16 + r;
+#pragma unroll
+          for (int s = 0; s < 8; ++s) {
+            const int idx = BKC ? nn * C::B_LD + kc + 8 * q + s : (kc + 8 * q + s) * C::B_LD + nn;
+            fbh[j][s] = __builtin_bit_cast(__bf16, bh[idx]);
+            fbl[j][s] = __builtin_bit_cast(__bf16, bl[idx]);
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < C::FM; ++i)
+#pragma unroll
+          for (int j = 0; j < C::FN; ++j) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fal[i], fbh[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fah[i], fbl[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fah[i], fbh[j], acc[i][j], 0, 0, 0);
+          }
+      }
+    }
+    if (kt + 1 < nk) sstore(buf ^ 1);
+    __syncthreads();
+  }
+
+  // epilogue: accumulator t of lane l is C[4 (l >> 4) + t][l & 15] of its block
+  double *__restrict__ Cp = static_cast<double *>(d.C);
+  double alpha = d.alpha, beta = d.beta;
+  int64_t ldc = d.ldc;
+  if (d.split > 1) {
+    Cp = static_cast<double *>(d.ws) + ks * M * N;
+    alpha = 1.0;
+    beta = 0.0;
+    ldc = N;
+  }
+#pragma unroll
+  for (int i = 0; i < C::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < C::FN; ++j) {
+      const int64_t gn = n0 + wn0 + j * 16 + r;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int64_t gm = m0 + wm0 + i * 16 + 4 * q + t;
+        if (gm < M && gn < N) {
+          double *p = Cp + gm * ldc + gn;
+          const double v = alpha * static_cast<double>(acc[i][j][t]);
+          *p = (beta == 0.0) ? v : v + beta * *p;
+        }
+      }
+    }
+}
+
+struct LTile {
+  const char *name;
+  int BM, BN, BK;
+  void (*launch[4])(const GemmDesc &, int64_t, int64_t, hipStream_t);
+  void (*launch_ladder)(const GemmDesc &, int64_t, int64_t, hipStream_t);
+};
+
+template <int MODE, int BM, int BN, int BK, int WM, int WN, bool AKC, bool BKC, int TAG = 0>
+void launch_l(const GemmDesc &d, int64_t tm, int64_t tn, hipStream_t s) {
+  hipLaunchKernelGGL((gemm_lowp_kernel<MODE, BM, BN, BK, WM, WN, AKC, BKC, TAG>), dim3(tm * tn * d.split),
+                     dim3(WM * WN * kWave), 0, s, d, tm, tn);
+}
+
+#define CC_LTILE(MODE, BM, BN, BK, WM, WN)                                                          \
+  LTile {                                                                                           \
+    #BM "x" #BN "x" #BK "_w" #WM "x" #WN, BM, BN, BK,                                               \
+        {&launch_l<MODE, BM, BN, BK, WM, WN, false, false>, &launch_l<MODE, BM, BN, BK, WM, WN, false, true>, \
+         &launch_l<MODE, BM, BN, BK, WM, WN, true, false>, &launch_l<MODE, BM, BN, BK, WM, WN, true, true>},  \
+        &launch_l<MODE, BM, BN, BK, WM, WN, true, true, 1>                                          \
+  }
+
+const LTile kF32Tiles[] = {
+    CC_LTILE(PREC_F32, 128, 128, 16, 2, 2), CC_LTILE(PREC_F32, 64, 64, 16, 2, 2),
+    CC_LTILE(PREC_F32, 32, 32, 16, 2, 2),   CC_LTILE(PREC_F32, 128, 64, 16, 2, 2),
+    CC_LTILE(PREC_F32, 64, 128, 16, 2, 2),  CC_LTILE(PREC_F32, 128, 128, 32, 2, 2),
+};
+const LTile kB3Tiles[] = {
+    CC_LTILE(PREC_BF16X3, 128, 128, 32, 2, 2), CC_LTILE(PREC_BF16X3, 64, 64, 32, 2, 2),
+    CC_LTILE(PREC_BF16X3, 32, 32, 32, 2, 2),   CC_LTILE(PREC_BF16X3, 128, 64, 32, 2, 2),
+    CC_LTILE(PREC_BF16X3, 64, 128, 32, 2, 2),  CC_LTILE(PREC_BF16X3, 128, 128, 64, 2, 2),
+};
+constexpr int kNumL = 6;
+
+int pick_l(const LTile *tiles, int64_t M, int64_t N) {
+  int best = 0;
+  double best_cost = 1e300;
+  for (int t = 0; t < kNumL; ++t) {
+    const double n = double((M + tiles[t].BM - 1) / tiles[t].BM) * double((N + tiles[t].BN - 1) / tiles[t].BN);
+    const double cost = std::ceil(n / 256.0) * (double(tiles[t].BM) * tiles[t].BN + 4096.0);
+    if (cost < best_cost) {
+      best_cost = cost;
+      best = t;
+    }
+  }
+  return best;
+}
+
+}  // namespace
+
+int gemm_lowp_num_tiles() { return kNumL; }
+const char *gemm_lowp_tile_name(int prec, int id) {
+  if (id < 0 || id >= kNumL) return "?";
+  return prec == PREC_F32 ? kF32Tiles[id].name : kB3Tiles[id].name;
+}
+
+void gemm_lowp(const GemmDesc &d, int prec, hipStream_t s, int tile_id) {
+  if (d.M <= 0 || d.N <= 0) return;
+  CC_REQUIRE(prec == PREC_F32 || prec == PREC_BF16X3, -1, "gemm_lowp: precision");
+  const bool akc = (d.sak == 1), bkc = (d.sbk == 1);
+  CC_REQUIRE(akc || d.sam == 1, -1, "gemm: A needs a unit stride in m or k");
+  CC_REQUIRE(bkc || d.sbn == 1, -1, "gemm: B needs a unit stride in n or k");
+  if (d.K <= 0) {
+    gemm_f64(d, s, -1);  // pure scaling of C: no products involved
+    return;
+  }
+  const LTile *tiles = prec == PREC_F32 ? kF32Tiles : kB3Tiles;
+  if (tile_id < 0 || tile_id >= kNumL) tile_id = pick_l(tiles, d.M, d.N);
+  const LTile &ti = tiles[tile_id];
+  const int64_t tm = (d.M + ti.BM - 1) / ti.BM, tn = (d.N + ti.BN - 1) / ti.BN;
+  CC_REQUIRE(d.split >= 1 && (d.split == 1 || d.ws != nullptr), -1, "gemm: split-K workspace");
+  CC_REQUIRE(tm * tn * d.split < (int64_t(1) << 31), -1, "gemm: too many tiles");
+  if (d.ladder && akc && bkc) ti.launch_ladder(d, tm, tn, s);
+  else ti.launch[(akc ? 2 : 0) + (bkc ? 1 : 0)](d, tm, tn, s);
+  CC_HIP_CHECK(hipGetLastError());
+  if (d.split > 1) splitk_reduce(false, d.ws, d.split, d.M, d.N, d.C, d.ldc, d.alpha, d.beta, s);
+}
+
 void gemm_c128(const GemmDesc &, hipStream_t) {
   throw CCError(-6, "complex contractions are not built yet");
 }
+
 }  // namespace ccmi

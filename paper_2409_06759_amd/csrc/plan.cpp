@@ -484,10 +484,10 @@ struct Planner {
   }
 };
 
-void run_gemm(cc_plan *p, GemmDesc &d, int tile, hipStream_t s) {
+void run_gemm(cc_plan *p, GemmDesc &d, const Step &st, hipStream_t s) {
   if (p->cplx) gemm_c128(d, s);
-  else if (p->prec == PREC_F64) gemm_f64(d, s, tile);
-  else gemm_lowp(d, p->prec, s, tile);
+  else if (p->cur_prec == PREC_F64) gemm_f64(d, s, st.tile);
+  else gemm_lowp(d, p->cur_prec, s, st.tile_lp[p->cur_prec]);
 }
 
 void *ptr_of(cc_plan *p, int s) {
@@ -509,7 +509,7 @@ void exec(cc_plan *p, Step &st, hipStream_t s) {
       d.B = ptr_of(p, st.b);
       d.C = ptr_of(p, st.c);
       d.ws = st.b2 >= 0 ? ptr_of(p, st.b2) : nullptr;
-      run_gemm(p, d, st.tile, s);
+      run_gemm(p, d, st, s);
       break;
     }
     case Step::OUTER:
@@ -625,8 +625,10 @@ void plan_run(cc_plan *p) {
 // iteration (on the plan's own buffers) and keep the fastest.  Results are
 // cached per (M, N, K, layouts) for the life of the process.
 void plan_autotune(cc_plan *p, int reps) {
-  if (p->cplx || p->prec != PREC_F64) return;
+  if (p->cplx) return;
   static std::map<std::string, int> cache;
+  const int prec = p->cur_prec;
+  const int ntiles = prec == PREC_F64 ? gemm_f64_num_tiles() : gemm_lowp_num_tiles();
   hipStream_t s = p->ctx->stream;
   hipEvent_t e0, e1;
   CC_HIP_CHECK(hipEventCreate(&e0));
@@ -635,23 +637,29 @@ void plan_autotune(cc_plan *p, int reps) {
     for (Step *st : p->gemm_steps) {
       GemmDesc d = st->gemm;
       const bool akc = d.sak == 1, bkc = d.sbk == 1;
-      const std::string key = std::to_string(d.M) + "x" + std::to_string(d.N) + "x" +
-                              std::to_string(d.K) + (akc ? "k" : "m") + (bkc ? "k" : "n");
+      const std::string key = std::to_string(prec) + ":" + std::to_string(d.M) + "x" +
+                              std::to_string(d.N) + "x" + std::to_string(d.K) + (akc ? "k" : "m") +
+                              (bkc ? "k" : "n");
+      int &slot = prec == PREC_F64 ? st->tile : st->tile_lp[prec];
       auto it = cache.find(key);
       if (it != cache.end()) {
-        st->tile = it->second;
+        slot = it->second;
         continue;
       }
       d.A = ptr_of(p, st->a);
       d.B = ptr_of(p, st->b);
       d.C = ptr_of(p, st->c);
       d.ws = st->b2 >= 0 ? ptr_of(p, st->b2) : nullptr;
-      int best = st->tile;
+      int best = slot;
       float best_ms = 1e30f;
-      for (int t = 0; t < gemm_f64_num_tiles(); ++t) {
-        gemm_f64(d, s, t);
+      auto launch = [&](int t) {
+        if (prec == PREC_F64) gemm_f64(d, s, t);
+        else gemm_lowp(d, prec, s, t);
+      };
+      for (int t = 0; t < ntiles; ++t) {
+        launch(t);
         CC_HIP_CHECK(hipEventRecord(e0, s));
-        for (int r = 0; r < reps; ++r) gemm_f64(d, s, t);
+        for (int r = 0; r < reps; ++r) launch(t);
         CC_HIP_CHECK(hipEventRecord(e1, s));
         CC_HIP_CHECK(hipEventSynchronize(e1));
         float ms = 0.f;
@@ -661,7 +669,7 @@ void plan_autotune(cc_plan *p, int reps) {
           best = t;
         }
       }
-      st->tile = best;
+      slot = best;
       cache[key] = best;
     }
   } catch (...) {
@@ -684,7 +692,9 @@ std::string plan_profile_table(const cc_plan *p) {
     std::string tag = st.tag.empty() ? "-" : st.tag;
     for (auto &c : tag)
       if (c == ' ') c = '_';
-    if (st.kind == Step::GEMM) tag += "@" + std::string(gemm_f64_tile_name(st.tile));
+    if (st.kind == Step::GEMM)
+      tag += "@" + std::string(p->cur_prec == PREC_F64 ? gemm_f64_tile_name(st.tile)
+                                                        : gemm_lowp_tile_name(p->cur_prec, st.tile_lp[p->cur_prec]));
     os << i << " " << kinds[st.kind] << " " << tag << " " << p->step_calls[i]
        << " " << p->step_ms[i] << " " << (p->step_calls[i] ? p->step_ms[i] / p->step_calls[i] : 0.0)
        << " " << st.flops << "\n";

@@ -48,7 +48,8 @@ struct Step {
   PermDesc perm{};
   GemmDesc gemm{};
   OuterArgs outer{};
-  int tile = -1;
+  int tile = -1;        // FP64 tile
+  int tile_lp[3] = {-1, -1, -1};  // per reduced precision (index = cc_prec)
   int64_t nelem = 0;
   double flops = 0.0;
   std::string tag;
@@ -59,6 +60,7 @@ struct Step {
 struct cc_plan {
   cc_ctx *ctx = nullptr;
   int o = 0, v = 0, method = 0, prec = 0;
+  int cur_prec = 0;  // precision of the contractions in the next run
   bool cplx = false;
   size_t esize = 8;
   std::vector<ccmi::Slot> slots;
@@ -83,6 +85,7 @@ struct cc_plan {
   double graph_shift = 0.0;
   bool graph_update = false;
   int graph_dressed = 0;
+  int graph_prec = -1;
   double flops_per_iter = 0.0, ladder_flops = 0.0;
   std::vector<ccmi::Step *> gemm_steps;
   // per-step timing (HIP events around every step of an iteration)

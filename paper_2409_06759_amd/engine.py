@@ -144,6 +144,9 @@ class Plan:
         self.ctx.enter()
         self.ctx.check(self.ctx.lib.cc_plan_autotune(self.h, C.byref(_amps(t1, t2)), reps))
 
+    def set_precision(self, prec: int):
+        self.ctx.check(self.ctx.lib.cc_plan_set_precision(self.h, prec))
+
     def profile(self, enable: bool = True):
         self.ctx.check(self.ctx.lib.cc_plan_profile(self.h, 1 if enable else 0))
 
@@ -191,13 +194,14 @@ def energy(ctx, dsys, method, t1, t2):
 
 
 def iterate(ctx, dsys, method, t1, t2, tol=1e-8, max_iter=100, level_shift=0.0, prec=F64,
-            use_graph=True, refine_every=0, diverge_window=0, hist_cap=None, dressed=False):
+            use_graph=True, refine_tol=0.0, diverge_window=0, hist_cap=None, dressed=False,
+            autotune=False):
     cap = hist_cap or max_iter
     hr = (C.c_double * cap)()
     he = (C.c_double * cap)()
-    opts = L.CCIterOpts(tol, max_iter, prec, level_shift, refine_every, 1 if use_graph else 0, 1,
-                        diverge_window, 1 if dressed else 0)
-    rep = L.CCIterReport(0, 0, 0.0, 0.0, 0.0, 0.0, 0.0, C.cast(hr, C.POINTER(C.c_double)),
+    opts = L.CCIterOpts(tol, max_iter, prec, level_shift, refine_tol, 1 if use_graph else 0, 1,
+                        diverge_window, 1 if dressed else 0, 1 if autotune else 0)
+    rep = L.CCIterReport(0, 0, 0.0, 0.0, 0.0, 0.0, 0.0, 0, C.cast(hr, C.POINTER(C.c_double)),
                          C.cast(he, C.POINTER(C.c_double)), cap)
     ctx.enter()
     rc = ctx.lib.cc_iterate(ctx.h, C.byref(dsys.struct), method, C.byref(opts), C.byref(_amps(t1, t2)),
@@ -206,7 +210,7 @@ def iterate(ctx, dsys, method, t1, t2, tol=1e-8, max_iter=100, level_shift=0.0, 
     n = min(rep.iters, cap)
     return {"status": rc, "iters": rep.iters, "converged": bool(rep.converged), "rnorm": rep.rnorm,
             "energy": complex(rep.e_re, rep.e_im) if dsys.is_complex else rep.e_re,
-            "seconds": rep.seconds, "setup_seconds": rep.setup_seconds,
+            "seconds": rep.seconds, "setup_seconds": rep.setup_seconds, "lowp_iters": rep.lowp_iters,
             "hist_rnorm": list(hr[:n]), "hist_e": list(he[:n])}
 
 

@@ -72,3 +72,30 @@ def test_permute_accumulate(ctx):
     E.permute(ctx, torch.from_numpy(x).cuda(), (0, 2, 3, 1), out=out, alpha=2.0, beta=-1.0)
     ref = 2.0 * x.transpose(0, 2, 3, 1) - y
     assert np.abs(out.cpu().numpy() - ref).max() < 1e-14
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
+@pytest.mark.parametrize("shape", [(16, 16, 16), (17, 33, 65), (64, 576, 576), (100, 129, 37), (257, 300, 49)])
+@pytest.mark.parametrize("akc,bkc", [(True, True), (False, False), (True, False)])
+def test_gemm_lowp_error_bound(ctx, prec, shape, akc, bkc):
+    """Reduced precision: |C - C_ref| <= 2 eps_eff (|alpha| |A||B|^T) + FP64 rounding of beta C.
+    eps_eff = (K + 2) 2^-24 (FP32 inputs, FP32 accumulation) plus 3 * 2^-17 for
+    the split-bf16 product (hi*hi + hi*lo + lo*hi; lo*lo and the second split's
+    remainder dropped)."""
+    from paper_2409_06759_amd import engine as E
+    M, N, K = shape
+    print(f"gemm {prec} M={M} N={N} K={K} akc={akc} bkc={bkc}", flush=True)
+    rng = np.random.default_rng(M + 3 * N + 7 * K)
+    A = rng.normal(size=(M, K))
+    B = rng.normal(size=(N, K))
+    C0 = rng.normal(size=(M, N))
+    alpha, beta = 0.5, -1.25
+    ref = alpha * (A @ B.T) + beta * C0
+    Ad = torch.from_numpy(A if akc else np.ascontiguousarray(A.T)).cuda()
+    Bd = torch.from_numpy(B if bkc else np.ascontiguousarray(B.T)).cuda()
+    Cd = torch.from_numpy(C0).cuda()
+    E.gemm(ctx, Ad, Bd, Cd, alpha, beta, a_kcontig=akc, b_kcontig=bkc, prec=E.PRECS[prec])
+    eps = (K + 2) * 2.0 ** -24 + (3 * 2.0 ** -17 if prec == "bf16x3" else 0.0)
+    bound = 2 * eps * abs(alpha) * (np.abs(A) @ np.abs(B).T) + 4 * np.finfo(float).eps * np.abs(beta * C0)
+    err = np.abs(Cd.cpu().numpy() - ref)
+    assert np.all(err <= bound), (err / bound).max()

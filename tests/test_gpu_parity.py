@@ -191,3 +191,37 @@ def test_dressed_denominator_trajectory(E, ctx, method):
     assert np.abs(t2.cpu().numpy() - ref["t2"]).max() < 1e-12
     if method == "ccsd":
         assert np.abs(t1.cpu().numpy() - ref["t1"]).max() < 1e-12
+
+
+@pytest.mark.parametrize("prec,tol", [("f32", 2e-6), ("bf16x3", 5e-5)])
+@pytest.mark.parametrize("ov", [(3, 5), (8, 24)])
+def test_reduced_precision_residual(E, ctx, prec, tol, ov):
+    """Residual with reduced-precision contractions against the FP64 oracle.
+    Terms are O(1e-2) with at most v^2 = 576 products each: FP32 gives
+    <= 576 * 2^-24 * 1e-2 ~ 3e-7 per GEMM, split-bf16 adds ~3 * 2^-17 * 1e-2."""
+    o, v = ov
+    s = make_system(o, v, 2000 + o * v)
+    t1, t2 = _amps(o, v, o * v)
+    F, V = Fock.from_system(s), Integrals.from_system(s)
+    r1_ref, r2_ref = residual(F, V, t1, t2)
+    d = E.DeviceSystem(s)
+    r1, r2, rn = E.residual(ctx, d, E.CCSD, torch.from_numpy(t1).cuda(), torch.from_numpy(t2).cuda(),
+                            prec=E.PRECS[prec])
+    r2 = r2.cpu().numpy()
+    assert np.abs(r2 - r2_ref).max() < tol
+    assert np.abs(r1.cpu().numpy() - r1_ref).max() < tol
+    assert np.array_equal(r2, -r2.transpose(1, 0, 2, 3))
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
+def test_mixed_precision_refines_to_fp64_solution(E, ctx, prec):
+    o, v = 8, 24
+    s = make_system(o, v)
+    F, V = Fock.from_system(s), Integrals.from_system(s)
+    ref = jacobi(F, V, "ccsd", tol=1e-11, max_iter=100, dressed=True)
+    d = E.DeviceSystem(s)
+    t1, t2 = E.zeros_amps(d, E.CCSD)
+    out = E.iterate(ctx, d, E.CCSD, t1, t2, tol=1e-10, max_iter=100, prec=E.PRECS[prec], dressed=True)
+    assert out["converged"]
+    assert 0 < out["lowp_iters"] < out["iters"]
+    assert abs(out["energy"] - ref["energy"]) < 1e-10

@@ -29,10 +29,26 @@ o..o+v-1 (the paper orders spaces by rising orbital energy).
 """
 from __future__ import annotations
 
+import concurrent.futures as _cf
 import dataclasses
+import os
 from typing import Dict, Optional
 
 import numpy as np
+
+# NumPy releases the GIL inside its array loops, so row chunks of a block are
+# filled concurrently; the values do not depend on the number of threads.
+_THREADS = max(1, min(16, os.cpu_count() or 1))
+
+
+def _parallel_rows(nrows: int, rows_per_chunk: int, fn) -> None:
+    starts = list(range(0, nrows, rows_per_chunk))
+    if _THREADS == 1 or len(starts) == 1:
+        for r0 in starts:
+            fn(r0)
+        return
+    with _cf.ThreadPoolExecutor(_THREADS) as ex:
+        list(ex.map(fn, starts))
 
 BASE_SEED = 240906759
 SIGMA = 0.01
@@ -114,8 +130,9 @@ def _pair_matrix(seed: int, n: int, gl: np.ndarray, gr: np.ndarray, is_complex: 
     out_dtype = np.complex128 if is_complex else np.float64
     G = np.empty((gl.size, gr.size), dtype=out_dtype)
     a = gl[:, None]
-    rows = max(1, (1 << 22) // max(1, gr.size))
-    for r0 in range(0, gl.size, rows):
+    rows = max(1, (1 << 20) // max(1, gr.size))
+
+    def fill(r0):
         aa = a[r0:r0 + rows]
         lo = np.minimum(aa, gr[None, :]).astype(np.uint64)
         hi = np.maximum(aa, gr[None, :]).astype(np.uint64)
@@ -129,6 +146,8 @@ def _pair_matrix(seed: int, n: int, gl: np.ndarray, gr: np.ndarray, is_complex: 
         else:
             val = n1 * sigma
         G[r0:r0 + rows] = val
+
+    _parallel_rows(gl.size, rows, fill)
     # pairs that do not exist (p == q) carry index -1 and sign 0; zero them
     if gl.size and gl[0] < 0:
         G[0, :] = 0
@@ -152,13 +171,16 @@ def integral_block(o: int, v: int, spaces: str, seed: int, is_complex: bool = Fa
     if out is None:
         out = np.empty(shape, dtype=dt)
     flat = out.reshape(S[0].size * S[1].size, S[2].size * S[3].size)
-    rows = max(1, (1 << 24) // max(1, flat.shape[1]))
-    for r0 in range(0, flat.shape[0], rows):
+    rows = max(1, (1 << 22) // max(1, flat.shape[1]))
+
+    def fill(r0):
         r1 = min(flat.shape[0], r0 + rows)
         blk = G[invl[r0:r1]][:, invr]
         blk *= sl[r0:r1, None]
         blk *= sr[None, :]
         flat[r0:r1] = blk
+
+    _parallel_rows(flat.shape[0], rows, fill)
     return out
 
 

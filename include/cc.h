@@ -65,6 +65,7 @@ typedef enum { CC_PREC_F64 = 0, CC_PREC_F32 = 1, CC_PREC_BF16X3 = 2 } cc_prec;
 
 typedef struct cc_ctx cc_ctx;
 typedef struct cc_plan cc_plan;
+typedef struct cc_batch cc_batch;
 
 /* One system: sizes plus device pointers to the Fock and integral blocks
  * (layouts above).  f_ov may be all zeros but must be a valid pointer. */
@@ -168,6 +169,36 @@ int cc_gemm(cc_ctx *ctx, int prec, int scalar, int64_t M, int64_t N, int64_t K, 
  * perm[d]; in is dense row-major with dims in_dims. */
 int cc_permute(cc_ctx *ctx, int scalar, int rank, const int64_t *in_dims, const int32_t *perm,
                double alpha, const void *in, double beta, void *out);
+
+/* ---- batches of independent systems --------------------------------------
+ * n systems (each its own o, v and integral blocks; all real or all complex)
+ * iterated together.  Each iteration step of the contraction list is ONE
+ * grouped launch over all systems; the whole iteration is replayed as one
+ * HIP graph.  The amplitude buffers amps[b] are bound at creation (they are
+ * updated in place by every step) and must stay valid until destruction.
+ * The contraction precision is fixed at creation. */
+int cc_batch_create(cc_ctx *ctx, int n, const cc_system *systems, int method, int prec, cc_amps *amps,
+                    cc_batch **batch);
+int cc_batch_destroy(cc_batch *batch);
+/* One Jacobi step of every system (see cc_plan_step); no host sync. */
+int cc_batch_step(cc_batch *batch, double level_shift, int dressed);
+/* Per-system ||R||, Re E, Im E of the last step (arrays of n; syncs). */
+int cc_batch_scalars(cc_batch *batch, double *rnorm, double *e_re, double *e_im);
+/* Choose one GEMM tile configuration per contraction class by timing the
+ * grouped launches (FP64 real batches). */
+int cc_batch_autotune(cc_batch *batch, int reps);
+/* Iterate until every system has ||R|| < tol (converged systems keep being
+ * updated, which leaves them converged).  reports: array of n (host); each
+ * records the iteration at which its system first met the tolerance and the
+ * scalars there.  n_converged (may be NULL) receives the count.  Returns
+ * CC_OK, CC_ENOTCONV or CC_EDIVERGED. */
+int cc_batch_iterate(cc_batch *batch, const cc_iter_opts *opts, cc_iter_report *reports,
+                     int32_t *n_converged);
+/* Per-step timing of the grouped launches (see cc_plan_profile). */
+int cc_batch_profile(cc_batch *batch, int enable);
+const char *cc_batch_profile_table(const cc_batch *batch);
+/* Algorithmic flops of one batch iteration (sum over systems). */
+double cc_batch_flops(const cc_batch *batch);
 
 /* ---- introspection ------------------------------------------------------ */
 /* Text listing of the plan's setup and per-iteration steps (permutes, GEMMs

@@ -25,7 +25,9 @@ EXPORTS = (
     "cc_plan_create", "cc_plan_destroy", "cc_plan_workspace_bytes", "cc_plan_residual",
     "cc_plan_step", "cc_plan_scalars", "cc_residual", "cc_energy", "cc_iterate", "cc_gemm",
     "cc_permute", "cc_plan_describe", "cc_plan_describe_dry", "cc_plan_flops", "cc_plan_profile",
-    "cc_plan_profile_table", "cc_plan_autotune", "cc_plan_set_precision",
+    "cc_plan_profile_table", "cc_plan_autotune", "cc_plan_set_precision", "cc_batch_create",
+    "cc_batch_destroy", "cc_batch_step", "cc_batch_scalars", "cc_batch_autotune", "cc_batch_iterate",
+    "cc_batch_profile", "cc_batch_profile_table", "cc_batch_flops",
 )
 
 
@@ -94,6 +96,15 @@ def load() -> C.CDLL:
         "cc_plan_profile": (C.c_int, [vp, C.c_int]),
         "cc_plan_autotune": (C.c_int, [vp, P(CCAmps), C.c_int]),
         "cc_plan_set_precision": (C.c_int, [vp, C.c_int]),
+        "cc_batch_create": (C.c_int, [vp, C.c_int, P(CCSystemStruct), C.c_int, C.c_int, P(CCAmps), P(vp)]),
+        "cc_batch_destroy": (C.c_int, [vp]),
+        "cc_batch_step": (C.c_int, [vp, dbl, C.c_int]),
+        "cc_batch_scalars": (C.c_int, [vp, P(dbl), P(dbl), P(dbl)]),
+        "cc_batch_autotune": (C.c_int, [vp, C.c_int]),
+        "cc_batch_iterate": (C.c_int, [vp, P(CCIterOpts), P(CCIterReport), P(i32)]),
+        "cc_batch_profile": (C.c_int, [vp, C.c_int]),
+        "cc_batch_profile_table": (C.c_char_p, [vp]),
+        "cc_batch_flops": (dbl, [vp]),
         "cc_plan_profile_table": (C.c_char_p, [vp]),
     }
     for name, (res, args) in sig.items():

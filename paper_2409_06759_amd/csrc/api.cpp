@@ -148,6 +148,13 @@ cc_plan *make_plan(cc_ctx *ctx, const cc_system *sys, int method, int prec) {
 
 }  // namespace
 
+namespace ccmi {
+cc_plan *make_plan_checked(cc_ctx *ctx, const cc_system *sys, int method, int prec) {
+  return make_plan(ctx, sys, method, prec);
+}
+void check_amps(const cc_amps *t, int method) { validate_amps(t, method, "t"); }
+}  // namespace ccmi
+
 extern "C" {
 
 const char *cc_status_string(int s) {

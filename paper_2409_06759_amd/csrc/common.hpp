@@ -56,14 +56,36 @@ struct GemmDesc {
 
 enum Prec { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16X3 = 2 };
 
+// Grouped launches: entry b of a group describes system b's share; the
+// workgroup range of system b is [off[b], off[b+1]).
+struct GemmGroupEntry {
+  GemmDesc d;
+  int64_t tilesM, tilesN;
+};
+
+__device__ __forceinline__ int group_find(const int64_t *off, int n, int64_t bid) {
+  int lo = 0, hi = n - 1;  // largest b with off[b] <= bid
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= bid) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 // Tile configuration chosen by the tuner for one GEMM shape.
 struct GemmTile {
   int id;  // index into the instantiated configuration table
 };
 
 void gemm_f64(const GemmDesc &d, hipStream_t s, int tile_id = -1);
+void gemm_f64_grouped_launch(const GemmGroupEntry *dev_entries, const int64_t *dev_off, int n,
+                             int64_t blocks, bool akc, bool bkc, int tile_id, hipStream_t s);
+void gemm_f64_tile_shape(int tile_id, int *bm, int *bn);
 void gemm_lowp(const GemmDesc &d, int prec, hipStream_t s, int tile_id = -1);
-void gemm_c128(const GemmDesc &d, hipStream_t s);
+void gemm_c128(const GemmDesc &d, hipStream_t s, int tile_id = -1);
+int gemm_c128_num_tiles();
+const char *gemm_c128_tile_name(int id);
 int gemm_f64_num_tiles();
 const char *gemm_f64_tile_name(int id);
 int gemm_f64_pick(int64_t M, int64_t N, int64_t K, bool a_kc, bool b_kc);

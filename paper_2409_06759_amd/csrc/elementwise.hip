@@ -39,7 +39,7 @@ __device__ __forceinline__ double im(double2 a) { return a.y; }
 
 constexpr int RED_THREADS = 256;
 
-// Block-wide sum in a fixed order (tree over LDS); result in thread 0.
+// Block-wide sum in a fixed order (tree over LDS); result in every thread.
 __device__ __forceinline__ double block_sum(double v, double *sh) {
   const int t = threadIdx.x;
   sh[t] = v;
@@ -53,27 +53,19 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
   return r;
 }
 
-// ------------------------------------------------------------- permutation --
-struct PermArgs {
-  int rank;
-  int64_t dims[kMaxRank];
-  int64_t istr[kMaxRank];
-  int64_t ostr[kMaxRank];
-  double alpha, beta;
-  int conj;
-  int d_o, d_i;          // tiled dims: output unit-stride dim and input unit-stride dim
-  int64_t rest_dims[kMaxRank];  // dims other than d_o, d_i (rank-2 entries used)
-  int64_t rest_istr[kMaxRank], rest_ostr[kMaxRank];
-  int nrest;
-  int64_t n_rest_total, tiles_o, tiles_i;
-};
 
-// Plain path: input and output share their unit-stride dimension.
+constexpr int64_t CH = 1024;      // elements per workgroup, flat kernels
+constexpr int64_t CH_TAU = 2048;  // elements per workgroup, tau + energy
+
+// ------------------------------------------------------------- permutation --
+// Flat path: input and output share their unit-stride dimension.
 template <class T>
-__global__ __launch_bounds__(256) void permute_flat_kernel(PermArgs p, const T *__restrict__ in,
-                                                           T *__restrict__ out, int64_t total) {
-  for (int64_t e = blockIdx.x * int64_t(256) + threadIdx.x; e < total;
-       e += int64_t(gridDim.x) * 256) {
+__device__ __forceinline__ void perm_flat_body(const PermEntry &E, int64_t bid) {
+  const PermArgs &p = E.p;
+  const T *__restrict__ in = static_cast<const T *>(E.in);
+  T *__restrict__ out = static_cast<T *>(E.out);
+  const int64_t e1 = std::min<int64_t>(p.total, (bid + 1) * CH);
+  for (int64_t e = bid * CH + threadIdx.x; e < e1; e += 256) {
     int64_t rem = e, io = 0, oo = 0;
     for (int d = p.rank - 1; d >= 0; --d) {
       const int64_t x = rem % p.dims[d];
@@ -93,10 +85,12 @@ __global__ __launch_bounds__(256) void permute_flat_kernel(PermArgs p, const T *
 // read coalesced along the input's fast dim, written coalesced along the
 // output's fast dim through a padded LDS tile.
 template <class T>
-__global__ __launch_bounds__(256) void permute_tiled_kernel(PermArgs p, const T *__restrict__ in,
-                                                            T *__restrict__ out) {
+__device__ __forceinline__ void perm_tiled_body(const PermEntry &E, int64_t bid) {
+  const PermArgs &p = E.p;
+  const T *__restrict__ in = static_cast<const T *>(E.in);
+  T *__restrict__ out = static_cast<T *>(E.out);
   __shared__ T tile[32][33];
-  int64_t b = blockIdx.x;
+  int64_t b = bid;
   const int64_t ti = b % p.tiles_i; b /= p.tiles_i;
   const int64_t to = b % p.tiles_o; b /= p.tiles_o;
   int64_t ib = 0, ob = 0;
@@ -109,7 +103,6 @@ __global__ __launch_bounds__(256) void permute_tiled_kernel(PermArgs p, const T 
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   const int64_t Do = p.dims[p.d_o], Di = p.dims[p.d_i];
   const int64_t i0 = ti * 32, o0 = to * 32;
-  // load: x runs along the input's unit-stride dim
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int64_t xi = i0 + tx, xo = o0 + ty + 8 * k;
@@ -130,61 +123,16 @@ __global__ __launch_bounds__(256) void permute_tiled_kernel(PermArgs p, const T 
   }
 }
 
-template <class T>
-void permute_impl(const PermDesc &d, const void *in, void *out, hipStream_t s) {
-  PermArgs p{};
-  p.rank = d.rank;
-  int64_t total = 1;
-  for (int i = 0; i < d.rank; ++i) {
-    p.dims[i] = d.out_dims[i];
-    p.istr[i] = d.in_strides[i];
-    p.ostr[i] = d.out_strides[i];
-    total *= d.out_dims[i];
-  }
-  if (total == 0) return;
-  p.alpha = d.alpha;
-  p.beta = d.beta;
-  p.conj = d.conj;
-  int d_o = -1, d_i = -1;
-  for (int i = 0; i < d.rank; ++i) {
-    if (p.ostr[i] == 1 && p.dims[i] > 1) d_o = i;
-    if (p.istr[i] == 1 && p.dims[i] > 1) d_i = i;
-  }
-  const T *ip = static_cast<const T *>(in);
-  T *op = static_cast<T *>(out);
-  if (d_o < 0 || d_i < 0 || d_o == d_i) {
-    const int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
-    hipLaunchKernelGGL(permute_flat_kernel<T>, dim3(blocks), dim3(256), 0, s, p, ip, op, total);
-  } else {
-    p.d_o = d_o;
-    p.d_i = d_i;
-    p.nrest = 0;
-    p.n_rest_total = 1;
-    for (int i = 0; i < d.rank; ++i) {
-      if (i == d_o || i == d_i) continue;
-      p.rest_dims[p.nrest] = p.dims[i];
-      p.rest_istr[p.nrest] = p.istr[i];
-      p.rest_ostr[p.nrest] = p.ostr[i];
-      p.n_rest_total *= p.dims[i];
-      ++p.nrest;
-    }
-    p.tiles_o = (p.dims[d_o] + 31) / 32;
-    p.tiles_i = (p.dims[d_i] + 31) / 32;
-    const int64_t blocks = p.n_rest_total * p.tiles_o * p.tiles_i;
-    CC_REQUIRE(blocks < (int64_t(1) << 31), -1, "permute: grid too large");
-    hipLaunchKernelGGL(permute_tiled_kernel<T>, dim3(blocks), dim3(256), 0, s, p, ip, op);
-  }
-  CC_HIP_CHECK(hipGetLastError());
-}
-
 // ------------------------------------------------------------ outer product --
 // C[I] += alpha * A[sum_d I_d sa_d] * B[sum_d I_d sb_d]  (rank <= 4)
 template <class T>
-__global__ __launch_bounds__(256) void outer_kernel(OuterArgs p, const T *__restrict__ A,
-                                                    const T *__restrict__ B, T *__restrict__ C,
-                                                    int64_t total) {
-  for (int64_t e = blockIdx.x * int64_t(256) + threadIdx.x; e < total;
-       e += int64_t(gridDim.x) * 256) {
+__device__ __forceinline__ void outer_body(const OuterEntry &E, int64_t bid) {
+  const OuterArgs &p = E.a;
+  const T *__restrict__ A = static_cast<const T *>(E.A);
+  const T *__restrict__ B = static_cast<const T *>(E.B);
+  T *__restrict__ C = static_cast<T *>(E.C);
+  const int64_t e1 = std::min<int64_t>(E.total, (bid + 1) * CH);
+  for (int64_t e = bid * CH + threadIdx.x; e < e1; e += 256) {
     int64_t rem = e, ia = 0, ibb = 0;
     for (int d = p.rank - 1; d >= 0; --d) {
       const int64_t x = rem % p.dims[d];
@@ -199,43 +147,49 @@ __global__ __launch_bounds__(256) void outer_kernel(OuterArgs p, const T *__rest
   }
 }
 
+// ------------------------------------------------------------------- fill --
+template <class T>
+__device__ __forceinline__ void fill_body(const FillEntry &E, int64_t bid) {
+  T *__restrict__ p = static_cast<T *>(E.p);
+  const int64_t e1 = std::min<int64_t>(E.n, (bid + 1) * CH);
+  for (int64_t e = bid * CH + threadIdx.x; e < e1; e += 256) p[e] = zero<T>();
+}
+
 // ---------------------------------------------------------- split-K sum --
 // C = alpha * sum_s W[s] + beta * C, s in increasing order (deterministic).
 template <class T>
-__global__ __launch_bounds__(256) void splitk_kernel(const T *__restrict__ W, int split, int64_t M,
-                                                     int64_t N, T *__restrict__ C, int64_t ldc,
-                                                     double alpha, double beta) {
-  const int64_t total = M * N;
-  for (int64_t e = blockIdx.x * int64_t(256) + threadIdx.x; e < total;
-       e += int64_t(gridDim.x) * 256) {
+__device__ __forceinline__ void splitk_body(const SplitkEntry &E, int64_t bid) {
+  const T *__restrict__ W = static_cast<const T *>(E.ws);
+  T *__restrict__ C = static_cast<T *>(E.C);
+  const int64_t total = E.M * E.N;
+  const int64_t e1 = std::min<int64_t>(total, (bid + 1) * CH);
+  for (int64_t e = bid * CH + threadIdx.x; e < e1; e += 256) {
     T acc = W[e];
-    for (int k = 1; k < split; ++k) acc = add(acc, W[int64_t(k) * total + e]);
-    const int64_t m = e / N, n = e % N;
-    T v = sc(alpha, acc);
-    if (beta != 0.0) v = add(v, sc(beta, C[m * ldc + n]));
-    C[m * ldc + n] = v;
+    for (int k = 1; k < E.split; ++k) acc = add(acc, W[int64_t(k) * total + e]);
+    const int64_t m = e / E.N, n = e % E.N;
+    T v = sc(E.alpha, acc);
+    if (E.beta != 0.0) v = add(v, sc(E.beta, C[m * E.ldc + n]));
+    C[m * E.ldc + n] = v;
   }
-}
-
-// ------------------------------------------------------------------- fill --
-template <class T>
-__global__ __launch_bounds__(256) void fill_kernel(T *__restrict__ p, T val, int64_t n) {
-  for (int64_t e = blockIdx.x * int64_t(256) + threadIdx.x; e < n; e += int64_t(gridDim.x) * 256)
-    p[e] = val;
 }
 
 // --------------------------------------------------- tau + energy partials --
 // tau = t2 + (t_i^a t_j^b - t_i^b t_j^a), taut = t2 + 1/2 (...),
-// energy partial: 1/4 sum <ij||ab> tau_ij^ab  (+ sum f_ia t_i^a by block 0).
+// energy partial: 1/4 sum <ij||ab> tau_ij^ab  (+ sum f_ia t_i^a by unit 0).
 template <class T>
-__global__ __launch_bounds__(RED_THREADS) void tau_energy_kernel(
-    int o, int v, const T *__restrict__ t1, const T *__restrict__ t2, const T *__restrict__ oovv,
-    const T *__restrict__ fov, T *__restrict__ tau, T *__restrict__ taut, double *partials) {
+__device__ __forceinline__ void tau_body(const TauEntry &E, int64_t bid) {
   __shared__ double sh[RED_THREADS];
+  const T *__restrict__ t1 = static_cast<const T *>(E.t1);
+  const T *__restrict__ t2 = static_cast<const T *>(E.t2);
+  const T *__restrict__ oovv = static_cast<const T *>(E.oovv);
+  const T *__restrict__ fov = static_cast<const T *>(E.fov);
+  T *__restrict__ tau = static_cast<T *>(E.tau);
+  T *__restrict__ taut = static_cast<T *>(E.taut);
+  const int o = E.o, v = E.v;
   const int64_t vv = int64_t(v) * v, total = int64_t(o) * o * vv;
   double er = 0.0, ei = 0.0;
-  for (int64_t e = blockIdx.x * int64_t(RED_THREADS) + threadIdx.x; e < total;
-       e += int64_t(gridDim.x) * RED_THREADS) {
+  const int64_t e1 = std::min<int64_t>(total, (bid + 1) * CH_TAU);
+  for (int64_t e = bid * CH_TAU + threadIdx.x; e < e1; e += RED_THREADS) {
     T x = t2[e];
     if (t1 != nullptr) {
       const int b = e % v, a = (e / v) % v;
@@ -253,7 +207,7 @@ __global__ __launch_bounds__(RED_THREADS) void tau_energy_kernel(
   }
   er = 0.25 * er;
   ei = 0.25 * ei;
-  if (blockIdx.x == 0 && t1 != nullptr) {
+  if (bid == 0 && t1 != nullptr) {
     for (int e = threadIdx.x; e < o * v; e += RED_THREADS) {
       const T w = mul(fov[e], t1[e]);
       er += re(w);
@@ -263,8 +217,8 @@ __global__ __launch_bounds__(RED_THREADS) void tau_energy_kernel(
   const double sr = block_sum(er, sh);
   const double si = block_sum(ei, sh);
   if (threadIdx.x == 0) {
-    partials[2 * blockIdx.x] = sr;
-    partials[2 * blockIdx.x + 1] = si;
+    E.partials[2 * bid] = sr;
+    E.partials[2 * bid + 1] = si;
   }
 }
 
@@ -289,20 +243,23 @@ __device__ __forceinline__ void tri_decode(int64_t k, int n, int &i, int &j) {
 }
 
 template <class T>
-__global__ __launch_bounds__(256) void r2_assemble_kernel(R2Args p, const T *__restrict__ XP,
-                                                          const T *__restrict__ Xij,
-                                                          const T *__restrict__ Xab,
-                                                          const T *__restrict__ Xr,
-                                                          T *__restrict__ R, T *__restrict__ t2,
-                                                          double *partials) {
+__device__ __forceinline__ void asm_body(const AsmEntry &E, int64_t bid) {
+  const R2Args &p = E.a;
+  const T *__restrict__ XP = static_cast<const T *>(E.XP);
+  const T *__restrict__ Xij = static_cast<const T *>(E.Xij);
+  const T *__restrict__ Xab = static_cast<const T *>(E.Xab);
+  const T *__restrict__ Xr = static_cast<const T *>(E.Xr);
+  T *__restrict__ R = static_cast<T *>(E.R);
+  T *__restrict__ t2 = static_cast<T *>(E.t2);
+  double *partials = E.partials;
   __shared__ T sab[32][33], sr_ij[32][33], sr_ji[32][33], sv[32][33], st[32][33];
   __shared__ double sh[RED_THREADS];
   const int o = p.o, v = p.v;
   const int tiles = (v + 31) / 32;
   const int64_t ntp = int64_t(tiles) * (tiles + 1) / 2;
   int ta, tb, i, j;
-  tri_decode(blockIdx.x % ntp, tiles, ta, tb);
-  tri_decode(blockIdx.x / ntp, o, i, j);
+  tri_decode(bid % ntp, tiles, ta, tb);
+  tri_decode(bid / ntp, o, i, j);
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   const int64_t vv = int64_t(v) * v;
   const int64_t base_ij = (int64_t(i) * o + j) * vv, base_ji = (int64_t(j) * o + i) * vv;
@@ -394,27 +351,48 @@ __global__ __launch_bounds__(256) void r2_assemble_kernel(R2Args p, const T *__r
     }
   }
   const double s = block_sum(nrm, sh);
-  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  if (threadIdx.x == 0) partials[bid] = s;
 }
 
-// singles: R1 already assembled; norm partial and optional update
+
+// ----------------------------------------------------------------- singles --
+// R1 already assembled: norm partial and optional update.
 template <class T>
-__global__ __launch_bounds__(RED_THREADS) void r1_update_kernel(int o, int v, const T *__restrict__ R1,
-                                                                T *__restrict__ t1, const double *d_oo,
-                                                                const double *d_vv, double shift,
-                                                                int dressed, const T *Fo, const T *Fv,
-                                                                double *partial) {
+__device__ __forceinline__ void r1_body(const R1Entry &E) {
   __shared__ double sh[RED_THREADS];
+  const T *__restrict__ R1 = static_cast<const T *>(E.R1);
+  T *__restrict__ t1 = static_cast<T *>(E.t1);
+  const T *Fo = static_cast<const T *>(E.Fo), *Fv = static_cast<const T *>(E.Fv);
+  const int o = E.o, v = E.v;
   double nrm = 0.0;
   for (int e = threadIdx.x; e < o * v; e += RED_THREADS) {
     const int i = e / v, a = e % v;
     const T r = R1[e];
     nrm += abs2(r);
-    const double D = dressed ? re(Fo[int64_t(i) * o + i]) - re(Fv[int64_t(a) * v + a]) : d_oo[i] - d_vv[a];
-    if (t1 != nullptr) t1[e] = add(t1[e], sc(1.0 / (D - shift), r));
+    const double D = E.dressed ? re(Fo[int64_t(i) * o + i]) - re(Fv[int64_t(a) * v + a])
+                               : E.d_oo[i] - E.d_vv[a];
+    if (t1 != nullptr) t1[e] = add(t1[e], sc(1.0 / (D - E.shift), r));
   }
   const double s = block_sum(nrm, sh);
-  if (threadIdx.x == 0) partial[0] = s;
+  if (threadIdx.x == 0) E.partial[0] = s;
+}
+
+// scalars[0] = ||R||, scalars[1..2] = E (re, im); fixed summation order.
+__device__ __forceinline__ void fin_body(const FinEntry &E) {
+  __shared__ double sh[RED_THREADS];
+  double a = 0.0, b = 0.0, c = 0.0;
+  for (int k = threadIdx.x; k < E.ne; k += RED_THREADS) {
+    a += E.epart[2 * k];
+    b += E.epart[2 * k + 1];
+  }
+  for (int k = threadIdx.x; k < E.nn; k += RED_THREADS) c += E.n2part[k];
+  const double sa = block_sum(a, sh), sb = block_sum(b, sh), scn = block_sum(c, sh);
+  if (threadIdx.x == 0) {
+    const double n2 = scn + (E.n1part ? E.n1part[0] : 0.0);
+    E.scalars[0] = sqrt(n2);
+    E.scalars[1] = sa;
+    E.scalars[2] = sb;
+  }
 }
 
 // Fock diagonals (real parts) into contiguous arrays.
@@ -426,149 +404,221 @@ __global__ void fock_diag_kernel(int o, int v, const T *foo, const T *fvv, doubl
   }
 }
 
-// scalars[0] = ||R||, scalars[1..2] = E (re, im); fixed summation order.
-__global__ __launch_bounds__(RED_THREADS) void finalize_kernel(const double *epart, int ne,
-                                                               const double *n2part, int nn,
-                                                               const double *n1part,
-                                                               double *scalars) {
-  __shared__ double sh[RED_THREADS];
-  double a = 0.0, b = 0.0, c = 0.0;
-  for (int k = threadIdx.x; k < ne; k += RED_THREADS) {
-    a += epart[2 * k];
-    b += epart[2 * k + 1];
+// ------------------------------------------------------- kernels (both forms)
+#define CC_EW_KERNELS(NAME, ENTRY, BODY)                                                          \
+  template <class T>                                                                              \
+  __global__ __launch_bounds__(256) void k_##NAME(ENTRY e) {                                     \
+    BODY<T>(e, blockIdx.x);                                                                       \
+  }                                                                                               \
+  template <class T>                                                                              \
+  __global__ __launch_bounds__(256) void g_##NAME(const ENTRY *__restrict__ es,                  \
+                                                  const int64_t *__restrict__ off, int n) {      \
+    const int b = group_find(off, n, blockIdx.x);                                                 \
+    BODY<T>(es[b], int64_t(blockIdx.x) - off[b]);                                                 \
   }
-  for (int k = threadIdx.x; k < nn; k += RED_THREADS) c += n2part[k];
-  const double sa = block_sum(a, sh), sb = block_sum(b, sh), scn = block_sum(c, sh);
-  if (threadIdx.x == 0) {
-    const double n2 = scn + (n1part ? n1part[0] : 0.0);
-    scalars[0] = sqrt(n2);
-    scalars[1] = sa;
-    scalars[2] = sb;
-  }
-}
+
+CC_EW_KERNELS(perm_flat, PermEntry, perm_flat_body)
+CC_EW_KERNELS(perm_tiled, PermEntry, perm_tiled_body)
+CC_EW_KERNELS(outer, OuterEntry, outer_body)
+CC_EW_KERNELS(fill, FillEntry, fill_body)
+CC_EW_KERNELS(splitk, SplitkEntry, splitk_body)
+CC_EW_KERNELS(tau, TauEntry, tau_body)
+CC_EW_KERNELS(asm, AsmEntry, asm_body)
+
+template <class T>
+__global__ __launch_bounds__(RED_THREADS) void k_r1(R1Entry e) { r1_body<T>(e); }
+template <class T>
+__global__ __launch_bounds__(RED_THREADS) void g_r1(const R1Entry *__restrict__ es) { r1_body<T>(es[blockIdx.x]); }
+__global__ __launch_bounds__(RED_THREADS) void k_fin(FinEntry e) { fin_body(e); }
+__global__ __launch_bounds__(RED_THREADS) void g_fin(const FinEntry *__restrict__ es) { fin_body(es[blockIdx.x]); }
+
+int64_t chunks(int64_t n, int64_t ch) { return std::max<int64_t>(1, (n + ch - 1) / ch); }
 
 }  // namespace
 
-// ================================================================ launchers ==
-void permute_f64(const PermDesc &d, const void *in, void *out, hipStream_t s) {
-  permute_impl<double>(d, in, out, s);
-}
-void permute_c128(const PermDesc &d, const void *in, void *out, hipStream_t s) {
-  permute_impl<double2>(d, in, out, s);
-}
-
-void outer_acc(const OuterArgs &a, bool cplx, const void *A, const void *B, void *C, hipStream_t s) {
+// ============================================================ host: entries ==
+PermEntry make_perm_entry(const PermDesc &d, const void *in, void *out) {
+  PermEntry e{};
+  PermArgs &p = e.p;
+  p.rank = d.rank;
   int64_t total = 1;
-  for (int i = 0; i < a.rank; ++i) total *= a.dims[i];
-  if (total == 0) return;
-  const int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
-  if (cplx)
-    hipLaunchKernelGGL(outer_kernel<double2>, dim3(blocks), dim3(256), 0, s, a,
-                       static_cast<const double2 *>(A), static_cast<const double2 *>(B),
-                       static_cast<double2 *>(C), total);
-  else
-    hipLaunchKernelGGL(outer_kernel<double>, dim3(blocks), dim3(256), 0, s, a,
-                       static_cast<const double *>(A), static_cast<const double *>(B),
-                       static_cast<double *>(C), total);
-  CC_HIP_CHECK(hipGetLastError());
+  for (int i = 0; i < d.rank; ++i) {
+    p.dims[i] = d.out_dims[i];
+    p.istr[i] = d.in_strides[i];
+    p.ostr[i] = d.out_strides[i];
+    total *= d.out_dims[i];
+  }
+  p.total = total;
+  p.alpha = d.alpha;
+  p.beta = d.beta;
+  p.conj = d.conj;
+  int d_o = -1, d_i = -1;
+  for (int i = 0; i < d.rank; ++i) {
+    if (p.ostr[i] == 1 && p.dims[i] > 1) d_o = i;
+    if (p.istr[i] == 1 && p.dims[i] > 1) d_i = i;
+  }
+  e.in = in;
+  e.out = out;
+  if (total == 0) {
+    e.units = 0;
+    return e;
+  }
+  if (d_o < 0 || d_i < 0 || d_o == d_i) {
+    e.tiled = 0;
+    e.units = chunks(total, CH);
+  } else {
+    e.tiled = 1;
+    p.d_o = d_o;
+    p.d_i = d_i;
+    p.nrest = 0;
+    p.n_rest_total = 1;
+    for (int i = 0; i < d.rank; ++i) {
+      if (i == d_o || i == d_i) continue;
+      p.rest_dims[p.nrest] = p.dims[i];
+      p.rest_istr[p.nrest] = p.istr[i];
+      p.rest_ostr[p.nrest] = p.ostr[i];
+      p.n_rest_total *= p.dims[i];
+      ++p.nrest;
+    }
+    p.tiles_o = (p.dims[d_o] + 31) / 32;
+    p.tiles_i = (p.dims[d_i] + 31) / 32;
+    e.units = p.n_rest_total * p.tiles_o * p.tiles_i;
+  }
+  return e;
 }
 
-void splitk_reduce(bool cplx, const void *ws, int split, int64_t M, int64_t N, void *C, int64_t ldc,
-                   double alpha, double beta, hipStream_t s) {
-  const int64_t total = M * N;
-  if (total == 0) return;
-  const int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
-  if (cplx)
-    hipLaunchKernelGGL(splitk_kernel<double2>, dim3(blocks), dim3(256), 0, s,
-                       static_cast<const double2 *>(ws), split, M, N, static_cast<double2 *>(C), ldc,
-                       alpha, beta);
-  else
-    hipLaunchKernelGGL(splitk_kernel<double>, dim3(blocks), dim3(256), 0, s,
-                       static_cast<const double *>(ws), split, M, N, static_cast<double *>(C), ldc,
-                       alpha, beta);
-  CC_HIP_CHECK(hipGetLastError());
+OuterEntry make_outer_entry(const OuterArgs &a, const void *A, const void *B, void *C) {
+  OuterEntry e{};
+  e.a = a;
+  e.A = A;
+  e.B = B;
+  e.C = C;
+  e.total = 1;
+  for (int i = 0; i < a.rank; ++i) e.total *= a.dims[i];
+  e.units = e.total ? chunks(e.total, CH) : 0;
+  return e;
 }
 
-void fill_zero(void *p, int64_t n_elems, bool cplx, hipStream_t s) {
-  if (n_elems <= 0) return;
-  const int64_t blocks = std::min<int64_t>((n_elems + 255) / 256, 65536);
-  if (cplx)
-    hipLaunchKernelGGL(fill_kernel<double2>, dim3(blocks), dim3(256), 0, s,
-                       static_cast<double2 *>(p), make_double2(0.0, 0.0), n_elems);
-  else
-    hipLaunchKernelGGL(fill_kernel<double>, dim3(blocks), dim3(256), 0, s, static_cast<double *>(p),
-                       0.0, n_elems);
-  CC_HIP_CHECK(hipGetLastError());
+FillEntry make_fill_entry(void *p, int64_t n) { return FillEntry{p, n, n > 0 ? chunks(n, CH) : 0}; }
+
+SplitkEntry make_splitk_entry(const void *ws, int split, int64_t M, int64_t N, void *C, int64_t ldc, double alpha,
+                              double beta) {
+  return SplitkEntry{ws, split, M, N, C, ldc, alpha, beta, M * N > 0 ? chunks(M * N, CH) : 0};
 }
 
-int tau_energy_blocks(int o, int v) {
-  const int64_t total = int64_t(o) * o * v * v;
-  return int(std::max<int64_t>(1, std::min<int64_t>((total + RED_THREADS - 1) / RED_THREADS, 2048)));
+int64_t tau_units(int o, int v) { return chunks(int64_t(o) * o * v * v, CH_TAU); }
+
+TauEntry make_tau_entry(int o, int v, const void *t1, const void *t2, const void *oovv, const void *fov,
+                        void *tau, void *taut, double *partials) {
+  return TauEntry{o, v, t1, t2, oovv, fov, tau, taut, partials, tau_units(o, v)};
 }
 
-void tau_energy(bool cplx, int o, int v, const void *t1, const void *t2, const void *oovv,
-                const void *fov, void *tau, void *taut, double *partials, hipStream_t s) {
-  const int blocks = tau_energy_blocks(o, v);
-  if (cplx)
-    hipLaunchKernelGGL(tau_energy_kernel<double2>, dim3(blocks), dim3(RED_THREADS), 0, s, o, v,
-                       (const double2 *)t1, (const double2 *)t2, (const double2 *)oovv,
-                       (const double2 *)fov, (double2 *)tau, (double2 *)taut, partials);
-  else
-    hipLaunchKernelGGL(tau_energy_kernel<double>, dim3(blocks), dim3(RED_THREADS), 0, s, o, v,
-                       (const double *)t1, (const double *)t2, (const double *)oovv,
-                       (const double *)fov, (double *)tau, (double *)taut, partials);
-  CC_HIP_CHECK(hipGetLastError());
-}
-
-int64_t r2_assemble_blocks(int o, int v) {
+int64_t asm_units(int o, int v) {
   const int64_t tiles = (v + 31) / 32;
   return (int64_t(o) * (o + 1) / 2) * (tiles * (tiles + 1) / 2);
 }
 
-void r2_assemble(bool cplx, const R2Args &a, const void *XP, const void *Xij, const void *Xab,
-                 const void *Xr, void *R, void *t2, double *partials, hipStream_t s) {
-  const int64_t blocks = r2_assemble_blocks(a.o, a.v);
-  CC_REQUIRE(blocks < (int64_t(1) << 31), -1, "r2_assemble: grid too large");
-  if (cplx)
-    hipLaunchKernelGGL(r2_assemble_kernel<double2>, dim3(blocks), dim3(256), 0, s, a,
-                       (const double2 *)XP, (const double2 *)Xij, (const double2 *)Xab,
-                       (const double2 *)Xr, (double2 *)R, (double2 *)t2, partials);
-  else
-    hipLaunchKernelGGL(r2_assemble_kernel<double>, dim3(blocks), dim3(256), 0, s, a,
-                       (const double *)XP, (const double *)Xij, (const double *)Xab,
-                       (const double *)Xr, (double *)R, (double *)t2, partials);
+AsmEntry make_asm_entry(const R2Args &a, const void *XP, const void *Xij, const void *Xab, const void *Xr, void *R,
+                        void *t2, double *partials) {
+  return AsmEntry{a, XP, Xij, Xab, Xr, R, t2, partials, asm_units(a.o, a.v)};
+}
+
+// ========================================================= host: launches ==
+#define CC_LAUNCH1(KER, E, UNITS, CPLX, S)                                                          \
+  do {                                                                                            \
+    if ((UNITS) <= 0) return;                                                                     \
+    CC_REQUIRE((UNITS) < (int64_t(1) << 31), -1, "grid too large");                               \
+    if (CPLX) hipLaunchKernelGGL(KER<double2>, dim3(UNITS), dim3(256), 0, S, E);                  \
+    else hipLaunchKernelGGL(KER<double>, dim3(UNITS), dim3(256), 0, S, E);                        \
+    CC_HIP_CHECK(hipGetLastError());                                                              \
+  } while (0)
+
+#define CC_LAUNCHG(KER, E, OFF, N, BLOCKS, CPLX, S)                                                 \
+  do {                                                                                            \
+    if ((BLOCKS) <= 0) return;                                                                    \
+    CC_REQUIRE((BLOCKS) < (int64_t(1) << 31), -1, "grid too large");                              \
+    if (CPLX) hipLaunchKernelGGL(KER<double2>, dim3(BLOCKS), dim3(256), 0, S, E, OFF, N);         \
+    else hipLaunchKernelGGL(KER<double>, dim3(BLOCKS), dim3(256), 0, S, E, OFF, N);               \
+    CC_HIP_CHECK(hipGetLastError());                                                              \
+  } while (0)
+
+void launch_perm(const PermEntry &e, bool cplx, hipStream_t s) {
+  if (e.tiled) CC_LAUNCH1(k_perm_tiled, e, e.units, cplx, s);
+  else CC_LAUNCH1(k_perm_flat, e, e.units, cplx, s);
+}
+void launch_outer(const OuterEntry &e, bool cplx, hipStream_t s) { CC_LAUNCH1(k_outer, e, e.units, cplx, s); }
+void launch_fill(const FillEntry &e, bool cplx, hipStream_t s) { CC_LAUNCH1(k_fill, e, e.units, cplx, s); }
+void launch_splitk(const SplitkEntry &e, bool cplx, hipStream_t s) { CC_LAUNCH1(k_splitk, e, e.units, cplx, s); }
+void launch_tau(const TauEntry &e, bool cplx, hipStream_t s) { CC_LAUNCH1(k_tau, e, e.units, cplx, s); }
+void launch_asm(const AsmEntry &e, bool cplx, hipStream_t s) { CC_LAUNCH1(k_asm, e, e.units, cplx, s); }
+void launch_r1(const R1Entry &e, bool cplx, hipStream_t s) {
+  if (cplx) hipLaunchKernelGGL(k_r1<double2>, dim3(1), dim3(RED_THREADS), 0, s, e);
+  else hipLaunchKernelGGL(k_r1<double>, dim3(1), dim3(RED_THREADS), 0, s, e);
+  CC_HIP_CHECK(hipGetLastError());
+}
+void launch_fin(const FinEntry &e, hipStream_t s) {
+  hipLaunchKernelGGL(k_fin, dim3(1), dim3(RED_THREADS), 0, s, e);
   CC_HIP_CHECK(hipGetLastError());
 }
 
-void r1_update(bool cplx, int o, int v, const void *R1, void *t1, const double *d_oo,
-               const double *d_vv, double shift, int dressed, const void *Fo, const void *Fv,
-               double *partial, hipStream_t s) {
-  if (cplx)
-    hipLaunchKernelGGL(r1_update_kernel<double2>, dim3(1), dim3(RED_THREADS), 0, s, o, v,
-                       (const double2 *)R1, (double2 *)t1, d_oo, d_vv, shift, dressed,
-                       (const double2 *)Fo, (const double2 *)Fv, partial);
-  else
-    hipLaunchKernelGGL(r1_update_kernel<double>, dim3(1), dim3(RED_THREADS), 0, s, o, v,
-                       (const double *)R1, (double *)t1, d_oo, d_vv, shift, dressed,
-                       (const double *)Fo, (const double *)Fv, partial);
+void launch_perm_grouped(const PermEntry *e, const int64_t *off, int n, int64_t blocks, bool tiled, bool cplx,
+                         hipStream_t s) {
+  if (tiled) CC_LAUNCHG(g_perm_tiled, e, off, n, blocks, cplx, s);
+  else CC_LAUNCHG(g_perm_flat, e, off, n, blocks, cplx, s);
+}
+void launch_outer_grouped(const OuterEntry *e, const int64_t *off, int n, int64_t blocks, bool cplx, hipStream_t s) {
+  CC_LAUNCHG(g_outer, e, off, n, blocks, cplx, s);
+}
+void launch_fill_grouped(const FillEntry *e, const int64_t *off, int n, int64_t blocks, bool cplx, hipStream_t s) {
+  CC_LAUNCHG(g_fill, e, off, n, blocks, cplx, s);
+}
+void launch_splitk_grouped(const SplitkEntry *e, const int64_t *off, int n, int64_t blocks, bool cplx,
+                           hipStream_t s) {
+  CC_LAUNCHG(g_splitk, e, off, n, blocks, cplx, s);
+}
+void launch_tau_grouped(const TauEntry *e, const int64_t *off, int n, int64_t blocks, bool cplx, hipStream_t s) {
+  CC_LAUNCHG(g_tau, e, off, n, blocks, cplx, s);
+}
+void launch_asm_grouped(const AsmEntry *e, const int64_t *off, int n, int64_t blocks, bool cplx, hipStream_t s) {
+  CC_LAUNCHG(g_asm, e, off, n, blocks, cplx, s);
+}
+void launch_r1_grouped(const R1Entry *e, int n, bool cplx, hipStream_t s) {
+  if (n <= 0) return;
+  if (cplx) hipLaunchKernelGGL(g_r1<double2>, dim3(n), dim3(RED_THREADS), 0, s, e);
+  else hipLaunchKernelGGL(g_r1<double>, dim3(n), dim3(RED_THREADS), 0, s, e);
+  CC_HIP_CHECK(hipGetLastError());
+}
+void launch_fin_grouped(const FinEntry *e, int n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(g_fin, dim3(n), dim3(RED_THREADS), 0, s, e);
   CC_HIP_CHECK(hipGetLastError());
 }
 
-void fock_diag(bool cplx, int o, int v, const void *foo, const void *fvv, double *d_oo,
-               double *d_vv, hipStream_t s) {
-  if (cplx)
-    hipLaunchKernelGGL(fock_diag_kernel<double2>, dim3(1), dim3(256), 0, s, o, v,
-                       (const double2 *)foo, (const double2 *)fvv, d_oo, d_vv);
-  else
-    hipLaunchKernelGGL(fock_diag_kernel<double>, dim3(1), dim3(256), 0, s, o, v,
-                       (const double *)foo, (const double *)fvv, d_oo, d_vv);
-  CC_HIP_CHECK(hipGetLastError());
+// ====================================================== host: conveniences ==
+void permute_f64(const PermDesc &d, const void *in, void *out, hipStream_t s) {
+  launch_perm(make_perm_entry(d, in, out), false, s);
 }
-
-void finalize_scalars(const double *epart, int ne, const double *n2part, int nn,
-                      const double *n1part, double *scalars, hipStream_t s) {
-  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(RED_THREADS), 0, s, epart, ne, n2part, nn,
-                     n1part, scalars);
+void permute_c128(const PermDesc &d, const void *in, void *out, hipStream_t s) {
+  launch_perm(make_perm_entry(d, in, out), true, s);
+}
+void outer_acc(const OuterArgs &a, bool cplx, const void *A, const void *B, void *C, hipStream_t s) {
+  launch_outer(make_outer_entry(a, A, B, C), cplx, s);
+}
+void fill_zero(void *p, int64_t n_elems, bool cplx, hipStream_t s) {
+  launch_fill(make_fill_entry(p, n_elems), cplx, s);
+}
+void splitk_reduce(bool cplx, const void *ws, int split, int64_t M, int64_t N, void *C, int64_t ldc,
+                   double alpha, double beta, hipStream_t s) {
+  launch_splitk(make_splitk_entry(ws, split, M, N, C, ldc, alpha, beta), cplx, s);
+}
+void fock_diag(bool cplx, int o, int v, const void *foo, const void *fvv, double *d_oo, double *d_vv,
+               hipStream_t s) {
+  if (cplx)
+    hipLaunchKernelGGL(fock_diag_kernel<double2>, dim3(1), dim3(256), 0, s, o, v, (const double2 *)foo,
+                       (const double2 *)fvv, d_oo, d_vv);
+  else
+    hipLaunchKernelGGL(fock_diag_kernel<double>, dim3(1), dim3(256), 0, s, o, v, (const double *)foo,
+                       (const double *)fvv, d_oo, d_vv);
   CC_HIP_CHECK(hipGetLastError());
 }
 

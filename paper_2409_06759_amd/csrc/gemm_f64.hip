@@ -44,15 +44,15 @@ struct Cfg {
   static_assert((BM * BK) % NT == 0 && (BN * BK) % NT == 0, "load split");
 };
 
-template <int BM, int BN, int BK, int WM, int WN, bool AKC, bool BKC, int TAG>
-__global__ __launch_bounds__(WM *WN *kWave) void gemm_f64_kernel(GemmDesc d, int64_t tilesM,
-                                                                  int64_t tilesN) {
+// One workgroup's share of a GEMM: logical tile L0 in [0, tiles * split).
+template <int BM, int BN, int BK, int WM, int WN, bool AKC, bool BKC>
+__device__ __forceinline__ void gemm_f64_body(const GemmDesc &d, int64_t tilesM, int64_t tilesN,
+                                              int64_t L0) {
   using C = Cfg<BM, BN, BK, WM, WN, AKC, BKC>;
   __shared__ double smem[2 * (C::A_ELEMS + C::B_ELEMS)];
   // buffer b of A at smem + b*A_ELEMS, of B at smem + 2*A_ELEMS + b*B_ELEMS
 
-  const int64_t tiles = tilesM * tilesN, total = tiles * d.split;
-  const int64_t L0 = xcd_remap(blockIdx.x, total);
+  const int64_t tiles = tilesM * tilesN;
   const int64_t ks = L0 / tiles, L = L0 % tiles;
   const int64_t m0 = (L % tilesM) * BM, n0 = (L / tilesM) * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -177,12 +177,36 @@ __global__ __launch_bounds__(WM *WN *kWave) void gemm_f64_kernel(GemmDesc d, int
     }
 }
 
+template <int BM, int BN, int BK, int WM, int WN, bool AKC, bool BKC, int TAG>
+__global__ __launch_bounds__(WM *WN *kWave) void gemm_f64_kernel(GemmDesc d, int64_t tilesM,
+                                                                  int64_t tilesN) {
+  const int64_t total = tilesM * tilesN * d.split;
+  gemm_f64_body<BM, BN, BK, WM, WN, AKC, BKC>(d, tilesM, tilesN, xcd_remap(blockIdx.x, total));
+}
+
+// Grouped launch: one workgroup range per system; system b owns logical
+// tiles [g.off[b], g.off[b+1]).  Same arithmetic as the single launch.
+template <int BM, int BN, int BK, int WM, int WN, bool AKC, bool BKC>
+__global__ __launch_bounds__(WM *WN *kWave) void gemm_f64_grouped(const GemmGroupEntry *__restrict__ e,
+                                                                   const int64_t *__restrict__ off, int n) {
+  const int b = group_find(off, n, blockIdx.x);
+  const GemmGroupEntry &g = e[b];
+  gemm_f64_body<BM, BN, BK, WM, WN, AKC, BKC>(g.d, g.tilesM, g.tilesN, int64_t(blockIdx.x) - off[b]);
+}
+
 struct TileInfo {
   const char *name;
   int BM, BN, BK, threads;
   void (*launch[4])(const GemmDesc &, int64_t, int64_t, hipStream_t);  // [akc*2 + bkc]
   void (*launch_ladder)(const GemmDesc &, int64_t, int64_t, hipStream_t);  // both K-contiguous
+  void (*launch_grouped[4])(const GemmGroupEntry *, const int64_t *, int, int64_t, hipStream_t);
 };
+
+template <int BM, int BN, int BK, int WM, int WN, bool AKC, bool BKC>
+void launch_grp(const GemmGroupEntry *e, const int64_t *off, int n, int64_t blocks, hipStream_t s) {
+  hipLaunchKernelGGL((gemm_f64_grouped<BM, BN, BK, WM, WN, AKC, BKC>), dim3(blocks), dim3(WM * WN * kWave),
+                     0, s, e, off, n);
+}
 
 // TAG only changes the kernel's symbol name: TAG 1 is the particle-particle
 // ladder, so that profilers report it on its own line.
@@ -197,7 +221,9 @@ void launch_cfg(const GemmDesc &d, int64_t tm, int64_t tn, hipStream_t s) {
     #BM "x" #BN "x" #BK "_w" #WM "x" #WN, BM, BN, BK, WM *WN * kWave, {                      \
       &launch_cfg<BM, BN, BK, WM, WN, false, false>, &launch_cfg<BM, BN, BK, WM, WN, false, true>, \
           &launch_cfg<BM, BN, BK, WM, WN, true, false>, &launch_cfg<BM, BN, BK, WM, WN, true, true> \
-    }, &launch_cfg<BM, BN, BK, WM, WN, true, true, 1>                                        \
+    }, &launch_cfg<BM, BN, BK, WM, WN, true, true, 1>,                                       \
+    {&launch_grp<BM, BN, BK, WM, WN, false, false>, &launch_grp<BM, BN, BK, WM, WN, false, true>, \
+     &launch_grp<BM, BN, BK, WM, WN, true, false>, &launch_grp<BM, BN, BK, WM, WN, true, true>}   \
   }
 
 const TileInfo kTiles[] = {
@@ -245,6 +271,20 @@ int gemm_split_pick(int64_t M, int64_t N, int64_t K, int) {
   int64_t split = (512 + tiles - 1) / tiles;
   split = std::min<int64_t>(split, std::max<int64_t>(1, K / 256));
   return int(std::max<int64_t>(1, std::min<int64_t>(split, 128)));
+}
+
+void gemm_f64_grouped_launch(const GemmGroupEntry *dev_entries, const int64_t *dev_off, int n,
+                             int64_t blocks, bool akc, bool bkc, int tile_id, hipStream_t s) {
+  if (blocks <= 0) return;
+  CC_REQUIRE(tile_id >= 0 && tile_id < kNumTiles, -7, "grouped gemm: tile");
+  CC_REQUIRE(blocks < (int64_t(1) << 31), -1, "grouped gemm: too many tiles");
+  kTiles[tile_id].launch_grouped[(akc ? 2 : 0) + (bkc ? 1 : 0)](dev_entries, dev_off, n, blocks, s);
+  CC_HIP_CHECK(hipGetLastError());
+}
+
+void gemm_f64_tile_shape(int tile_id, int *bm, int *bn) {
+  *bm = kTiles[tile_id].BM;
+  *bn = kTiles[tile_id].BN;
 }
 
 void gemm_f64(const GemmDesc &d, hipStream_t s, int tile_id) {

@@ -310,8 +310,4 @@ void gemm_lowp(const GemmDesc &d, int prec, hipStream_t s, int tile_id) {
   if (d.split > 1) splitk_reduce(false, d.ws, d.split, d.M, d.N, d.C, d.ldc, d.alpha, d.beta, s);
 }
 
-void gemm_c128(const GemmDesc &, hipStream_t) {
-  throw CCError(-6, "complex contractions are not built yet");
-}
-
 }  // namespace ccmi

@@ -1,4 +1,11 @@
 // Launchers of the device kernels (declarations shared by the host code).
+//
+// Every data-movement / elementwise kernel is described by an "entry" struct
+// that holds one system's arguments and device pointers.  A single launch
+// takes one entry by value; a grouped launch takes a device array of entries
+// (one per system of a batch) and an offset table: system b owns workgroups
+// [off[b], off[b+1]).  Both launch forms run the same device body, so a
+// batched result equals the single-system one bit for bit.
 #pragma once
 
 #include "common.hpp"
@@ -7,12 +14,64 @@
 
 namespace ccmi {
 
+struct PermArgs {
+  int rank;
+  int64_t dims[kMaxRank];
+  int64_t istr[kMaxRank];
+  int64_t ostr[kMaxRank];
+  double alpha, beta;
+  int conj;
+  int d_o, d_i;  // tiled dims: output unit-stride dim and input unit-stride dim
+  int64_t rest_dims[kMaxRank], rest_istr[kMaxRank], rest_ostr[kMaxRank];
+  int nrest;
+  int64_t n_rest_total, tiles_o, tiles_i;
+  int64_t total;
+};
+
+struct PermEntry {
+  PermArgs p;
+  const void *in;
+  void *out;
+  int tiled;
+  int64_t units;
+};
+
 struct OuterArgs {
   int rank;
   int64_t dims[4];
   int64_t sa[4], sb[4];  // strides of A and B for each C dimension (0 = not indexed)
   double alpha;
   int conj_a, conj_b;
+};
+
+struct OuterEntry {
+  OuterArgs a;
+  const void *A, *B;
+  void *C;
+  int64_t total, units;
+};
+
+struct FillEntry {
+  void *p;
+  int64_t n, units;
+};
+
+struct SplitkEntry {
+  const void *ws;
+  int split;
+  int64_t M, N;
+  void *C;
+  int64_t ldc;
+  double alpha, beta;
+  int64_t units;
+};
+
+struct TauEntry {
+  int o, v;
+  const void *t1, *t2, *oovv, *fov;  // t1 == nullptr: CCD (tau = t2, not written)
+  void *tau, *taut;
+  double *partials;  // 2 per unit (re, im)
+  int64_t units;
 };
 
 struct R2Args {
@@ -23,22 +82,73 @@ struct R2Args {
   const void *Fo, *Fv;              // dressed [o][o] and [v][v] one-body intermediates
 };
 
+struct AsmEntry {
+  R2Args a;
+  const void *XP, *Xij, *Xab, *Xr;
+  void *R, *t2;  // either may be nullptr
+  double *partials;
+  int64_t units;
+};
+
+struct R1Entry {
+  int o, v;
+  const void *R1;
+  void *t1;  // nullptr: no update
+  const double *d_oo, *d_vv;
+  double shift;
+  int dressed;
+  const void *Fo, *Fv;
+  double *partial;
+};
+
+struct FinEntry {
+  const double *epart;
+  int ne;
+  const double *n2part;
+  int nn;
+  const double *n1part;  // may be nullptr
+  double *scalars;       // [0] = ||R||, [1] = Re E, [2] = Im E
+};
+
+// ---- entry construction (host) ---------------------------------------------
+PermEntry make_perm_entry(const PermDesc &d, const void *in, void *out);
+OuterEntry make_outer_entry(const OuterArgs &a, const void *A, const void *B, void *C);
+FillEntry make_fill_entry(void *p, int64_t n);
+SplitkEntry make_splitk_entry(const void *ws, int split, int64_t M, int64_t N, void *C, int64_t ldc,
+                              double alpha, double beta);
+TauEntry make_tau_entry(int o, int v, const void *t1, const void *t2, const void *oovv, const void *fov,
+                        void *tau, void *taut, double *partials);
+AsmEntry make_asm_entry(const R2Args &a, const void *XP, const void *Xij, const void *Xab, const void *Xr,
+                        void *R, void *t2, double *partials);
+int64_t tau_units(int o, int v);
+int64_t asm_units(int o, int v);
+
+// ---- single launches ---------------------------------------------------------
+void launch_perm(const PermEntry &e, bool cplx, hipStream_t s);
+void launch_outer(const OuterEntry &e, bool cplx, hipStream_t s);
+void launch_fill(const FillEntry &e, bool cplx, hipStream_t s);
+void launch_splitk(const SplitkEntry &e, bool cplx, hipStream_t s);
+void launch_tau(const TauEntry &e, bool cplx, hipStream_t s);
+void launch_asm(const AsmEntry &e, bool cplx, hipStream_t s);
+void launch_r1(const R1Entry &e, bool cplx, hipStream_t s);
+void launch_fin(const FinEntry &e, hipStream_t s);
+
+// ---- grouped launches (entries and offsets in device memory) -----------------
+void launch_perm_grouped(const PermEntry *e, const int64_t *off, int n, int64_t blocks, bool tiled, bool cplx,
+                         hipStream_t s);
+void launch_outer_grouped(const OuterEntry *e, const int64_t *off, int n, int64_t blocks, bool cplx, hipStream_t s);
+void launch_fill_grouped(const FillEntry *e, const int64_t *off, int n, int64_t blocks, bool cplx, hipStream_t s);
+void launch_splitk_grouped(const SplitkEntry *e, const int64_t *off, int n, int64_t blocks, bool cplx,
+                           hipStream_t s);
+void launch_tau_grouped(const TauEntry *e, const int64_t *off, int n, int64_t blocks, bool cplx, hipStream_t s);
+void launch_asm_grouped(const AsmEntry *e, const int64_t *off, int n, int64_t blocks, bool cplx, hipStream_t s);
+void launch_r1_grouped(const R1Entry *e, int n, bool cplx, hipStream_t s);
+void launch_fin_grouped(const FinEntry *e, int n, hipStream_t s);
+
+// ---- conveniences used by the single-system planner --------------------------
 void outer_acc(const OuterArgs &a, bool cplx, const void *A, const void *B, void *C, hipStream_t s);
 void fill_zero(void *p, int64_t n_elems, bool cplx, hipStream_t s);
-
-int tau_energy_blocks(int o, int v);
-void tau_energy(bool cplx, int o, int v, const void *t1, const void *t2, const void *oovv,
-                const void *fov, void *tau, void *taut, double *partials, hipStream_t s);
-
-int64_t r2_assemble_blocks(int o, int v);
-void r2_assemble(bool cplx, const R2Args &a, const void *XP, const void *Xij, const void *Xab,
-                 const void *Xr, void *R, void *t2, double *partials, hipStream_t s);
-void r1_update(bool cplx, int o, int v, const void *R1, void *t1, const double *d_oo,
-               const double *d_vv, double shift, int dressed, const void *Fo, const void *Fv,
-               double *partial, hipStream_t s);
-void fock_diag(bool cplx, int o, int v, const void *foo, const void *fvv, double *d_oo,
-               double *d_vv, hipStream_t s);
-void finalize_scalars(const double *epart, int ne, const double *n2part, int nn,
-                      const double *n1part, double *scalars, hipStream_t s);
+void fock_diag(bool cplx, int o, int v, const void *foo, const void *fvv, double *d_oo, double *d_vv,
+               hipStream_t s);
 
 }  // namespace ccmi

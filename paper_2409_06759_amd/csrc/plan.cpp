@@ -347,7 +347,7 @@ struct Planner {
     g.flops = (p->cplx ? 8.0 : 2.0) * double(M) * double(N) * double(Kd);
     g.tag = op.tag;
     g.gemm.ladder = std::string(op.tag) == "ladder" ? 1 : 0;
-    g.gemm.split = p->cplx ? 1 : gemm_split_pick(M, N, Kd, -1);
+    g.gemm.split = gemm_split_pick(M, N, Kd, -1);
     if (g.gemm.split > 1) {
       splitws_elems = std::max<int64_t>(splitws_elems, int64_t(g.gemm.split) * M * N);
       g.b2 = splitws;
@@ -485,16 +485,46 @@ struct Planner {
 };
 
 void run_gemm(cc_plan *p, GemmDesc &d, const Step &st, hipStream_t s) {
-  if (p->cplx) gemm_c128(d, s);
+  if (p->cplx) gemm_c128(d, s, st.tile_z);
   else if (p->cur_prec == PREC_F64) gemm_f64(d, s, st.tile);
   else gemm_lowp(d, p->cur_prec, s, st.tile_lp[p->cur_prec]);
 }
+
+}  // namespace
 
 void *ptr_of(cc_plan *p, int s) {
   const Slot &sl = p->slots[s];
   if (sl.external) return sl.name == "t1" ? p->t1 : p->t2;
   return sl.ptr;
 }
+
+TauEntry tau_entry(cc_plan *p) {
+  const bool ccsd = p->method == CC_CCSD;
+  return make_tau_entry(p->o, p->v, ccsd ? p->t1 : nullptr, p->t2, p->slots[p->index["oovv"]].ptr,
+                        p->slots[p->index["fov"]].ptr, ccsd ? p->slots[p->index["tau"]].ptr : nullptr,
+                        ccsd ? p->slots[p->index["taut"]].ptr : nullptr, p->epart);
+}
+
+AsmEntry asm_entry(cc_plan *p) {
+  R2Args a{p->o, p->v, p->d_oo, p->d_vv, p->shift, p->dressed, p->slots[p->index["GG"]].ptr,
+           p->slots[p->index["FF"]].ptr};
+  return make_asm_entry(a, p->slots[p->index["XP"]].ptr, p->slots[p->index["Xij"]].ptr,
+                        p->slots[p->index["Xab"]].ptr, p->slots[p->index["Xr"]].ptr, p->r2_out,
+                        p->update ? p->t2 : nullptr, p->n2part);
+}
+
+R1Entry r1_entry(cc_plan *p) {
+  return R1Entry{p->o, p->v, p->slots[p->index["R1"]].ptr, p->update ? p->t1 : nullptr, p->d_oo, p->d_vv,
+                 p->shift, p->dressed, p->slots[p->index["Fmi"]].ptr, p->slots[p->index["Fae"]].ptr,
+                 p->n1part};
+}
+
+FinEntry fin_entry(cc_plan *p) {
+  return FinEntry{p->epart, p->n_epart, p->n2part, p->n_n2part,
+                  p->method == CC_CCSD ? p->n1part : nullptr, p->scalars};
+}
+
+namespace {
 
 void exec(cc_plan *p, Step &st, hipStream_t s) {
   const bool cplx = p->cplx;
@@ -518,33 +548,22 @@ void exec(cc_plan *p, Step &st, hipStream_t s) {
     case Step::FILL:
       fill_zero(ptr_of(p, st.c), st.nelem, cplx, s);
       break;
-    case Step::TAU_E: {
-      const bool ccsd = p->method == CC_CCSD;
-      tau_energy(cplx, p->o, p->v, ccsd ? p->t1 : nullptr, p->t2, p->slots[p->index["oovv"]].ptr,
-                 p->slots[p->index["fov"]].ptr, ccsd ? p->slots[p->index["tau"]].ptr : nullptr,
-                 ccsd ? p->slots[p->index["taut"]].ptr : nullptr, p->epart, s);
+    case Step::TAU_E:
+      launch_tau(tau_entry(p), cplx, s);
       break;
-    }
-    case Step::ASSEMBLE: {
-      R2Args a{p->o, p->v, p->d_oo, p->d_vv, p->shift, p->dressed, p->slots[p->index["GG"]].ptr,
-               p->slots[p->index["FF"]].ptr};
-      r2_assemble(cplx, a, p->slots[p->index["XP"]].ptr, p->slots[p->index["Xij"]].ptr,
-                  p->slots[p->index["Xab"]].ptr, p->slots[p->index["Xr"]].ptr, p->r2_out,
-                  p->update ? p->t2 : nullptr, p->n2part, s);
+    case Step::ASSEMBLE:
+      launch_asm(asm_entry(p), cplx, s);
       break;
-    }
     case Step::R1UPD: {
       void *R1 = p->slots[p->index["R1"]].ptr;
       if (p->r1_out)
         CC_HIP_CHECK(hipMemcpyAsync(p->r1_out, R1, size_t(p->o) * p->v * p->esize,
                                     hipMemcpyDeviceToDevice, s));
-      r1_update(cplx, p->o, p->v, R1, p->update ? p->t1 : nullptr, p->d_oo, p->d_vv, p->shift,
-                p->dressed, p->slots[p->index["Fmi"]].ptr, p->slots[p->index["Fae"]].ptr, p->n1part, s);
+      launch_r1(r1_entry(p), cplx, s);
       break;
     }
     case Step::FINALIZE:
-      finalize_scalars(p->epart, p->n_epart, p->n2part, p->n_n2part,
-                       p->method == CC_CCSD ? p->n1part : nullptr, p->scalars, s);
+      launch_fin(fin_entry(p), s);
       break;
   }
 }
@@ -565,8 +584,8 @@ void plan_build(cc_plan *p, const cc_system *sys) {
     s.ptr = dev_alloc(bytes);
     p->workspace += bytes;
   }
-  p->n_epart = tau_energy_blocks(p->o, p->v);
-  p->n_n2part = int(r2_assemble_blocks(p->o, p->v));
+  p->n_epart = int(tau_units(p->o, p->v));
+  p->n_n2part = int(asm_units(p->o, p->v));
   p->d_oo = static_cast<double *>(dev_alloc(sizeof(double) * p->o));
   p->d_vv = static_cast<double *>(dev_alloc(sizeof(double) * p->v));
   p->epart = static_cast<double *>(dev_alloc(sizeof(double) * 2 * p->n_epart));
@@ -625,10 +644,10 @@ void plan_run(cc_plan *p) {
 // iteration (on the plan's own buffers) and keep the fastest.  Results are
 // cached per (M, N, K, layouts) for the life of the process.
 void plan_autotune(cc_plan *p, int reps) {
-  if (p->cplx) return;
   static std::map<std::string, int> cache;
-  const int prec = p->cur_prec;
-  const int ntiles = prec == PREC_F64 ? gemm_f64_num_tiles() : gemm_lowp_num_tiles();
+  const int prec = p->cplx ? 9 : p->cur_prec;  // 9: complex128 tiles
+  const int ntiles = p->cplx ? gemm_c128_num_tiles()
+                             : (prec == PREC_F64 ? gemm_f64_num_tiles() : gemm_lowp_num_tiles());
   hipStream_t s = p->ctx->stream;
   hipEvent_t e0, e1;
   CC_HIP_CHECK(hipEventCreate(&e0));
@@ -640,7 +659,7 @@ void plan_autotune(cc_plan *p, int reps) {
       const std::string key = std::to_string(prec) + ":" + std::to_string(d.M) + "x" +
                               std::to_string(d.N) + "x" + std::to_string(d.K) + (akc ? "k" : "m") +
                               (bkc ? "k" : "n");
-      int &slot = prec == PREC_F64 ? st->tile : st->tile_lp[prec];
+      int &slot = p->cplx ? st->tile_z : (prec == PREC_F64 ? st->tile : st->tile_lp[prec]);
       auto it = cache.find(key);
       if (it != cache.end()) {
         slot = it->second;
@@ -653,7 +672,8 @@ void plan_autotune(cc_plan *p, int reps) {
       int best = slot;
       float best_ms = 1e30f;
       auto launch = [&](int t) {
-        if (prec == PREC_F64) gemm_f64(d, s, t);
+        if (p->cplx) gemm_c128(d, s, t);
+        else if (prec == PREC_F64) gemm_f64(d, s, t);
         else gemm_lowp(d, prec, s, t);
       };
       for (int t = 0; t < ntiles; ++t) {
@@ -693,8 +713,9 @@ std::string plan_profile_table(const cc_plan *p) {
     for (auto &c : tag)
       if (c == ' ') c = '_';
     if (st.kind == Step::GEMM)
-      tag += "@" + std::string(p->cur_prec == PREC_F64 ? gemm_f64_tile_name(st.tile)
-                                                        : gemm_lowp_tile_name(p->cur_prec, st.tile_lp[p->cur_prec]));
+      tag += "@" + std::string(p->cplx ? gemm_c128_tile_name(st.tile_z)
+                               : p->cur_prec == PREC_F64 ? gemm_f64_tile_name(st.tile)
+                                                         : gemm_lowp_tile_name(p->cur_prec, st.tile_lp[p->cur_prec]));
     os << i << " " << kinds[st.kind] << " " << tag << " " << p->step_calls[i]
        << " " << p->step_ms[i] << " " << (p->step_calls[i] ? p->step_ms[i] / p->step_calls[i] : 0.0)
        << " " << st.flops << "\n";
@@ -706,7 +727,7 @@ void plan_run_energy(cc_plan *p) {
   hipStream_t s = p->ctx->stream;
   for (Step &st : p->iter)
     if (st.kind == Step::TAU_E) exec(p, st, s);
-  finalize_scalars(p->epart, p->n_epart, p->n2part, 0, nullptr, p->scalars, s);
+  launch_fin(FinEntry{p->epart, p->n_epart, p->n2part, 0, nullptr, p->scalars}, s);
 }
 
 std::string plan_describe(const cc_plan *p) {

@@ -50,6 +50,7 @@ struct Step {
   OuterArgs outer{};
   int tile = -1;        // FP64 tile
   int tile_lp[3] = {-1, -1, -1};  // per reduced precision (index = cc_prec)
+  int tile_z = -1;      // complex128 tile
   int64_t nelem = 0;
   double flops = 0.0;
   std::string tag;
@@ -104,4 +105,11 @@ void plan_run_energy(cc_plan *p);    // tau + energy only
 std::string plan_describe(const cc_plan *p);
 void plan_autotune(cc_plan *p, int reps);
 std::string plan_profile_table(const cc_plan *p);
+TauEntry tau_entry(cc_plan *p);
+AsmEntry asm_entry(cc_plan *p);
+R1Entry r1_entry(cc_plan *p);
+FinEntry fin_entry(cc_plan *p);
+void *ptr_of(cc_plan *p, int slot);
+cc_plan *make_plan_checked(cc_ctx *ctx, const cc_system *sys, int method, int prec);
+void check_amps(const cc_amps *t, int method);
 }  // namespace ccmi

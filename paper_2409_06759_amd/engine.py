@@ -238,3 +238,69 @@ def permute(ctx, x, perm, out=None, alpha=1.0, beta=0.0):
     ctx.enter()
     ctx.check(ctx.lib.cc_permute(ctx.h, scalar, x.dim(), dims, pr, alpha, _ptr(x), beta, _ptr(out)))
     return out
+
+
+class Batch:
+    """Many independent systems iterated together (one grouped launch per
+    step of the contraction list, the iteration replayed as one graph)."""
+
+    def __init__(self, ctx: Context, dsystems, method: int = CCSD, prec: int = F64, amps=None):
+        self.ctx, self.dsystems, self.method, self.n = ctx, list(dsystems), method, len(dsystems)
+        self.amps = amps if amps is not None else [zeros_amps(d, method) for d in self.dsystems]
+        arr_s = (L.CCSystemStruct * self.n)(*[d.struct for d in self.dsystems])
+        arr_a = (L.CCAmps * self.n)(*[_amps(t1, t2) for t1, t2 in self.amps])
+        self._keep = (arr_s, arr_a)
+        self.h = C.c_void_p()
+        ctx.enter()
+        ctx.check(ctx.lib.cc_batch_create(ctx.h, self.n, arr_s, method, prec, arr_a, C.byref(self.h)))
+
+    def step(self, shift: float = 0.0, dressed: bool = False):
+        self.ctx.enter()
+        self.ctx.check(self.ctx.lib.cc_batch_step(self.h, shift, 1 if dressed else 0))
+
+    def scalars(self):
+        rn, er, ei = (C.c_double * self.n)(), (C.c_double * self.n)(), (C.c_double * self.n)()
+        self.ctx.check(self.ctx.lib.cc_batch_scalars(self.h, rn, er, ei))
+        return list(rn), list(er), list(ei)
+
+    def autotune(self, reps: int = 2):
+        self.ctx.enter()
+        self.ctx.check(self.ctx.lib.cc_batch_autotune(self.h, reps))
+
+    def iterate(self, tol=1e-8, max_iter=200, level_shift=0.0, dressed=False, prec=F64, use_graph=True):
+        opts = L.CCIterOpts(tol, max_iter, prec, level_shift, 0.0, 1 if use_graph else 0, 1, 0,
+                            1 if dressed else 0, 0)
+        reps = (L.CCIterReport * self.n)()
+        nconv = C.c_int32()
+        self.ctx.enter()
+        rc = self.ctx.lib.cc_batch_iterate(self.h, C.byref(opts), reps, C.byref(nconv))
+        self.ctx.check(rc, ok=(L.CC_OK, L.CC_ENOTCONV, L.CC_EDIVERGED))
+        return {"status": rc, "n_converged": nconv.value,
+                "systems": [{"iters": r.iters, "converged": bool(r.converged), "rnorm": r.rnorm,
+                             "energy": r.e_re, "seconds": r.seconds} for r in reps]}
+
+    def profile(self, enable: bool = True):
+        self.ctx.check(self.ctx.lib.cc_batch_profile(self.h, 1 if enable else 0))
+
+    def profile_table(self):
+        rows = []
+        for line in self.ctx.lib.cc_batch_profile_table(self.h).decode().splitlines():
+            if line.startswith("#") or not line.strip():
+                continue
+            i, kind, tag, calls, tot, avg, fl = line.split()
+            rows.append((int(i), kind, tag, int(calls), float(tot), float(avg), float(fl)))
+        return rows
+
+    def flops(self) -> float:
+        return self.ctx.lib.cc_batch_flops(self.h)
+
+    def close(self):
+        if self.h:
+            self.ctx.lib.cc_batch_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

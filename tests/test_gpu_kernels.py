@@ -99,3 +99,23 @@ def test_gemm_lowp_error_bound(ctx, prec, shape, akc, bkc):
     bound = 2 * eps * abs(alpha) * (np.abs(A) @ np.abs(B).T) + 4 * np.finfo(float).eps * np.abs(beta * C0)
     err = np.abs(Cd.cpu().numpy() - ref)
     assert np.all(err <= bound), (err / bound).max()
+
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (17, 33, 65), (64, 100, 300), (130, 70, 33)])
+@pytest.mark.parametrize("akc,bkc", [(True, True), (False, False), (False, True)])
+def test_gemm_c128_matches_numpy(ctx, shape, akc, bkc):
+    from paper_2409_06759_amd import engine as E
+    M, N, K = shape
+    rng = np.random.default_rng(M * 5 + N + K)
+    A = rng.normal(size=(M, K)) + 1j * rng.normal(size=(M, K))
+    B = rng.normal(size=(N, K)) + 1j * rng.normal(size=(N, K))
+    C0 = rng.normal(size=(M, N)) + 1j * rng.normal(size=(M, N))
+    alpha, beta = 0.5, -1.25
+    ref = alpha * (A @ B.T) + beta * C0
+    Ad = torch.from_numpy(A if akc else np.ascontiguousarray(A.T)).cuda()
+    Bd = torch.from_numpy(B if bkc else np.ascontiguousarray(B.T)).cuda()
+    Cd = torch.from_numpy(C0).cuda()
+    E.gemm(ctx, Ad, Bd, Cd, alpha, beta, a_kcontig=akc, b_kcontig=bkc)
+    bound = 4 * (K + 2) * np.finfo(float).eps * (abs(alpha) * (np.abs(A) @ np.abs(B).T) + abs(beta) * np.abs(C0))
+    assert np.all(np.abs(Cd.cpu().numpy() - ref) <= bound)

@@ -69,15 +69,69 @@ def test_residual_matches_oracle(E, ctx, method, ov):
     assert abs(e - energy(F, V, t1, t2)) < 1e-13
 
 
-def test_complex_not_yet_rejected_cleanly(E, ctx):
+def test_complex_reduced_precision_rejected(E, ctx):
+    from paper_2409_06759_amd import _lib as L
     s = make_system(3, 5, 9, is_complex=True)
     d = E.DeviceSystem(s)
     t1 = torch.zeros((3, 5), dtype=torch.complex128, device="cuda")
     t2 = torch.zeros((3, 3, 5, 5), dtype=torch.complex128, device="cuda")
-    try:
-        E.residual(ctx, d, E.CCSD, t1, t2)
-    except Exception as exc:  # complex GEMM may be unavailable: must be a clean error
-        assert "complex" in str(exc) or "-6" in str(exc)
+    with pytest.raises(L.CCError) as ei:
+        E.residual(ctx, d, E.CCSD, t1, t2, prec=E.F32)
+    assert ei.value.status == L.CC_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("method", ["ccd", "ccsd"])
+@pytest.mark.parametrize("ov", [(3, 5), (7, 23), (4, 40)])
+def test_complex_residual_matches_oracle(E, ctx, method, ov):
+    """Hermitian complex integrals: driver <ab||ij> = conj <ij||ab>, every
+    non-stored block a conjugated view; parity 1e-12 as in the real case."""
+    o, v = ov
+    s = make_system(o, v, 3000 + o * v, is_complex=True)
+    t1, t2 = _amps(o, v, 7 * o + v, cplx=True)
+    if method == "ccd":
+        t1 = None
+    F, V = Fock.from_system(s), Integrals.from_system(s)
+    r1_ref, r2_ref = residual(F, V, t1, t2)
+    d = E.DeviceSystem(s)
+    T1 = torch.from_numpy(t1).cuda() if t1 is not None else None
+    r1, r2, rn = E.residual(ctx, d, E.METHODS[method], T1, torch.from_numpy(t2).cuda())
+    r2 = r2.cpu().numpy()
+    assert np.abs(r2 - r2_ref).max() < 1e-12
+    if t1 is not None:
+        assert np.abs(r1.cpu().numpy() - r1_ref).max() < 1e-12
+    assert np.array_equal(r2, -r2.transpose(1, 0, 2, 3))
+    e = E.energy(ctx, d, E.METHODS[method], T1, torch.from_numpy(t2).cuda())
+    e_ref = energy(F, V, t1, t2)
+    assert abs(e.real - e_ref.real) < 1e-13 and abs(e.imag - e_ref.imag) < 1e-13
+
+
+def test_complex_with_zero_imaginary_equals_real(E, ctx):
+    o, v = 5, 17
+    s = make_system(o, v, 4)
+    sc = make_system(o, v, 4, is_complex=True)
+    for b in ("oooo", "ooov", "oovv", "ovvo", "ovvv", "vvvv"):
+        sc._blocks[b] = s.block(b).astype(np.complex128)
+    t1, t2 = _amps(o, v, 11)
+    d, dc = E.DeviceSystem(s), E.DeviceSystem(sc)
+    r1, r2, rn = E.residual(ctx, d, E.CCSD, torch.from_numpy(t1).cuda(), torch.from_numpy(t2).cuda())
+    z1, z2, zn = E.residual(ctx, dc, E.CCSD, torch.from_numpy(t1.astype(complex)).cuda(),
+                            torch.from_numpy(t2.astype(complex)).cuda())
+    assert torch.all(z2.imag == 0) and torch.all(z1.imag == 0)
+    assert np.abs(z2.real.cpu().numpy() - r2.cpu().numpy()).max() < 1e-14
+    assert abs(zn - rn) < 1e-12
+
+
+def test_complex_dressed_trajectory(E, ctx):
+    o, v = 6, 26
+    s = make_system(o, v, 79, is_complex=True)
+    F, V = Fock.from_system(s), Integrals.from_system(s)
+    ref = jacobi(F, V, "ccsd", tol=0.0, max_iter=6, dressed=True)
+    d = E.DeviceSystem(s)
+    t1, t2 = E.zeros_amps(d, E.CCSD)
+    out = E.iterate(ctx, d, E.CCSD, t1, t2, tol=1e-30, max_iter=6, dressed=True)
+    assert np.allclose(out["hist_e"], np.real(ref["hist_e"]), rtol=0, atol=1e-12)
+    assert abs(out["energy"] - ref["hist_e"][-1]) < 1e-12  # complex: Re and Im
+    assert np.abs(t2.cpu().numpy() - ref["t2"]).max() < 1e-12
 
 
 def test_ccd_c1_trajectory(E, ctx):

@@ -200,6 +200,52 @@ const char *cc_batch_profile_table(const cc_batch *batch);
 /* Algorithmic flops of one batch iteration (sum over systems). */
 double cc_batch_flops(const cc_batch *batch);
 
+/* ---- learned initial amplitudes -------------------------------------------
+ * A 3 -> 128 -> 128 -> 1 ReLU network maps the MP2 features of each unique
+ * doubles amplitude (i<j, a<b) -- the integral <ij||ab>, the denominator
+ * D_ij^ab and the pair energy e_ij = sum_{a<b} <ij||ab>^2 / D_ij^ab -- to
+ * t_ij^ab.  With z the standardised features (z0 = x/sx, z1 = (D-mD)/sD,
+ * z2 = (e-me)/se) the output is t = st * (g(z) - g(-z0, z1, z2)) / 2, odd in
+ * <ij||ab>, so the guess is antisymmetric.  Real systems only.
+ * Parameters: cc_mlp_num_params() doubles in device memory, in the order
+ * W1[128][3], b1[128], W2[128][128], b2[128], W3[1][128], b3[1].
+ * prec: CC_PREC_F64 or CC_PREC_F32 (the dense layers on FP32 MFMA). */
+typedef struct {
+  double sx, mD, sD, me, se, st;
+} cc_mlp_stats;
+int64_t cc_mlp_num_params(void);
+/* number of unique amplitudes, C(o,2) * C(v,2) */
+int64_t cc_mlp_num_samples(int o, int v);
+/* Features of every unique amplitude in (ij, ab) order into z_out (device,
+ * 3 per sample): raw (x, D, e) when stats is NULL, standardised otherwise. */
+int cc_mlp_features(cc_ctx *ctx, const cc_system *sys, const cc_mlp_stats *stats, double *z_out);
+/* y_out[u] = t2 at unique amplitude u, divided by scale (device). */
+int cc_mlp_targets(cc_ctx *ctx, int o, int v, const double *t2, double scale, double *y_out);
+/* Column sums over n raw feature rows: out7 = (sum x^2, sum D, sum D^2,
+ * sum e, sum e^2, sum y^2 (0 if y is NULL), n) (host). */
+int cc_mlp_moments(cc_ctx *ctx, const double *raw, const double *y, int64_t n, double *out7);
+/* z_out = standardised raw rows; y_out = y / st when y is non-NULL (device). */
+int cc_mlp_standardise(cc_ctx *ctx, const double *raw, const double *y, int64_t n, const cc_mlp_stats *stats,
+                       double *z_out, double *y_out);
+/* f_out[u] = (g(z_u) - g(z~_u)) / 2 for n standardised rows (device). */
+int cc_mlp_forward(cc_ctx *ctx, int prec, const double *params, const double *z, int64_t n, double *f_out);
+/* Mean squared error of f against y over n rows and its gradient
+ * (device, cc_mlp_num_params() values); loss to host. */
+int cc_mlp_loss_grad(cc_ctx *ctx, int prec, const double *params, const double *z, const double *y, int64_t n,
+                     double *loss, double *grad_out);
+/* Adam training (beta1 0.9, beta2 0.999, eps 1e-8) on minibatches of
+ * `batch` consecutive rows of the order permutation (device int64 array of
+ * n, or NULL for 0..n-1), for `epochs` passes.  params, adam_m, adam_v are
+ * device arrays updated in place; *adam_t counts steps across calls.
+ * loss_hist (host, may be NULL) receives the mean minibatch loss per epoch. */
+int cc_mlp_train(cc_ctx *ctx, int prec, double *params, double *adam_m, double *adam_v, const double *z,
+                 const double *y, int64_t n, const int64_t *order, int64_t batch, int32_t epochs, double lr,
+                 int64_t *adam_t, double *loss_hist, int32_t hist_cap);
+/* Initial amplitudes from the network: t_out->t2 (all o*o*v*v elements,
+ * antisymmetric, zero diagonals) and t_out->t1 = 0 when non-NULL. */
+int cc_guess_mlp(cc_ctx *ctx, const cc_system *sys, int prec, const double *params, const cc_mlp_stats *stats,
+                 cc_amps *t_out);
+
 /* ---- introspection ------------------------------------------------------ */
 /* Text listing of the plan's setup and per-iteration steps (permutes, GEMMs
  * with shapes and tiles, elementwise kernels).  Valid until the next call on

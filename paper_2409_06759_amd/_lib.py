@@ -27,7 +27,9 @@ EXPORTS = (
     "cc_permute", "cc_plan_describe", "cc_plan_describe_dry", "cc_plan_flops", "cc_plan_profile",
     "cc_plan_profile_table", "cc_plan_autotune", "cc_plan_set_precision", "cc_batch_create",
     "cc_batch_destroy", "cc_batch_step", "cc_batch_scalars", "cc_batch_autotune", "cc_batch_iterate",
-    "cc_batch_profile", "cc_batch_profile_table", "cc_batch_flops",
+    "cc_batch_profile", "cc_batch_profile_table", "cc_batch_flops", "cc_mlp_num_params",
+    "cc_mlp_num_samples", "cc_mlp_features", "cc_mlp_targets", "cc_mlp_moments", "cc_mlp_forward",
+    "cc_mlp_loss_grad", "cc_mlp_train", "cc_guess_mlp", "cc_mlp_standardise",
 )
 
 
@@ -53,6 +55,10 @@ class CCIterReport(C.Structure):
                 ("e_re", C.c_double), ("e_im", C.c_double), ("seconds", C.c_double),
                 ("setup_seconds", C.c_double), ("lowp_iters", C.c_int32), ("hist_rnorm", C.POINTER(C.c_double)),
                 ("hist_e", C.POINTER(C.c_double)), ("hist_cap", C.c_int32)]
+
+
+class CCMlpStats(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("sx", "mD", "sD", "me", "se", "st")]
 
 
 class CCError(RuntimeError):
@@ -105,6 +111,16 @@ def load() -> C.CDLL:
         "cc_batch_profile": (C.c_int, [vp, C.c_int]),
         "cc_batch_profile_table": (C.c_char_p, [vp]),
         "cc_batch_flops": (dbl, [vp]),
+        "cc_mlp_num_params": (i64, []),
+        "cc_mlp_num_samples": (i64, [C.c_int, C.c_int]),
+        "cc_mlp_features": (C.c_int, [vp, P(CCSystemStruct), P(CCMlpStats), vp]),
+        "cc_mlp_targets": (C.c_int, [vp, C.c_int, C.c_int, vp, dbl, vp]),
+        "cc_mlp_moments": (C.c_int, [vp, vp, vp, i64, P(dbl)]),
+        "cc_mlp_forward": (C.c_int, [vp, C.c_int, vp, vp, i64, vp]),
+        "cc_mlp_standardise": (C.c_int, [vp, vp, vp, i64, P(CCMlpStats), vp, vp]),
+        "cc_mlp_loss_grad": (C.c_int, [vp, C.c_int, vp, vp, vp, i64, P(dbl), vp]),
+        "cc_mlp_train": (C.c_int, [vp, C.c_int, vp, vp, vp, vp, vp, i64, vp, i64, i32, dbl, P(i64), P(dbl), i32]),
+        "cc_guess_mlp": (C.c_int, [vp, P(CCSystemStruct), C.c_int, vp, P(CCMlpStats), P(CCAmps)]),
         "cc_plan_profile_table": (C.c_char_p, [vp]),
     }
     for name, (res, args) in sig.items():

@@ -304,3 +304,102 @@ class Batch:
 
     def __exit__(self, *a):
         self.close()
+
+
+class MLP:
+    """Amplitude-guess network (parameters on the device, FP64 storage)."""
+
+    def __init__(self, ctx: Context, params: torch.Tensor, stats: dict, prec: int = F32):
+        self.ctx, self.params, self.stats, self.prec = ctx, params.contiguous(), dict(stats), prec
+        n = ctx.lib.cc_mlp_num_params()
+        assert self.params.numel() == n and self.params.dtype == torch.float64
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.t = C.c_int64(0)
+
+    @staticmethod
+    def init_params(seed: int = 0, device="cuda") -> torch.Tensor:
+        """He-normal weights, zero biases (seeded; drawn on the host)."""
+        rng = np.random.default_rng(seed)
+        h = 128
+        parts = [rng.normal(size=(h, 3)) * np.sqrt(2 / 3), np.zeros(h), rng.normal(size=(h, h)) * np.sqrt(2 / h),
+                 np.zeros(h), rng.normal(size=(1, h)) * np.sqrt(2 / h), np.zeros(1)]
+        return torch.from_numpy(np.concatenate([p.ravel() for p in parts])).to(device)
+
+    def _st(self):
+        return L.CCMlpStats(*[self.stats[k] for k in ("sx", "mD", "sD", "me", "se", "st")])
+
+    @staticmethod
+    def raw_features(ctx: Context, dsys: DeviceSystem) -> torch.Tensor:
+        n = ctx.lib.cc_mlp_num_samples(dsys.o, dsys.v)
+        z = torch.empty((n, 3), dtype=torch.float64, device=dsys.t["oovv"].device)
+        ctx.enter()
+        ctx.check(ctx.lib.cc_mlp_features(ctx.h, C.byref(dsys.struct), None, _ptr(z)))
+        return z
+
+    @staticmethod
+    def targets(ctx: Context, o: int, v: int, t2: torch.Tensor, scale: float = 1.0) -> torch.Tensor:
+        n = ctx.lib.cc_mlp_num_samples(o, v)
+        y = torch.empty(n, dtype=torch.float64, device=t2.device)
+        ctx.enter()
+        ctx.check(ctx.lib.cc_mlp_targets(ctx.h, o, v, _ptr(t2), scale, _ptr(y)))
+        return y
+
+    @staticmethod
+    def fit_stats(ctx: Context, raw: torch.Tensor, y: torch.Tensor) -> dict:
+        out = (C.c_double * 7)()
+        ctx.enter()
+        ctx.check(ctx.lib.cc_mlp_moments(ctx.h, _ptr(raw), _ptr(y), raw.shape[0], out))
+        sx2, sD, sD2, se, se2, sy2, n = list(out)
+        mD, me = sD / n, se / n
+        return {"sx": (sx2 / n) ** 0.5, "mD": mD, "sD": max(sD2 / n - mD * mD, 1e-300) ** 0.5, "me": me,
+                "se": max(se2 / n - me * me, 1e-300) ** 0.5, "st": (sy2 / n) ** 0.5}
+
+    def standardise(self, raw: torch.Tensor, y: Optional[torch.Tensor] = None):
+        z = torch.empty_like(raw)
+        ys = torch.empty_like(y) if y is not None else None
+        st = self._st()
+        self.ctx.enter()
+        self.ctx.check(self.ctx.lib.cc_mlp_standardise(self.ctx.h, _ptr(raw), _ptr(y), raw.shape[0], C.byref(st),
+                                                       _ptr(z), _ptr(ys)))
+        return z, ys
+
+    def forward(self, z: torch.Tensor) -> torch.Tensor:
+        f = torch.empty(z.shape[0], dtype=torch.float64, device=z.device)
+        self.ctx.enter()
+        self.ctx.check(self.ctx.lib.cc_mlp_forward(self.ctx.h, self.prec, _ptr(self.params), _ptr(z), z.shape[0],
+                                                   _ptr(f)))
+        return f
+
+    def loss_grad(self, z: torch.Tensor, y: torch.Tensor):
+        g = torch.empty_like(self.params)
+        loss = C.c_double()
+        self.ctx.enter()
+        self.ctx.check(self.ctx.lib.cc_mlp_loss_grad(self.ctx.h, self.prec, _ptr(self.params), _ptr(z), _ptr(y),
+                                                     z.shape[0], C.byref(loss), _ptr(g)))
+        return loss.value, g
+
+    def train(self, z: torch.Tensor, y: torch.Tensor, epochs: int = 1, batch: int = 65536, lr: float = 1e-3,
+              order: Optional[torch.Tensor] = None):
+        hist = (C.c_double * epochs)()
+        self.ctx.enter()
+        self.ctx.check(self.ctx.lib.cc_mlp_train(self.ctx.h, self.prec, _ptr(self.params), _ptr(self.m),
+                                                 _ptr(self.v), _ptr(z), _ptr(y), z.shape[0], _ptr(order), batch,
+                                                 epochs, lr, C.byref(self.t), hist, epochs))
+        return list(hist)
+
+    def guess(self, dsys: DeviceSystem, t1, t2):
+        st = self._st()
+        self.ctx.enter()
+        self.ctx.check(self.ctx.lib.cc_guess_mlp(self.ctx.h, C.byref(dsys.struct), self.prec, _ptr(self.params),
+                                                 C.byref(st), C.byref(_amps(t1, t2))))
+
+    def save(self, path):
+        np.savez(path, params=self.params.cpu().numpy(),
+                 stats=np.array([self.stats[k] for k in ("sx", "mD", "sD", "me", "se", "st")]))
+
+    @classmethod
+    def load(cls, ctx: Context, path, prec: int = F32, device="cuda"):
+        d = np.load(path, allow_pickle=False)
+        keys = ("sx", "mD", "sD", "me", "se", "st")
+        return cls(ctx, torch.from_numpy(d["params"]).to(device), dict(zip(keys, d["stats"].tolist())), prec)

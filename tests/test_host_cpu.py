@@ -33,7 +33,7 @@ def _has_gpu():
 def test_header_symbols_exported():
     L, lib = _lib()
     hdr = (ROOT / "include" / "cc.h").read_text()
-    declared = set(re.findall(r"^\s*(?:const\s+)?[a-z_]+\s*\*?\s*(cc_[a-z0-9_]+)\s*\(", hdr, re.M))
+    declared = set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(cc_[a-z0-9_]+)\s*\(", hdr, re.M))
     assert declared, "no declarations parsed"
     assert declared == set(L.EXPORTS), declared ^ set(L.EXPORTS)
     for name in declared:

@@ -88,6 +88,7 @@ void read_scalars(cc_plan *p, double *rn, double *er, double *ei) {
 // One update step; replays a captured graph when asked and when the
 // amplitude pointers and shift match the capture.
 void run_step(cc_plan *p, bool use_graph) {
+  ccmi::plan_prepare(p);
   if (!use_graph) {
     ccmi::plan_run(p);
     return;
@@ -433,7 +434,34 @@ int cc_gemm(cc_ctx *ctx, int prec, int scalar, int64_t M, int64_t N, int64_t K, 
       const char *tv = std::getenv("CC_GEMM_TILE");  // tuning sweeps: force one tile configuration
       ccmi::gemm_f64(d, ctx->stream, tv ? std::atoi(tv) : -1);
     }
-    else ccmi::gemm_lowp(d, prec, ctx->stream, -1);
+    else {
+      // operands converted once into temporary 4-byte copies (CC_GEMM_LPIN=0:
+      // convert while staging instead)
+      const char *lv = std::getenv("CC_GEMM_LPIN");
+      void *sa = nullptr, *sb = nullptr;
+      if (K > 0 && !(lv && lv[0] == '0')) {
+        const int64_t na = (M - 1) * sam + (K - 1) * sak + 1, nb = (N - 1) * sbn + (K - 1) * sbk + 1;
+        CC_HIP_CHECK(hipMalloc(&sa, size_t(na) * 4));
+        if (hipMalloc(&sb, size_t(nb) * 4) != hipSuccess) {
+          (void)hipFree(sa);
+          throw CCError(CC_ENOMEM, "GEMM operand copy allocation failed");
+        }
+        ccmi::convert_shadow(prec, static_cast<const double *>(A), na, sa, ctx->stream);
+        ccmi::convert_shadow(prec, static_cast<const double *>(B), nb, sb, ctx->stream);
+        d.A = sa;
+        d.B = sb;
+        d.a_plane = na;
+        d.b_plane = nb;
+        d.lp_in = 1;
+      }
+      const char *tv = std::getenv("CC_GEMM_TILE");
+      ccmi::gemm_lowp(d, prec, ctx->stream, tv ? std::atoi(tv) : -1);
+      const hipError_t e = hipStreamSynchronize(ctx->stream);
+      if (sa) (void)hipFree(sa);
+      if (sb) (void)hipFree(sb);
+      CC_HIP_CHECK(e);
+      return CC_OK;
+    }
     CC_HIP_CHECK(hipStreamSynchronize(ctx->stream));
     return CC_OK;
   });

@@ -52,7 +52,15 @@ struct GemmDesc {
   int ladder = 0;              // 1: launch the ladder's own kernel symbol (profiling)
   int split = 1;               // split-K factor; > 1 needs ws of split*M*N elements
   void *ws = nullptr;
+  // reduced precision with converted operands ("shadows"): A and B point to
+  // FP32 (F32) or to bf16 hi planes whose lo planes follow at +a_plane /
+  // +b_plane elements (BF16X3), indexed exactly like the FP64 tensors.
+  int lp_in = 0;
+  int64_t a_plane = 0, b_plane = 0;
 };
+
+// FP64 tensor -> reduced-precision shadow with the same element indexing.
+void convert_shadow(int prec, const double *src, int64_t n, void *dst, hipStream_t s);
 
 enum Prec { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16X3 = 2 };
 

@@ -5,13 +5,19 @@
 //           lo = bf16(x - hi); the product keeps hi*hi + hi*lo + lo*hi
 //           (v_mfma_f32_16x16x32_bf16, FP32 accumulate), dropping lo*lo
 //           (split-bfloat16 products: Henry, Tang & Heinecke, ARITH 2019).
-// Operands stay FP64 in HBM; the conversion happens while a tile is staged
-// into LDS, so the rest of the residual path (permutations, assembly, norms,
-// denominators, energy) is unchanged FP64.  Tiling, double buffering, split-K
-// and the XCD-aware tile order follow the FP64 kernel.
+// Two ways to get the operands in:
+// * FP64 tensors, rounded/split while a tile is staged into LDS;
+// * converted copies made once by convert_shadow (FP32, or a bf16 hi plane
+//   followed by a bf16 lo plane, same element indexing as the FP64 tensor),
+//   read with 16-byte vector loads and stored to LDS unchanged.  The LDS
+//   contents, hence the results, are identical for both.
+// Everything outside the contractions (permutations, assembly, norms,
+// denominators, energy) stays FP64.  Tiling, double buffering, split-K and
+// the XCD-aware tile order follow the FP64 kernel.
 #include "common.hpp"
 
 #include <cmath>
+#include <type_traits>
 
 namespace ccmi {
 namespace {
@@ -45,7 +51,7 @@ struct LCfg {
   static_assert((BM * BK) % NT == 0 && (BN * BK) % NT == 0, "load split");
 };
 
-template <int MODE, int BM, int BN, int BK, int WM, int WN, bool AKC, bool BKC, int TAG>
+template <int MODE, int BM, int BN, int BK, int WM, int WN, bool AKC, bool BKC, int TAG, bool LPIN>
 __global__ __launch_bounds__(WM *WN *kWave) void gemm_lowp_kernel(GemmDesc d, int64_t tilesM,
                                                                    int64_t tilesN) {
   using C = LCfg<MODE, BM, BN, BK, WM, WN, AKC, BKC>;
@@ -64,61 +70,141 @@ __global__ __launch_bounds__(WM *WN *kWave) void gemm_lowp_kernel(GemmDesc d, in
   const int wm0 = (wave / WN) * C::WTM, wn0 = (wave % WN) * C::WTN;
   const int q = lane >> 4, r = lane & 15;
 
-  const double *__restrict__ A = static_cast<const double *>(d.A);
-  const double *__restrict__ B = static_cast<const double *>(d.B);
   const int64_t M = d.M, N = d.N;
   const int64_t kchunk = ((d.K + d.split - 1) / d.split + BK - 1) / BK * BK;
   const int64_t kb = ks * kchunk;
   const int64_t K = std::max<int64_t>(0, std::min<int64_t>(d.K - kb, kchunk));
-  A += kb * d.sak;
-  B += kb * d.sbk;
-
-  float ra[C::LA], rb[C::LB];
-  auto gload = [&](int64_t k0) {
-#pragma unroll
-    for (int i = 0; i < C::LA; ++i) {
-      const int e = tid + i * C::NT;
-      int mm, kk;
-      if (AKC) { mm = e / BK; kk = e % BK; } else { kk = e / BM; mm = e % BM; }
-      const int64_t gm = m0 + mm, gk = k0 + kk;
-      ra[i] = (gm < M && gk < K) ? static_cast<float>(A[gm * d.sam + gk * d.sak]) : 0.0f;
-    }
-#pragma unroll
-    for (int i = 0; i < C::LB; ++i) {
-      const int e = tid + i * C::NT;
-      int nn, kk;
-      if (BKC) { nn = e / BK; kk = e % BK; } else { kk = e / BN; nn = e % BN; }
-      const int64_t gn = n0 + nn, gk = k0 + kk;
-      rb[i] = (gn < N && gk < K) ? static_cast<float>(B[gn * d.sbn + gk * d.sbk]) : 0.0f;
-    }
-  };
   auto a_base = [&](int buf) { return smem + buf * A_BYTES; };
   auto b_base = [&](int buf) { return smem + 2 * A_BYTES + buf * B_BYTES; };
-  auto sstore = [&](int buf) {
-#pragma unroll
-    for (int i = 0; i < C::LA; ++i) {
-      const int e = tid + i * C::NT;
-      const int idx = AKC ? (e / BK) * C::A_LD + (e % BK) : (e / BM) * C::A_LD + (e % BM);
-      if (MODE == PREC_F32) {
-        reinterpret_cast<float *>(a_base(buf))[idx] = ra[i];
+
+  // ---- path 1: FP64 operands, rounded/split while staging --------------------
+  const double *__restrict__ A = static_cast<const double *>(d.A) + kb * d.sak;
+  const double *__restrict__ B = static_cast<const double *>(d.B) + kb * d.sbk;
+  constexpr int LA1 = LPIN ? 1 : C::LA, LB1 = LPIN ? 1 : C::LB;
+  float ra[LA1], rb[LB1];
+  // ---- path 2: converted operands, 16-byte vectors straight into LDS --------
+  typedef typename std::conditional<MODE == PREC_F32, float, unsigned short>::type EL;
+  constexpr int VEC = 16 / int(sizeof(EL));
+  constexpr int AR = AKC ? BM : BK, AC = AKC ? BK : BM, BR = BKC ? BN : BK, BC = BKC ? BK : BN;
+  constexpr int ANV = AR * AC / VEC, BNV = BR * BC / VEC;
+  constexpr int AVT = LPIN ? (ANV + C::NT - 1) / C::NT : 1, BVT = LPIN ? (BNV + C::NT - 1) / C::NT : 1;
+  uint4 va[AVT][NPART], vb[BVT][NPART];
+  const EL *__restrict__ Al = static_cast<const EL *>(d.A) + kb * d.sak;
+  const EL *__restrict__ Bl = static_cast<const EL *>(d.B) + kb * d.sbk;
+  const bool vec_a = ((AKC ? d.sam : d.sak) % VEC == 0) && ((reinterpret_cast<uintptr_t>(Al) & 15) == 0) &&
+                     (d.a_plane % VEC == 0);
+  const bool vec_b = ((BKC ? d.sbn : d.sbk) % VEC == 0) && ((reinterpret_cast<uintptr_t>(Bl) & 15) == 0) &&
+                     (d.b_plane % VEC == 0);
+
+  // one operand's vector loads: rows along the strided dim, VEC columns along
+  // the unit-stride dim; out-of-range elements read as zero
+  auto vload = [&](const EL *base, int64_t plane, int64_t rstride, int64_t r_lim, int64_t c_lim, int64_t r0,
+                   int64_t c0, bool vec_ok, int v, int ncolv, uint4 *out) {
+    const int r = v / ncolv, c = (v % ncolv) * VEC;
+    const int64_t gr = r0 + r, gc = c0 + c;
+    for (int pl = 0; pl < NPART; ++pl) {
+      const EL *src = base + pl * plane + gr * rstride + gc;
+      if (vec_ok && gr < r_lim && gc + VEC <= c_lim) {
+        out[pl] = *reinterpret_cast<const uint4 *>(src);
       } else {
-        const unsigned short h = bf16_bits(ra[i]);
-        unsigned short *p = reinterpret_cast<unsigned short *>(a_base(buf));
-        p[idx] = h;
-        p[C::A_ELEMS + idx] = bf16_bits(ra[i] - bf16_to_float(h));
+        union {
+          uint4 u;
+          EL e[VEC];
+        } tmp;
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) tmp.e[q] = (gr < r_lim && gc + q < c_lim) ? src[q] : EL(0);
+        out[pl] = tmp.u;
       }
     }
+  };
+
+  auto gload = [&](int64_t k0) {
+    if constexpr (LPIN) {
 #pragma unroll
-    for (int i = 0; i < C::LB; ++i) {
-      const int e = tid + i * C::NT;
-      const int idx = BKC ? (e / BK) * C::B_LD + (e % BK) : (e / BN) * C::B_LD + (e % BN);
-      if (MODE == PREC_F32) {
-        reinterpret_cast<float *>(b_base(buf))[idx] = rb[i];
-      } else {
-        const unsigned short h = bf16_bits(rb[i]);
-        unsigned short *p = reinterpret_cast<unsigned short *>(b_base(buf));
-        p[idx] = h;
-        p[C::B_ELEMS + idx] = bf16_bits(rb[i] - bf16_to_float(h));
+      for (int i = 0; i < AVT; ++i) {
+        const int v = tid + i * C::NT;
+        if (v < ANV) {
+          if (AKC) vload(Al, d.a_plane, d.sam, M, K, m0, k0, vec_a, v, AC / VEC, va[i]);
+          else vload(Al, d.a_plane, d.sak, K, M, k0, m0, vec_a, v, AC / VEC, va[i]);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < BVT; ++i) {
+        const int v = tid + i * C::NT;
+        if (v < BNV) {
+          if (BKC) vload(Bl, d.b_plane, d.sbn, N, K, n0, k0, vec_b, v, BC / VEC, vb[i]);
+          else vload(Bl, d.b_plane, d.sbk, K, N, k0, n0, vec_b, v, BC / VEC, vb[i]);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < C::LA; ++i) {
+        const int e = tid + i * C::NT;
+        int mm, kk;
+        if (AKC) { mm = e / BK; kk = e % BK; } else { kk = e / BM; mm = e % BM; }
+        const int64_t gm = m0 + mm, gk = k0 + kk;
+        ra[i] = (gm < M && gk < K) ? static_cast<float>(A[gm * d.sam + gk * d.sak]) : 0.0f;
+      }
+#pragma unroll
+      for (int i = 0; i < C::LB; ++i) {
+        const int e = tid + i * C::NT;
+        int nn, kk;
+        if (BKC) { nn = e / BK; kk = e % BK; } else { kk = e / BN; nn = e % BN; }
+        const int64_t gn = n0 + nn, gk = k0 + kk;
+        rb[i] = (gn < N && gk < K) ? static_cast<float>(B[gn * d.sbn + gk * d.sbk]) : 0.0f;
+      }
+    }
+  };
+  auto sstore = [&](int buf) {
+    if constexpr (LPIN) {
+#pragma unroll
+      for (int i = 0; i < AVT; ++i) {
+        const int v = tid + i * C::NT;
+        if (v < ANV) {
+          const int r = v / (AC / VEC), c = (v % (AC / VEC)) * VEC;
+          EL *dst = reinterpret_cast<EL *>(a_base(buf));
+#pragma unroll
+          for (int pl = 0; pl < NPART; ++pl)
+            *reinterpret_cast<uint4 *>(dst + pl * C::A_ELEMS + r * C::A_LD + c) = va[i][pl];
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < BVT; ++i) {
+        const int v = tid + i * C::NT;
+        if (v < BNV) {
+          const int r = v / (BC / VEC), c = (v % (BC / VEC)) * VEC;
+          EL *dst = reinterpret_cast<EL *>(b_base(buf));
+#pragma unroll
+          for (int pl = 0; pl < NPART; ++pl)
+            *reinterpret_cast<uint4 *>(dst + pl * C::B_ELEMS + r * C::B_LD + c) = vb[i][pl];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < C::LA; ++i) {
+        const int e = tid + i * C::NT;
+        const int idx = AKC ? (e / BK) * C::A_LD + (e % BK) : (e / BM) * C::A_LD + (e % BM);
+        if (MODE == PREC_F32) {
+          reinterpret_cast<float *>(a_base(buf))[idx] = ra[i];
+        } else {
+          const unsigned short h = bf16_bits(ra[i]);
+          unsigned short *p = reinterpret_cast<unsigned short *>(a_base(buf));
+          p[idx] = h;
+          p[C::A_ELEMS + idx] = bf16_bits(ra[i] - bf16_to_float(h));
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < C::LB; ++i) {
+        const int e = tid + i * C::NT;
+        const int idx = BKC ? (e / BK) * C::B_LD + (e % BK) : (e / BN) * C::B_LD + (e % BN);
+        if (MODE == PREC_F32) {
+          reinterpret_cast<float *>(b_base(buf))[idx] = rb[i];
+        } else {
+          const unsigned short h = bf16_bits(rb[i]);
+          unsigned short *p = reinterpret_cast<unsigned short *>(b_base(buf));
+          p[idx] = h;
+          p[C::B_ELEMS + idx] = bf16_bits(rb[i] - bf16_to_float(h));
+        }
       }
     }
   };
@@ -242,8 +328,12 @@ struct LTile {
 
 template <int MODE, int BM, int BN, int BK, int WM, int WN, bool AKC, bool BKC, int TAG = 0>
 void launch_l(const GemmDesc &d, int64_t tm, int64_t tn, hipStream_t s) {
-  hipLaunchKernelGGL((gemm_lowp_kernel<MODE, BM, BN, BK, WM, WN, AKC, BKC, TAG>), dim3(tm * tn * d.split),
-                     dim3(WM * WN * kWave), 0, s, d, tm, tn);
+  if (d.lp_in)
+    hipLaunchKernelGGL((gemm_lowp_kernel<MODE, BM, BN, BK, WM, WN, AKC, BKC, TAG, true>),
+                       dim3(tm * tn * d.split), dim3(WM * WN * kWave), 0, s, d, tm, tn);
+  else
+    hipLaunchKernelGGL((gemm_lowp_kernel<MODE, BM, BN, BK, WM, WN, AKC, BKC, TAG, false>),
+                       dim3(tm * tn * d.split), dim3(WM * WN * kWave), 0, s, d, tm, tn);
 }
 
 #define CC_LTILE(MODE, BM, BN, BK, WM, WN)                                                          \
@@ -280,7 +370,34 @@ int pick_l(const LTile *tiles, int64_t M, int64_t N) {
   return best;
 }
 
+__global__ __launch_bounds__(256) void to_f32_kernel(const double *__restrict__ src, int64_t n,
+                                                     float *__restrict__ dst) {
+  for (int64_t e = blockIdx.x * int64_t(256) + threadIdx.x; e < n; e += int64_t(gridDim.x) * 256)
+    dst[e] = static_cast<float>(src[e]);
+}
+
+__global__ __launch_bounds__(256) void to_bf16x2_kernel(const double *__restrict__ src, int64_t n,
+                                                        unsigned short *__restrict__ hi) {
+  unsigned short *__restrict__ lo = hi + n;
+  for (int64_t e = blockIdx.x * int64_t(256) + threadIdx.x; e < n; e += int64_t(gridDim.x) * 256) {
+    const float x = static_cast<float>(src[e]);
+    const unsigned short h = bf16_bits(x);
+    hi[e] = h;
+    lo[e] = bf16_bits(x - bf16_to_float(h));
+  }
+}
+
 }  // namespace
+
+void convert_shadow(int prec, const double *src, int64_t n, void *dst, hipStream_t s) {
+  if (n <= 0) return;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+  if (prec == PREC_F32)
+    hipLaunchKernelGGL(to_f32_kernel, dim3(blocks), dim3(256), 0, s, src, n, static_cast<float *>(dst));
+  else
+    hipLaunchKernelGGL(to_bf16x2_kernel, dim3(blocks), dim3(256), 0, s, src, n, static_cast<unsigned short *>(dst));
+  CC_HIP_CHECK(hipGetLastError());
+}
 
 int gemm_lowp_num_tiles() { return kNumL; }
 const char *gemm_lowp_tile_name(int prec, int id) {

@@ -484,18 +484,85 @@ struct Planner {
   }
 };
 
-void run_gemm(cc_plan *p, GemmDesc &d, const Step &st, hipStream_t s) {
-  if (p->cplx) gemm_c128(d, s, st.tile_z);
-  else if (p->cur_prec == PREC_F64) gemm_f64(d, s, st.tile);
-  else gemm_lowp(d, p->cur_prec, s, st.tile_lp[p->cur_prec]);
-}
-
 }  // namespace
 
 void *ptr_of(cc_plan *p, int s) {
   const Slot &sl = p->slots[s];
   if (sl.external) return sl.name == "t1" ? p->t1 : p->t2;
   return sl.ptr;
+}
+
+namespace {
+
+int64_t slot_elems(const cc_plan *p, int s) {
+  const Slot &sl = p->slots[s];
+  if (sl.external) return sl.name == "t1" ? int64_t(p->o) * p->v : int64_t(p->o) * p->o * p->v * p->v;
+  return sl.elems;
+}
+
+// Point a reduced-precision GEMM at the converted copies of its operands,
+// converting a copy first when its slot was written since the last
+// conversion in this run.
+void use_shadows(cc_plan *p, GemmDesc &d, const Step &st, hipStream_t s, bool convert) {
+  for (int which = 0; which < 2; ++which) {
+    const int sl = which ? st.b : st.a;
+    void *sh = p->shadow[sl];
+    if (!sh) return;
+    if (convert && !p->shadow_ok[sl]) {
+      convert_shadow(p->cur_prec, static_cast<const double *>(ptr_of(p, sl)), slot_elems(p, sl), sh, s);
+      p->shadow_ok[sl] = 1;
+    }
+  }
+  d.A = p->shadow[st.a];
+  d.B = p->shadow[st.b];
+  d.a_plane = slot_elems(p, st.a);
+  d.b_plane = slot_elems(p, st.b);
+  d.lp_in = 1;
+}
+
+void run_gemm(cc_plan *p, GemmDesc &d, const Step &st, hipStream_t s) {
+  if (p->cplx) gemm_c128(d, s, st.tile_z);
+  else if (p->cur_prec == PREC_F64) gemm_f64(d, s, st.tile);
+  else {
+    use_shadows(p, d, st, s, true);
+    gemm_lowp(d, p->cur_prec, s, st.tile_lp[p->cur_prec]);
+  }
+}
+
+void invalidate(cc_plan *p, int sl) {
+  if (sl >= 0 && !p->shadow_ok.empty()) p->shadow_ok[sl] = 0;
+}
+
+}  // namespace
+
+// Reduced-precision runs read each GEMM operand from a 4-byte-per-element
+// copy (FP32, or bf16 hi plane followed by bf16 lo plane) made by one
+// conversion pass: constant operands once per precision, the others once per
+// write.  Allocation and the constant conversions happen here, outside any
+// graph capture.
+void plan_prepare(cc_plan *p) {
+  if (p->cplx || p->cur_prec == PREC_F64) return;
+  const size_t n = p->slots.size();
+  if (p->shadow.size() != n) {
+    p->shadow.assign(n, nullptr);
+    p->shadow_prec.assign(n, -1);
+    p->shadow_ok.assign(n, 0);
+  }
+  hipStream_t s = p->ctx->stream;
+  for (const Step &st : p->iter) {
+    if (st.kind != Step::GEMM) continue;
+    for (int sl : {st.a, st.b}) {
+      if (!p->shadow[sl]) {
+        CC_HIP_CHECK(hipMalloc(&p->shadow[sl], size_t(slot_elems(p, sl)) * 4));
+        p->shadow_prec[sl] = -1;
+      }
+      if (p->slots[sl].constant && p->shadow_prec[sl] != p->cur_prec) {
+        convert_shadow(p->cur_prec, static_cast<const double *>(ptr_of(p, sl)), slot_elems(p, sl),
+                       p->shadow[sl], s);
+        p->shadow_prec[sl] = p->cur_prec;
+      }
+    }
+  }
 }
 
 TauEntry tau_entry(cc_plan *p) {
@@ -528,6 +595,11 @@ namespace {
 
 void exec(cc_plan *p, Step &st, hipStream_t s) {
   const bool cplx = p->cplx;
+  invalidate(p, st.c);
+  if (st.kind == Step::TAU_E && p->method == CC_CCSD) {
+    invalidate(p, p->index["tau"]);
+    invalidate(p, p->index["taut"]);
+  }
   switch (st.kind) {
     case Step::PERMUTE:
       if (cplx) permute_c128(st.perm, ptr_of(p, st.a), ptr_of(p, st.c), s);
@@ -608,12 +680,23 @@ void plan_free(cc_plan *p) {
   p->graph = nullptr;
   for (Slot &s : p->slots)
     if (s.owned && s.ptr) (void)hipFree(s.ptr);
+  for (void *q : p->shadow)
+    if (q) (void)hipFree(q);
+  p->shadow.clear();
   for (double *q : {p->d_oo, p->d_vv, p->epart, p->n2part, p->n1part, p->scalars})
     if (q) (void)hipFree(q);
 }
 
 void plan_run(cc_plan *p) {
   hipStream_t s = p->ctx->stream;
+  if (!p->cplx && p->cur_prec != PREC_F64) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    CC_HIP_CHECK(hipStreamIsCapturing(s, &cs));
+    if (cs == hipStreamCaptureStatusNone) plan_prepare(p);
+    CC_REQUIRE(p->shadow.size() == p->slots.size(), CC_EINTERNAL, "operand copies not prepared");
+    for (size_t i = 0; i < p->slots.size(); ++i)
+      p->shadow_ok[i] = p->slots[i].constant && p->shadow_prec[i] == p->cur_prec;
+  }
   if (!p->profiling) {
     for (Step &st : p->iter) exec(p, st, s);
     return;
@@ -646,6 +729,7 @@ void plan_run(cc_plan *p) {
 void plan_autotune(cc_plan *p, int reps) {
   static std::map<std::string, int> cache;
   const int prec = p->cplx ? 9 : p->cur_prec;  // 9: complex128 tiles
+  plan_prepare(p);
   const int ntiles = p->cplx ? gemm_c128_num_tiles()
                              : (prec == PREC_F64 ? gemm_f64_num_tiles() : gemm_lowp_num_tiles());
   hipStream_t s = p->ctx->stream;
@@ -669,6 +753,7 @@ void plan_autotune(cc_plan *p, int reps) {
       d.B = ptr_of(p, st->b);
       d.C = ptr_of(p, st->c);
       d.ws = st->b2 >= 0 ? ptr_of(p, st->b2) : nullptr;
+      if (!p->cplx && prec != PREC_F64) use_shadows(p, d, *st, s, false);
       int best = slot;
       float best_ms = 1e30f;
       auto launch = [&](int t) {

@@ -94,6 +94,10 @@ struct cc_plan {
   std::vector<hipEvent_t> events;
   std::vector<double> step_ms;   // accumulated per iteration step
   std::vector<int64_t> step_calls;
+  // reduced-precision operand copies (4 bytes per element), per slot
+  std::vector<void *> shadow;
+  std::vector<int> shadow_prec;   // precision held by a constant slot's copy
+  std::vector<char> shadow_ok;    // copy matches the slot in the current run
 };
 
 namespace ccmi {
@@ -101,6 +105,7 @@ void plan_layout(cc_plan *p, const cc_system *sys);  // planning only, no device
 void plan_build(cc_plan *p, const cc_system *sys);
 void plan_free(cc_plan *p);
 void plan_run(cc_plan *p);           // enqueue one residual (+ update) on the stream
+void plan_prepare(cc_plan *p);       // allocate / refresh operand copies; never under capture
 void plan_run_energy(cc_plan *p);    // tau + energy only
 std::string plan_describe(const cc_plan *p);
 void plan_autotune(cc_plan *p, int reps);

@@ -101,6 +101,32 @@ def test_gemm_lowp_error_bound(ctx, prec, shape, akc, bkc):
     assert np.all(err <= bound), (err / bound).max()
 
 
+@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
+@pytest.mark.parametrize("shape", [(17, 33, 65), (100, 129, 37), (257, 300, 100), (64, 576, 576)])
+@pytest.mark.parametrize("akc,bkc", [(True, True), (False, False), (True, False), (False, True)])
+def test_gemm_lowp_converted_operands_match_inline(ctx, monkeypatch, prec, shape, akc, bkc):
+    """Operands converted once into 4-byte copies and read with vector loads
+    give bit-identical results to rounding/splitting FP64 operands while
+    staging (same LDS contents, same accumulation order).  Odd leading
+    dimensions take the scalar-load fallback."""
+    from paper_2409_06759_amd import engine as E
+    M, N, K = shape
+    print(f"gemm staging {prec} M={M} N={N} K={K} akc={akc} bkc={bkc}", flush=True)
+    rng = np.random.default_rng(M + N + K)
+    A = rng.normal(size=(M, K))
+    B = rng.normal(size=(N, K))
+    C0 = rng.normal(size=(M, N))
+    Ad = torch.from_numpy(A if akc else np.ascontiguousarray(A.T)).cuda()
+    Bd = torch.from_numpy(B if bkc else np.ascontiguousarray(B.T)).cuda()
+    out = []
+    for lpin in ("1", "0"):
+        monkeypatch.setenv("CC_GEMM_LPIN", lpin)
+        Cd = torch.from_numpy(C0).cuda()
+        E.gemm(ctx, Ad, Bd, Cd, 0.5, -1.25, a_kcontig=akc, b_kcontig=bkc, prec=E.PRECS[prec])
+        out.append(Cd.cpu().numpy())
+    assert np.array_equal(out[0], out[1])
+
+
 
 @pytest.mark.parametrize("shape", [(1, 1, 1), (17, 33, 65), (64, 100, 300), (130, 70, 33)])
 @pytest.mark.parametrize("akc,bkc", [(True, True), (False, False), (False, True)])

@@ -86,6 +86,76 @@ def cpu_baseline(sysm, method, flops_per_step):
                       f"o={o} v={v}: {el:.1f} s", "seconds": el}
 
 
+def bench_batched(ctx, E, torch, steps, warmup):
+    """64 uneven systems (o in [4,16], v in [20,60]), one grouped launch per
+    step of the contraction list, FP64 and FP32 contractions; then all 64
+    iterated to ||R|| < 1e-8 in FP64."""
+    from ccinputs.synth import batch_shapes, make_system
+    shapes = batch_shapes(64)
+    ds = [E.DeviceSystem(make_system(o, v, seed), drop_host=True) for o, v, seed in shapes]
+    out = {"systems": len(ds), "o_range": [min(s[0] for s in shapes), max(s[0] for s in shapes)],
+           "v_range": [min(s[1] for s in shapes), max(s[1] for s in shapes)]}
+    for pname in ("f64", "f32"):
+        with E.Batch(ctx, ds, E.CCSD, prec=E.PRECS[pname]) as B:
+            B.step(0.0, True)
+            torch.cuda.synchronize()
+            B.autotune(2)
+            for _ in range(warmup):
+                B.step(0.0, True)
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            for _ in range(steps):
+                B.step(0.0, True)
+            torch.cuda.synchronize()
+            el = (time.perf_counter() - ts) / steps
+            fl = B.flops()
+            out[pname] = {"ms_per_step": round(el * 1e3, 3), "tflops": round(fl / el / 1e12, 3),
+                          "flops_per_step": fl}
+        log(f"[bench] batched {pname}: {el * 1e3:.3f} ms/step, {fl / el / 1e12:.2f} TFLOP/s")
+    with E.Batch(ctx, ds, E.CCSD) as B:
+        r = B.iterate(tol=1e-8, max_iter=300, dressed=True)
+        out["time_to_1e-8"] = {"n_converged": r["n_converged"],
+                               "seconds": round(max(x["seconds"] for x in r["systems"]), 3),
+                               "max_iterations": max(x["iters"] for x in r["systems"])}
+    log(f"[bench] batched time to 1e-8: {out['time_to_1e-8']}")
+    return out
+
+
+def bench_complex(ctx, E, torch, steps, warmup, o=40, v=200):
+    """Complex128 Hermitian system: FP64 complex MFMA contraction steps."""
+    from ccinputs.synth import make_system
+    t0 = time.time()
+    d = E.DeviceSystem(make_system(o, v, is_complex=True), drop_host=True)
+    log(f"[bench] complex o={o} v={v} resident ({time.time() - t0:.1f}s)")
+    with E.Plan(ctx, d, E.CCSD) as plan:
+        t1, t2 = E.zeros_amps(d, E.CCSD)
+        plan.step(t1, t2, 0.0, True)
+        torch.cuda.synchronize()
+        plan.autotune(t1, t2, 1)
+        for _ in range(warmup):
+            plan.step(t1, t2, 0.0, True)
+        plan.profile(True)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        for _ in range(steps):
+            plan.step(t1, t2, 0.0, True)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - ts) / steps
+        rows = plan.profile_table()
+        plan.profile(False)
+        lad = [r for r in rows if r[1] == "GEMM" and r[2].startswith("ladder@")]
+        lad_ms = lad[0][5]
+        lf = plan.flops(ladder_only=True)
+        rn, e, _ = plan.scalars()
+        res = {"o": o, "v": v, "ms_per_step": round(el * 1e3, 2), "tflops": round(plan.flops() / el / 1e12, 3),
+               "flops_per_step": plan.flops(), "ladder_ms": round(lad_ms, 3),
+               "ladder_tflops": round(lf / (lad_ms / 1e3) / 1e12, 3),
+               "ladder_frac_fp64_peak": round(lf / (lad_ms / 1e3) / 1e12 / PEAK_FP64_TFLOPS, 4),
+               "steps": steps, "rnorm_last": rn}
+    log(f"[bench] complex: {res}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,6 +171,9 @@ def main():
                     help="contraction precision of the timed steps")
     ap.add_argument("--converge-precs", default="f64,f32,bf16x3",
                     help="precisions whose time to ||R||<1e-8 is reported (reduced ones refine in FP64)")
+    ap.add_argument("--extras", default="batched",
+                    help="comma list of extra workloads reported in the same line: batched (64 uneven "
+                         "systems), complex (complex128 o=40 v=200)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB copy (for HBM counter scaling)")
     args = ap.parse_args()
@@ -183,6 +256,16 @@ def main():
             log(f"[bench] {pname}: time to ||R||<1e-8 {out['seconds']:.2f}s, {out['iters']} iterations "
                 f"({out['lowp_iters']} reduced), E={out['energy']:.10f}")
 
+    extras = {}
+    for name in [x for x in args.extras.split(",") if x]:
+        if name == "batched":
+            extras["batched"] = bench_batched(ctx, E, torch, max(args.steps, 5), args.warmup)
+        elif name == "complex":
+            plan.close()
+            extras["complex"] = bench_complex(ctx, E, torch, 3, 1)
+        else:
+            raise SystemExit(f"unknown extra workload {name}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle (one residual evaluation)...")
@@ -207,6 +290,7 @@ def main():
         "cpu_baseline": ({k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")} if cpu else None),
         "time_to_1e-8": conv or None,
     }
+    line.update(extras)
     print(json.dumps(line), flush=True)
     plan.close()
     ctx.close()

@@ -127,11 +127,16 @@ void build_tables(cc_batch *B) {
           const int64_t work = st.gemm.M * st.gemm.N * st.gemm.K;
           if (work > best) {
             best = work;
-            g.tile = st.tile >= 0 ? st.tile : gemm_f64_pick(st.gemm.M, st.gemm.N, st.gemm.K, g.akc, g.bkc);
+            if (B->prec == PREC_F64)
+              g.tile = st.tile >= 0 ? st.tile : gemm_f64_pick(st.gemm.M, st.gemm.N, st.gemm.K, g.akc, g.bkc);
+            else
+              g.tile = st.tile_lp[B->prec] >= 0 ? st.tile_lp[B->prec]
+                                                 : gemm_lowp_pick(B->prec, st.gemm.M, st.gemm.N);
           }
         }
         int bm, bn;
-        gemm_f64_tile_shape(g.tile, &bm, &bn);
+        if (B->prec == PREC_F64) gemm_f64_tile_shape(g.tile, &bm, &bn);
+        else gemm_lowp_tile_shape(B->prec, g.tile, &bm, &bn);
         for (cc_plan *p : B->plans) {
           const Step &st = p->iter[k];
           GemmGroupEntry e{};
@@ -245,8 +250,8 @@ void run_gstep(cc_batch *B, size_t k, hipStream_t s) {
   const GStep &g = B->gsteps[k];
   const bool cplx = B->cplx;
   const int n = B->n;
-  if (!g.grouped || (g.kind == Step::GEMM && (cplx || B->prec != PREC_F64))) {
-    // per-system launches (complex and reduced-precision GEMMs, degenerate shapes)
+  if (!g.grouped || (g.kind == Step::GEMM && cplx)) {
+    // per-system launches (complex GEMMs, degenerate shapes)
     for (cc_plan *p : B->plans) {
       Step &st = p->iter[k];
       if (st.kind == Step::GEMM) {
@@ -272,7 +277,11 @@ void run_gstep(cc_batch *B, size_t k, hipStream_t s) {
       launch_perm_grouped(dev_at<PermEntry>(B, g.entry_off), off, n, g.blocks, g.tiled, cplx, s);
       break;
     case Step::GEMM:
-      gemm_f64_grouped_launch(dev_at<GemmGroupEntry>(B, g.entry_off), off, n, g.blocks, g.akc, g.bkc, g.tile, s);
+      if (B->prec == PREC_F64)
+        gemm_f64_grouped_launch(dev_at<GemmGroupEntry>(B, g.entry_off), off, n, g.blocks, g.akc, g.bkc, g.tile, s);
+      else
+        gemm_lowp_grouped_launch(dev_at<GemmGroupEntry>(B, g.entry_off), off, n, g.blocks, g.akc, g.bkc, B->prec,
+                                 g.tile, s);
       if (g.sk_blocks > 0)
         launch_splitk_grouped(dev_at<SplitkEntry>(B, g.sk_entry_off), dev_at<int64_t>(B, g.sk_off_off), n,
                               g.sk_blocks, cplx, s);
@@ -330,7 +339,10 @@ void batch_run(cc_batch *B) {
 // Time every FP64 tile configuration of each grouped GEMM (a contraction
 // class across the batch) and keep the fastest.
 void batch_autotune(cc_batch *B, int reps) {
-  if (B->cplx || B->prec != PREC_F64) return;
+  if (B->cplx) return;
+  const int prec = B->prec;
+  const int ntiles = prec == PREC_F64 ? gemm_f64_num_tiles() : gemm_lowp_num_tiles();
+  auto tile_of = [prec](Step &st) -> int & { return prec == PREC_F64 ? st.tile : st.tile_lp[prec]; };
   hipStream_t s = B->ctx->stream;
   hipEvent_t e0, e1;
   CC_HIP_CHECK(hipEventCreate(&e0));
@@ -340,8 +352,8 @@ void batch_autotune(cc_batch *B, int reps) {
       if (B->gsteps[k].kind != Step::GEMM || !B->gsteps[k].grouped) continue;
       int best = B->gsteps[k].tile;
       float best_ms = 1e30f;
-      for (int t = 0; t < gemm_f64_num_tiles(); ++t) {
-        for (cc_plan *p : B->plans) p->iter[k].tile = t;
+      for (int t = 0; t < ntiles; ++t) {
+        for (cc_plan *p : B->plans) tile_of(p->iter[k]) = t;
         build_tables(B);
         run_gstep(B, k, s);
         CC_HIP_CHECK(hipEventRecord(e0, s));
@@ -355,7 +367,7 @@ void batch_autotune(cc_batch *B, int reps) {
           best = t;
         }
       }
-      for (cc_plan *p : B->plans) p->iter[k].tile = best;
+      for (cc_plan *p : B->plans) tile_of(p->iter[k]) = best;
     }
   } catch (...) {
     (void)hipEventDestroy(e0);

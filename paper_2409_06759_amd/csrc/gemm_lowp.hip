@@ -51,9 +51,8 @@ struct LCfg {
   static_assert((BM * BK) % NT == 0 && (BN * BK) % NT == 0, "load split");
 };
 
-template <int MODE, int BM, int BN, int BK, int WM, int WN, bool AKC, bool BKC, int TAG, bool LPIN>
-__global__ __launch_bounds__(WM *WN *kWave) void gemm_lowp_kernel(GemmDesc d, int64_t tilesM,
-                                                                   int64_t tilesN) {
+template <int MODE, int BM, int BN, int BK, int WM, int WN, bool AKC, bool BKC, bool LPIN>
+__device__ __forceinline__ void gemm_lowp_body(const GemmDesc &d, int64_t tilesM, int64_t tilesN, int64_t L0) {
   using C = LCfg<MODE, BM, BN, BK, WM, WN, AKC, BKC>;
   // F32: one float array per operand and buffer.  BF16X3: hi and lo arrays
   // (16-bit) per operand and buffer, laid out as [hi | lo].
@@ -62,8 +61,7 @@ __global__ __launch_bounds__(WM *WN *kWave) void gemm_lowp_kernel(GemmDesc d, in
   constexpr int A_BYTES = C::A_ELEMS * ESZ * NPART, B_BYTES = C::B_ELEMS * ESZ * NPART;
   __shared__ __attribute__((aligned(16))) unsigned char smem[2 * (A_BYTES + B_BYTES)];
 
-  const int64_t tiles = tilesM * tilesN, total = tiles * d.split;
-  const int64_t L0 = xcd_remap(blockIdx.x, total);
+  const int64_t tiles = tilesM * tilesN;
   const int64_t ks = L0 / tiles, L = L0 % tiles;
   const int64_t m0 = (L % tilesM) * BM, n0 = (L / tilesM) * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -319,12 +317,37 @@ __global__ __launch_bounds__(WM *WN *kWave) void gemm_lowp_kernel(GemmDesc d, in
     }
 }
 
+template <int MODE, int BM, int BN, int BK, int WM, int WN, bool AKC, bool BKC, int TAG, bool LPIN>
+__global__ __launch_bounds__(WM *WN *kWave) void gemm_lowp_kernel(GemmDesc d, int64_t tilesM,
+                                                                   int64_t tilesN) {
+  gemm_lowp_body<MODE, BM, BN, BK, WM, WN, AKC, BKC, LPIN>(d, tilesM, tilesN,
+                                                           xcd_remap(blockIdx.x, tilesM * tilesN * d.split));
+}
+
+// Grouped launch over many systems (FP64 operands converted while staging):
+// system b owns logical tiles [off[b], off[b+1]).
+template <int MODE, int BM, int BN, int BK, int WM, int WN, bool AKC, bool BKC>
+__global__ __launch_bounds__(WM *WN *kWave) void gemm_lowp_grouped(const GemmGroupEntry *__restrict__ e,
+                                                                    const int64_t *__restrict__ off, int n) {
+  const int b = group_find(off, n, blockIdx.x);
+  const GemmGroupEntry &g = e[b];
+  gemm_lowp_body<MODE, BM, BN, BK, WM, WN, AKC, BKC, false>(g.d, g.tilesM, g.tilesN,
+                                                            int64_t(blockIdx.x) - off[b]);
+}
+
 struct LTile {
   const char *name;
   int BM, BN, BK;
   void (*launch[4])(const GemmDesc &, int64_t, int64_t, hipStream_t);
   void (*launch_ladder)(const GemmDesc &, int64_t, int64_t, hipStream_t);
+  void (*launch_grouped[4])(const GemmGroupEntry *, const int64_t *, int, int64_t, hipStream_t);
 };
+
+template <int MODE, int BM, int BN, int BK, int WM, int WN, bool AKC, bool BKC>
+void launch_lg(const GemmGroupEntry *e, const int64_t *off, int n, int64_t blocks, hipStream_t s) {
+  hipLaunchKernelGGL((gemm_lowp_grouped<MODE, BM, BN, BK, WM, WN, AKC, BKC>), dim3(blocks),
+                     dim3(WM * WN * kWave), 0, s, e, off, n);
+}
 
 template <int MODE, int BM, int BN, int BK, int WM, int WN, bool AKC, bool BKC, int TAG = 0>
 void launch_l(const GemmDesc &d, int64_t tm, int64_t tn, hipStream_t s) {
@@ -341,7 +364,9 @@ void launch_l(const GemmDesc &d, int64_t tm, int64_t tn, hipStream_t s) {
     #BM "x" #BN "x" #BK "_w" #WM "x" #WN, BM, BN, BK,                                               \
         {&launch_l<MODE, BM, BN, BK, WM, WN, false, false>, &launch_l<MODE, BM, BN, BK, WM, WN, false, true>, \
          &launch_l<MODE, BM, BN, BK, WM, WN, true, false>, &launch_l<MODE, BM, BN, BK, WM, WN, true, true>},  \
-        &launch_l<MODE, BM, BN, BK, WM, WN, true, true, 1>                                          \
+        &launch_l<MODE, BM, BN, BK, WM, WN, true, true, 1>,                                         \
+        {&launch_lg<MODE, BM, BN, BK, WM, WN, false, false>, &launch_lg<MODE, BM, BN, BK, WM, WN, false, true>, \
+         &launch_lg<MODE, BM, BN, BK, WM, WN, true, false>, &launch_lg<MODE, BM, BN, BK, WM, WN, true, true>}  \
   }
 
 const LTile kF32Tiles[] = {
@@ -400,6 +425,25 @@ void convert_shadow(int prec, const double *src, int64_t n, void *dst, hipStream
 }
 
 int gemm_lowp_num_tiles() { return kNumL; }
+
+int gemm_lowp_pick(int prec, int64_t M, int64_t N) { return pick_l(prec == PREC_F32 ? kF32Tiles : kB3Tiles, M, N); }
+
+void gemm_lowp_tile_shape(int prec, int tile_id, int *bm, int *bn) {
+  const LTile &t = (prec == PREC_F32 ? kF32Tiles : kB3Tiles)[tile_id];
+  *bm = t.BM;
+  *bn = t.BN;
+}
+
+void gemm_lowp_grouped_launch(const GemmGroupEntry *dev_entries, const int64_t *dev_off, int n, int64_t blocks,
+                              bool akc, bool bkc, int prec, int tile_id, hipStream_t s) {
+  if (blocks <= 0) return;
+  CC_REQUIRE(prec == PREC_F32 || prec == PREC_BF16X3, -1, "grouped gemm: precision");
+  CC_REQUIRE(tile_id >= 0 && tile_id < kNumL, -7, "grouped gemm: tile");
+  CC_REQUIRE(blocks < (int64_t(1) << 31), -1, "grouped gemm: too many tiles");
+  (prec == PREC_F32 ? kF32Tiles : kB3Tiles)[tile_id].launch_grouped[(akc ? 2 : 0) + (bkc ? 1 : 0)](
+      dev_entries, dev_off, n, blocks, s);
+  CC_HIP_CHECK(hipGetLastError());
+}
 const char *gemm_lowp_tile_name(int prec, int id) {
   if (id < 0 || id >= kNumL) return "?";
   return prec == PREC_F32 ? kF32Tiles[id].name : kB3Tiles[id].name;

@@ -71,3 +71,29 @@ def test_batch_c4_shapes_run(E, ctx):
         B.step(0.0, True)
         rn, e, _ = B.scalars()
     assert all(np.isfinite(rn)) and all(x < 0 for x in e)
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
+def test_batch_reduced_precision_equals_single_system(E, ctx, prec):
+    """Grouped reduced-precision GEMMs (operands converted while staging)
+    against single-system plans (operands converted once into copies): the
+    same products in the same order, so equal to FP64 rounding of the
+    epilogues."""
+    systems = [make_system(o, v, seed) for o, v, seed in SHAPES]
+    ds = [E.DeviceSystem(s) for s in systems]
+    P = E.PRECS[prec]
+    with E.Batch(ctx, ds, E.CCSD, prec=P) as B:
+        B.autotune(1)
+        for _ in range(3):
+            B.step(0.0, True)
+        rn_b, e_b, _ = B.scalars()
+        amps_b = B.amps
+        for b, d in enumerate(ds):
+            t1, t2 = E.zeros_amps(d, E.CCSD)
+            with E.Plan(ctx, d, E.CCSD, prec=P) as p:
+                for _ in range(3):
+                    p.step(t1, t2, 0.0, True)
+                rn, e, _ = p.scalars()
+            print(f"{prec} system {b}: dE={abs(e - e_b[b]):.3e} drn={abs(rn - rn_b[b]):.3e}", flush=True)
+            assert abs(e - e_b[b]) < 1e-12 * max(1.0, abs(e)) and abs(rn - rn_b[b]) < 1e-12
+            assert (amps_b[b][1] - t2).abs().max().item() < 1e-13

@@ -95,6 +95,12 @@ typedef struct {
   int32_t dressed;     /* 0: D from the bare Fock diagonal; 1: from the diagonals of the
                           T-dressed one-body intermediates of the current iterate */
   int32_t autotune;    /* 1: run the GEMM tile autotuner before iterating (counted as setup) */
+  int32_t correction;  /* reduced prec only, 1: in the FP64 phase, evaluate each contraction that
+                          is linear in the amplitudes (one constant operand, >= 1% of the work) as
+                          a stored FP64 product at reference amplitudes plus a reduced-precision
+                          product of the change since the reference (defect correction); a new
+                          reference is taken whenever ||R|| fell 1000-fold since the last one,
+                          and convergence is confirmed by one plain FP64 step */
 } cc_iter_opts;
 
 typedef struct {
@@ -105,6 +111,7 @@ typedef struct {
   double seconds;      /* wall time of the loop (setup excluded) */
   double setup_seconds;/* plan creation: derived integral views, workspace */
   int32_t lowp_iters;  /* iterations done in reduced precision before the FP64 phase */
+  int32_t corr_iters;  /* FP64-phase iterations that used the reference + correction form */
   double *hist_rnorm;  /* host arrays of capacity hist_cap, or NULL */
   double *hist_e;      /* E per iteration (real part) */
   int32_t hist_cap;
@@ -257,6 +264,12 @@ const char *cc_plan_describe_dry(int o, int v, int method, int scalar);
 /* Precision of the contractions of the following steps (cc_prec); the
  * plan's creation precision is the initial value. */
 int cc_plan_set_precision(cc_plan *plan, int prec);
+/* Reference + correction form of the linear contractions for the following
+ * FP64 steps (see cc_iter_opts.correction): mode 0 off; mode 1 takes a
+ * reference at the next step's amplitudes and uses it from then on; prec
+ * (CC_PREC_F32 or CC_PREC_BF16X3) is the precision of the correction
+ * products.  Real systems only (EUNSUPPORTED for complex). */
+int cc_plan_set_correction(cc_plan *plan, int mode, int prec);
 /* Autotuner: times every instantiated GEMM tile configuration (of the
  * plan's current precision) for each distinct GEMM shape of the plan (reps launches each, on the plan's own
  * buffers, with t as the amplitude operand) and keeps the fastest.  Choices

@@ -89,14 +89,15 @@ void read_scalars(cc_plan *p, double *rn, double *er, double *ei) {
 // amplitude pointers and shift match the capture.
 void run_step(cc_plan *p, bool use_graph) {
   ccmi::plan_prepare(p);
-  if (!use_graph) {
+  if (!use_graph || p->delta_mode == 2) {  // a reference run is never captured
     ccmi::plan_run(p);
     return;
   }
   const bool same = p->graph && p->graph_key[0] == p->t1 && p->graph_key[1] == p->t2 &&
                     p->graph_key[2] == p->r1_out && p->graph_key[3] == p->r2_out &&
                     p->graph_shift == p->shift && p->graph_update == p->update &&
-                    p->graph_dressed == p->dressed && p->graph_prec == p->cur_prec;
+                    p->graph_dressed == p->dressed && p->graph_prec == p->cur_prec &&
+                    p->graph_delta == p->delta_mode;
   if (!same) {
     if (p->graph) (void)hipGraphExecDestroy(p->graph);
     p->graph = nullptr;
@@ -120,6 +121,7 @@ void run_step(cc_plan *p, bool use_graph) {
     p->graph_update = p->update;
     p->graph_dressed = p->dressed;
     p->graph_prec = p->cur_prec;
+    p->graph_delta = p->delta_mode;
   }
   CC_HIP_CHECK(hipGraphLaunch(p->graph, p->ctx->stream));
 }
@@ -330,13 +332,19 @@ int cc_iterate(cc_ctx *ctx, const cc_system *sys, int method, const cc_iter_opts
     validate_amps(t, method, "t");
     const auto t0 = std::chrono::steady_clock::now();
     cc_plan *p = make_plan(ctx, sys, method, opts->prec);
-    const auto t1c = std::chrono::steady_clock::now();
     int status = CC_ENOTCONV;
     int iters = 0;
     double rn = NAN, er = NAN, ei = NAN, best = INFINITY;
     int grew = 0;
     std::vector<double> seen;  // norms seen in the current precision
     int switched_at = -1;
+    int corr_iters = 0;
+    double ref_rn = INFINITY;   // norm at the last reference (correction form)
+    bool confirming = false;    // the next step is the plain FP64 confirmation
+    const bool use_corr = opts->correction != 0 && opts->prec != CC_PREC_F64 && !p->cplx &&
+                          !p->deltas.empty();
+    if (use_corr) p->delta_prec = opts->prec;
+    std::chrono::steady_clock::time_point t1c;
     try {
       p->t1 = t->t1;
       p->t2 = t->t2;
@@ -351,10 +359,20 @@ int cc_iterate(cc_ctx *ctx, const cc_system *sys, int method, const cc_iter_opts
         }
         p->cur_prec = opts->prec;
       }
+      ccmi::plan_prepare(p);
+      CC_HIP_CHECK(hipStreamSynchronize(p->ctx->stream));
+      t1c = std::chrono::steady_clock::now();
       for (int it = 0; it < opts->max_iter; ++it) {
+        const int mode_now = p->delta_mode;
         run_step(p, opts->use_graph != 0);
         ++iters;
+        if (mode_now != 0) ++corr_iters;
         read_scalars(p, &rn, &er, &ei);
+        if (mode_now == 2) {
+          ref_rn = rn;
+        } else if (mode_now == 1 && rn < 1e-3 * ref_rn) {
+          p->delta_mode = 2;  // refresh the reference at the next step
+        }
         if (rep && rep->hist_rnorm && it < rep->hist_cap) rep->hist_rnorm[it] = rn;
         if (rep && rep->hist_e && it < rep->hist_cap) rep->hist_e[it] = er;
         if (!std::isfinite(rn) || !std::isfinite(er)) {
@@ -362,8 +380,15 @@ int cc_iterate(cc_ctx *ctx, const cc_system *sys, int method, const cc_iter_opts
           break;
         }
         if (rn < opts->tol && p->cur_prec == CC_PREC_F64) {
-          status = CC_OK;
-          break;
+          if (mode_now != 1) {  // plain or reference step: an FP64 evaluation
+            status = CC_OK;
+            break;
+          }
+          // correction form reached tol: confirm with a plain FP64 step
+          p->delta_mode = 0;
+          confirming = true;
+        } else if (confirming && std::isfinite(rn)) {
+          confirming = false;  // not confirmed: stay with plain FP64 steps
         }
         if (p->cur_prec != CC_PREC_F64) {
           // refinement: leave reduced precision once the norm is below
@@ -377,6 +402,10 @@ int cc_iterate(cc_ctx *ctx, const cc_system *sys, int method, const cc_iter_opts
             switched_at = it + 1;
             best = INFINITY;
             grew = 0;
+            if (use_corr) {
+              p->delta_mode = 2;
+              ccmi::plan_prepare(p);  // reference buffers, outside any capture
+            }
           }
         }
         if (rn < best) {
@@ -400,6 +429,7 @@ int cc_iterate(cc_ctx *ctx, const cc_system *sys, int method, const cc_iter_opts
       rep->e_im = ei;
       rep->seconds = std::chrono::duration<double>(t2c - t1c).count();
       rep->lowp_iters = switched_at < 0 ? (opts->prec == CC_PREC_F64 ? 0 : iters) : switched_at;
+      rep->corr_iters = corr_iters;
       rep->setup_seconds = std::chrono::duration<double>(t1c - t0).count();
     }
     cc_plan_destroy(p);
@@ -537,6 +567,19 @@ int cc_plan_set_precision(cc_plan *p, int prec) {
   return guarded(p->ctx, [&] {
     validate_method(p->method, prec, p->cplx ? CC_C128 : CC_R64);
     p->cur_prec = prec;
+    return CC_OK;
+  });
+}
+
+int cc_plan_set_correction(cc_plan *p, int mode, int prec) {
+  if (!p) return fail(nullptr, CC_EINVAL, "plan is NULL");
+  return guarded(p->ctx, [&] {
+    if (mode != 0 && mode != 1) throw CCError(CC_EINVAL, "mode must be 0 or 1");
+    if (prec != CC_PREC_F32 && prec != CC_PREC_BF16X3)
+      throw CCError(CC_EINVAL, "correction precision must be F32 or BF16X3");
+    if (p->cplx) throw CCError(CC_EUNSUPPORTED, "correction form is real-only");
+    p->delta_prec = prec;
+    p->delta_mode = mode ? 2 : 0;
     return CC_OK;
   });
 }

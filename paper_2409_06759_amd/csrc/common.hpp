@@ -61,6 +61,11 @@ struct GemmDesc {
 
 // FP64 tensor -> reduced-precision shadow with the same element indexing.
 void convert_shadow(int prec, const double *src, int64_t n, void *dst, hipStream_t s);
+// dst = reduced-precision (a - ref), same layout as convert_shadow.
+void convert_delta(int prec, const double *a, const double *ref, int64_t n, void *dst, hipStream_t s);
+void copy_f64(double *dst, const double *src, int64_t n, hipStream_t s);
+// C = beta C + P with P dense M x N and C of leading dimension ldc.
+void add_product(double *C, int64_t ldc, double beta, const double *P, int64_t M, int64_t N, hipStream_t s);
 
 enum Prec { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16X3 = 2 };
 

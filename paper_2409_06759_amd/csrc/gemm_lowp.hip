@@ -412,7 +412,65 @@ __global__ __launch_bounds__(256) void to_bf16x2_kernel(const double *__restrict
   }
 }
 
+__global__ __launch_bounds__(256) void delta_f32_kernel(const double *__restrict__ a, const double *__restrict__ ref,
+                                                        int64_t n, float *__restrict__ dst) {
+  for (int64_t e = blockIdx.x * int64_t(256) + threadIdx.x; e < n; e += int64_t(gridDim.x) * 256)
+    dst[e] = static_cast<float>(a[e] - ref[e]);
+}
+
+__global__ __launch_bounds__(256) void delta_bf16x2_kernel(const double *__restrict__ a,
+                                                           const double *__restrict__ ref, int64_t n,
+                                                           unsigned short *__restrict__ hi) {
+  unsigned short *__restrict__ lo = hi + n;
+  for (int64_t e = blockIdx.x * int64_t(256) + threadIdx.x; e < n; e += int64_t(gridDim.x) * 256) {
+    const float x = static_cast<float>(a[e] - ref[e]);
+    const unsigned short h = bf16_bits(x);
+    hi[e] = h;
+    lo[e] = bf16_bits(x - bf16_to_float(h));
+  }
+}
+
+__global__ __launch_bounds__(256) void copy_f64_kernel(const double *__restrict__ src, int64_t n,
+                                                       double *__restrict__ dst) {
+  for (int64_t e = blockIdx.x * int64_t(256) + threadIdx.x; e < n; e += int64_t(gridDim.x) * 256) dst[e] = src[e];
+}
+
+// C[m][n] = beta C[m][n] + P[m][n]   (P dense M x N; C not read when beta = 0)
+__global__ __launch_bounds__(256) void add_product_kernel(double *__restrict__ C, int64_t ldc, double beta,
+                                                          const double *__restrict__ P, int64_t M, int64_t N) {
+  const int64_t total = M * N;
+  for (int64_t e = blockIdx.x * int64_t(256) + threadIdx.x; e < total; e += int64_t(gridDim.x) * 256) {
+    const int64_t m = e / N, c = e % N;
+    double *q = C + m * ldc + c;
+    *q = (beta == 0.0) ? P[e] : beta * *q + P[e];
+  }
+}
+
+int64_t ew_blocks(int64_t n) { return std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 65536)); }
+
 }  // namespace
+
+void convert_delta(int prec, const double *a, const double *ref, int64_t n, void *dst, hipStream_t s) {
+  if (n <= 0) return;
+  if (prec == PREC_F32)
+    hipLaunchKernelGGL(delta_f32_kernel, dim3(ew_blocks(n)), dim3(256), 0, s, a, ref, n, static_cast<float *>(dst));
+  else
+    hipLaunchKernelGGL(delta_bf16x2_kernel, dim3(ew_blocks(n)), dim3(256), 0, s, a, ref, n,
+                       static_cast<unsigned short *>(dst));
+  CC_HIP_CHECK(hipGetLastError());
+}
+
+void copy_f64(double *dst, const double *src, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(copy_f64_kernel, dim3(ew_blocks(n)), dim3(256), 0, s, src, n, dst);
+  CC_HIP_CHECK(hipGetLastError());
+}
+
+void add_product(double *C, int64_t ldc, double beta, const double *P, int64_t M, int64_t N, hipStream_t s) {
+  if (M <= 0 || N <= 0) return;
+  hipLaunchKernelGGL(add_product_kernel, dim3(ew_blocks(M * N)), dim3(256), 0, s, C, ldc, beta, P, M, N);
+  CC_HIP_CHECK(hipGetLastError());
+}
 
 void convert_shadow(int prec, const double *src, int64_t n, void *dst, hipStream_t s) {
   if (n <= 0) return;

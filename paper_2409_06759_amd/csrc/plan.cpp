@@ -533,6 +533,47 @@ void invalidate(cc_plan *p, int sl) {
   if (sl >= 0 && !p->shadow_ok.empty()) p->shadow_ok[sl] = 0;
 }
 
+// Mode 2: store X_ref and alpha X_ref Y (FP64), then C = beta C + that.
+// Mode 1: C = beta C + alpha X_ref Y + alpha (X - X_ref) Y, the last product
+// in reduced precision; its rounding error scales with |X - X_ref|.
+void run_delta_gemm(cc_plan *p, GemmDesc &d, const Step &st, hipStream_t s) {
+  DeltaRef &r = p->deltas[st.delta];
+  CC_REQUIRE(r.ref_op && r.ref_out && r.dshadow, CC_EINTERNAL, "reference buffers not prepared");
+  const int var_slot = r.var ? st.b : st.a, con_slot = r.var ? st.a : st.b;
+  const double *X = static_cast<const double *>(ptr_of(p, var_slot));
+  double *C = static_cast<double *>(d.C);
+  if (p->delta_mode == 2) {
+    copy_f64(r.ref_op, X, r.n_op, s);
+    GemmDesc g = d;
+    g.C = r.ref_out;
+    g.ldc = d.N;
+    g.beta = 0.0;
+    gemm_f64(g, s, st.tile);
+    add_product(C, d.ldc, d.beta, r.ref_out, d.M, d.N, s);
+    return;
+  }
+  CC_REQUIRE(p->shadow.size() == p->slots.size() && p->shadow[con_slot] &&
+                 p->shadow_prec[con_slot] == p->delta_prec,
+             CC_EINTERNAL, "constant operand copy not prepared");
+  convert_delta(p->delta_prec, X, r.ref_op, r.n_op, r.dshadow, s);
+  add_product(C, d.ldc, d.beta, r.ref_out, d.M, d.N, s);
+  GemmDesc g = d;
+  if (r.var) {
+    g.B = r.dshadow;
+    g.b_plane = r.n_op;
+    g.A = p->shadow[con_slot];
+    g.a_plane = slot_elems(p, con_slot);
+  } else {
+    g.A = r.dshadow;
+    g.a_plane = r.n_op;
+    g.B = p->shadow[con_slot];
+    g.b_plane = slot_elems(p, con_slot);
+  }
+  g.lp_in = 1;
+  g.beta = 1.0;
+  gemm_lowp(g, p->delta_prec, s, st.tile_lp[p->delta_prec]);
+}
+
 }  // namespace
 
 // Reduced-precision runs read each GEMM operand from a 4-byte-per-element
@@ -541,7 +582,11 @@ void invalidate(cc_plan *p, int sl) {
 // write.  Allocation and the constant conversions happen here, outside any
 // graph capture.
 void plan_prepare(cc_plan *p) {
-  if (p->cplx || p->cur_prec == PREC_F64) return;
+  if (p->cplx) return;
+  const bool lowp = p->cur_prec != PREC_F64;
+  const bool delta = !lowp && p->delta_mode != 0 && !p->deltas.empty();
+  if (!lowp && !delta) return;
+  const int prec = lowp ? p->cur_prec : p->delta_prec;
   const size_t n = p->slots.size();
   if (p->shadow.size() != n) {
     p->shadow.assign(n, nullptr);
@@ -550,17 +595,25 @@ void plan_prepare(cc_plan *p) {
   }
   hipStream_t s = p->ctx->stream;
   for (const Step &st : p->iter) {
-    if (st.kind != Step::GEMM) continue;
+    if (st.kind != Step::GEMM || (!lowp && st.delta < 0)) continue;
     for (int sl : {st.a, st.b}) {
+      if (!lowp && !p->slots[sl].constant) continue;  // the correction reads its own copy
       if (!p->shadow[sl]) {
         CC_HIP_CHECK(hipMalloc(&p->shadow[sl], size_t(slot_elems(p, sl)) * 4));
         p->shadow_prec[sl] = -1;
       }
-      if (p->slots[sl].constant && p->shadow_prec[sl] != p->cur_prec) {
-        convert_shadow(p->cur_prec, static_cast<const double *>(ptr_of(p, sl)), slot_elems(p, sl),
-                       p->shadow[sl], s);
-        p->shadow_prec[sl] = p->cur_prec;
+      if (p->slots[sl].constant && p->shadow_prec[sl] != prec) {
+        convert_shadow(prec, static_cast<const double *>(ptr_of(p, sl)), slot_elems(p, sl), p->shadow[sl], s);
+        p->shadow_prec[sl] = prec;
       }
+    }
+  }
+  if (delta) {
+    for (DeltaRef &d : p->deltas) {
+      const GemmDesc &g = p->iter[d.step].gemm;
+      if (!d.ref_op) CC_HIP_CHECK(hipMalloc(reinterpret_cast<void **>(&d.ref_op), size_t(d.n_op) * 8));
+      if (!d.ref_out) CC_HIP_CHECK(hipMalloc(reinterpret_cast<void **>(&d.ref_out), size_t(g.M) * g.N * 8));
+      if (!d.dshadow) CC_HIP_CHECK(hipMalloc(&d.dshadow, size_t(d.n_op) * 4));
     }
   }
 }
@@ -611,7 +664,8 @@ void exec(cc_plan *p, Step &st, hipStream_t s) {
       d.B = ptr_of(p, st.b);
       d.C = ptr_of(p, st.c);
       d.ws = st.b2 >= 0 ? ptr_of(p, st.b2) : nullptr;
-      run_gemm(p, d, st, s);
+      if (st.delta >= 0 && p->delta_mode != 0 && !cplx && p->cur_prec == PREC_F64) run_delta_gemm(p, d, st, s);
+      else run_gemm(p, d, st, s);
       break;
     }
     case Step::OUTER:
@@ -671,6 +725,22 @@ void plan_build(cc_plan *p, const cc_system *sys) {
   CC_HIP_CHECK(hipStreamSynchronize(s));
   for (Step &st : p->iter)
     if (st.kind == Step::GEMM) p->gemm_steps.push_back(&st);
+  // contractions linear in the amplitudes worth a reference + correction
+  // evaluation: one constant operand and at least 1% of the iteration's work
+  if (!p->cplx) {
+    for (size_t k = 0; k < p->iter.size(); ++k) {
+      Step &st = p->iter[k];
+      if (st.kind != Step::GEMM || st.flops < 0.01 * p->flops_per_iter) continue;
+      const bool ca = p->slots[st.a].constant, cb = p->slots[st.b].constant;
+      if (ca == cb) continue;
+      DeltaRef d;
+      d.step = int(k);
+      d.var = ca ? 1 : 0;
+      d.n_op = slot_elems(p, ca ? st.b : st.a);
+      st.delta = int(p->deltas.size());
+      p->deltas.push_back(d);
+    }
+  }
 }
 
 void plan_free(cc_plan *p) {
@@ -683,19 +753,33 @@ void plan_free(cc_plan *p) {
   for (void *q : p->shadow)
     if (q) (void)hipFree(q);
   p->shadow.clear();
+  for (DeltaRef &d : p->deltas) {
+    for (void *q : {static_cast<void *>(d.ref_op), static_cast<void *>(d.ref_out), d.dshadow})
+      if (q) (void)hipFree(q);
+    d.ref_op = d.ref_out = nullptr;
+    d.dshadow = nullptr;
+  }
   for (double *q : {p->d_oo, p->d_vv, p->epart, p->n2part, p->n1part, p->scalars})
     if (q) (void)hipFree(q);
 }
 
 void plan_run(cc_plan *p) {
   hipStream_t s = p->ctx->stream;
-  if (!p->cplx && p->cur_prec != PREC_F64) {
+  if (!p->cplx) {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     CC_HIP_CHECK(hipStreamIsCapturing(s, &cs));
     if (cs == hipStreamCaptureStatusNone) plan_prepare(p);
+  }
+  if (!p->cplx && p->cur_prec != PREC_F64) {
     CC_REQUIRE(p->shadow.size() == p->slots.size(), CC_EINTERNAL, "operand copies not prepared");
     for (size_t i = 0; i < p->slots.size(); ++i)
       p->shadow_ok[i] = p->slots[i].constant && p->shadow_prec[i] == p->cur_prec;
+  }
+  if (p->delta_mode == 2 && !p->cplx && p->cur_prec == PREC_F64 && !p->deltas.empty()) {
+    // this run stores the reference; the following ones correct it
+    for (Step &st : p->iter) exec(p, st, s);
+    p->delta_mode = 1;
+    return;
   }
   if (!p->profiling) {
     for (Step &st : p->iter) exec(p, st, s);

@@ -51,9 +51,22 @@ struct Step {
   int tile = -1;        // FP64 tile
   int tile_lp[3] = {-1, -1, -1};  // per reduced precision (index = cc_prec)
   int tile_z = -1;      // complex128 tile
+  int delta = -1;       // index into cc_plan::deltas (GEMM linear in the amplitudes)
   int64_t nelem = 0;
   double flops = 0.0;
   std::string tag;
+};
+
+// A contraction with one constant operand, evaluated as a stored FP64
+// product at reference amplitudes plus a reduced-precision product of the
+// change since the reference: C = beta C + alpha X_ref Y + alpha (X - X_ref) Y.
+struct DeltaRef {
+  int step = -1;
+  int var = 0;                    // 0: A varies, 1: B varies
+  int64_t n_op = 0;               // elements of the varying operand's slot
+  double *ref_op = nullptr;       // FP64 copy of the varying operand at the reference
+  double *ref_out = nullptr;      // alpha * X_ref Y, dense M x N
+  void *dshadow = nullptr;        // reduced-precision (X - X_ref)
 };
 
 }  // namespace ccmi
@@ -98,6 +111,12 @@ struct cc_plan {
   std::vector<void *> shadow;
   std::vector<int> shadow_prec;   // precision held by a constant slot's copy
   std::vector<char> shadow_ok;    // copy matches the slot in the current run
+  // reference + correction mode of the FP64 contractions (0 off, 1 use the
+  // stored reference, 2 take a new reference in the next run)
+  int delta_mode = 0;
+  int delta_prec = 1;             // precision of the correction products
+  std::vector<ccmi::DeltaRef> deltas;
+  int graph_delta = -1;
 };
 
 namespace ccmi {

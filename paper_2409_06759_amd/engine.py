@@ -147,6 +147,11 @@ class Plan:
     def set_precision(self, prec: int):
         self.ctx.check(self.ctx.lib.cc_plan_set_precision(self.h, prec))
 
+    def set_correction(self, mode: int, prec: int = F32):
+        """1: the next FP64 step takes a reference, later ones add a
+        reduced-precision correction to it (cc_plan_set_correction)."""
+        self.ctx.check(self.ctx.lib.cc_plan_set_correction(self.h, mode, prec))
+
     def profile(self, enable: bool = True):
         self.ctx.check(self.ctx.lib.cc_plan_profile(self.h, 1 if enable else 0))
 
@@ -195,13 +200,17 @@ def energy(ctx, dsys, method, t1, t2):
 
 def iterate(ctx, dsys, method, t1, t2, tol=1e-8, max_iter=100, level_shift=0.0, prec=F64,
             use_graph=True, refine_tol=0.0, diverge_window=0, hist_cap=None, dressed=False,
-            autotune=False):
+            autotune=False, correction=True):
+    """Jacobi iteration (cc_iterate).  Reduced `prec` runs its contractions in
+    that precision until the norm stagnates, then finishes with FP64 steps
+    (with `correction`, in reference + reduced-precision-correction form for
+    the contractions linear in the amplitudes)."""
     cap = hist_cap or max_iter
     hr = (C.c_double * cap)()
     he = (C.c_double * cap)()
     opts = L.CCIterOpts(tol, max_iter, prec, level_shift, refine_tol, 1 if use_graph else 0, 1,
-                        diverge_window, 1 if dressed else 0, 1 if autotune else 0)
-    rep = L.CCIterReport(0, 0, 0.0, 0.0, 0.0, 0.0, 0.0, 0, C.cast(hr, C.POINTER(C.c_double)),
+                        diverge_window, 1 if dressed else 0, 1 if autotune else 0, 1 if correction else 0)
+    rep = L.CCIterReport(0, 0, 0.0, 0.0, 0.0, 0.0, 0.0, 0, 0, C.cast(hr, C.POINTER(C.c_double)),
                          C.cast(he, C.POINTER(C.c_double)), cap)
     ctx.enter()
     rc = ctx.lib.cc_iterate(ctx.h, C.byref(dsys.struct), method, C.byref(opts), C.byref(_amps(t1, t2)),
@@ -211,6 +220,7 @@ def iterate(ctx, dsys, method, t1, t2, tol=1e-8, max_iter=100, level_shift=0.0, 
     return {"status": rc, "iters": rep.iters, "converged": bool(rep.converged), "rnorm": rep.rnorm,
             "energy": complex(rep.e_re, rep.e_im) if dsys.is_complex else rep.e_re,
             "seconds": rep.seconds, "setup_seconds": rep.setup_seconds, "lowp_iters": rep.lowp_iters,
+            "corr_iters": rep.corr_iters,
             "hist_rnorm": list(hr[:n]), "hist_e": list(he[:n])}
 
 
@@ -269,7 +279,7 @@ class Batch:
 
     def iterate(self, tol=1e-8, max_iter=200, level_shift=0.0, dressed=False, prec=F64, use_graph=True):
         opts = L.CCIterOpts(tol, max_iter, prec, level_shift, 0.0, 1 if use_graph else 0, 1, 0,
-                            1 if dressed else 0, 0)
+                            1 if dressed else 0, 0, 0)
         reps = (L.CCIterReport * self.n)()
         nconv = C.c_int32()
         self.ctx.enter()

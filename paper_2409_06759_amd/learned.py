@@ -91,31 +91,46 @@ def guess_with_fallback(ctx, plan, dsys, mlp):
     return m1, m2, "mp2", rn_mlp, rn_mp2, t_inf
 
 
-def evaluate(ctx, mlp, o=32, v=160, seed=BASE_SEED, tol=1e-8, max_iter=1000, log=None):
-    """Iterations and time to ||R|| < tol from the network's guess and from MP2."""
+def evaluate(ctx, mlp, o=32, v=160, seed=BASE_SEED, tol=1e-8, max_iter=1000, precs=("f64",), log=None):
+    """Iterations and time to ||R|| < tol from the network's guess and from
+    MP2, for each contraction precision in `precs` (reduced ones finish in
+    FP64).  Times include the guess (network inference, or the MP2 step)."""
     s = make_system(o, v, seed)
     d = E.DeviceSystem(s, drop_host=True)
-    res = {}
+    res = {"o": o, "v": v}
     with E.Plan(ctx, d, E.CCSD) as plan:
         t1, t2, src, rn_mlp, rn_mp2, t_inf = guess_with_fallback(ctx, plan, d, mlp)
-        for name in ("mlp", "mp2"):
-            if name == "mlp":
+        del t1, t2
+        for pname in precs:
+            for name in ("mlp", "mp2"):
                 a1, a2 = E.zeros_amps(d, E.CCSD)
-                mlp.guess(d, a1, a2)
-            else:
-                a1, a2 = mp2_guess(plan, d)
-            out = E.iterate(ctx, d, E.CCSD, a1, a2, tol=tol, max_iter=max_iter, dressed=True)
-            res[name] = {"iterations": out["iters"], "seconds": out["seconds"], "energy": out["energy"],
-                         "converged": out["converged"]}
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                if name == "mlp":
+                    mlp.guess(d, a1, a2)
+                else:
+                    plan.step(a1, a2, 0.0, False)
+                    a1.zero_()
+                torch.cuda.synchronize()
+                t_guess = time.perf_counter() - t0
+                out = E.iterate(ctx, d, E.CCSD, a1, a2, tol=tol, max_iter=max_iter, dressed=True,
+                                prec=E.PRECS[pname], autotune=True)
+                res.setdefault(pname, {})[name] = {
+                    "iterations": out["iters"], "reduced_precision_iterations": out["lowp_iters"],
+                    "seconds": out["seconds"] + t_guess, "guess_seconds": t_guess, "energy": out["energy"],
+                    "converged": out["converged"]}
+                if log:
+                    log(f"[learned] o={o} v={v} {pname} from {name} guess: {out['iters']} it, "
+                        f"{out['seconds'] + t_guess:.2f}s (guess {t_guess * 1e3:.1f} ms), E={out['energy']:.10f}")
     res["inference_seconds"] = t_inf
     res["rnorm_guess"] = {"mlp": rn_mlp, "mp2": rn_mp2}
     res["chosen"] = src
-    res["iterations_saved"] = res["mp2"]["iterations"] - res["mlp"]["iterations"]
-    res["speedup_vs_mp2"] = res["mp2"]["seconds"] / (res["mlp"]["seconds"] + t_inf)
+    base = res[precs[0]]
+    res["mlp"], res["mp2"] = base["mlp"], base["mp2"]
+    res["iterations_saved"] = base["mp2"]["iterations"] - base["mlp"]["iterations"]
+    res["speedup_vs_mp2"] = base["mp2"]["seconds"] / base["mlp"]["seconds"]
     if log:
-        log(f"[learned] o={o} v={v}: MLP guess {res['mlp']['iterations']} it / {res['mlp']['seconds']:.2f}s "
-            f"(+{t_inf * 1e3:.1f} ms inference), MP2 guess {res['mp2']['iterations']} it / "
-            f"{res['mp2']['seconds']:.2f}s; ||R|| guess mlp {rn_mlp:.3e} mp2 {rn_mp2:.3e}")
+        log(f"[learned] ||R|| of the guess: mlp {rn_mlp:.3e}, mp2 {rn_mp2:.3e}; inference {t_inf * 1e3:.1f} ms")
     return res
 
 
@@ -129,10 +144,12 @@ def main(argv=None):
     tr.add_argument("--lr", type=float, default=1e-3)
     tr.add_argument("--out", required=True)
     tr.add_argument("--eval", action="store_true", help="evaluate on o=32 v=160 after training")
+    tr.add_argument("--precs", default="f64", help="contraction precisions of the evaluation")
     ev = sub.add_parser("eval")
     ev.add_argument("--params", required=True)
     ev.add_argument("--o", type=int, default=32)
     ev.add_argument("--v", type=int, default=160)
+    ev.add_argument("--precs", default="f64")
     args = ap.parse_args(argv)
     log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
     ctx = E.Context(0)
@@ -145,11 +162,11 @@ def main(argv=None):
         summary = {"systems": args.systems, "samples": int(raw.shape[0]), "data_seconds": t_gen,
                    "loss_per_epoch": hist, "stats": mlp.stats}
         if args.eval:
-            summary["eval"] = evaluate(ctx, mlp, log=log)
+            summary["eval"] = evaluate(ctx, mlp, precs=tuple(args.precs.split(",")), log=log)
         print(json.dumps(summary))
     else:
         mlp = E.MLP.load(ctx, args.params)
-        print(json.dumps(evaluate(ctx, mlp, o=args.o, v=args.v, log=log)))
+        print(json.dumps(evaluate(ctx, mlp, o=args.o, v=args.v, precs=tuple(args.precs.split(",")), log=log)))
 
 
 if __name__ == "__main__":

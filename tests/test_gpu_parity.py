@@ -275,7 +275,55 @@ def test_mixed_precision_refines_to_fp64_solution(E, ctx, prec):
     ref = jacobi(F, V, "ccsd", tol=1e-11, max_iter=100, dressed=True)
     d = E.DeviceSystem(s)
     t1, t2 = E.zeros_amps(d, E.CCSD)
-    out = E.iterate(ctx, d, E.CCSD, t1, t2, tol=1e-10, max_iter=100, prec=E.PRECS[prec], dressed=True)
-    assert out["converged"]
-    assert 0 < out["lowp_iters"] < out["iters"]
-    assert abs(out["energy"] - ref["energy"]) < 1e-10
+    for corr in (False, True):
+        t1, t2 = E.zeros_amps(d, E.CCSD)
+        out = E.iterate(ctx, d, E.CCSD, t1, t2, tol=1e-10, max_iter=100, prec=E.PRECS[prec], dressed=True,
+                        correction=corr)
+        print(f"{prec} correction={corr}: {out['iters']} it, {out['lowp_iters']} reduced, "
+              f"{out['corr_iters']} corrected, dE={abs(out['energy'] - ref['energy']):.2e}", flush=True)
+        assert out["converged"]
+        assert 0 < out["lowp_iters"] < out["iters"]
+        assert (out["corr_iters"] > 0) == corr
+        assert abs(out["energy"] - ref["energy"]) < 1e-10
+
+
+@pytest.mark.parametrize("prec,eps", [("f32", 2.0 ** -24), ("bf16x3", 2.0 ** -16)])
+def test_correction_form_error_scales_with_the_change(E, ctx, prec, eps):
+    """Reference + correction: at the reference amplitudes the residual is
+    the FP64 one; at t_ref + delta its error is about eps * |delta| terms,
+    far below the plain reduced-precision residual's error."""
+    o, v = 6, 28
+    s = make_system(o, v, 41)
+    d = E.DeviceSystem(s)
+    rng = np.random.default_rng(9)
+
+    def amps(scale):
+        a1 = rng.normal(size=(o, v)) * scale
+        a2 = rng.normal(size=(o, o, v, v)) * scale
+        a2 = a2 - a2.transpose(1, 0, 2, 3)
+        a2 = a2 - a2.transpose(0, 1, 3, 2)
+        return a1, a2
+
+    r1, r2 = amps(0.05)
+    d1, d2 = amps(1e-6)
+    t_ref = [torch.from_numpy(x).cuda() for x in (r1, r2)]
+    t_new = [torch.from_numpy(x).cuda() for x in (r1 + d1, r2 + d2)]
+
+    def res(plan, t):
+        q1, q2, _ = plan.residual(t[0], t[1])
+        return torch.cat([q1.flatten(), q2.flatten()]).cpu().numpy()
+
+    with E.Plan(ctx, d, E.CCSD) as p64:
+        exact_ref, exact_new = res(p64, t_ref), res(p64, t_new)
+    with E.Plan(ctx, d, E.CCSD, prec=E.PRECS[prec]) as p:
+        plain_err = np.abs(res(p, t_new) - exact_new).max()
+        p.set_precision(E.F64)
+        p.set_correction(1, E.PRECS[prec])
+        at_ref = res(p, t_ref)      # stores the reference
+        corrected = res(p, t_new)   # reference + correction
+    scale = np.abs(exact_new).max()
+    print(f"{prec}: plain {plain_err:.2e}, at ref {np.abs(at_ref - exact_ref).max():.2e}, "
+          f"corrected {np.abs(corrected - exact_new).max():.2e} (|R| {scale:.2e})", flush=True)
+    assert np.abs(at_ref - exact_ref).max() < 1e-13 * max(1.0, scale)
+    assert np.abs(corrected - exact_new).max() < 1e-3 * plain_err
+    assert np.abs(corrected - exact_new).max() < 1e3 * eps * 1e-6 * max(1.0, scale)

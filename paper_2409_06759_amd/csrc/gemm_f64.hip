@@ -49,7 +49,7 @@ template <int BM, int BN, int BK, int WM, int WN, bool AKC, bool BKC>
 __device__ __forceinline__ void gemm_f64_body(const GemmDesc &d, int64_t tilesM, int64_t tilesN,
                                               int64_t L0) {
   using C = Cfg<BM, BN, BK, WM, WN, AKC, BKC>;
-  __shared__ double smem[2 * (C::A_ELEMS + C::B_ELEMS)];
+  __shared__ __attribute__((aligned(16))) double smem[2 * (C::A_ELEMS + C::B_ELEMS)];
   // buffer b of A at smem + b*A_ELEMS, of B at smem + 2*A_ELEMS + b*B_ELEMS
 
   const int64_t tiles = tilesM * tilesN;
@@ -69,40 +69,58 @@ __device__ __forceinline__ void gemm_f64_body(const GemmDesc &d, int64_t tilesM,
   A += kb * d.sak;
   B += kb * d.sbk;
 
-  double ra[C::LA], rb[C::LB];
+  // Global -> register staging in 16-byte vectors (two doubles along the
+  // unit-stride dimension) when the strides and base allow it; otherwise the
+  // same vectors are assembled element by element.  Out-of-range elements are 0.
+  constexpr int AR = AKC ? BM : BK, AC = AKC ? BK : BM, BR = BKC ? BN : BK, BC = BKC ? BK : BN;
+  constexpr int ANV = AR * AC / 2, BNV = BR * BC / 2;
+  constexpr int AVT = (ANV + C::NT - 1) / C::NT, BVT = (BNV + C::NT - 1) / C::NT;
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  d2 ra[AVT], rb[BVT];
+  const bool vec_a = ((AKC ? d.sam : d.sak) % 2 == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
+  const bool vec_b = ((BKC ? d.sbn : d.sbk) % 2 == 0) && ((reinterpret_cast<uintptr_t>(B) & 15) == 0);
 
+  auto vload = [&](const double *base, int64_t rstride, int64_t r_lim, int64_t c_lim, int64_t r0, int64_t c0,
+                   bool vec_ok, int v, int ncolv) -> d2 {
+    const int rr = v / ncolv, cc = (v % ncolv) * 2;
+    const int64_t gr = r0 + rr, gc = c0 + cc;
+    const double *src = base + gr * rstride + gc;
+    if (vec_ok && gr < r_lim && gc + 2 <= c_lim) return *reinterpret_cast<const d2 *>(src);
+    d2 t;
+    t.x = (gr < r_lim && gc < c_lim) ? src[0] : 0.0;
+    t.y = (gr < r_lim && gc + 1 < c_lim) ? src[1] : 0.0;
+    return t;
+  };
   auto gload = [&](int64_t k0) {
 #pragma unroll
-    for (int i = 0; i < C::LA; ++i) {
-      const int e = tid + i * C::NT;
-      int mm, kk;
-      if (AKC) { mm = e / BK; kk = e % BK; } else { kk = e / BM; mm = e % BM; }
-      const int64_t gm = m0 + mm, gk = k0 + kk;
-      ra[i] = (gm < M && gk < K) ? A[gm * d.sam + gk * d.sak] : 0.0;
+    for (int i = 0; i < AVT; ++i) {
+      const int v = tid + i * C::NT;
+      if (ANV % C::NT == 0 || v < ANV)
+        ra[i] = AKC ? vload(A, d.sam, M, K, m0, k0, vec_a, v, AC / 2) : vload(A, d.sak, K, M, k0, m0, vec_a, v, AC / 2);
     }
 #pragma unroll
-    for (int i = 0; i < C::LB; ++i) {
-      const int e = tid + i * C::NT;
-      int nn, kk;
-      if (BKC) { nn = e / BK; kk = e % BK; } else { kk = e / BN; nn = e % BN; }
-      const int64_t gn = n0 + nn, gk = k0 + kk;
-      rb[i] = (gn < N && gk < K) ? B[gn * d.sbn + gk * d.sbk] : 0.0;
+    for (int i = 0; i < BVT; ++i) {
+      const int v = tid + i * C::NT;
+      if (BNV % C::NT == 0 || v < BNV)
+        rb[i] = BKC ? vload(B, d.sbn, N, K, n0, k0, vec_b, v, BC / 2) : vload(B, d.sbk, K, N, k0, n0, vec_b, v, BC / 2);
     }
   };
   auto sstore = [&](int buf) {
 #pragma unroll
-    for (int i = 0; i < C::LA; ++i) {
-      const int e = tid + i * C::NT;
-      double *as = smem + buf * C::A_ELEMS;
-      if (AKC) as[(e / BK) * C::A_LD + (e % BK)] = ra[i];
-      else as[(e / BM) * C::A_LD + (e % BM)] = ra[i];
+    for (int i = 0; i < AVT; ++i) {
+      const int v = tid + i * C::NT;
+      if (ANV % C::NT == 0 || v < ANV) {
+        const int rr = v / (AC / 2), cc = (v % (AC / 2)) * 2;
+        *reinterpret_cast<d2 *>(smem + buf * C::A_ELEMS + rr * C::A_LD + cc) = ra[i];
+      }
     }
 #pragma unroll
-    for (int i = 0; i < C::LB; ++i) {
-      const int e = tid + i * C::NT;
-      double *bs = smem + 2 * C::A_ELEMS + buf * C::B_ELEMS;
-      if (BKC) bs[(e / BK) * C::B_LD + (e % BK)] = rb[i];
-      else bs[(e / BN) * C::B_LD + (e % BN)] = rb[i];
+    for (int i = 0; i < BVT; ++i) {
+      const int v = tid + i * C::NT;
+      if (BNV % C::NT == 0 || v < BNV) {
+        const int rr = v / (BC / 2), cc = (v % (BC / 2)) * 2;
+        *reinterpret_cast<d2 *>(smem + 2 * C::A_ELEMS + buf * C::B_ELEMS + rr * C::B_LD + cc) = rb[i];
+      }
     }
   };
 
@@ -235,6 +253,9 @@ const TileInfo kTiles[] = {
     CC_TILE(128, 64, 16, 2, 2),
     CC_TILE(64, 128, 16, 2, 2),
     CC_TILE(128, 128, 32, 2, 2),
+    CC_TILE(64, 64, 32, 2, 2),
+    CC_TILE(128, 64, 32, 2, 2),
+    CC_TILE(64, 128, 32, 2, 2),
 };
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 

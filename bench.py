@@ -257,7 +257,7 @@ def main():
                 f"({out['lowp_iters']} reduced), E={out['energy']:.10f}")
 
     extras = {}
-    for name in [x for x in args.extras.split(",") if x]:
+    for name in [x for x in args.extras.split(",") if x and x != "none"]:
         if name == "batched":
             extras["batched"] = bench_batched(ctx, E, torch, max(args.steps, 5), args.warmup)
         elif name == "complex":

@@ -373,13 +373,15 @@ const LTile kF32Tiles[] = {
     CC_LTILE(PREC_F32, 128, 128, 16, 2, 2), CC_LTILE(PREC_F32, 64, 64, 16, 2, 2),
     CC_LTILE(PREC_F32, 32, 32, 16, 2, 2),   CC_LTILE(PREC_F32, 128, 64, 16, 2, 2),
     CC_LTILE(PREC_F32, 64, 128, 16, 2, 2),  CC_LTILE(PREC_F32, 128, 128, 32, 2, 2),
+    CC_LTILE(PREC_F32, 128, 128, 16, 4, 2), CC_LTILE(PREC_F32, 128, 128, 32, 4, 2),
 };
 const LTile kB3Tiles[] = {
     CC_LTILE(PREC_BF16X3, 128, 128, 32, 2, 2), CC_LTILE(PREC_BF16X3, 64, 64, 32, 2, 2),
     CC_LTILE(PREC_BF16X3, 32, 32, 32, 2, 2),   CC_LTILE(PREC_BF16X3, 128, 64, 32, 2, 2),
     CC_LTILE(PREC_BF16X3, 64, 128, 32, 2, 2),  CC_LTILE(PREC_BF16X3, 128, 128, 64, 2, 2),
+    CC_LTILE(PREC_BF16X3, 128, 128, 32, 4, 2), CC_LTILE(PREC_BF16X3, 256, 128, 32, 4, 2),
 };
-constexpr int kNumL = 6;
+constexpr int kNumL = 8;
 
 int pick_l(const LTile *tiles, int64_t M, int64_t N) {
   int best = 0;

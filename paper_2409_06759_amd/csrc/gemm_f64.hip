@@ -256,6 +256,11 @@ const TileInfo kTiles[] = {
     CC_TILE(64, 64, 32, 2, 2),
     CC_TILE(128, 64, 32, 2, 2),
     CC_TILE(64, 128, 32, 2, 2),
+    CC_TILE(128, 128, 16, 4, 2),
+    CC_TILE(128, 64, 16, 4, 2),
+    CC_TILE(64, 128, 16, 2, 4),
+    CC_TILE(128, 128, 16, 4, 4),
+    CC_TILE(256, 64, 16, 8, 2),
 };
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 

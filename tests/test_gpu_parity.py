@@ -5,6 +5,9 @@ Tolerances (FP64 everywhere): residual elements agree to 1e-12 absolute
 MFMA tiles); energies along a Jacobi trajectory agree to 1e-12 Eh; the
 residual's (ij) and (ab) antisymmetry holds bitwise.
 """
+import json
+import pathlib
+
 import numpy as np
 import pytest
 
@@ -149,6 +152,10 @@ def test_ccd_c1_trajectory(E, ctx):
     _, d2 = denominators(F)
     g = V.get("oovv")
     assert abs(out["hist_e"][1] - 0.25 * np.sum(g * g / d2)) < 1e-13
+    # the stored oracle trajectory (tests/golden, written from the oracle alone)
+    gold = json.loads((pathlib.Path(__file__).resolve().parent / "golden" / "c1_ccd_trajectory.json").read_text())
+    assert np.allclose(out["hist_e"], gold["hist_e"], rtol=0, atol=1e-12)
+    assert np.allclose(out["hist_rnorm"], gold["hist_rnorm"], rtol=1e-10, atol=1e-14)
 
 
 def test_ccsd_converges_like_oracle(E, ctx):

@@ -239,3 +239,14 @@ def test_orbital_rotation_invariance(method):
                  tol=1e-12, max_iter=300)
     assert ref["converged"] and res["converged"]
     assert abs(res["energy"] - ref["energy"]) < 1e-10
+
+
+def test_stored_c1_trajectory_is_the_oracles():
+    """tests/golden/c1_ccd_trajectory.json equals a fresh oracle run."""
+    import json
+    import pathlib
+    gold = json.loads((pathlib.Path(__file__).resolve().parent / "golden" / "c1_ccd_trajectory.json").read_text())
+    s = make_system(8, 24)
+    r = jacobi(Fock.from_system(s), Integrals.from_system(s), "ccd", tol=0.0, max_iter=10)
+    assert np.allclose(r["hist_e"], gold["hist_e"], rtol=0, atol=1e-14)
+    assert np.allclose(r["hist_r"], gold["hist_rnorm"], rtol=1e-12, atol=0)

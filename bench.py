@@ -121,6 +121,37 @@ def bench_batched(ctx, E, torch, steps, warmup):
     return out
 
 
+def bench_shard_share(ctx, E, torch, o=32, v=160, gpus=8):
+    """The ladder GEMM one GPU would run if vvvv's (ab) rows were split over
+    `gpus` devices: M = o^2, N = v^2 / gpus, K = v^2; best FP64 tile."""
+    M, N, K = o * o, v * v // gpus, v * v
+    A = torch.randn(M, K, dtype=torch.float64, device="cuda") * 0.01
+    B = torch.randn(N, K, dtype=torch.float64, device="cuda") * 0.01
+    Cm = torch.zeros(M, N, dtype=torch.float64, device="cuda")
+    best = None
+    old = os.environ.get("CC_GEMM_TILE")
+    try:
+        for t in range(E.gemm_tile_count(ctx)):
+            os.environ["CC_GEMM_TILE"] = str(t)
+            E.gemm(ctx, A, B, Cm, 0.5, 0.0)
+            ts = time.perf_counter()
+            for _ in range(3):
+                E.gemm(ctx, A, B, Cm, 0.5, 0.0)
+            el = (time.perf_counter() - ts) / 3
+            if best is None or el < best[0]:
+                best = (el, t)
+    finally:
+        if old is None:
+            os.environ.pop("CC_GEMM_TILE", None)
+        else:
+            os.environ["CC_GEMM_TILE"] = old
+    el = best[0]
+    res = {"M": M, "N": N, "K": K, "ms": round(el * 1e3, 3), "tflops": round(2 * M * N * K / el / 1e12, 2),
+           "frac_fp64_peak": round(2 * M * N * K / el / 1e12 / PEAK_FP64_TFLOPS, 4)}
+    log(f"[bench] ladder share at {gpus} GPUs: {res}")
+    return res
+
+
 def bench_complex(ctx, E, torch, steps, warmup, o=40, v=200):
     """Complex128 Hermitian system: FP64 complex MFMA contraction steps."""
     from ccinputs.synth import make_system
@@ -156,6 +187,32 @@ def bench_complex(ctx, E, torch, steps, warmup, o=40, v=200):
     return res
 
 
+def bench_learned(ctx, E, torch, dsys, f64_seconds, precs=("f64", "bf16x3")):
+    """Time to ||R|| < 1e-8 from the trained network's t2 guess (t1 = 0),
+    inference included, against the FP64 run from t = 0."""
+    import numpy as np
+    f = ROOT / "paper_2409_06759_amd" / "data" / "mlp_guess.npz"
+    if not f.exists():
+        return None
+    mlp = E.MLP.load(ctx, str(f))
+    out = {"params": str(f.relative_to(ROOT))}
+    for pname in precs:
+        a1, a2 = E.zeros_amps(dsys, E.CCSD)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mlp.guess(dsys, a1, a2)
+        torch.cuda.synchronize()
+        t_inf = time.perf_counter() - t0
+        r = E.iterate(ctx, dsys, E.CCSD, a1, a2, tol=1e-8, max_iter=1500, dressed=True, autotune=True,
+                      prec=E.PRECS[pname])
+        tot = r["seconds"] + t_inf
+        out[pname] = {"converged": r["converged"], "iterations": r["iters"], "seconds": round(tot, 3),
+                      "inference_seconds": round(t_inf, 4), "energy": r["energy"],
+                      "speedup_vs_f64": round(f64_seconds / tot, 3) if f64_seconds else None}
+        log(f"[bench] learned guess + {pname}: {r['iters']} iterations, {tot:.2f}s (inference {t_inf * 1e3:.1f} ms)")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -171,9 +228,11 @@ def main():
                     help="contraction precision of the timed steps")
     ap.add_argument("--converge-precs", default="f64,f32,bf16x3",
                     help="precisions whose time to ||R||<1e-8 is reported (reduced ones refine in FP64)")
-    ap.add_argument("--extras", default="batched",
+    ap.add_argument("--extras", default="batched,learned,share",
                     help="comma list of extra workloads reported in the same line: batched (64 uneven "
-                         "systems), complex (complex128 o=40 v=200)")
+                         "systems), learned (time to 1e-8 from the trained network's guess), share (the "
+                         "one-GPU share of an 8-GPU ladder), complex "
+                         "(complex128 o=40 v=200); 'none' for no extras")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB copy (for HBM counter scaling)")
     args = ap.parse_args()
@@ -260,6 +319,12 @@ def main():
     for name in [x for x in args.extras.split(",") if x and x != "none"]:
         if name == "batched":
             extras["batched"] = bench_batched(ctx, E, torch, max(args.steps, 5), args.warmup)
+        elif name == "learned":
+            if args.config == "c2":
+                f64s = conv.get("f64", {}).get("seconds")
+                extras["learned"] = bench_learned(ctx, E, torch, dsys, f64s)
+        elif name == "share":
+            extras["ladder_share_g8"] = bench_shard_share(ctx, E, torch, o, v)
         elif name == "complex":
             plan.close()
             extras["complex"] = bench_complex(ctx, E, torch, 3, 1)

@@ -497,6 +497,12 @@ int cc_gemm(cc_ctx *ctx, int prec, int scalar, int64_t M, int64_t N, int64_t K, 
   });
 }
 
+int cc_gemm_tile_count(int prec) {
+  if (prec == CC_PREC_F64) return ccmi::gemm_f64_num_tiles();
+  if (prec == CC_PREC_F32 || prec == CC_PREC_BF16X3) return ccmi::gemm_lowp_num_tiles();
+  return -1;
+}
+
 int cc_permute(cc_ctx *ctx, int scalar, int rank, const int64_t *in_dims, const int32_t *perm,
                double alpha, const void *in, double beta, void *out) {
   if (!ctx) return fail(nullptr, CC_EINVAL, "ctx is NULL");

@@ -237,6 +237,12 @@ def gemm(ctx, A, B, Cm, alpha=1.0, beta=0.0, a_kcontig=True, b_kcontig=True, pre
                               beta, _ptr(Cm), N))
 
 
+def gemm_tile_count(ctx, prec=F64) -> int:
+    """Number of GEMM tile configurations of a precision (for forced-tile
+    sweeps through the CC_GEMM_TILE environment variable)."""
+    return ctx.lib.cc_gemm_tile_count(prec)
+
+
 def permute(ctx, x, perm, out=None, alpha=1.0, beta=0.0):
     """out = alpha * x.permute(perm) + beta * out (dense result)."""
     shape = [x.shape[p] for p in perm]

@@ -97,3 +97,29 @@ def test_batch_reduced_precision_equals_single_system(E, ctx, prec):
             print(f"{prec} system {b}: dE={abs(e - e_b[b]):.3e} drn={abs(rn - rn_b[b]):.3e}", flush=True)
             assert abs(e - e_b[b]) < 1e-12 * max(1.0, abs(e)) and abs(rn - rn_b[b]) < 1e-12
             assert (amps_b[b][1] - t2).abs().max().item() < 1e-13
+
+
+def test_batch_c4_full_workload(E, ctx):
+    """All 64 systems of the batched workload iterated together to 1e-10:
+    each equals its own single-system solve bitwise, and three of them (the
+    smallest, a middle and the largest) equal the oracle's converged energy."""
+    shapes = batch_shapes(64)
+    systems = [make_system(o, v, seed) for o, v, seed in shapes]
+    ds = [E.DeviceSystem(s) for s in systems]
+    with E.Batch(ctx, ds, E.CCSD) as B:
+        out = B.iterate(tol=1e-10, max_iter=200, dressed=True)
+    assert out["n_converged"] == 64
+    size = [o * o * v * v for o, v, _ in shapes]
+    order = np.argsort(size)
+    pick = [int(order[0]), int(order[len(order) // 2]), int(order[-1])]
+    for b in range(64):
+        t1, t2 = E.zeros_amps(ds[b], E.CCSD)
+        single = E.iterate(ctx, ds[b], E.CCSD, t1, t2, tol=1e-10, max_iter=200, dressed=True)
+        assert single["iters"] == out["systems"][b]["iters"]
+        assert single["energy"] == out["systems"][b]["energy"]
+    for b in pick:
+        o, v, _ = shapes[b]
+        print(f"oracle check: system {b} o={o} v={v}", flush=True)
+        ref = jacobi(Fock.from_system(systems[b]), Integrals.from_system(systems[b]), "ccsd", tol=1e-10,
+                     max_iter=200, dressed=True)
+        assert abs(ref["energy"] - out["systems"][b]["energy"]) < 1e-10

@@ -111,10 +111,12 @@ def test_ladder_is_one_direct_gemm():
 
 @pytest.mark.parametrize("method", [0, 1])
 @pytest.mark.parametrize("cplx", [False, True])
-def test_plan_listing_reproduces_oracle(method, cplx):
-    """Interpret the planner's steps with NumPy; compare with the oracle."""
+@pytest.mark.parametrize("ov", [(4, 7), (1, 4), (2, 1), (1, 1), (3, 2)])
+def test_plan_listing_reproduces_oracle(method, cplx, ov):
+    """Interpret the planner's steps with NumPy; compare with the oracle
+    (including the degenerate sizes with no i<j or no a<b pair)."""
     _, lib = _lib()
-    o, v = 4, 7
+    o, v = ov
     steps, slots, alias = _parse(lib.cc_plan_describe_dry(o, v, method, 1 if cplx else 0).decode())
     dt = np.complex128 if cplx else np.float64
     s = make_system(o, v, 3, is_complex=cplx, sigma=0.1)

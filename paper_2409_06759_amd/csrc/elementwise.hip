@@ -156,18 +156,29 @@ __device__ __forceinline__ void fill_body(const FillEntry &E, int64_t bid) {
 }
 
 // ---------------------------------------------------------- split-K sum --
-// C = alpha * sum_s W[s] + beta * C, s in increasing order (deterministic).
+// C = alpha * sum_s W[s] + beta * C.  A workgroup covers 256 / lanes
+// outputs; lane l of an output sums the partials s = l, l + lanes, ... in
+// increasing order, then lane 0 adds the lanes' sums in lane order.  The
+// order depends only on (split, lanes), never on timing.
 template <class T>
 __device__ __forceinline__ void splitk_body(const SplitkEntry &E, int64_t bid) {
+  __shared__ T part[256];
   const T *__restrict__ W = static_cast<const T *>(E.ws);
   T *__restrict__ C = static_cast<T *>(E.C);
   const int64_t total = E.M * E.N;
-  const int64_t e1 = std::min<int64_t>(total, (bid + 1) * CH);
-  for (int64_t e = bid * CH + threadIdx.x; e < e1; e += 256) {
-    T acc = W[e];
-    for (int k = 1; k < E.split; ++k) acc = add(acc, W[int64_t(k) * total + e]);
+  const int L = E.lanes, nout = 256 / L;
+  const int oi = threadIdx.x % nout, lane = threadIdx.x / nout;
+  const int64_t e = bid * nout + oi;
+  T acc = zero<T>();
+  if (e < total)
+    for (int k = lane; k < E.split; k += L) acc = add(acc, W[int64_t(k) * total + e]);
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  if (lane == 0 && e < total) {
+    T sum = part[oi];
+    for (int l = 1; l < L; ++l) sum = add(sum, part[l * nout + oi]);
     const int64_t m = e / E.N, n = e % E.N;
-    T v = sc(E.alpha, acc);
+    T v = sc(E.alpha, sum);
     if (E.beta != 0.0) v = add(v, sc(E.beta, C[m * E.ldc + n]));
     C[m * E.ldc + n] = v;
   }
@@ -503,7 +514,9 @@ FillEntry make_fill_entry(void *p, int64_t n) { return FillEntry{p, n, n > 0 ? c
 
 SplitkEntry make_splitk_entry(const void *ws, int split, int64_t M, int64_t N, void *C, int64_t ldc, double alpha,
                               double beta) {
-  return SplitkEntry{ws, split, M, N, C, ldc, alpha, beta, M * N > 0 ? chunks(M * N, CH) : 0};
+  int lanes = 1;
+  while (lanes < 16 && 2 * lanes <= split) lanes *= 2;
+  return SplitkEntry{ws, split, lanes, M, N, C, ldc, alpha, beta, M * N > 0 ? chunks(M * N, 256 / lanes) : 0};
 }
 
 int64_t tau_units(int o, int v) { return chunks(int64_t(o) * o * v * v, CH_TAU); }

@@ -288,15 +288,16 @@ int gemm_f64_pick(int64_t M, int64_t N, int64_t K, bool, bool) {
   return best;
 }
 
-// Split-K factor: enough workgroups to cover the chip when the output has
-// few tiles and the contraction is long (e.g. M = N = o, K = o v^2).
+// Split-K factor: about 1024 workgroups (four per CU) when the output has
+// few tiles and the contraction is long (e.g. M = N = o, K = o v^2), each
+// split covering at least 256 of K.
 // Independent of the tile so that the autotuner can change tiles freely.
 int gemm_split_pick(int64_t M, int64_t N, int64_t K, int) {
   const int64_t tiles = ((M + 63) / 64) * ((N + 63) / 64);
-  if (tiles >= 256) return 1;
-  int64_t split = (512 + tiles - 1) / tiles;
+  if (tiles >= 1024) return 1;  // four 64x64 tiles per CU or more
+  int64_t split = (1024 + tiles - 1) / tiles;
   split = std::min<int64_t>(split, std::max<int64_t>(1, K / 256));
-  return int(std::max<int64_t>(1, std::min<int64_t>(split, 128)));
+  return int(std::max<int64_t>(1, std::min<int64_t>(split, 1024)));
 }
 
 void gemm_f64_grouped_launch(const GemmGroupEntry *dev_entries, const int64_t *dev_off, int n,

@@ -59,6 +59,7 @@ struct FillEntry {
 struct SplitkEntry {
   const void *ws;
   int split;
+  int lanes;  // threads summing one output (power of two <= 16); 256 / lanes outputs per workgroup
   int64_t M, N;
   void *C;
   int64_t ldc;

@@ -45,7 +45,7 @@ def _amps(o, v, seed, scale=0.01, cplx=False):
 
 
 @pytest.mark.parametrize("method", ["ccd", "ccsd"])
-@pytest.mark.parametrize("ov", [(3, 5), (8, 24), (12, 37), (5, 70)])
+@pytest.mark.parametrize("ov", [(3, 5), (8, 24), (12, 37), (5, 70), (1, 4), (2, 1), (1, 1), (2, 3)])
 def test_residual_matches_oracle(E, ctx, method, ov):
     o, v = ov
     print(f"residual {method} o={o} v={v}", flush=True)

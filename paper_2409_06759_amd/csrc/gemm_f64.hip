@@ -294,8 +294,8 @@ int gemm_f64_pick(int64_t M, int64_t N, int64_t K, bool, bool) {
 // Independent of the tile so that the autotuner can change tiles freely.
 int gemm_split_pick(int64_t M, int64_t N, int64_t K, int) {
   const int64_t tiles = ((M + 63) / 64) * ((N + 63) / 64);
-  if (tiles >= 1024) return 1;  // four 64x64 tiles per CU or more
-  int64_t split = (1024 + tiles - 1) / tiles;
+  if (tiles >= 2048) return 1;  // eight 64x64 tiles per CU or more
+  int64_t split = (2048 + tiles - 1) / tiles;
   split = std::min<int64_t>(split, std::max<int64_t>(1, K / 256));
   return int(std::max<int64_t>(1, std::min<int64_t>(split, 1024)));
 }

@@ -14,6 +14,10 @@ tiny system, with no diagrams at all:
   = 1/4 sum t_ij^ab E_ai E_bj (cluster operators of the CC section).
 * Hbar = exp(-T) H exp(T); exp is the terminating power series (T is
   nilpotent on the N-electron space).
+* `cluster_general` / `evaluate_general` extend the same construction to
+  cluster operators and projections of any excitation level:
+  T_m = sum over i1<..<im, a1<..<am of t_{i1..im}^{a1..am} E_{a1 i1}..E_{am im},
+  |Phi_{i1..im}^{a1..am}> = E_{a1 i1}..E_{am im} |Phi_0>.
 * E - E_HF = <Phi_0|Hbar|Phi_0> - <Phi_0|H|Phi_0>;
   R_i^a = <Phi_i^a|Hbar|Phi_0>, |Phi_i^a> = E_ai |Phi_0>;
   R_ij^ab = <Phi_ij^ab|Hbar|Phi_0>, |Phi_ij^ab> = a+_a a+_b a_j a_i |Phi_0>.
@@ -116,6 +120,52 @@ class Projector:
                         if c != 0:
                             T += 0.25 * c * (E[a, i] @ E[b, j])
         return T
+
+    def excitation(self, holes, parts):
+        """E_{a1 i1} ... E_{am im} as a matrix (|Phi_{i1..im}^{a1..am}> = this applied to |Phi_0>)."""
+        M = np.eye(self.H.shape[0])
+        for i, a in zip(holes, parts):
+            M = M @ self.E[a + self.o, i]
+        return M
+
+    def cluster_general(self, amps):
+        """T = sum_m T_m, T_m = (1/m!)^2 sum t_{i1..im}^{a1..am} a+_a1..a+_am a_im..a_i1
+        = sum over i1<..<im, a1<..<am of t E_{a1 i1}..E_{am im}; amps maps m to an
+        antisymmetric tensor t[i1..im, a1..am] (any level, generalising T1 and T2)."""
+        o, v = self.o, self.v
+        dt = np.result_type(self.H.dtype, *[a.dtype for a in amps.values() if a is not None])
+        T = np.zeros(self.H.shape, dtype=dt)
+        for m, t in amps.items():
+            if t is None:
+                continue
+            for holes in itertools.combinations(range(o), m):
+                for parts in itertools.combinations(range(v), m):
+                    c = t[holes + parts]
+                    if c != 0:
+                        T += c * self.excitation(holes, parts)
+        return T
+
+    def evaluate_general(self, amps, levels):
+        """(E - E_HF, {k: R_k[i1..ik, a1..ak]}) with R_k = <Phi_k| exp(-T) H exp(T) |Phi_0>
+        for the projection levels k in `levels` (Eq. eq:amp), T from cluster_general."""
+        T = self.cluster_general(amps)
+        Hb = _expm_nilpotent(-T) @ self.H @ _expm_nilpotent(T)
+        col = Hb[:, self.ref]
+        phi0 = np.zeros(Hb.shape[0])
+        phi0[self.ref] = 1.0
+        out = {}
+        o, v = self.o, self.v
+        for k in levels:
+            R = np.zeros((o,) * k + (v,) * k, dtype=col.dtype)
+            for holes in itertools.product(range(o), repeat=k):
+                if len(set(holes)) < k:
+                    continue
+                for parts in itertools.product(range(v), repeat=k):
+                    if len(set(parts)) < k:
+                        continue
+                    R[holes + parts] = (self.excitation(holes, parts) @ phi0) @ col
+            out[k] = R
+        return col[self.ref] - self.e_hf, out
 
     def hbar(self, t1, t2):
         T = self.cluster(t1, t2)

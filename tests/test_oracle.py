@@ -250,3 +250,71 @@ def test_stored_c1_trajectory_is_the_oracles():
     r = jacobi(Fock.from_system(s), Integrals.from_system(s), "ccd", tol=0.0, max_iter=10)
     assert np.allclose(r["hist_e"], gold["hist_e"], rtol=0, atol=1e-14)
     assert np.allclose(r["hist_r"], gold["hist_rnorm"], rtol=1e-12, atol=0)
+
+
+# ---- the projection at any excitation level (cluster_general) -------------
+
+def _antisym(x, m):
+    import itertools
+    out = np.zeros_like(x)
+    for ph in itertools.permutations(range(m)):
+        for pp in itertools.permutations(range(m)):
+            sg = round(np.linalg.det(np.eye(m)[list(ph)]) * np.linalg.det(np.eye(m)[list(pp)]))
+            out = out + sg * np.transpose(x, list(ph) + [m + q for q in pp])
+    return out
+
+
+def test_general_projection_reduces_to_singles_doubles():
+    o, v = 2, 4
+    s = make_system(o, v, 21, sigma=0.1)
+    P = Projector(s.fock(), s.full_integrals(), o)
+    rng = np.random.default_rng(4)
+    t1 = rng.normal(size=(o, v)) * 0.1
+    t2 = _antisym(rng.normal(size=(o, o, v, v)) * 0.1, 2)
+    assert np.array_equal(P.cluster_general({1: t1, 2: t2}), P.cluster(t1, t2)) or np.allclose(
+        P.cluster_general({1: t1, 2: t2}), P.cluster(t1, t2), atol=1e-15)
+    e, R1, R2 = P.evaluate(t1, t2)
+    e_g, R = P.evaluate_general({1: t1, 2: t2}, (1, 2))
+    assert abs(e - e_g) < 1e-14 and np.abs(R[1] - R1).max() < 1e-14 and np.abs(R[2] - R2).max() < 1e-14
+
+
+def test_triples_cluster_operator_normalisation():
+    """<Phi_ijk^abc| T3 |Phi_0> = t_ijk^abc for every index triple (the 1/36
+    and the operator order of T3 and of the triply excited bra)."""
+    o, v = 3, 3
+    s = make_system(o, v, 22, sigma=0.1)
+    P = Projector(s.fock(), s.full_integrals(), o)
+    t3 = _antisym(np.random.default_rng(5).normal(size=(o,) * 3 + (v,) * 3), 3)
+    T = P.cluster_general({3: t3})
+    phi0 = np.zeros(T.shape[0])
+    phi0[P.ref] = 1.0
+    import itertools
+    for holes in itertools.product(range(o), repeat=3):
+        for parts in itertools.product(range(v), repeat=3):
+            bra = P.excitation(holes, parts) @ phi0
+            assert abs(bra @ (T @ phi0) - t3[holes + parts]) < 1e-13
+
+
+def test_ccsdt_is_exact_for_three_electrons():
+    """CCSDT (projection residuals, Jacobi) reproduces the FCI correlation
+    energy of a three-electron system."""
+    import itertools
+    o, v = 3, 3
+    s = make_system(o, v, 11, sigma=0.05)
+    P = Projector(s.fock(), s.full_integrals(), o)
+    eo, ev = np.diag(s.fock())[:o], np.diag(s.fock())[o:]
+    D = {}
+    for m in (1, 2, 3):
+        d = np.zeros((o,) * m + (v,) * m)
+        for idx in itertools.product(*([range(o)] * m + [range(v)] * m)):
+            d[idx] = sum(eo[q] for q in idx[:m]) - sum(ev[q] for q in idx[m:])
+        D[m] = d
+    amps = {m: np.zeros((o,) * m + (v,) * m) for m in (1, 2, 3)}
+    for _ in range(200):
+        e, R = P.evaluate_general(amps, (1, 2, 3))
+        if np.sqrt(sum(np.sum(R[m] ** 2) for m in R)) < 1e-11:
+            break
+        for m in (1, 2, 3):
+            amps[m] = amps[m] + R[m] / D[m]
+    e_fci = np.linalg.eigvalsh(P.H)[0] - P.e_hf
+    assert abs(e - e_fci) < 1e-11

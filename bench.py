@@ -152,6 +152,35 @@ def bench_shard_share(ctx, E, torch, o=32, v=160, gpus=8):
     return res
 
 
+def bench_generated(ctx, E, torch, dsys, builtin_plan, reps=3):
+    """The CCSD residual evaluated from the diagram generator's contraction
+    list (derived equations, binary ops, cc_plan_create_ops) against the
+    built-in factorised table, at the same amplitudes."""
+    from paper_2409_06759_amd.codegen.emit import op_list
+    t0 = time.perf_counter()
+    text = op_list("ccsd", dsys.o, dsys.v)
+    t_gen = time.perf_counter() - t0
+    t1, t2 = E.zeros_amps(dsys, E.CCSD)
+    builtin_plan.step(t1, t2, 0.0, True)
+    builtin_plan.step(t1, t2, 0.0, True)
+    rb1, rb2, rnb = builtin_plan.residual(t1, t2)
+    with E.Plan(ctx, dsys, E.CCSD, ops=text) as p:
+        p.autotune(t1, t2, 1)
+        r1, r2, rn = p.residual(t1, t2)
+        diff = max((r2 - rb2).abs().max().item(), (r1 - rb1).abs().max().item())
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        for _ in range(reps):
+            p.residual(t1, t2, want_r=False)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - ts) / reps
+        res = {"ops": text.count("\nop "), "derive_and_emit_seconds": round(t_gen, 3),
+               "ms_per_residual": round(el * 1e3, 2), "flops": p.flops(), "tflops": round(p.flops() / el / 1e12, 2),
+               "max_abs_diff_vs_builtin": diff, "workspace_gb": round(p.workspace_bytes() / 1e9, 1)}
+    log(f"[bench] generated contraction list: {res}")
+    return res
+
+
 def bench_complex(ctx, E, torch, steps, warmup, o=40, v=200):
     """Complex128 Hermitian system: FP64 complex MFMA contraction steps."""
     from ccinputs.synth import make_system
@@ -228,10 +257,11 @@ def main():
                     help="contraction precision of the timed steps")
     ap.add_argument("--converge-precs", default="f64,f32,bf16x3",
                     help="precisions whose time to ||R||<1e-8 is reported (reduced ones refine in FP64)")
-    ap.add_argument("--extras", default="batched,learned,share",
+    ap.add_argument("--extras", default="batched,learned,share,generated",
                     help="comma list of extra workloads reported in the same line: batched (64 uneven "
                          "systems), learned (time to 1e-8 from the trained network's guess), share (the "
-                         "one-GPU share of an 8-GPU ladder), complex "
+                         "one-GPU share of an 8-GPU ladder), generated (the residual from the diagram "
+                         "generator's contraction list), complex "
                          "(complex128 o=40 v=200); 'none' for no extras")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB copy (for HBM counter scaling)")
@@ -316,6 +346,7 @@ def main():
                 f"({out['lowp_iters']} reduced), E={out['energy']:.10f}")
 
     extras = {}
+    plan_closed = False
     for name in [x for x in args.extras.split(",") if x and x != "none"]:
         if name == "batched":
             extras["batched"] = bench_batched(ctx, E, torch, max(args.steps, 5), args.warmup)
@@ -323,10 +354,14 @@ def main():
             if args.config == "c2":
                 f64s = conv.get("f64", {}).get("seconds")
                 extras["learned"] = bench_learned(ctx, E, torch, dsys, f64s)
+        elif name == "generated":
+            if method == "ccsd" and not plan_closed:
+                extras["generated"] = bench_generated(ctx, E, torch, dsys, plan)
         elif name == "share":
             extras["ladder_share_g8"] = bench_shard_share(ctx, E, torch, o, v)
         elif name == "complex":
             plan.close()
+            plan_closed = True
             extras["complex"] = bench_complex(ctx, E, torch, 3, 1)
         else:
             raise SystemExit(f"unknown extra workload {name}")

@@ -133,6 +133,24 @@ const char *cc_status_string(int status);
  * views the contraction list needs and allocates the workspace. */
 int cc_plan_create(cc_ctx *ctx, const cc_system *sys, int method, int prec, cc_plan **plan);
 int cc_plan_destroy(cc_plan *plan);
+/* A plan whose residual contractions come from the text `ops` instead of the
+ * built-in factorised table: the list emitted by the diagram generator
+ * (paper, Sec. "Coupled cluster amplitude equations": the equations are
+ * derived, then evaluated as binary contractions).  Lines (host memory,
+ * copied): "work NAME SPACES" declares an intermediate (SPACES over o/v);
+ * "op TAG C cl ALPHA A al B bl [conjA] [conjB] [swap=xy]" accumulates
+ * C[cl] += ALPHA * A[al] * B[bl] (summing labels absent from cl; B bl "-"
+ * for C[cl] += ALPHA * A[al]); '#' starts a comment.  Index labels i..n run
+ * over occupied orbitals, the others over virtual ones.  Tensors: foo, fov,
+ * fvv, oooo, ooov, oovv, ovvo, ovvv, vvvv (inputs), t1, t2 (amplitudes),
+ * the declared intermediates, and the residual accumulators XP (R2 as is),
+ * Xij (R2 += X - X(i<->j)), Xab (R2 += X - X(a<->b)), Xr (both
+ * antisymmetrisers) and R1, all labelled ijab / ia.  conjA/conjB conjugate
+ * an operand (complex systems).  The energy and norms are computed as for
+ * cc_plan_create; dressed denominators are not available (EUNSUPPORTED in
+ * cc_plan_step).  A malformed list gives CC_EINVAL with the line number. */
+int cc_plan_create_ops(cc_ctx *ctx, const cc_system *sys, int method, int prec, const char *ops,
+                       cc_plan **plan);
 /* Workspace bytes held by the plan (derived views + intermediates). */
 size_t cc_plan_workspace_bytes(const cc_plan *plan);
 
@@ -265,6 +283,9 @@ const char *cc_plan_describe(const cc_plan *plan);
 /* The same listing for a plan of the given sizes, built without a device
  * (no allocation, no kernel launch). */
 const char *cc_plan_describe_dry(int o, int v, int method, int scalar);
+/* Listing of a plan built from a caller-supplied op list (see
+ * cc_plan_create_ops), without a device; "error: ..." on a bad list. */
+const char *cc_plan_describe_ops_dry(int o, int v, int method, int scalar, const char *ops);
 /* Precision of the contractions of the following steps (cc_prec); the
  * plan's creation precision is the initial value. */
 int cc_plan_set_precision(cc_plan *plan, int prec);

@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -126,11 +127,13 @@ void run_step(cc_plan *p, bool use_graph) {
   CC_HIP_CHECK(hipGraphLaunch(p->graph, p->ctx->stream));
 }
 
-cc_plan *make_plan(cc_ctx *ctx, const cc_system *sys, int method, int prec) {
+cc_plan *make_plan(cc_ctx *ctx, const cc_system *sys, int method, int prec,
+                   std::shared_ptr<ccmi::OpList> custom = nullptr) {
   validate_system(sys);
   validate_method(method, prec, sys->scalar);
   set_device(ctx);
   cc_plan *p = new cc_plan();
+  p->custom = std::move(custom);
   p->ctx = ctx;
   p->o = sys->o;
   p->v = sys->v;
@@ -229,6 +232,18 @@ int cc_plan_create(cc_ctx *ctx, const cc_system *sys, int method, int prec, cc_p
   });
 }
 
+int cc_plan_create_ops(cc_ctx *ctx, const cc_system *sys, int method, int prec, const char *ops,
+                       cc_plan **plan) {
+  if (!ctx) return fail(nullptr, CC_EINVAL, "ctx is NULL");
+  if (!plan) return fail(ctx, CC_EINVAL, "plan pointer is NULL");
+  *plan = nullptr;
+  return guarded(ctx, [&] {
+    auto list = std::make_shared<ccmi::OpList>(ccmi::parse_op_list(ops));
+    *plan = make_plan(ctx, sys, method, prec, list);
+    return CC_OK;
+  });
+}
+
 int cc_plan_destroy(cc_plan *p) {
   if (!p) return CC_OK;
   (void)hipSetDevice(p->ctx->device);
@@ -271,6 +286,8 @@ int cc_plan_step(cc_plan *p, cc_amps *t, double level_shift, int dressed) {
     p->r1_out = nullptr;
     p->r2_out = nullptr;
     p->update = true;
+    if (dressed && p->custom)
+      throw CCError(CC_EUNSUPPORTED, "dressed denominators need the built-in contraction table");
     p->shift = level_shift;
     p->dressed = dressed ? 1 : 0;
     ccmi::plan_run(p);
@@ -542,6 +559,30 @@ int cc_permute(cc_ctx *ctx, int scalar, int rank, const int64_t *in_dims, const 
 const char *cc_plan_describe(const cc_plan *p) {
   static thread_local std::string s;
   s = p ? ccmi::plan_describe(p) : std::string();
+  return s.c_str();
+}
+
+const char *cc_plan_describe_ops_dry(int o, int v, int method, int scalar, const char *ops) {
+  static thread_local std::string s;
+  try {
+    if (o < 1 || v < 1) throw CCError(CC_EINVAL, "o and v must be >= 1");
+    validate_method(method, CC_PREC_F64, scalar);
+    cc_plan p;
+    if (ops) p.custom = std::make_shared<ccmi::OpList>(ccmi::parse_op_list(ops));
+    p.o = o;
+    p.v = v;
+    p.method = method;
+    p.cplx = scalar == CC_C128;
+    p.esize = p.cplx ? 16 : 8;
+    cc_system sys{};
+    sys.o = o;
+    sys.v = v;
+    sys.scalar = scalar;
+    ccmi::plan_layout(&p, &sys);
+    s = ccmi::plan_describe(&p);
+  } catch (const std::exception &e) {
+    s = std::string("error: ") + e.what();
+  }
   return s.c_str();
 }
 

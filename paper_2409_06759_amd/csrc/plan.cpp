@@ -440,6 +440,22 @@ struct Planner {
                              {"Xab", "oovv"}, {"Xr", "oovv"},  {"R1", "ov"},   {"Zs", "oovo"},
                              {"FF", "vv"},   {"GG", "oo"},    {"Q", "oovo"}};
     for (auto &w : work) add_slot(w[0], w[1], false, false, true);
+    std::vector<OpSpec> custom_ops;
+    if (p->custom) {
+      for (const auto &w : p->custom->work) {
+        if (p->index.count(w.first)) throw CCError(CC_EINVAL, "op list: tensor " + w.first + " already exists");
+        for (char c : w.second)
+          if (c != 'o' && c != 'v') throw CCError(CC_EINVAL, "op list: spaces of " + w.first + " must be o/v");
+        add_slot(w.first, w.second, false, false, true);
+      }
+      for (const OpText &o : p->custom->ops) {
+        const bool un = o.B.empty();
+        custom_ops.push_back(OpSpec{o.C.c_str(), o.cl.c_str(), o.alpha, o.A.c_str(), o.al.c_str(),
+                                    un ? nullptr : o.B.c_str(), un ? nullptr : o.bl.c_str(), o.conjA, o.conjB,
+                                    o.swap.empty() ? nullptr : o.swap.c_str(),
+                                    o.A == "t1" || (!un && o.B == "t1"), o.tag.c_str()});
+      }
+    }
     scratch = add_work("scratch", {1});
     splitws = add_work("splitk_ws", {1});
 
@@ -447,10 +463,26 @@ struct Planner {
     te.kind = Step::TAU_E;
     te.tag = "tau_energy";
     p->iter.push_back(te);
-    for (const OpSpec &op : kOps) {
-      if (op.needs_t1 && !ccsd) continue;
-      if (op.B == nullptr) unary(op);
-      else contract(op);
+    auto run_ops = [&](const OpSpec *ops, size_t n) {
+      for (size_t q = 0; q < n; ++q) {
+        const OpSpec &op = ops[q];
+        if (op.needs_t1 && !ccsd) {
+          if (p->custom) throw CCError(CC_EINVAL, std::string("op list: ") + op.tag + " reads t1 in a CCD plan");
+          continue;
+        }
+        if (op.B == nullptr) unary(op);
+        else contract(op);
+      }
+    };
+    if (p->custom) {
+      try {
+        run_ops(custom_ops.data(), custom_ops.size());
+      } catch (const CCError &e) {
+        if (e.status != CC_EINTERNAL) throw;
+        throw CCError(CC_EINVAL, std::string("op list: ") + e.what());
+      }
+    } else {
+      run_ops(kOps, sizeof(kOps) / sizeof(kOps[0]));
     }
     for (const char *x : {"XP", "Xij", "Xab", "Xr"}) {
       const int s = slot(x);
@@ -695,6 +727,56 @@ void exec(cc_plan *p, Step &st, hipStream_t s) {
 }
 
 }  // namespace
+
+OpList parse_op_list(const char *text) {
+  if (!text) throw CCError(CC_EINVAL, "op list is NULL");
+  OpList out;
+  std::istringstream in(text);
+  std::string line;
+  int lineno = 0;
+  auto bad = [&](const std::string &why) {
+    throw CCError(CC_EINVAL, "op list line " + std::to_string(lineno) + ": " + why);
+  };
+  while (std::getline(in, line)) {
+    ++lineno;
+    const size_t hash = line.find('#');
+    if (hash != std::string::npos) line.resize(hash);
+    std::istringstream ls(line);
+    std::vector<std::string> tok;
+    for (std::string t; ls >> t;) tok.push_back(t);
+    if (tok.empty()) continue;
+    if (tok[0] == "work") {
+      if (tok.size() != 3) bad("expected: work NAME SPACES");
+      out.work.emplace_back(tok[1], tok[2]);
+    } else if (tok[0] == "op") {
+      if (tok.size() < 9) bad("expected: op TAG C cl ALPHA A al B bl [flags]");
+      OpText o;
+      o.tag = tok[1];
+      o.C = tok[2];
+      o.cl = tok[3];
+      char *end = nullptr;
+      o.alpha = std::strtod(tok[4].c_str(), &end);
+      if (!end || *end != '\0') bad("bad coefficient " + tok[4]);
+      o.A = tok[5];
+      o.al = tok[6];
+      if (tok[7] != "-") {
+        o.B = tok[7];
+        o.bl = tok[8];
+      }
+      for (size_t q = 9; q < tok.size(); ++q) {
+        if (tok[q] == "conjA") o.conjA = true;
+        else if (tok[q] == "conjB") o.conjB = true;
+        else if (tok[q].rfind("swap=", 0) == 0 && tok[q].size() == 7) o.swap = tok[q].substr(5);
+        else if (tok[q] != "-") bad("unknown flag " + tok[q]);
+      }
+      out.ops.push_back(o);
+    } else {
+      bad("unknown keyword " + tok[0]);
+    }
+  }
+  if (out.ops.empty()) throw CCError(CC_EINVAL, "op list has no ops");
+  return out;
+}
 
 void plan_layout(cc_plan *p, const cc_system *sys) {
   Planner pl{p};

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -69,6 +70,22 @@ struct DeltaRef {
   void *dshadow = nullptr;        // reduced-precision (X - X_ref)
 };
 
+// A caller-supplied contraction list (e.g. emitted by the diagram
+// generator): intermediates to allocate and binary / unary ops in the
+// format of the built-in table, with owned strings.
+struct OpText {
+  std::string C, cl, A, al, B, bl, swap, tag;
+  double alpha = 1.0;
+  bool conjA = false, conjB = false;
+};
+struct OpList {
+  std::vector<std::pair<std::string, std::string>> work;  // name, spaces
+  std::vector<OpText> ops;
+};
+// Parses "work NAME SPACES" and "op TAG C cl ALPHA A al B bl [conjA] [conjB]
+// [swap=xy]" lines (B and bl "-" for a unary accumulate; '#' comments).
+OpList parse_op_list(const char *text);
+
 }  // namespace ccmi
 
 struct cc_plan {
@@ -77,6 +94,7 @@ struct cc_plan {
   int cur_prec = 0;  // precision of the contractions in the next run
   bool cplx = false;
   size_t esize = 8;
+  std::shared_ptr<ccmi::OpList> custom;  // null: the built-in contraction table
   std::vector<ccmi::Slot> slots;
   std::map<std::string, int> index;
   std::vector<ccmi::Step> setup, iter;

@@ -105,11 +105,19 @@ def _amps(t1, t2):
 
 
 class Plan:
-    def __init__(self, ctx: Context, dsys: DeviceSystem, method: int = CCSD, prec: int = F64):
+    """A planned residual (cc_plan_create), or, with `ops`, one built from a
+    contraction list such as `codegen.emit.op_list` (cc_plan_create_ops)."""
+
+    def __init__(self, ctx: Context, dsys: DeviceSystem, method: int = CCSD, prec: int = F64,
+                 ops: Optional[str] = None):
         self.ctx, self.dsys, self.method = ctx, dsys, method
         self.h = C.c_void_p()
         ctx.enter()
-        ctx.check(ctx.lib.cc_plan_create(ctx.h, C.byref(dsys.struct), method, prec, C.byref(self.h)))
+        if ops is None:
+            ctx.check(ctx.lib.cc_plan_create(ctx.h, C.byref(dsys.struct), method, prec, C.byref(self.h)))
+        else:
+            ctx.check(ctx.lib.cc_plan_create_ops(ctx.h, C.byref(dsys.struct), method, prec, ops.encode(),
+                                                 C.byref(self.h)))
 
     def residual(self, t1, t2, want_r=True):
         r1 = r2 = None

@@ -84,3 +84,33 @@ def test_derived_higher_order_equations_equal_projection(method, o, v):
     for k in levels:
         got = evaluate(eq[k], fock, V.get, amps)
         assert np.abs(got - R[k]).max() < 1e-12 * max(1.0, np.abs(R[k]).max()), k
+
+
+@pytest.mark.parametrize("method", [0, 1])
+@pytest.mark.parametrize("cplx", [False, True])
+@pytest.mark.parametrize("ov", [(4, 7), (3, 5), (1, 3), (2, 2)])
+def test_emitted_op_list_plans_reproduce_oracle(method, cplx, ov):
+    """The binary contraction list emitted from the derived equations, laid
+    out by the engine's planner (cc_plan_describe_ops_dry) and executed by
+    the NumPy interpreter of the listing, equals the oracle residual."""
+    from plan_interp import run_listing
+    from paper_2409_06759_amd import _lib as L
+    from paper_2409_06759_amd.codegen.emit import op_list
+    lib = L.load()
+    o, v = ov
+    text = op_list("ccsd" if method else "ccd", o, v)
+    listing = lib.cc_plan_describe_ops_dry(o, v, method, 1 if cplx else 0, text.encode()).decode()
+    assert not listing.startswith("error"), listing[:200]
+    R1, R2, r1_ref, r2_ref = run_listing(listing, o, v, method, cplx)
+    assert np.abs(R2 - r2_ref).max() < 1e-13
+    if method:
+        assert np.abs(R1 - r1_ref).max() < 1e-13
+
+
+def test_op_list_errors_name_the_line():
+    from paper_2409_06759_amd import _lib as L
+    lib = L.load()
+    bad = b"work G1 oo\nop x XP ijab 1.0 oovv ijab\n"
+    assert lib.cc_plan_describe_ops_dry(3, 4, 1, 0, bad).decode().startswith("error: op list line 2")
+    assert b"unknown tensor" in lib.cc_plan_describe_ops_dry(3, 4, 1, 0, b"op x XP ijab 1.0 nope ijab - -\n")
+    assert b"reads t1" in lib.cc_plan_describe_ops_dry(3, 4, 0, 0, b"op x R1 ia 1.0 t1 ia - -\n")

@@ -9,6 +9,7 @@ singles, and for the doubles XP / Xij / Xab / Xr according to which
 antisymmetriser the term carries (none, P(ij), P(ab), both).  Integral
 blocks are mapped onto the six stored orientations with antisymmetry
 (<pq||rs> = -<qp||rs> = -<pq||sr>) and Hermiticity (<pq||rs> = conj <rs||pq>).
+Intermediates formed identically by several terms are computed once.
 The text is the input of cc_plan_create_ops.
 """
 from __future__ import annotations
@@ -117,8 +118,32 @@ def _best_order(ops: List[str], out: str, dims: Dict[str, int]):
     return best[0]
 
 
-def op_list(method: str, o: int = 32, v: int = 160) -> str:
-    """The cc_plan_create_ops text of the method's singles and doubles."""
+def _canon(*label_strings: str) -> Tuple[str, ...]:
+    """Relabel jointly by first appearance, holes to i, j, ... and particles
+    to a, b, ..., so that equal contractions get equal keys."""
+    m: Dict[str, str] = {}
+    nh = npart = 0
+    out = []
+    for ls in label_strings:
+        r = []
+        for c in ls:
+            if c not in m:
+                if c in OCC:
+                    m[c] = OCC[nh]
+                    nh += 1
+                else:
+                    m[c] = VIR[npart]
+                    npart += 1
+            r.append(m[c])
+        out.append("".join(r))
+    return tuple(out)
+
+
+def op_list(method: str, o: int = 32, v: int = 160, share: bool = True) -> str:
+    """The cc_plan_create_ops text of the method's singles and doubles.
+    With `share`, an intermediate that an earlier term already formed (the
+    same operands contracted the same way, up to relabelling) is reused."""
+    formed: Dict[Tuple, str] = {}
     eq = equations(method)
     dims = {c: o for c in OCC}
     dims.update({c: v for c in VIR})
@@ -160,8 +185,15 @@ def op_list(method: str, o: int = 32, v: int = 160) -> str:
                     cname, alpha = target, coeff
                     res = tl
                 else:
+                    k1 = (a[0], a[2], b[0], b[2]) + _canon(a[1], b[1], res)
+                    k2 = (b[0], b[2], a[0], a[2]) + _canon(b[1], a[1], res)
+                    key = min(k1, k2)
+                    if share and key in formed:
+                        cur = [cur[q] for q in range(len(cur)) if q not in (i, j)] + [(formed[key], res, False)]
+                        continue
                     ng += 1
                     cname, alpha = f"G{ng}", 1.0
+                    formed[key] = cname
                     work.append(f"work {cname} {''.join(_space(c) for c in res)}")
                 flags = (" conjA" if a[2] else "") + (" conjB" if b[2] else "")
                 ops.append(f"op {tag}{'' if last else '_' + str(s_i)} {cname} {res} {alpha!r} "

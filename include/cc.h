@@ -145,12 +145,22 @@ int cc_plan_destroy(cc_plan *plan);
  * fvv, oooo, ooov, oovv, ovvo, ovvv, vvvv (inputs), t1, t2 (amplitudes),
  * the declared intermediates, and the residual accumulators XP (R2 as is),
  * Xij (R2 += X - X(i<->j)), Xab (R2 += X - X(a<->b)), Xr (both
- * antisymmetrisers) and R1, all labelled ijab / ia.  conjA/conjB conjugate
+ * antisymmetrisers) and R1, all labelled ijab / ia; with triples also t3
+ * (ijkabc) and Y3 (R3 = full antisymmetriser of Y3, see
+ * cc_plan_set_triples).  conjA/conjB conjugate
  * an operand (complex systems).  The energy and norms are computed as for
  * cc_plan_create; dressed denominators are not available (EUNSUPPORTED in
  * cc_plan_step).  A malformed list gives CC_EINVAL with the line number. */
 int cc_plan_create_ops(cc_ctx *ctx, const cc_system *sys, int method, int prec, const char *ops,
                        cc_plan **plan);
+/* Triples for a CCSD op-list plan that reads t3 or accumulates Y3 (the
+ * CCSDT equations of the diagram generator): t3[i][j][k][a][b][c] (device,
+ * antisymmetric, o^3 v^3 elements) is read by every residual and updated by
+ * cc_plan_step (t3 += R3 / (D_ijk^abc - shift), bare denominators); r3 (or
+ * NULL) receives R3 = the full (ijk)x(abc) antisymmetriser of Y3 on every
+ * cc_plan_residual.  The residual norm includes R3.  Pointers are kept by
+ * the plan until the next call.  CC_EINVAL if the plan has no triples. */
+int cc_plan_set_triples(cc_plan *plan, void *t3, void *r3);
 /* Workspace bytes held by the plan (derived views + intermediates). */
 size_t cc_plan_workspace_bytes(const cc_plan *plan);
 

@@ -75,8 +75,10 @@ def _target(term: Term) -> Tuple[str, str]:
     k = len(term.ext_h)
     if k == 1:
         return "R1", "ia"
+    if k == 3:
+        return "Y3", "ijkabc"  # R3 = full antisymmetriser of Y3 (terms pre-divided by stab)
     if k != 2:
-        raise ValueError("the engine evaluates singles and doubles")
+        raise ValueError("the engine evaluates up to triples")
     same_p = any("a" in t.idx and "b" in t.idx for t in term.tensors)
     same_h = any("i" in t.idx and "j" in t.idx for t in term.tensors)
     if same_p and same_h:
@@ -109,6 +111,8 @@ def _best_order(ops: List[str], out: str, dims: Dict[str, int]):
             res = "".join(c for c in union if c in keep)
             if len(rest) == 0:
                 res = out
+            if len(res) > 6:  # the engine's tensors have rank <= 6
+                continue
             f = 2
             for c in union:
                 f *= dims[c]
@@ -140,7 +144,8 @@ def _canon(*label_strings: str) -> Tuple[str, ...]:
 
 
 def op_list(method: str, o: int = 32, v: int = 160, share: bool = True) -> str:
-    """The cc_plan_create_ops text of the method's singles and doubles.
+    """The cc_plan_create_ops text of the method's singles and doubles
+    (and triples, accumulated into Y3, for CCSDT).
     With `share`, an intermediate that an earlier term already formed (the
     same operands contracted the same way, up to relabelling) is reused."""
     formed: Dict[Tuple, str] = {}
@@ -167,16 +172,21 @@ def op_list(method: str, o: int = 32, v: int = 160, share: bool = True) -> str:
                     name, lab, conj = map_fock(t.block, idx)
                     operands.append((name, lab, conj))
                 else:
-                    if t.name not in ("t1", "t2"):
-                        raise ValueError("the engine stores t1 and t2 only")
+                    if t.name not in ("t1", "t2", "t3"):
+                        raise ValueError("the engine stores t1, t2 and t3 only")
                     operands.append((t.name, idx, False))
             target, tl = _target(term)
+            if target == "Y3":
+                coeff /= term.stab
             tag = f"g{k}_{n}"
             if len(operands) == 1:
                 name, lab, conj = operands[0]
                 ops.append(f"op {tag} {target} {tl} {coeff!r} {name} {lab} - -" + (" conjA" if conj else ""))
                 continue
-            flops, steps = _best_order([x[1] for x in operands], tl, dims)
+            best = _best_order([x[1] for x in operands], tl, dims)
+            if best is None:
+                raise ValueError(f"no contraction order within rank 6 for {term.text()}")
+            flops, steps = best
             cur = list(operands)
             for s_i, (i, j, res) in enumerate(steps):
                 a, b = cur[i], cur[j]

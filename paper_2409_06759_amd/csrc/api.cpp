@@ -244,6 +244,18 @@ int cc_plan_create_ops(cc_ctx *ctx, const cc_system *sys, int method, int prec, 
   });
 }
 
+int cc_plan_set_triples(cc_plan *p, void *t3, void *r3) {
+  if (!p) return fail(nullptr, CC_EINVAL, "plan is NULL");
+  return guarded(p->ctx, [&] {
+    if (!p->triples) throw CCError(CC_EINVAL, "the plan's contraction list has no triples");
+    check_ptr(t3, "t3");
+    if (r3) check_ptr(r3, "r3");
+    p->t3 = t3;
+    p->r3_out = r3;
+    return CC_OK;
+  });
+}
+
 int cc_plan_destroy(cc_plan *p) {
   if (!p) return CC_OK;
   (void)hipSetDevice(p->ctx->device);

@@ -389,6 +389,55 @@ __device__ __forceinline__ void r1_body(const R1Entry &E) {
 }
 
 // scalars[0] = ||R||, scalars[1..2] = E (re, im); fixed summation order.
+constexpr int64_t CH_T3 = 1024;
+
+// Triples: R3 = sum over permutations (s of ijk, r of abc) of
+// sign(s) sign(r) Y3[s(ijk)][r(abc)].
+template <class T>
+__device__ __forceinline__ void t3_body(const T3Entry &E, int64_t bid) {
+  __shared__ double sh[RED_THREADS];
+  const int o = E.o, v = E.v;
+  const int64_t oo = int64_t(o) * o, vvv = int64_t(v) * v * v, total = oo * o * vvv;
+  const T *__restrict__ Y = static_cast<const T *>(E.Y3);
+  T *__restrict__ R = static_cast<T *>(E.R3);
+  T *__restrict__ t3 = static_cast<T *>(E.t3);
+  // the six permutations of three slots and their signs
+  const int P[6][3] = {{0, 1, 2}, {1, 2, 0}, {2, 0, 1}, {1, 0, 2}, {0, 2, 1}, {2, 1, 0}};
+  const double S[6] = {1, 1, 1, -1, -1, -1};
+  double nrm = 0.0;
+  const int64_t e1 = std::min<int64_t>(total, (bid + 1) * CH_T3);
+  for (int64_t e = bid * CH_T3 + threadIdx.x; e < e1; e += RED_THREADS) {
+    int64_t r = e;
+    const int c = int(r % v); r /= v;
+    const int b = int(r % v); r /= v;
+    const int a = int(r % v); r /= v;
+    const int k = int(r % o); r /= o;
+    const int j = int(r % o); r /= o;
+    const int i = int(r);
+    T val = zero<T>();
+    if (i != j && j != k && i != k && a != b && b != c && a != c) {
+      const int h[3] = {i, j, k}, q[3] = {a, b, c};
+      for (int s1 = 0; s1 < 6; ++s1) {
+        const int64_t hb = ((int64_t(h[P[s1][0]]) * o + h[P[s1][1]]) * o + h[P[s1][2]]) * vvv;
+        for (int s2 = 0; s2 < 6; ++s2) {
+          const int64_t idx = hb + (int64_t(q[P[s2][0]]) * v + q[P[s2][1]]) * v + q[P[s2][2]];
+          val = add(val, sc(S[s1] * S[s2], Y[idx]));
+        }
+      }
+      nrm += abs2(val);
+      if (t3 != nullptr) {
+        const double D = E.d_oo[i] + E.d_oo[j] + E.d_oo[k] - E.d_vv[a] - E.d_vv[b] - E.d_vv[c] - E.shift;
+        t3[e] = add(t3[e], sc(1.0 / D, val));
+      }
+    } else if (t3 != nullptr) {
+      t3[e] = zero<T>();
+    }
+    if (R != nullptr) R[e] = val;
+  }
+  const double tot = block_sum(nrm, sh);
+  if (threadIdx.x == 0) E.partials[bid] = tot;
+}
+
 __device__ __forceinline__ void fin_body(const FinEntry &E) {
   __shared__ double sh[RED_THREADS];
   double a = 0.0, b = 0.0, c = 0.0;
@@ -397,6 +446,7 @@ __device__ __forceinline__ void fin_body(const FinEntry &E) {
     b += E.epart[2 * k + 1];
   }
   for (int k = threadIdx.x; k < E.nn; k += RED_THREADS) c += E.n2part[k];
+  for (int k = threadIdx.x; k < E.nn3; k += RED_THREADS) c += E.n3part[k];
   const double sa = block_sum(a, sh), sb = block_sum(b, sh), scn = block_sum(c, sh);
   if (threadIdx.x == 0) {
     const double n2 = scn + (E.n1part ? E.n1part[0] : 0.0);
@@ -435,6 +485,7 @@ CC_EW_KERNELS(fill, FillEntry, fill_body)
 CC_EW_KERNELS(splitk, SplitkEntry, splitk_body)
 CC_EW_KERNELS(tau, TauEntry, tau_body)
 CC_EW_KERNELS(asm, AsmEntry, asm_body)
+CC_EW_KERNELS(t3, T3Entry, t3_body)
 
 template <class T>
 __global__ __launch_bounds__(RED_THREADS) void k_r1(R1Entry e) { r1_body<T>(e); }
@@ -526,6 +577,8 @@ TauEntry make_tau_entry(int o, int v, const void *t1, const void *t2, const void
   return TauEntry{o, v, t1, t2, oovv, fov, tau, taut, partials, tau_units(o, v)};
 }
 
+int64_t t3_units(int o, int v) { return chunks(int64_t(o) * o * o * v * v * v, CH_T3); }
+
 int64_t asm_units(int o, int v) {
   const int64_t tiles = (v + 31) / 32;
   return (int64_t(o) * (o + 1) / 2) * (tiles * (tiles + 1) / 2);
@@ -564,6 +617,7 @@ void launch_fill(const FillEntry &e, bool cplx, hipStream_t s) { CC_LAUNCH1(k_fi
 void launch_splitk(const SplitkEntry &e, bool cplx, hipStream_t s) { CC_LAUNCH1(k_splitk, e, e.units, cplx, s); }
 void launch_tau(const TauEntry &e, bool cplx, hipStream_t s) { CC_LAUNCH1(k_tau, e, e.units, cplx, s); }
 void launch_asm(const AsmEntry &e, bool cplx, hipStream_t s) { CC_LAUNCH1(k_asm, e, e.units, cplx, s); }
+void launch_t3(const T3Entry &e, bool cplx, hipStream_t s) { CC_LAUNCH1(k_t3, e, e.units, cplx, s); }
 void launch_r1(const R1Entry &e, bool cplx, hipStream_t s) {
   if (cplx) hipLaunchKernelGGL(k_r1<double2>, dim3(1), dim3(RED_THREADS), 0, s, e);
   else hipLaunchKernelGGL(k_r1<double>, dim3(1), dim3(RED_THREADS), 0, s, e);

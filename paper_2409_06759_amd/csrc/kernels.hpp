@@ -109,6 +109,23 @@ struct FinEntry {
   int nn;
   const double *n1part;  // may be nullptr
   double *scalars;       // [0] = ||R||, [1] = Re E, [2] = Im E
+  const double *n3part = nullptr;  // triples norm partials (may be nullptr)
+  int nn3 = 0;
+};
+
+// R3 = full antisymmetriser of the accumulated triples contributions Y3
+// (sum over the 36 signed permutations of (ijk) and (abc)), exact zeros for
+// repeated indices, optional Jacobi update t3 += R3 / (D - shift) with bare
+// denominators, and per-workgroup partial sums of |R3|^2.
+struct T3Entry {
+  int o, v;
+  const void *Y3;
+  void *R3;   // nullptr: not stored
+  void *t3;   // nullptr: no update
+  const double *d_oo, *d_vv;
+  double shift;
+  double *partials;
+  int64_t units;
 };
 
 // ---- entry construction (host) ---------------------------------------------
@@ -123,6 +140,7 @@ AsmEntry make_asm_entry(const R2Args &a, const void *XP, const void *Xij, const 
                         void *R, void *t2, double *partials);
 int64_t tau_units(int o, int v);
 int64_t asm_units(int o, int v);
+int64_t t3_units(int o, int v);
 
 // ---- single launches ---------------------------------------------------------
 void launch_perm(const PermEntry &e, bool cplx, hipStream_t s);
@@ -131,6 +149,7 @@ void launch_fill(const FillEntry &e, bool cplx, hipStream_t s);
 void launch_splitk(const SplitkEntry &e, bool cplx, hipStream_t s);
 void launch_tau(const TauEntry &e, bool cplx, hipStream_t s);
 void launch_asm(const AsmEntry &e, bool cplx, hipStream_t s);
+void launch_t3(const T3Entry &e, bool cplx, hipStream_t s);
 void launch_r1(const R1Entry &e, bool cplx, hipStream_t s);
 void launch_fin(const FinEntry &e, hipStream_t s);
 

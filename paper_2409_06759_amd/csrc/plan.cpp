@@ -442,6 +442,13 @@ struct Planner {
     for (auto &w : work) add_slot(w[0], w[1], false, false, true);
     std::vector<OpSpec> custom_ops;
     if (p->custom) {
+      for (const OpText &o : p->custom->ops)
+        if (o.A == "t3" || o.B == "t3" || o.C == "Y3") p->triples = true;
+      if (p->triples) {
+        if (!ccsd) throw CCError(CC_EINVAL, "op list: triples need the CCSD method (singles and doubles)");
+        add_slot("t3", "ooovvv", false, true, false);
+        add_slot("Y3", "ooovvv", false, false, true);
+      }
       for (const auto &w : p->custom->work) {
         if (p->index.count(w.first)) throw CCError(CC_EINVAL, "op list: tensor " + w.first + " already exists");
         for (char c : w.second)
@@ -495,10 +502,27 @@ struct Planner {
         p->iter.push_back(f);
       }
     }
+    if (p->triples) {
+      const int y = slot("Y3");
+      if (!p->touched[y]) {
+        Step f;
+        f.kind = Step::FILL;
+        f.c = y;
+        f.nelem = p->slots[y].elems;
+        f.tag = "zero Y3";
+        p->iter.push_back(f);
+      }
+    }
     Step as;
     as.kind = Step::ASSEMBLE;
     as.tag = "r2_assemble_update";
     p->iter.push_back(as);
+    if (p->triples) {
+      Step t3s;
+      t3s.kind = Step::TRIPLES;
+      t3s.tag = "r3_antisymmetrise_update";
+      p->iter.push_back(t3s);
+    }
     if (ccsd) {
       Step r1;
       r1.kind = Step::R1UPD;
@@ -520,7 +544,7 @@ struct Planner {
 
 void *ptr_of(cc_plan *p, int s) {
   const Slot &sl = p->slots[s];
-  if (sl.external) return sl.name == "t1" ? p->t1 : p->t2;
+  if (sl.external) return sl.name == "t1" ? p->t1 : (sl.name == "t3" ? p->t3 : p->t2);
   return sl.ptr;
 }
 
@@ -528,7 +552,11 @@ namespace {
 
 int64_t slot_elems(const cc_plan *p, int s) {
   const Slot &sl = p->slots[s];
-  if (sl.external) return sl.name == "t1" ? int64_t(p->o) * p->v : int64_t(p->o) * p->o * p->v * p->v;
+  if (sl.external) {
+    if (sl.name == "t1") return int64_t(p->o) * p->v;
+    if (sl.name == "t3") return int64_t(p->o) * p->o * p->o * p->v * p->v * p->v;
+    return int64_t(p->o) * p->o * p->v * p->v;
+  }
   return sl.elems;
 }
 
@@ -672,8 +700,18 @@ R1Entry r1_entry(cc_plan *p) {
 }
 
 FinEntry fin_entry(cc_plan *p) {
-  return FinEntry{p->epart, p->n_epart, p->n2part, p->n_n2part,
-                  p->method == CC_CCSD ? p->n1part : nullptr, p->scalars};
+  FinEntry f{p->epart, p->n_epart, p->n2part, p->n_n2part,
+             p->method == CC_CCSD ? p->n1part : nullptr, p->scalars};
+  if (p->triples) {
+    f.n3part = p->n3part;
+    f.nn3 = p->n_n3part;
+  }
+  return f;
+}
+
+T3Entry t3_entry(cc_plan *p) {
+  return T3Entry{p->o, p->v, p->slots[p->index["Y3"]].ptr, p->r3_out, p->update ? p->t3 : nullptr,
+                 p->d_oo, p->d_vv, p->shift, p->n3part, t3_units(p->o, p->v)};
 }
 
 namespace {
@@ -722,6 +760,10 @@ void exec(cc_plan *p, Step &st, hipStream_t s) {
     }
     case Step::FINALIZE:
       launch_fin(fin_entry(p), s);
+      break;
+    case Step::TRIPLES:
+      CC_REQUIRE(p->t3 != nullptr, CC_EINVAL, "triples amplitudes not bound (cc_plan_set_triples)");
+      launch_t3(t3_entry(p), cplx, s);
       break;
   }
 }
@@ -799,6 +841,10 @@ void plan_build(cc_plan *p, const cc_system *sys) {
   p->epart = static_cast<double *>(dev_alloc(sizeof(double) * 2 * p->n_epart));
   p->n2part = static_cast<double *>(dev_alloc(sizeof(double) * p->n_n2part));
   p->n1part = static_cast<double *>(dev_alloc(sizeof(double) * 2));
+  if (p->triples) {
+    p->n_n3part = int(t3_units(p->o, p->v));
+    p->n3part = static_cast<double *>(dev_alloc(sizeof(double) * p->n_n3part));
+  }
   p->scalars = static_cast<double *>(dev_alloc(sizeof(double) * 4));
   hipStream_t s = p->ctx->stream;
   fock_diag(p->cplx, p->o, p->v, sys->f_oo, sys->f_vv, p->d_oo, p->d_vv, s);
@@ -841,7 +887,7 @@ void plan_free(cc_plan *p) {
     d.ref_op = d.ref_out = nullptr;
     d.dshadow = nullptr;
   }
-  for (double *q : {p->d_oo, p->d_vv, p->epart, p->n2part, p->n1part, p->scalars})
+  for (double *q : {p->d_oo, p->d_vv, p->epart, p->n2part, p->n1part, p->scalars, p->n3part})
     if (q) (void)hipFree(q);
 }
 
@@ -959,7 +1005,7 @@ std::string plan_profile_table(const cc_plan *p) {
   os << "# step kind tag calls total_ms avg_ms flops_per_call\n";
   for (size_t i = 0; i < p->step_ms.size() && i < p->iter.size(); ++i) {
     const Step &st = p->iter[i];
-    static const char *kinds[] = {"PERMUTE", "GEMM", "OUTER", "FILL", "TAU_E", "ASSEMBLE", "R1UPD", "FINALIZE"};
+    static const char *kinds[] = {"PERMUTE", "GEMM", "OUTER", "FILL", "TAU_E", "ASSEMBLE", "R1UPD", "FINALIZE", "TRIPLES"};
     std::string tag = st.tag.empty() ? "-" : st.tag;
     for (auto &c : tag)
       if (c == ' ') c = '_';
@@ -983,6 +1029,7 @@ void plan_run_energy(cc_plan *p) {
 
 std::string plan_describe(const cc_plan *p) {
   std::ostringstream os;
+  os.precision(17);  // coefficients round-trip exactly
   auto nm = [&](int s) { return s >= 0 ? p->slots[s].name : std::string("-"); };
   auto dump = [&](const char *title, const std::vector<Step> &v) {
     os << title << "\n";

@@ -44,7 +44,7 @@ struct Slot {
 };
 
 struct Step {
-  enum Kind { PERMUTE, GEMM, OUTER, FILL, TAU_E, ASSEMBLE, R1UPD, FINALIZE } kind;
+  enum Kind { PERMUTE, GEMM, OUTER, FILL, TAU_E, ASSEMBLE, R1UPD, FINALIZE, TRIPLES } kind;
   int a = -1, b = -1, c = -1, b2 = -1;  // b2: split-K workspace of a GEMM
   PermDesc perm{};
   GemmDesc gemm{};
@@ -95,6 +95,11 @@ struct cc_plan {
   bool cplx = false;
   size_t esize = 8;
   std::shared_ptr<ccmi::OpList> custom;  // null: the built-in contraction table
+  // triples (op lists that read t3 or accumulate Y3): bound per plan
+  bool triples = false;
+  void *t3 = nullptr, *r3_out = nullptr;
+  double *n3part = nullptr;
+  int n_n3part = 0;
   std::vector<ccmi::Slot> slots;
   std::map<std::string, int> index;
   std::vector<ccmi::Step> setup, iter;
@@ -148,6 +153,7 @@ std::string plan_describe(const cc_plan *p);
 void plan_autotune(cc_plan *p, int reps);
 std::string plan_profile_table(const cc_plan *p);
 TauEntry tau_entry(cc_plan *p);
+T3Entry t3_entry(cc_plan *p);
 AsmEntry asm_entry(cc_plan *p);
 R1Entry r1_entry(cc_plan *p);
 FinEntry fin_entry(cc_plan *p);

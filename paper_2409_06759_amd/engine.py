@@ -152,6 +152,12 @@ class Plan:
         self.ctx.enter()
         self.ctx.check(self.ctx.lib.cc_plan_autotune(self.h, C.byref(_amps(t1, t2)), reps))
 
+    def set_triples(self, t3, r3=None):
+        """Bind t3 (and optionally an R3 output) for a plan whose op list has
+        triples (cc_plan_set_triples)."""
+        self._triples = (t3, r3)
+        self.ctx.check(self.ctx.lib.cc_plan_set_triples(self.h, _ptr(t3), _ptr(r3)))
+
     def set_precision(self, prec: int):
         self.ctx.check(self.ctx.lib.cc_plan_set_precision(self.h, prec))
 

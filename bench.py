@@ -181,6 +181,32 @@ def bench_generated(ctx, E, torch, dsys, builtin_plan, reps=3):
     return res
 
 
+def bench_ccsdt(ctx, E, torch, o=10, v=40, steps=3):
+    """CCSDT iterations from the generated contraction list (t3 stored
+    dense, o^3 v^3 elements), bare-denominator Jacobi from t = 0."""
+    from ccinputs.synth import make_system
+    from paper_2409_06759_amd.codegen.emit import op_list
+    d = E.DeviceSystem(make_system(o, v), drop_host=True)
+    t1, t2 = E.zeros_amps(d, E.CCSD)
+    t3 = torch.zeros((o,) * 3 + (v,) * 3, dtype=torch.float64, device="cuda")
+    with E.Plan(ctx, d, E.CCSD, ops=op_list("ccsdt", o, v)) as p:
+        p.set_triples(t3)
+        p.step(t1, t2, 0.0, False)
+        p.autotune(t1, t2, 1)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        for _ in range(steps):
+            p.step(t1, t2, 0.0, False)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - ts) / steps
+        rn, e, _ = p.scalars()
+        res = {"o": o, "v": v, "ms_per_iteration": round(el * 1e3, 2), "flops": p.flops(),
+               "tflops": round(p.flops() / el / 1e12, 2), "t3_elements": o ** 3 * v ** 3,
+               "energy_after": e, "rnorm_after": rn, "iterations": steps + 1}
+    log(f"[bench] CCSDT (generated) {res}")
+    return res
+
+
 def bench_complex(ctx, E, torch, steps, warmup, o=40, v=200):
     """Complex128 Hermitian system: FP64 complex MFMA contraction steps."""
     from ccinputs.synth import make_system
@@ -257,11 +283,11 @@ def main():
                     help="contraction precision of the timed steps")
     ap.add_argument("--converge-precs", default="f64,f32,bf16x3",
                     help="precisions whose time to ||R||<1e-8 is reported (reduced ones refine in FP64)")
-    ap.add_argument("--extras", default="batched,learned,share,generated",
+    ap.add_argument("--extras", default="batched,learned,share,generated,ccsdt",
                     help="comma list of extra workloads reported in the same line: batched (64 uneven "
                          "systems), learned (time to 1e-8 from the trained network's guess), share (the "
                          "one-GPU share of an 8-GPU ladder), generated (the residual from the diagram "
-                         "generator's contraction list), complex "
+                         "generator's contraction list), ccsdt (CCSDT o=10 v=40 from the generated list), complex "
                          "(complex128 o=40 v=200); 'none' for no extras")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB copy (for HBM counter scaling)")
@@ -359,6 +385,8 @@ def main():
                 extras["generated"] = bench_generated(ctx, E, torch, dsys, plan)
         elif name == "share":
             extras["ladder_share_g8"] = bench_shard_share(ctx, E, torch, o, v)
+        elif name == "ccsdt":
+            extras["ccsdt"] = bench_ccsdt(ctx, E, torch)
         elif name == "complex":
             plan.close()
             plan_closed = True

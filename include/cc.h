@@ -101,6 +101,7 @@ typedef struct {
                           product of the change since the reference (defect correction); a new
                           reference is taken whenever ||R|| fell 1000-fold since the last one,
                           and convergence is confirmed by one plain FP64 step */
+  int32_t packed;      /* 1: particle-particle ladder over packed pairs (see CC_PLAN_PACKED_LADDER) */
 } cc_iter_opts;
 
 typedef struct {
@@ -133,6 +134,18 @@ const char *cc_status_string(int status);
  * views the contraction list needs and allocates the workspace. */
 int cc_plan_create(cc_ctx *ctx, const cc_system *sys, int method, int prec, cc_plan **plan);
 int cc_plan_destroy(cc_plan *plan);
+/* Plan options for cc_plan_create2. */
+enum {
+  /* The particle-particle ladder R_ij^ab += 1/2 sum_ef tau_ij^ef <ab||ef>
+   * evaluated over i<j, a<b, e<f only (the summand is symmetric in e<->f,
+   * and R is antisymmetric), one GEMM of o(o-1)/2 x v(v-1)/2 x v(v-1)/2:
+   * eight times fewer operations than the dense ladder, with a packed copy
+   * of vvvv (v^2 (v-1)^2 / 4 elements) made at plan creation.  Flop counts
+   * of such a plan count the packed ladder. */
+  CC_PLAN_PACKED_LADDER = 1
+};
+/* cc_plan_create with option flags (0 = cc_plan_create). */
+int cc_plan_create2(cc_ctx *ctx, const cc_system *sys, int method, int prec, int flags, cc_plan **plan);
 /* A plan whose residual contractions come from the text `ops` instead of the
  * built-in factorised table: the list emitted by the diagram generator
  * (paper, Sec. "Coupled cluster amplitude equations": the equations are

@@ -25,7 +25,7 @@ EXPORTS = (
     "cc_plan_create", "cc_plan_destroy", "cc_plan_workspace_bytes", "cc_plan_residual",
     "cc_plan_step", "cc_plan_scalars", "cc_residual", "cc_energy", "cc_iterate", "cc_gemm",
     "cc_permute", "cc_plan_describe", "cc_plan_describe_dry", "cc_plan_flops", "cc_plan_profile",
-    "cc_plan_profile_table", "cc_plan_autotune", "cc_plan_set_precision", "cc_plan_set_correction", "cc_gemm_tile_count", "cc_plan_create_ops", "cc_plan_describe_ops_dry", "cc_plan_set_triples", "cc_batch_create",
+    "cc_plan_profile_table", "cc_plan_autotune", "cc_plan_set_precision", "cc_plan_set_correction", "cc_gemm_tile_count", "cc_plan_create_ops", "cc_plan_describe_ops_dry", "cc_plan_set_triples", "cc_plan_create2", "cc_batch_create",
     "cc_batch_destroy", "cc_batch_step", "cc_batch_scalars", "cc_batch_autotune", "cc_batch_iterate",
     "cc_batch_profile", "cc_batch_profile_table", "cc_batch_flops", "cc_mlp_num_params",
     "cc_mlp_num_samples", "cc_mlp_features", "cc_mlp_targets", "cc_mlp_moments", "cc_mlp_forward",
@@ -47,7 +47,7 @@ class CCIterOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("prec", C.c_int32),
                 ("level_shift", C.c_double), ("refine_tol", C.c_double), ("use_graph", C.c_int32),
                 ("check_every", C.c_int32), ("diverge_window", C.c_int32), ("dressed", C.c_int32),
-                ("autotune", C.c_int32), ("correction", C.c_int32)]
+                ("autotune", C.c_int32), ("correction", C.c_int32), ("packed", C.c_int32)]
 
 
 class CCIterReport(C.Structure):
@@ -108,6 +108,7 @@ def load() -> C.CDLL:
         "cc_plan_create_ops": (C.c_int, [vp, P(CCSystemStruct), C.c_int, C.c_int, C.c_char_p, P(vp)]),
         "cc_plan_describe_ops_dry": (C.c_char_p, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_char_p]),
         "cc_plan_set_triples": (C.c_int, [vp, vp, vp]),
+        "cc_plan_create2": (C.c_int, [vp, P(CCSystemStruct), C.c_int, C.c_int, C.c_int, P(vp)]),
         "cc_batch_create": (C.c_int, [vp, C.c_int, P(CCSystemStruct), C.c_int, C.c_int, P(CCAmps), P(vp)]),
         "cc_batch_destroy": (C.c_int, [vp]),
         "cc_batch_step": (C.c_int, [vp, dbl, C.c_int]),

@@ -128,12 +128,13 @@ void run_step(cc_plan *p, bool use_graph) {
 }
 
 cc_plan *make_plan(cc_ctx *ctx, const cc_system *sys, int method, int prec,
-                   std::shared_ptr<ccmi::OpList> custom = nullptr) {
+                   std::shared_ptr<ccmi::OpList> custom = nullptr, bool packed = false) {
   validate_system(sys);
   validate_method(method, prec, sys->scalar);
   set_device(ctx);
   cc_plan *p = new cc_plan();
   p->custom = std::move(custom);
+  p->packed = packed;
   p->ctx = ctx;
   p->o = sys->o;
   p->v = sys->v;
@@ -228,6 +229,17 @@ int cc_plan_create(cc_ctx *ctx, const cc_system *sys, int method, int prec, cc_p
   *plan = nullptr;
   return guarded(ctx, [&] {
     *plan = make_plan(ctx, sys, method, prec);
+    return CC_OK;
+  });
+}
+
+int cc_plan_create2(cc_ctx *ctx, const cc_system *sys, int method, int prec, int flags, cc_plan **plan) {
+  if (!ctx) return fail(nullptr, CC_EINVAL, "ctx is NULL");
+  if (!plan) return fail(ctx, CC_EINVAL, "plan pointer is NULL");
+  *plan = nullptr;
+  return guarded(ctx, [&] {
+    if (flags & ~int(CC_PLAN_PACKED_LADDER)) throw CCError(CC_EINVAL, "unknown plan flags");
+    *plan = make_plan(ctx, sys, method, prec, nullptr, (flags & CC_PLAN_PACKED_LADDER) != 0);
     return CC_OK;
   });
 }
@@ -360,7 +372,7 @@ int cc_iterate(cc_ctx *ctx, const cc_system *sys, int method, const cc_iter_opts
     if (!(opts->level_shift >= 0.0)) throw CCError(CC_EINVAL, "level_shift must be >= 0");
     validate_amps(t, method, "t");
     const auto t0 = std::chrono::steady_clock::now();
-    cc_plan *p = make_plan(ctx, sys, method, opts->prec);
+    cc_plan *p = make_plan(ctx, sys, method, opts->prec, nullptr, opts->packed != 0);
     int status = CC_ENOTCONV;
     int iters = 0;
     double rn = NAN, er = NAN, ei = NAN, best = INFINITY;

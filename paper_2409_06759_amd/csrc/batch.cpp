@@ -592,7 +592,7 @@ const char *cc_batch_profile_table(const cc_batch *B) {
   static thread_local std::string s;
   s.clear();
   if (!B) return s.c_str();
-  static const char *kinds[] = {"PERMUTE", "GEMM", "OUTER", "FILL", "TAU_E", "ASSEMBLE", "R1UPD", "FINALIZE", "TRIPLES"};
+  static const char *kinds[] = {"PERMUTE", "GEMM", "OUTER", "FILL", "TAU_E", "ASSEMBLE", "R1UPD", "FINALIZE", "TRIPLES", "PAIR"};
   s = "# step kind tag calls total_ms avg_ms flops_per_call\n";
   for (size_t k = 0; k < B->gsteps.size() && k < B->step_ms.size(); ++k) {
     const auto &g = B->gsteps[k];

@@ -389,6 +389,21 @@ __device__ __forceinline__ void r1_body(const R1Entry &E) {
 }
 
 // scalars[0] = ||R||, scalars[1..2] = E (re, im); fixed summation order.
+template <class T>
+__device__ __forceinline__ void pair_body(const PairEntry &E, int64_t bid) {
+  const T *__restrict__ src = static_cast<const T *>(E.src);
+  T *__restrict__ dst = static_cast<T *>(E.dst);
+  const int64_t total = E.nP * E.nQ;
+  const int64_t e1 = std::min<int64_t>(total, (bid + 1) * CH);
+  for (int64_t e = bid * CH + threadIdx.x; e < e1; e += 256) {
+    const int64_t P = e / E.nQ, Q = e % E.nQ;
+    const int r0 = E.rows[2 * P], r1 = E.rows[2 * P + 1], c0 = E.cols[2 * Q], c1 = E.cols[2 * Q + 1];
+    const int64_t q = ((int64_t(r0) * E.d1 + r1) * E.d2 + c0) * E.d2 + c1;
+    if (E.scatter) dst[q] = add(dst[q], src[e]);
+    else dst[e] = src[q];
+  }
+}
+
 constexpr int64_t CH_T3 = 1024;
 
 // Triples: R3 = sum over permutations (s of ijk, r of abc) of
@@ -486,6 +501,7 @@ CC_EW_KERNELS(splitk, SplitkEntry, splitk_body)
 CC_EW_KERNELS(tau, TauEntry, tau_body)
 CC_EW_KERNELS(asm, AsmEntry, asm_body)
 CC_EW_KERNELS(t3, T3Entry, t3_body)
+CC_EW_KERNELS(pair, PairEntry, pair_body)
 
 template <class T>
 __global__ __launch_bounds__(RED_THREADS) void k_r1(R1Entry e) { r1_body<T>(e); }
@@ -579,6 +595,11 @@ TauEntry make_tau_entry(int o, int v, const void *t1, const void *t2, const void
 
 int64_t t3_units(int o, int v) { return chunks(int64_t(o) * o * o * v * v * v, CH_T3); }
 
+PairEntry make_pair_entry(const void *src, void *dst, const int *rows, const int *cols, int64_t nP, int64_t nQ,
+                          int64_t d1, int64_t d2, int scatter) {
+  return PairEntry{src, dst, rows, cols, nP, nQ, d1, d2, scatter, nP * nQ > 0 ? chunks(nP * nQ, CH) : 0};
+}
+
 int64_t asm_units(int o, int v) {
   const int64_t tiles = (v + 31) / 32;
   return (int64_t(o) * (o + 1) / 2) * (tiles * (tiles + 1) / 2);
@@ -618,6 +639,7 @@ void launch_splitk(const SplitkEntry &e, bool cplx, hipStream_t s) { CC_LAUNCH1(
 void launch_tau(const TauEntry &e, bool cplx, hipStream_t s) { CC_LAUNCH1(k_tau, e, e.units, cplx, s); }
 void launch_asm(const AsmEntry &e, bool cplx, hipStream_t s) { CC_LAUNCH1(k_asm, e, e.units, cplx, s); }
 void launch_t3(const T3Entry &e, bool cplx, hipStream_t s) { CC_LAUNCH1(k_t3, e, e.units, cplx, s); }
+void launch_pair(const PairEntry &e, bool cplx, hipStream_t s) { CC_LAUNCH1(k_pair, e, e.units, cplx, s); }
 void launch_r1(const R1Entry &e, bool cplx, hipStream_t s) {
   if (cplx) hipLaunchKernelGGL(k_r1<double2>, dim3(1), dim3(RED_THREADS), 0, s, e);
   else hipLaunchKernelGGL(k_r1<double>, dim3(1), dim3(RED_THREADS), 0, s, e);

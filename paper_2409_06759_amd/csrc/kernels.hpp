@@ -113,6 +113,18 @@ struct FinEntry {
   int nn3 = 0;
 };
 
+// Packed pair storage (i<j, a<b): gather dst[P][Q] = src[r(P)][c(Q)] from a
+// [d1][d1][d2][d2] tensor, or scatter-add dst4[r(P)][c(Q)] += src[P][Q].
+struct PairEntry {
+  const void *src;
+  void *dst;
+  const int *rows, *cols;  // pair tables: rows[2P], rows[2P+1] (first < second)
+  int64_t nP, nQ;
+  int64_t d1, d2;
+  int scatter;
+  int64_t units;
+};
+
 // R3 = full antisymmetriser of the accumulated triples contributions Y3
 // (sum over the 36 signed permutations of (ijk) and (abc)), exact zeros for
 // repeated indices, optional Jacobi update t3 += R3 / (D - shift) with bare
@@ -141,6 +153,8 @@ AsmEntry make_asm_entry(const R2Args &a, const void *XP, const void *Xij, const 
 int64_t tau_units(int o, int v);
 int64_t asm_units(int o, int v);
 int64_t t3_units(int o, int v);
+PairEntry make_pair_entry(const void *src, void *dst, const int *rows, const int *cols, int64_t nP, int64_t nQ,
+                          int64_t d1, int64_t d2, int scatter);
 
 // ---- single launches ---------------------------------------------------------
 void launch_perm(const PermEntry &e, bool cplx, hipStream_t s);
@@ -150,6 +164,7 @@ void launch_splitk(const SplitkEntry &e, bool cplx, hipStream_t s);
 void launch_tau(const TauEntry &e, bool cplx, hipStream_t s);
 void launch_asm(const AsmEntry &e, bool cplx, hipStream_t s);
 void launch_t3(const T3Entry &e, bool cplx, hipStream_t s);
+void launch_pair(const PairEntry &e, bool cplx, hipStream_t s);
 void launch_r1(const R1Entry &e, bool cplx, hipStream_t s);
 void launch_fin(const FinEntry &e, hipStream_t s);
 

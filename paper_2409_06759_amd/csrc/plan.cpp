@@ -408,6 +408,65 @@ struct Planner {
     p->version[c]++;
   }
 
+  // R2(ij,ab) += alpha sum_ef tau(ij,ef) V(ab,ef) over i<j, a<b, e<f only:
+  // the summand is symmetric under e<->f, so the packed sum carries 2 alpha.
+  void packed_ladder(const OpSpec &op) {
+    const int64_t no = int64_t(p->o) * (p->o - 1) / 2, nv = int64_t(p->v) * (p->v - 1) / 2;
+    const int c = slot(op.C), a = slot(op.A);
+    if (no == 0 || nv == 0) return;  // no canonical element: nothing to add
+    Step g1;
+    g1.kind = Step::PAIR;
+    g1.a = a;
+    g1.c = slot("taup");
+    g1.pair_np = no;
+    g1.pair_nq = nv;
+    g1.pair_d1 = p->o;
+    g1.pair_d2 = p->v;
+    g1.pair_rows = 0;
+    g1.pair_cols = 1;
+    g1.tag = "pack_tau";
+    p->iter.push_back(g1);
+    p->version[g1.c]++;
+    Step g;
+    g.kind = Step::GEMM;
+    g.a = slot("taup");
+    g.b = slot("vvvvp");
+    g.c = slot("XPp");
+    g.gemm.M = no;
+    g.gemm.N = nv;
+    g.gemm.K = nv;
+    g.gemm.sam = nv;
+    g.gemm.sak = 1;
+    g.gemm.sbn = nv;
+    g.gemm.sbk = 1;
+    g.gemm.ldc = nv;
+    g.gemm.alpha = 2.0 * op.alpha;
+    g.gemm.beta = 0.0;
+    g.gemm.ladder = 1;
+    g.flops = (p->cplx ? 8.0 : 2.0) * double(no) * double(nv) * double(nv);
+    g.tag = "ladder";
+    g.gemm.split = gemm_split_pick(no, nv, nv, -1);
+    if (g.gemm.split > 1) {
+      splitws_elems = std::max<int64_t>(splitws_elems, int64_t(g.gemm.split) * no * nv);
+      g.b2 = splitws;
+    }
+    g.tile = p->cplx ? -1 : gemm_f64_pick(no, nv, nv, true, true);
+    p->iter.push_back(g);
+    p->version[g.c]++;
+    p->flops_per_iter += g.flops;
+    p->ladder_flops += g.flops;
+    Step g2 = g1;
+    g2.a = slot("XPp");
+    g2.c = c;
+    g2.pair_rows = 0;
+    g2.pair_cols = 1;
+    g2.pair_scatter = 1;
+    g2.tag = "unpack_ladder";
+    if (!p->touched[c]) throw CCError(CC_EINTERNAL, "packed ladder before the first write of its target");
+    p->iter.push_back(g2);
+    p->version[c]++;
+  }
+
   void unary(const OpSpec &op) {
     const int c = slot(op.C), a = slot(op.A);
     check_labels(c, op.cl);
@@ -465,6 +524,29 @@ struct Planner {
     }
     scratch = add_work("scratch", {1});
     splitws = add_work("splitk_ws", {1});
+    if (p->packed) {
+      if (p->custom) throw CCError(CC_EINVAL, "the packed ladder applies to the built-in table");
+      const int64_t no = std::max<int64_t>(1, int64_t(p->o) * (p->o - 1) / 2);
+      const int64_t nv = std::max<int64_t>(1, int64_t(p->v) * (p->v - 1) / 2);
+      add_work("taup", {no, nv});
+      add_work("XPp", {no, nv});
+      const int vp = add_work("vvvvp", {nv, nv});
+      p->slots[vp].constant = true;
+      if (int64_t(p->v) * (p->v - 1) / 2 > 0) {
+        Step st;
+        st.kind = Step::PAIR;
+        st.a = slot("vvvv");
+        st.c = vp;
+        st.pair_np = nv;
+        st.pair_nq = nv;
+        st.pair_d1 = p->v;
+        st.pair_d2 = p->v;
+        st.pair_rows = 1;
+        st.pair_cols = 1;
+        st.tag = "pack_vvvv";
+        p->setup.push_back(st);
+      }
+    }
 
     Step te;
     te.kind = Step::TAU_E;
@@ -478,6 +560,7 @@ struct Planner {
           continue;
         }
         if (op.B == nullptr) unary(op);
+        else if (p->packed && std::string(op.tag) == "ladder") packed_ladder(op);
         else contract(op);
       }
     };
@@ -761,6 +844,12 @@ void exec(cc_plan *p, Step &st, hipStream_t s) {
     case Step::FINALIZE:
       launch_fin(fin_entry(p), s);
       break;
+    case Step::PAIR:
+      launch_pair(make_pair_entry(ptr_of(p, st.a), ptr_of(p, st.c), st.pair_rows ? p->pairs_v : p->pairs_o,
+                                  st.pair_cols ? p->pairs_v : p->pairs_o, st.pair_np, st.pair_nq, st.pair_d1,
+                                  st.pair_d2, st.pair_scatter),
+                  cplx, s);
+      break;
     case Step::TRIPLES:
       CC_REQUIRE(p->t3 != nullptr, CC_EINVAL, "triples amplitudes not bound (cc_plan_set_triples)");
       launch_t3(t3_entry(p), cplx, s);
@@ -849,6 +938,22 @@ void plan_build(cc_plan *p, const cc_system *sys) {
   hipStream_t s = p->ctx->stream;
   fock_diag(p->cplx, p->o, p->v, sys->f_oo, sys->f_vv, p->d_oo, p->d_vv, s);
   fill_zero(p->n1part, 2, false, s);
+  if (p->packed) {
+    auto table = [&](int n, int **dst) {
+      std::vector<int> h;
+      for (int x = 0; x < n; ++x)
+        for (int y = x + 1; y < n; ++y) {
+          h.push_back(x);
+          h.push_back(y);
+        }
+      if (h.empty()) h.assign(2, 0);
+      *dst = static_cast<int *>(dev_alloc(sizeof(int) * h.size()));
+      CC_HIP_CHECK(hipMemcpyAsync(*dst, h.data(), sizeof(int) * h.size(), hipMemcpyHostToDevice, s));
+      CC_HIP_CHECK(hipStreamSynchronize(s));
+    };
+    table(p->o, &p->pairs_o);
+    table(p->v, &p->pairs_v);
+  }
   for (Step &st : p->setup) exec(p, st, s);
   CC_HIP_CHECK(hipStreamSynchronize(s));
   for (Step &st : p->iter)
@@ -888,6 +993,8 @@ void plan_free(cc_plan *p) {
     d.dshadow = nullptr;
   }
   for (double *q : {p->d_oo, p->d_vv, p->epart, p->n2part, p->n1part, p->scalars, p->n3part})
+    if (q) (void)hipFree(q);
+  for (int *q : {p->pairs_o, p->pairs_v})
     if (q) (void)hipFree(q);
 }
 
@@ -1005,7 +1112,7 @@ std::string plan_profile_table(const cc_plan *p) {
   os << "# step kind tag calls total_ms avg_ms flops_per_call\n";
   for (size_t i = 0; i < p->step_ms.size() && i < p->iter.size(); ++i) {
     const Step &st = p->iter[i];
-    static const char *kinds[] = {"PERMUTE", "GEMM", "OUTER", "FILL", "TAU_E", "ASSEMBLE", "R1UPD", "FINALIZE", "TRIPLES"};
+    static const char *kinds[] = {"PERMUTE", "GEMM", "OUTER", "FILL", "TAU_E", "ASSEMBLE", "R1UPD", "FINALIZE", "TRIPLES", "PAIR"};
     std::string tag = st.tag.empty() ? "-" : st.tag;
     for (auto &c : tag)
       if (c == ' ') c = '_';

@@ -44,7 +44,7 @@ struct Slot {
 };
 
 struct Step {
-  enum Kind { PERMUTE, GEMM, OUTER, FILL, TAU_E, ASSEMBLE, R1UPD, FINALIZE, TRIPLES } kind;
+  enum Kind { PERMUTE, GEMM, OUTER, FILL, TAU_E, ASSEMBLE, R1UPD, FINALIZE, TRIPLES, PAIR } kind;
   int a = -1, b = -1, c = -1, b2 = -1;  // b2: split-K workspace of a GEMM
   PermDesc perm{};
   GemmDesc gemm{};
@@ -53,6 +53,10 @@ struct Step {
   int tile_lp[3] = {-1, -1, -1};  // per reduced precision (index = cc_prec)
   int tile_z = -1;      // complex128 tile
   int delta = -1;       // index into cc_plan::deltas (GEMM linear in the amplitudes)
+  // PAIR: gather a (i<j, a<b) packed copy of slot a into slot c, or
+  // scatter-add slot a into slot c; row/col tables 0 = occupied pairs, 1 = virtual pairs
+  int64_t pair_np = 0, pair_nq = 0, pair_d1 = 0, pair_d2 = 0;
+  int pair_rows = 0, pair_cols = 0, pair_scatter = 0;
   int64_t nelem = 0;
   double flops = 0.0;
   std::string tag;
@@ -95,6 +99,9 @@ struct cc_plan {
   bool cplx = false;
   size_t esize = 8;
   std::shared_ptr<ccmi::OpList> custom;  // null: the built-in contraction table
+  // particle-particle ladder over packed pairs (i<j, e<f, a<b)
+  bool packed = false;
+  int *pairs_o = nullptr, *pairs_v = nullptr;  // device pair tables
   // triples (op lists that read t3 or accumulate Y3): bound per plan
   bool triples = false;
   void *t3 = nullptr, *r3_out = nullptr;

@@ -109,12 +109,13 @@ class Plan:
     contraction list such as `codegen.emit.op_list` (cc_plan_create_ops)."""
 
     def __init__(self, ctx: Context, dsys: DeviceSystem, method: int = CCSD, prec: int = F64,
-                 ops: Optional[str] = None):
+                 ops: Optional[str] = None, packed: bool = False):
         self.ctx, self.dsys, self.method = ctx, dsys, method
         self.h = C.c_void_p()
         ctx.enter()
         if ops is None:
-            ctx.check(ctx.lib.cc_plan_create(ctx.h, C.byref(dsys.struct), method, prec, C.byref(self.h)))
+            ctx.check(ctx.lib.cc_plan_create2(ctx.h, C.byref(dsys.struct), method, prec, 1 if packed else 0,
+                                              C.byref(self.h)))
         else:
             ctx.check(ctx.lib.cc_plan_create_ops(ctx.h, C.byref(dsys.struct), method, prec, ops.encode(),
                                                  C.byref(self.h)))
@@ -214,7 +215,7 @@ def energy(ctx, dsys, method, t1, t2):
 
 def iterate(ctx, dsys, method, t1, t2, tol=1e-8, max_iter=100, level_shift=0.0, prec=F64,
             use_graph=True, refine_tol=0.0, diverge_window=0, hist_cap=None, dressed=False,
-            autotune=False, correction=True):
+            autotune=False, correction=True, packed=False):
     """Jacobi iteration (cc_iterate).  Reduced `prec` runs its contractions in
     that precision until the norm stagnates, then finishes with FP64 steps
     (with `correction`, in reference + reduced-precision-correction form for
@@ -223,7 +224,8 @@ def iterate(ctx, dsys, method, t1, t2, tol=1e-8, max_iter=100, level_shift=0.0, 
     hr = (C.c_double * cap)()
     he = (C.c_double * cap)()
     opts = L.CCIterOpts(tol, max_iter, prec, level_shift, refine_tol, 1 if use_graph else 0, 1,
-                        diverge_window, 1 if dressed else 0, 1 if autotune else 0, 1 if correction else 0)
+                        diverge_window, 1 if dressed else 0, 1 if autotune else 0, 1 if correction else 0,
+                        1 if packed else 0)
     rep = L.CCIterReport(0, 0, 0.0, 0.0, 0.0, 0.0, 0.0, 0, 0, C.cast(hr, C.POINTER(C.c_double)),
                          C.cast(he, C.POINTER(C.c_double)), cap)
     ctx.enter()
@@ -299,7 +301,7 @@ class Batch:
 
     def iterate(self, tol=1e-8, max_iter=200, level_shift=0.0, dressed=False, prec=F64, use_graph=True):
         opts = L.CCIterOpts(tol, max_iter, prec, level_shift, 0.0, 1 if use_graph else 0, 1, 0,
-                            1 if dressed else 0, 0, 0)
+                            1 if dressed else 0, 0, 0, 0)
         reps = (L.CCIterReport * self.n)()
         nconv = C.c_int32()
         self.ctx.enter()

@@ -181,6 +181,44 @@ def bench_generated(ctx, E, torch, dsys, builtin_plan, reps=3):
     return res
 
 
+def bench_packed(ctx, E, torch, dsys, f64_seconds, steps=10):
+    """The same CCSD workload with the ladder over packed pairs (i<j, a<b,
+    e<f): step time (TFLOP/s of the packed count) and time to ||R|| < 1e-8
+    in FP64 and with split-bf16 contractions plus FP64 refinement."""
+    out = {}
+    with E.Plan(ctx, dsys, E.CCSD, packed=True) as p:
+        t1, t2 = E.zeros_amps(dsys, E.CCSD)
+        p.step(t1, t2, 0.0, True)
+        p.autotune(t1, t2, 2)
+        p.step(t1, t2, 0.0, True)
+        p.profile(True)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        for _ in range(steps):
+            p.step(t1, t2, 0.0, True)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - ts) / steps
+        rows = p.profile_table()
+        lad = [r for r in rows if r[1] == "GEMM" and r[2].startswith("ladder@")]
+        out["ms_per_step"] = round(el * 1e3, 3)
+        out["flops_per_step"] = p.flops()
+        out["tflops"] = round(p.flops() / el / 1e12, 2)
+        if lad:
+            lf = p.flops(ladder_only=True)
+            out["ladder_ms"] = round(lad[0][5], 3)
+            out["ladder_tflops"] = round(lf / (lad[0][5] / 1e3) / 1e12, 2)
+    for pname in ("f64", "bf16x3"):
+        u1, u2 = E.zeros_amps(dsys, E.CCSD)
+        r = E.iterate(ctx, dsys, E.CCSD, u1, u2, tol=1e-8, max_iter=1500, dressed=True, autotune=True,
+                      prec=E.PRECS[pname], packed=True)
+        out[f"time_to_1e-8_{pname}"] = {"converged": r["converged"], "iterations": r["iters"],
+                                        "seconds": round(r["seconds"], 3), "energy": r["energy"],
+                                        "speedup_vs_dense_f64": round(f64_seconds / r["seconds"], 3)
+                                        if f64_seconds else None}
+    log(f"[bench] packed ladder: {out}")
+    return out
+
+
 def bench_ccsdt(ctx, E, torch, o=10, v=40, steps=3):
     """CCSDT iterations from the generated contraction list (t3 stored
     dense, o^3 v^3 elements), bare-denominator Jacobi from t = 0."""
@@ -283,8 +321,9 @@ def main():
                     help="contraction precision of the timed steps")
     ap.add_argument("--converge-precs", default="f64,f32,bf16x3",
                     help="precisions whose time to ||R||<1e-8 is reported (reduced ones refine in FP64)")
-    ap.add_argument("--extras", default="batched,learned,share,generated,ccsdt",
-                    help="comma list of extra workloads reported in the same line: batched (64 uneven "
+    ap.add_argument("--extras", default="packed,batched,learned,share,generated,ccsdt",
+                    help="comma list of extra workloads reported in the same line: packed (the ladder "
+                         "over i<j, a<b, e<f), batched (64 uneven "
                          "systems), learned (time to 1e-8 from the trained network's guess), share (the "
                          "one-GPU share of an 8-GPU ladder), generated (the residual from the diagram "
                          "generator's contraction list), ccsdt (CCSDT o=10 v=40 from the generated list), complex "
@@ -385,6 +424,9 @@ def main():
                 extras["generated"] = bench_generated(ctx, E, torch, dsys, plan)
         elif name == "share":
             extras["ladder_share_g8"] = bench_shard_share(ctx, E, torch, o, v)
+        elif name == "packed":
+            if args.config == "c2":
+                extras["packed_ladder"] = bench_packed(ctx, E, torch, dsys, conv.get("f64", {}).get("seconds"))
         elif name == "ccsdt":
             extras["ccsdt"] = bench_ccsdt(ctx, E, torch)
         elif name == "complex":

@@ -136,12 +136,13 @@ int cc_plan_create(cc_ctx *ctx, const cc_system *sys, int method, int prec, cc_p
 int cc_plan_destroy(cc_plan *plan);
 /* Plan options for cc_plan_create2. */
 enum {
-  /* The particle-particle ladder R_ij^ab += 1/2 sum_ef tau_ij^ef <ab||ef>
-   * evaluated over i<j, a<b, e<f only (the summand is symmetric in e<->f,
-   * and R is antisymmetric), one GEMM of o(o-1)/2 x v(v-1)/2 x v(v-1)/2:
-   * eight times fewer operations than the dense ladder, with a packed copy
-   * of vvvv (v^2 (v-1)^2 / 4 elements) made at plan creation.  Flop counts
-   * of such a plan count the packed ladder. */
+  /* Contractions over canonical index pairs only (summands symmetric under
+   * the summed pair swap, R antisymmetric): the particle-particle ladder
+   * 1/2 sum_ef tau_ij^ef <ab||ef> as one GEMM of o(o-1)/2 x v(v-1)/2 x
+   * v(v-1)/2 (eight times fewer operations), the hole-hole ladder
+   * 1/2 sum_mn W_mnij tau_mn^ab over m<n, i<j, a<b, and Z_ij^am over e<f,
+   * i<j.  Packed copies of vvvv and ovvv are made at plan creation.  Flop
+   * counts of such a plan count the packed operations. */
   CC_PLAN_PACKED_LADDER = 1
 };
 /* cc_plan_create with option flags (0 = cc_plan_create). */

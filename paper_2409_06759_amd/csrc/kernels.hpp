@@ -113,15 +113,17 @@ struct FinEntry {
   int nn3 = 0;
 };
 
-// Packed pair storage (i<j, a<b): gather dst[P][Q] = src[r(P)][c(Q)] from a
-// [d1][d1][d2][d2] tensor, or scatter-add dst4[r(P)][c(Q)] += src[P][Q].
+// Packed index pairs: for a rank-4 tensor X[n0][n1][n2][n3] and index-pair
+// tables rows (P -> (x0, x1)) and cols (Q -> (x2, x3)):
+// mode 0 gathers dst[P][Q] = X[x0][x1][x2][x3] (X = src), mode 1 scatters
+// X[..] += src[P][Q] and mode 2 sets X[..] = src[P][Q] (X = dst).
 struct PairEntry {
   const void *src;
   void *dst;
-  const int *rows, *cols;  // pair tables: rows[2P], rows[2P+1] (first < second)
+  const int *rows, *cols;  // rows[2P], rows[2P+1]; cols[2Q], cols[2Q+1]
   int64_t nP, nQ;
-  int64_t d1, d2;
-  int scatter;
+  int64_t n1, n2, n3;      // dims 1..3 of X (dim 0 is implied)
+  int mode;
   int64_t units;
 };
 
@@ -154,7 +156,7 @@ int64_t tau_units(int o, int v);
 int64_t asm_units(int o, int v);
 int64_t t3_units(int o, int v);
 PairEntry make_pair_entry(const void *src, void *dst, const int *rows, const int *cols, int64_t nP, int64_t nQ,
-                          int64_t d1, int64_t d2, int scatter);
+                          int64_t n1, int64_t n2, int64_t n3, int mode);
 
 // ---- single launches ---------------------------------------------------------
 void launch_perm(const PermEntry &e, bool cplx, hipStream_t s);

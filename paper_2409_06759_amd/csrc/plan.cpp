@@ -408,63 +408,120 @@ struct Planner {
     p->version[c]++;
   }
 
-  // R2(ij,ab) += alpha sum_ef tau(ij,ef) V(ab,ef) over i<j, a<b, e<f only:
-  // the summand is symmetric under e<->f, so the packed sum carries 2 alpha.
-  void packed_ladder(const OpSpec &op) {
-    const int64_t no = int64_t(p->o) * (p->o - 1) / 2, nv = int64_t(p->v) * (p->v - 1) / 2;
-    const int c = slot(op.C), a = slot(op.A);
-    if (no == 0 || nv == 0) return;  // no canonical element: nothing to add
-    Step g1;
-    g1.kind = Step::PAIR;
-    g1.a = a;
-    g1.c = slot("taup");
-    g1.pair_np = no;
-    g1.pair_nq = nv;
-    g1.pair_d1 = p->o;
-    g1.pair_d2 = p->v;
-    g1.pair_rows = 0;
-    g1.pair_cols = 1;
-    g1.tag = "pack_tau";
-    p->iter.push_back(g1);
-    p->version[g1.c]++;
+  // ---- packed index pairs (i<j, m<n, a<b, e<f) ----------------------------
+  int tau_packed_version = -1;
+
+  Step pair_step(int a, int c, int64_t np, int64_t nq, int64_t n1, int64_t n2, int64_t n3, int rows, int cols,
+                 int mode, const char *tag) {
+    Step st;
+    st.kind = Step::PAIR;
+    st.a = a;
+    st.c = c;
+    st.pair_np = np;
+    st.pair_nq = nq;
+    st.pair_n[0] = n1;
+    st.pair_n[1] = n2;
+    st.pair_n[2] = n3;
+    st.pair_rows = rows;
+    st.pair_cols = cols;
+    st.pair_mode = mode;
+    st.tag = tag;
+    return st;
+  }
+
+  // tau packed over i<j (rows) and e<f (columns), gathered once per version of tau
+  int ensure_taup() {
+    const int tau = slot("tau"), tp = slot("taup");
+    if (tau_packed_version != p->version[tau]) {
+      const int64_t no = int64_t(p->o) * (p->o - 1) / 2, nv = int64_t(p->v) * (p->v - 1) / 2;
+      p->iter.push_back(pair_step(tau, tp, no, nv, p->o, p->v, p->v, 0, 1, 0, "pack_tau"));
+      p->version[tp]++;
+      tau_packed_version = p->version[tau];
+    }
+    return tp;
+  }
+
+  Step packed_gemm(int a, int b, int c, int64_t M, int64_t N, int64_t K, bool akc, bool bkc, double alpha,
+                   const char *tag) {
     Step g;
     g.kind = Step::GEMM;
-    g.a = slot("taup");
-    g.b = slot("vvvvp");
-    g.c = slot("XPp");
-    g.gemm.M = no;
-    g.gemm.N = nv;
-    g.gemm.K = nv;
-    g.gemm.sam = nv;
-    g.gemm.sak = 1;
-    g.gemm.sbn = nv;
-    g.gemm.sbk = 1;
-    g.gemm.ldc = nv;
-    g.gemm.alpha = 2.0 * op.alpha;
+    g.a = a;
+    g.b = b;
+    g.c = c;
+    g.gemm.M = M;
+    g.gemm.N = N;
+    g.gemm.K = K;
+    g.gemm.sam = akc ? K : 1;
+    g.gemm.sak = akc ? 1 : M;
+    g.gemm.sbn = bkc ? K : 1;
+    g.gemm.sbk = bkc ? 1 : N;
+    g.gemm.ldc = N;
+    g.gemm.alpha = alpha;
     g.gemm.beta = 0.0;
-    g.gemm.ladder = 1;
-    g.flops = (p->cplx ? 8.0 : 2.0) * double(no) * double(nv) * double(nv);
-    g.tag = "ladder";
-    g.gemm.split = gemm_split_pick(no, nv, nv, -1);
+    g.gemm.ladder = std::string(tag) == "ladder" ? 1 : 0;
+    g.flops = (p->cplx ? 8.0 : 2.0) * double(M) * double(N) * double(K);
+    g.tag = tag;
+    g.gemm.split = gemm_split_pick(M, N, K, -1);
     if (g.gemm.split > 1) {
-      splitws_elems = std::max<int64_t>(splitws_elems, int64_t(g.gemm.split) * no * nv);
+      splitws_elems = std::max<int64_t>(splitws_elems, int64_t(g.gemm.split) * M * N);
       g.b2 = splitws;
     }
-    g.tile = p->cplx ? -1 : gemm_f64_pick(no, nv, nv, true, true);
-    p->iter.push_back(g);
-    p->version[g.c]++;
+    g.tile = p->cplx ? -1 : gemm_f64_pick(M, N, K, akc, bkc);
     p->flops_per_iter += g.flops;
-    p->ladder_flops += g.flops;
-    Step g2 = g1;
-    g2.a = slot("XPp");
-    g2.c = c;
-    g2.pair_rows = 0;
-    g2.pair_cols = 1;
-    g2.pair_scatter = 1;
-    g2.tag = "unpack_ladder";
-    if (!p->touched[c]) throw CCError(CC_EINTERNAL, "packed ladder before the first write of its target");
-    p->iter.push_back(g2);
+    if (g.gemm.ladder) p->ladder_flops += g.flops;
+    return g;
+  }
+
+  // Contractions whose summed index pair (e<f or m<n) and output pairs
+  // (i<j, a<b) can run over canonical pairs only: the summand is symmetric
+  // under the summed swap (factor 2 on a sum over half of it), and only the
+  // canonical i<j (a<b) elements of the target are read later.
+  //   ladder:    XP(ij,ab)  += 1/2 sum_ef tau(ij,ef) <ab||ef>
+  //   hh_ladder: XP(ij,ab)  += 1/2 sum_mn W(mn,ij) tau(mn,ab)
+  //   Z:         Zs(ij,am)   =     sum_ef tau(ij,ef) <ma||ef>
+  bool packed_op(const OpSpec &op) {
+    const std::string tag = op.tag;
+    if (tag != "ladder" && tag != "hh_ladder" && tag != "Z") return false;
+    const int64_t no = int64_t(p->o) * (p->o - 1) / 2, nv = int64_t(p->v) * (p->v - 1) / 2;
+    const int c = slot(op.C);
+    if (no == 0 || nv == 0) {  // no canonical pair: the term contributes nothing that is read
+      if (tag == "Z") {
+        if (!p->touched[c]) {
+          Step f;
+          f.kind = Step::FILL;
+          f.c = c;
+          f.nelem = p->slots[c].elems;
+          f.tag = "zero Zs";
+          p->iter.push_back(f);
+          p->touched[c] = true;
+          p->version[c]++;
+        }
+      }
+      return true;
+    }
+    const int tp = ensure_taup();
+    const int xp = slot("XPp");
+    if (tag == "ladder") {
+      p->iter.push_back(packed_gemm(tp, slot("vvvvp"), xp, no, nv, nv, true, true, 2.0 * op.alpha, "ladder"));
+      p->iter.push_back(pair_step(xp, c, no, nv, p->o, p->v, p->v, 0, 1, 1, "unpack_ladder"));
+    } else if (tag == "hh_ladder") {
+      const int wg = slot("Wp");
+      p->iter.push_back(pair_step(slot("Wmnij"), wg, no, no, p->o, p->o, p->o, 0, 0, 0, "pack_Wmnij"));
+      p->version[wg]++;
+      // C(ij, ab) = sum_{m<n} Wp[mn][ij] taup[mn][ab]: both operands stored [K][...]
+      p->iter.push_back(packed_gemm(wg, tp, xp, no, nv, no, false, false, 2.0 * op.alpha, "hh_ladder"));
+      p->iter.push_back(pair_step(xp, c, no, nv, p->o, p->v, p->v, 0, 1, 1, "unpack_hh_ladder"));
+    } else {
+      const int zp = slot("Zp");
+      const int64_t nov = int64_t(p->o) * p->v;
+      p->iter.push_back(packed_gemm(tp, slot("ovvvp"), zp, no, nov, nv, true, true, 2.0 * op.alpha, "Z"));
+      // Zs[i][j][a][m] (i<j) <- Zp[ij][m a]; rows i>j stay as set up (zero)
+      p->iter.push_back(pair_step(zp, c, no, nov, p->o, p->v, p->o, 0, 3, 2, "unpack_Z"));
+    }
+    if (!p->touched[c] && tag != "Z") throw CCError(CC_EINTERNAL, "packed op before the first write of its target");
+    p->touched[c] = true;
     p->version[c]++;
+    return true;
   }
 
   void unary(const OpSpec &op) {
@@ -525,27 +582,29 @@ struct Planner {
     scratch = add_work("scratch", {1});
     splitws = add_work("splitk_ws", {1});
     if (p->packed) {
-      if (p->custom) throw CCError(CC_EINVAL, "the packed ladder applies to the built-in table");
-      const int64_t no = std::max<int64_t>(1, int64_t(p->o) * (p->o - 1) / 2);
-      const int64_t nv = std::max<int64_t>(1, int64_t(p->v) * (p->v - 1) / 2);
+      if (p->custom) throw CCError(CC_EINVAL, "packed pairs apply to the built-in table");
+      const int64_t no0 = int64_t(p->o) * (p->o - 1) / 2, nv0 = int64_t(p->v) * (p->v - 1) / 2;
+      const int64_t no = std::max<int64_t>(1, no0), nv = std::max<int64_t>(1, nv0);
+      const int64_t nov = int64_t(p->o) * p->v;
       add_work("taup", {no, nv});
       add_work("XPp", {no, nv});
+      add_work("Wp", {no, no});
+      add_work("Zp", {no, nov});
       const int vp = add_work("vvvvp", {nv, nv});
+      const int op_ = add_work("ovvvp", {nov, nv});
       p->slots[vp].constant = true;
-      if (int64_t(p->v) * (p->v - 1) / 2 > 0) {
-        Step st;
-        st.kind = Step::PAIR;
-        st.a = slot("vvvv");
-        st.c = vp;
-        st.pair_np = nv;
-        st.pair_nq = nv;
-        st.pair_d1 = p->v;
-        st.pair_d2 = p->v;
-        st.pair_rows = 1;
-        st.pair_cols = 1;
-        st.tag = "pack_vvvv";
-        p->setup.push_back(st);
+      p->slots[op_].constant = true;
+      if (nv0 > 0) {
+        p->setup.push_back(pair_step(slot("vvvv"), vp, nv, nv, p->v, p->v, p->v, 1, 1, 0, "pack_vvvv"));
+        p->setup.push_back(pair_step(slot("ovvv"), op_, nov, nv, p->v, p->v, p->v, 2, 1, 0, "pack_ovvv"));
       }
+      // rows i > j of Zs are never written by the packed Z: keep them zero
+      Step f;
+      f.kind = Step::FILL;
+      f.c = slot("Zs");
+      f.nelem = p->slots[f.c].elems;
+      f.tag = "zero Zs";
+      p->setup.push_back(f);
     }
 
     Step te;
@@ -560,7 +619,7 @@ struct Planner {
           continue;
         }
         if (op.B == nullptr) unary(op);
-        else if (p->packed && std::string(op.tag) == "ladder") packed_ladder(op);
+        else if (p->packed && packed_op(op)) continue;
         else contract(op);
       }
     };
@@ -845,9 +904,9 @@ void exec(cc_plan *p, Step &st, hipStream_t s) {
       launch_fin(fin_entry(p), s);
       break;
     case Step::PAIR:
-      launch_pair(make_pair_entry(ptr_of(p, st.a), ptr_of(p, st.c), st.pair_rows ? p->pairs_v : p->pairs_o,
-                                  st.pair_cols ? p->pairs_v : p->pairs_o, st.pair_np, st.pair_nq, st.pair_d1,
-                                  st.pair_d2, st.pair_scatter),
+      launch_pair(make_pair_entry(ptr_of(p, st.a), ptr_of(p, st.c), p->pair_tab[st.pair_rows],
+                                  p->pair_tab[st.pair_cols], st.pair_np, st.pair_nq, st.pair_n[0], st.pair_n[1],
+                                  st.pair_n[2], st.pair_mode),
                   cplx, s);
       break;
     case Step::TRIPLES:
@@ -939,20 +998,33 @@ void plan_build(cc_plan *p, const cc_system *sys) {
   fock_diag(p->cplx, p->o, p->v, sys->f_oo, sys->f_vv, p->d_oo, p->d_vv, s);
   fill_zero(p->n1part, 2, false, s);
   if (p->packed) {
-    auto table = [&](int n, int **dst) {
+    auto upload = [&](std::vector<int> h, int **dst) {
+      if (h.empty()) h.assign(2, 0);
+      *dst = static_cast<int *>(dev_alloc(sizeof(int) * h.size()));
+      CC_HIP_CHECK(hipMemcpyAsync(*dst, h.data(), sizeof(int) * h.size(), hipMemcpyHostToDevice, s));
+      CC_HIP_CHECK(hipStreamSynchronize(s));
+    };
+    auto pairs = [](int n) {
       std::vector<int> h;
       for (int x = 0; x < n; ++x)
         for (int y = x + 1; y < n; ++y) {
           h.push_back(x);
           h.push_back(y);
         }
-      if (h.empty()) h.assign(2, 0);
-      *dst = static_cast<int *>(dev_alloc(sizeof(int) * h.size()));
-      CC_HIP_CHECK(hipMemcpyAsync(*dst, h.data(), sizeof(int) * h.size(), hipMemcpyHostToDevice, s));
-      CC_HIP_CHECK(hipStreamSynchronize(s));
+      return h;
     };
-    table(p->o, &p->pairs_o);
-    table(p->v, &p->pairs_v);
+    std::vector<int> ma, am;
+    for (int m = 0; m < p->o; ++m)
+      for (int a = 0; a < p->v; ++a) {
+        ma.push_back(m);
+        ma.push_back(a);
+        am.push_back(a);
+        am.push_back(m);
+      }
+    upload(pairs(p->o), &p->pair_tab[0]);
+    upload(pairs(p->v), &p->pair_tab[1]);
+    upload(ma, &p->pair_tab[2]);
+    upload(am, &p->pair_tab[3]);
   }
   for (Step &st : p->setup) exec(p, st, s);
   CC_HIP_CHECK(hipStreamSynchronize(s));
@@ -994,7 +1066,7 @@ void plan_free(cc_plan *p) {
   }
   for (double *q : {p->d_oo, p->d_vv, p->epart, p->n2part, p->n1part, p->scalars, p->n3part})
     if (q) (void)hipFree(q);
-  for (int *q : {p->pairs_o, p->pairs_v})
+  for (int *q : p->pair_tab)
     if (q) (void)hipFree(q);
 }
 

@@ -53,10 +53,11 @@ struct Step {
   int tile_lp[3] = {-1, -1, -1};  // per reduced precision (index = cc_prec)
   int tile_z = -1;      // complex128 tile
   int delta = -1;       // index into cc_plan::deltas (GEMM linear in the amplitudes)
-  // PAIR: gather a (i<j, a<b) packed copy of slot a into slot c, or
-  // scatter-add slot a into slot c; row/col tables 0 = occupied pairs, 1 = virtual pairs
-  int64_t pair_np = 0, pair_nq = 0, pair_d1 = 0, pair_d2 = 0;
-  int pair_rows = 0, pair_cols = 0, pair_scatter = 0;
+  // PAIR: slot a -> slot c through index-pair tables (PairEntry): mode 0
+  // gathers packed rows/columns, 1 scatter-adds, 2 scatter-sets; tables:
+  // 0 occupied i<j, 1 virtual a<b, 2 (m,a) all, 3 (a,m) all (same order as 2)
+  int64_t pair_np = 0, pair_nq = 0, pair_n[3] = {0, 0, 0};
+  int pair_rows = 0, pair_cols = 0, pair_mode = 0;
   int64_t nelem = 0;
   double flops = 0.0;
   std::string tag;
@@ -101,7 +102,7 @@ struct cc_plan {
   std::shared_ptr<ccmi::OpList> custom;  // null: the built-in contraction table
   // particle-particle ladder over packed pairs (i<j, e<f, a<b)
   bool packed = false;
-  int *pairs_o = nullptr, *pairs_v = nullptr;  // device pair tables
+  int *pair_tab[4] = {nullptr, nullptr, nullptr, nullptr};  // device index-pair tables
   // triples (op lists that read t3 or accumulate Y3): bound per plan
   bool triples = false;
   void *t3 = nullptr, *r3_out = nullptr;

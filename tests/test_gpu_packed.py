@@ -1,5 +1,6 @@
-"""The packed particle-particle ladder (i<j, a<b, e<f; CC_PLAN_PACKED_LADDER)
-against the dense plan and the oracle."""
+"""Contractions over packed index pairs (the ladder over i<j, a<b, e<f, the
+hole-hole ladder over m<n and Z over e<f; CC_PLAN_PACKED_LADDER) against
+the dense plan and the oracle."""
 import json
 import pathlib
 
@@ -66,11 +67,16 @@ def test_packed_ladder_equals_oracle_and_dense(E, ctx, method, ov, cplx):
     if method == "ccsd":
         assert np.abs(out[True][0].cpu().numpy() - r1_ref).max() < 1e-12
     assert abs(out[True][2] - out[False][2]) < 1e-12 * max(1.0, out[False][2])
-    # flop accounting: the packed ladder has o(o-1)/2 x [v(v-1)/2]^2 MACs
+    # flop accounting: the packed ladder has o(o-1)/2 x [v(v-1)/2]^2 MACs, the
+    # packed hh ladder [o(o-1)/2]^2 v(v-1)/2 and the packed Z o(o-1)/2 x ov x v(v-1)/2
     no, nv = o * (o - 1) // 2, v * (v - 1) // 2
     mul = 8 if cplx else 2
     assert out[True][4] == mul * no * nv * nv
-    assert abs(out[True][3] - (out[False][3] - out[False][4] + out[True][4])) < 1
+    dense_hh, dense_z = mul * o ** 4 * v ** 2, (mul * o ** 3 * v ** 3 if method == "ccsd" else 0)
+    packed_hh = mul * no * no * nv if no and nv else 0
+    packed_z = (mul * no * o * v * nv if no and nv else 0) if method == "ccsd" else 0
+    expect = out[False][3] - out[False][4] - dense_hh - dense_z + out[True][4] + packed_hh + packed_z
+    assert abs(out[True][3] - expect) < 1e-6 * out[False][3]
 
 
 def test_packed_iteration_matches_dense(E, ctx):

@@ -90,7 +90,10 @@ typedef struct {
   double refine_tol;   /* reduced prec: switch to FP64 steps once ||R|| < refine_tol, or when the
                           norm fell by less than 10% over 5 steps (refinement phase) */
   int32_t use_graph;   /* 1: capture one iteration as a HIP graph and replay it */
-  int32_t check_every; /* read the norm back every this many iterations (>= 1) */
+  int32_t check_every; /* k >= 1: launch k steps, then read their norms and energies back at
+                          once (0 counts as 1); decisions on step n act from the next batch on,
+                          so up to k - 1 further updates may already be in t_inout when the
+                          report (iters, norm, energy of step n) says converged */
   int32_t diverge_window; /* EDIVERGED if the norm grew for this many checks in a row (0 = off) */
   int32_t dressed;     /* 0: D from the bare Fock diagonal; 1: from the diagonals of the
                           T-dressed one-body intermediates of the current iterate */

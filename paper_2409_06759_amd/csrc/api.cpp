@@ -403,60 +403,97 @@ int cc_iterate(cc_ctx *ctx, const cc_system *sys, int method, const cc_iter_opts
       ccmi::plan_prepare(p);
       CC_HIP_CHECK(hipStreamSynchronize(p->ctx->stream));
       t1c = std::chrono::steady_clock::now();
-      for (int it = 0; it < opts->max_iter; ++it) {
-        const int mode_now = p->delta_mode;
-        run_step(p, opts->use_graph != 0);
-        ++iters;
-        if (mode_now != 0) ++corr_iters;
-        read_scalars(p, &rn, &er, &ei);
-        if (mode_now == 2) {
-          ref_rn = rn;
-        } else if (mode_now == 1 && rn < 1e-3 * ref_rn) {
-          p->delta_mode = 2;  // refresh the reference at the next step
-        }
-        if (rep && rep->hist_rnorm && it < rep->hist_cap) rep->hist_rnorm[it] = rn;
-        if (rep && rep->hist_e && it < rep->hist_cap) rep->hist_e[it] = er;
-        if (!std::isfinite(rn) || !std::isfinite(er)) {
-          status = CC_EDIVERGED;
-          break;
-        }
-        if (rn < opts->tol && p->cur_prec == CC_PREC_F64) {
-          if (mode_now != 1) {  // plain or reference step: an FP64 evaluation
-            status = CC_OK;
-            break;
+      // Steps are launched in batches of check_every; each step's three
+      // scalars are copied to pinned memory asynchronously and the batch is
+      // examined after one synchronisation.  Decisions taken while examining
+      // step n (convergence, precision switch, new reference) apply from the
+      // next batch on, so up to check_every - 1 further steps may already
+      // have updated t; the report describes step n.
+      const int k = std::max(1, opts->check_every);
+      double *hbuf = nullptr;
+      if (hipHostMalloc(reinterpret_cast<void **>(&hbuf), sizeof(double) * 3 * k, hipHostMallocDefault) !=
+          hipSuccess) {
+        (void)hipGetLastError();
+        throw CCError(CC_ENOMEM, "pinned host allocation failed");
+      }
+      std::vector<int> modes(k), precs(k);
+      bool done = false;
+      int it = 0;
+      try {
+        while (it < opts->max_iter && !done) {
+          const int nb = std::min(k, opts->max_iter - it);
+          for (int q = 0; q < nb; ++q) {
+            modes[q] = p->delta_mode;
+            precs[q] = p->cur_prec;
+            run_step(p, opts->use_graph != 0);
+            CC_HIP_CHECK(hipMemcpyAsync(hbuf + 3 * q, p->scalars, 3 * sizeof(double), hipMemcpyDeviceToHost,
+                                        p->ctx->stream));
           }
-          // correction form reached tol: confirm with a plain FP64 step
-          p->delta_mode = 0;
-          confirming = true;
-        } else if (confirming && std::isfinite(rn)) {
-          confirming = false;  // not confirmed: stay with plain FP64 steps
-        }
-        if (p->cur_prec != CC_PREC_F64) {
-          // refinement: leave reduced precision once the norm is below
-          // refine_tol or has stopped falling (less than 10% over 5 steps);
-          // the following FP64 steps correct the reduced-precision iterate.
-          seen.push_back(rn);
-          const size_t n = seen.size();
-          const bool stagnant = n > 5 && seen[n - 1] > 0.9 * seen[n - 6];
-          if (rn < std::max(opts->refine_tol, opts->tol) || stagnant) {
-            p->cur_prec = CC_PREC_F64;
-            switched_at = it + 1;
-            best = INFINITY;
-            grew = 0;
-            if (use_corr) {
-              p->delta_mode = 2;
-              ccmi::plan_prepare(p);  // reference buffers, outside any capture
+          CC_HIP_CHECK(hipStreamSynchronize(p->ctx->stream));
+          for (int q = 0; q < nb && !done; ++q, ++it) {
+            const int mode_now = modes[q], prec_now = precs[q];
+            ++iters;
+            if (mode_now != 0) ++corr_iters;
+            rn = hbuf[3 * q];
+            er = hbuf[3 * q + 1];
+            ei = hbuf[3 * q + 2];
+            if (mode_now == 2) {
+              ref_rn = rn;
+            } else if (mode_now == 1 && rn < 1e-3 * ref_rn && p->delta_mode == 1) {
+              p->delta_mode = 2;  // refresh the reference at the next step
+            }
+            if (rep && rep->hist_rnorm && it < rep->hist_cap) rep->hist_rnorm[it] = rn;
+            if (rep && rep->hist_e && it < rep->hist_cap) rep->hist_e[it] = er;
+            if (!std::isfinite(rn) || !std::isfinite(er)) {
+              status = CC_EDIVERGED;
+              done = true;
+              break;
+            }
+            if (rn < opts->tol && prec_now == CC_PREC_F64) {
+              if (mode_now != 1) {  // plain or reference step: an FP64 evaluation
+                status = CC_OK;
+                done = true;
+                break;
+              }
+              // correction form reached tol: confirm with a plain FP64 step
+              p->delta_mode = 0;
+              confirming = true;
+            } else if (confirming && std::isfinite(rn)) {
+              confirming = false;  // not confirmed: stay with plain FP64 steps
+            }
+            if (prec_now != CC_PREC_F64 && p->cur_prec != CC_PREC_F64) {
+              // refinement: leave reduced precision once the norm is below
+              // refine_tol or has stopped falling (less than 10% over 5 steps);
+              // the following FP64 steps correct the reduced-precision iterate.
+              seen.push_back(rn);
+              const size_t n = seen.size();
+              const bool stagnant = n > 5 && seen[n - 1] > 0.9 * seen[n - 6];
+              if (rn < std::max(opts->refine_tol, opts->tol) || stagnant) {
+                p->cur_prec = CC_PREC_F64;
+                switched_at = it + 1;
+                best = INFINITY;
+                grew = 0;
+                if (use_corr) {
+                  p->delta_mode = 2;
+                  ccmi::plan_prepare(p);  // reference buffers, outside any capture
+                }
+              }
+            }
+            if (rn < best) {
+              best = rn;
+              grew = 0;
+            } else if (opts->diverge_window > 0 && ++grew >= opts->diverge_window) {
+              status = CC_EDIVERGED;
+              done = true;
+              break;
             }
           }
         }
-        if (rn < best) {
-          best = rn;
-          grew = 0;
-        } else if (opts->diverge_window > 0 && ++grew >= opts->diverge_window) {
-          status = CC_EDIVERGED;
-          break;
-        }
+      } catch (...) {
+        (void)hipHostFree(hbuf);
+        throw;
       }
+      (void)hipHostFree(hbuf);
     } catch (...) {
       cc_plan_destroy(p);
       throw;

@@ -215,7 +215,7 @@ def energy(ctx, dsys, method, t1, t2):
 
 def iterate(ctx, dsys, method, t1, t2, tol=1e-8, max_iter=100, level_shift=0.0, prec=F64,
             use_graph=True, refine_tol=0.0, diverge_window=0, hist_cap=None, dressed=False,
-            autotune=False, correction=True, packed=False):
+            autotune=False, correction=True, packed=False, check_every=1):
     """Jacobi iteration (cc_iterate).  Reduced `prec` runs its contractions in
     that precision until the norm stagnates, then finishes with FP64 steps
     (with `correction`, in reference + reduced-precision-correction form for
@@ -223,7 +223,7 @@ def iterate(ctx, dsys, method, t1, t2, tol=1e-8, max_iter=100, level_shift=0.0, 
     cap = hist_cap or max_iter
     hr = (C.c_double * cap)()
     he = (C.c_double * cap)()
-    opts = L.CCIterOpts(tol, max_iter, prec, level_shift, refine_tol, 1 if use_graph else 0, 1,
+    opts = L.CCIterOpts(tol, max_iter, prec, level_shift, refine_tol, 1 if use_graph else 0, check_every,
                         diverge_window, 1 if dressed else 0, 1 if autotune else 0, 1 if correction else 0,
                         1 if packed else 0)
     rep = L.CCIterReport(0, 0, 0.0, 0.0, 0.0, 0.0, 0.0, 0, 0, C.cast(hr, C.POINTER(C.c_double)),

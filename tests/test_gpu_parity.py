@@ -334,3 +334,27 @@ def test_correction_form_error_scales_with_the_change(E, ctx, prec, eps):
     assert np.abs(at_ref - exact_ref).max() < 1e-13 * max(1.0, scale)
     assert np.abs(corrected - exact_new).max() < 1e-3 * plain_err
     assert np.abs(corrected - exact_new).max() < 1e3 * eps * 1e-6 * max(1.0, scale)
+
+
+@pytest.mark.parametrize("prec", ["f64", "bf16x3"])
+def test_batched_norm_readback_reports_the_same_convergence(E, ctx, prec):
+    """check_every = 5 launches five steps per synchronisation.  In FP64 the
+    reported iteration count, norm, energy and history are those of
+    check_every = 1; with reduced precision the switch to FP64 acts from the
+    next batch, so the path differs by a few steps but not the solution."""
+    o, v = 8, 30
+    s = make_system(o, v, 14)
+    d = E.DeviceSystem(s)
+    out = {}
+    for k in (1, 5):
+        t1, t2 = E.zeros_amps(d, E.CCSD)
+        out[k] = E.iterate(ctx, d, E.CCSD, t1, t2, tol=1e-10, max_iter=200, dressed=True, prec=E.PRECS[prec],
+                           check_every=k)
+    assert out[5]["converged"] and out[1]["converged"]
+    if prec == "f64":
+        assert out[5]["iters"] == out[1]["iters"]
+        assert out[5]["energy"] == out[1]["energy"] and out[5]["rnorm"] == out[1]["rnorm"]
+        assert out[5]["hist_e"] == out[1]["hist_e"]
+    else:
+        assert abs(out[5]["iters"] - out[1]["iters"]) <= 10
+        assert abs(out[5]["energy"] - out[1]["energy"]) < 1e-10

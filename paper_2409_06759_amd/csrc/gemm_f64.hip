@@ -320,13 +320,8 @@ void gemm_f64(const GemmDesc &d, hipStream_t s, int tile_id) {
   CC_REQUIRE(akc || d.sam == 1, -1, "gemm: A needs a unit stride in m or k");
   CC_REQUIRE(bkc || d.sbn == 1, -1, "gemm: B needs a unit stride in n or k");
   if (d.K <= 0) {
-    // C = beta * C : a GEMM with an empty contraction still scales C.
-    GemmDesc z = d;
-    z.alpha = 0.0;
-    z.K = 1;
-    static const double zero[1] = {0.0};
-    (void)zero;
-    // handled by the elementwise scale kernel in the permute module
+    // C = beta * C: a GEMM with an empty contraction still scales C (an
+    // in-place, element-by-element identity permutation with alpha = beta)
     PermDesc p{};
     p.rank = 2;
     p.out_dims[0] = d.M; p.out_dims[1] = d.N;

@@ -21,6 +21,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <set>
 #include <sstream>
 
@@ -1118,7 +1119,10 @@ void plan_run(cc_plan *p) {
 // iteration (on the plan's own buffers) and keep the fastest.  Results are
 // cached per (M, N, K, layouts) for the life of the process.
 void plan_autotune(cc_plan *p, int reps) {
+  // shared by every context of the process (contexts may live on different
+  // host threads): lookups and inserts are serialised
   static std::map<std::string, int> cache;
+  static std::mutex cache_mutex;
   const int prec = p->cplx ? 9 : p->cur_prec;  // 9: complex128 tiles
   plan_prepare(p);
   const int ntiles = p->cplx ? gemm_c128_num_tiles()
@@ -1135,11 +1139,13 @@ void plan_autotune(cc_plan *p, int reps) {
                               std::to_string(d.N) + "x" + std::to_string(d.K) + (akc ? "k" : "m") +
                               (bkc ? "k" : "n");
       int &slot = p->cplx ? st->tile_z : (prec == PREC_F64 ? st->tile : st->tile_lp[prec]);
+      std::unique_lock<std::mutex> lk(cache_mutex);
       auto it = cache.find(key);
       if (it != cache.end()) {
         slot = it->second;
         continue;
       }
+      lk.unlock();
       d.A = ptr_of(p, st->a);
       d.B = ptr_of(p, st->b);
       d.C = ptr_of(p, st->c);
@@ -1166,6 +1172,7 @@ void plan_autotune(cc_plan *p, int reps) {
         }
       }
       slot = best;
+      lk.lock();
       cache[key] = best;
     }
   } catch (...) {

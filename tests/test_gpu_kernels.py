@@ -145,3 +145,16 @@ def test_gemm_c128_matches_numpy(ctx, shape, akc, bkc):
     E.gemm(ctx, Ad, Bd, Cd, alpha, beta, a_kcontig=akc, b_kcontig=bkc)
     bound = 4 * (K + 2) * np.finfo(float).eps * (abs(alpha) * (np.abs(A) @ np.abs(B).T) + abs(beta) * np.abs(C0))
     assert np.all(np.abs(Cd.cpu().numpy() - ref) <= bound)
+
+
+@pytest.mark.parametrize("prec,cplx", [("f64", False), ("f32", False), ("bf16x3", False), ("f64", True)])
+def test_gemm_with_empty_contraction_scales_c(ctx, prec, cplx):
+    """K = 0: C = beta C (no products)."""
+    from paper_2409_06759_amd import engine as E
+    dt = torch.complex128 if cplx else torch.float64
+    C0 = torch.randn(37, 53, dtype=dt)
+    Cd = C0.cuda()
+    A = torch.zeros((37, 0), dtype=dt, device="cuda")
+    B = torch.zeros((53, 0), dtype=dt, device="cuda")
+    E.gemm(ctx, A, B, Cd, 0.5, -1.5, prec=E.PRECS[prec])
+    assert torch.equal(Cd.cpu(), -1.5 * C0)

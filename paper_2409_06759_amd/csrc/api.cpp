@@ -218,6 +218,10 @@ int cc_destroy(cc_ctx *ctx) {
   if (!ctx) return CC_OK;
   (void)hipSetDevice(ctx->device);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  if (ctx->gemm_ws) {
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipFree(ctx->gemm_ws);
+  }
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
   return CC_OK;
@@ -537,10 +541,33 @@ int cc_gemm(cc_ctx *ctx, int prec, int scalar, int64_t M, int64_t N, int64_t K, 
       throw CCError(CC_EUNSUPPORTED, "complex GEMM is FP64 only");
     set_device(ctx);
     ccmi::GemmDesc d{M, N, K, A, sam, sak, B, sbn, sbk, C, ldc, alpha, beta};
+    const char *tv = std::getenv("CC_GEMM_TILE");  // tuning sweeps: force one tile configuration
+    const int tile = tv ? std::atoi(tv) : -1;
+    // room for the K-split tail of a launch whose last round would be mostly
+    // empty; without it (or with CC_GEMM_TAIL=0) the GEMM runs as one launch
+    const char *cv = std::getenv("CC_GEMM_TAIL");
+    const bool cut_ok = !(cv && cv[0] == '0');
+    auto tail_ws = [&](int64_t need) {
+      if (need <= 0 || !cut_ok) return;
+      if (need > ctx->gemm_ws_elems) {
+        CC_HIP_CHECK(hipStreamSynchronize(ctx->stream));
+        if (ctx->gemm_ws) (void)hipFree(ctx->gemm_ws);
+        ctx->gemm_ws = nullptr;
+        ctx->gemm_ws_elems = 0;
+        if (hipMalloc(&ctx->gemm_ws, size_t(need) * sizeof(double)) != hipSuccess) {
+          (void)hipGetLastError();
+          ctx->gemm_ws = nullptr;
+          return;
+        }
+        ctx->gemm_ws_elems = need;
+      }
+      d.ws = ctx->gemm_ws;
+      d.ws_elems = ctx->gemm_ws_elems;
+    };
     if (scalar == CC_C128) ccmi::gemm_c128(d, ctx->stream);
     else if (prec == CC_PREC_F64) {
-      const char *tv = std::getenv("CC_GEMM_TILE");  // tuning sweeps: force one tile configuration
-      ccmi::gemm_f64(d, ctx->stream, tv ? std::atoi(tv) : -1);
+      tail_ws(ccmi::gemm_f64_tail_ws(d, tile));
+      ccmi::gemm_f64(d, ctx->stream, tile);
     }
     else {
       // operands converted once into temporary 4-byte copies (CC_GEMM_LPIN=0:
@@ -562,8 +589,8 @@ int cc_gemm(cc_ctx *ctx, int prec, int scalar, int64_t M, int64_t N, int64_t K, 
         d.b_plane = nb;
         d.lp_in = 1;
       }
-      const char *tv = std::getenv("CC_GEMM_TILE");
-      ccmi::gemm_lowp(d, prec, ctx->stream, tv ? std::atoi(tv) : -1);
+      tail_ws(ccmi::gemm_lowp_tail_ws(d, prec, tile));
+      ccmi::gemm_lowp(d, prec, ctx->stream, tile);
       const hipError_t e = hipStreamSynchronize(ctx->stream);
       if (sa) (void)hipFree(sa);
       if (sb) (void)hipFree(sb);

@@ -49,9 +49,10 @@ struct GemmDesc {
   int64_t ldc;       // C[m*ldc + n]
   double alpha, beta;
   int conj_a = 0, conj_b = 0;  // complex only
-  int ladder = 0;              // 1: launch the ladder's own kernel symbol (profiling)
+  int ladder = 0;              // 1: the ladder's own kernel symbol (profiling); 2: its cut tail
   int split = 1;               // split-K factor; > 1 needs ws of split*M*N elements
   void *ws = nullptr;
+  int64_t ws_elems = 0;        // capacity of ws in elements (the tail cut checks it)
   // reduced precision with converted operands ("shadows"): A and B point to
   // FP32 (F32) or to bf16 hi planes whose lo planes follow at +a_plane /
   // +b_plane elements (BF16X3), indexed exactly like the FP64 tensors.
@@ -111,6 +112,50 @@ int gemm_lowp_num_tiles();
 const char *gemm_lowp_tile_name(int prec, int id);
 void splitk_reduce(bool cplx, const void *ws, int split, int64_t M, int64_t N, void *C, int64_t ldc,
                    double alpha, double beta, hipStream_t s);
+
+// ---- tail rounds ----
+// T workgroups on S resident slots (workgroups per CU x CUs) run in
+// ceil(T / S) rounds.  When the last round is at most half full, the GEMM is
+// cut into a main part of whole row or column panels that fills the full
+// rounds, and a tail sub-GEMM split along K whose split * tiles workgroups
+// fill one short round (partial sums in ws, reduced in a fixed order).
+struct TailCut {
+  int axis = 0;          // 0: no cut; 1: columns [0, main) are the main part; 2: rows [0, main)
+  int64_t main = 0;
+  int split = 1;
+  int64_t ws_elems = 0;  // split x tail rows x tail columns
+};
+TailCut gemm_tail_cut(int64_t M, int64_t N, int64_t K, int BM, int BN, int BK, int64_t slots);
+// Workspace that covers the tail cut of every tile configuration (0 when
+// the GEMM is too small for any cut); no device query needed.
+int64_t gemm_tail_ws_bound(int64_t M, int64_t N, int64_t K);
+// Exact workspace the tail cut of one launch needs (0: no cut).
+int64_t gemm_f64_tail_ws(const GemmDesc &d, int tile_id);
+int64_t gemm_lowp_tail_ws(const GemmDesc &d, int prec, int tile_id);
+int gpu_cu_count();
+
+// Runs `launch(desc)` on the main part and then on the K-split tail.  `esa`,
+// `esb` are the element sizes of A and B (pointer offsets of the panels).
+template <class Launch>
+void gemm_run_cut(const GemmDesc &d, const TailCut &tc, size_t esa, size_t esb, Launch &&launch) {
+  GemmDesc mainp = d, tail = d;
+  if (tc.axis == 1) {
+    mainp.N = tc.main;
+    tail.N = d.N - tc.main;
+    tail.B = static_cast<const char *>(d.B) + size_t(tc.main * d.sbn) * esb;
+    tail.C = static_cast<double *>(d.C) + tc.main;
+  } else {
+    mainp.M = tc.main;
+    tail.M = d.M - tc.main;
+    tail.A = static_cast<const char *>(d.A) + size_t(tc.main * d.sam) * esa;
+    tail.C = static_cast<double *>(d.C) + tc.main * d.ldc;
+  }
+  mainp.split = 1;
+  tail.split = tc.split;
+  if (tail.ladder) tail.ladder = 2;  // its own kernel symbol
+  launch(mainp);
+  launch(tail);
+}
 
 // ---- dense rank<=6 tensor views for permutation kernels ----
 constexpr int kMaxRank = 6;

@@ -21,6 +21,10 @@
 //   dispatched to the same XCD (shared L2 for the B panel).
 #include "common.hpp"
 
+#include <algorithm>
+#include <atomic>
+#include <mutex>
+
 #include <cmath>
 
 namespace ccmi {
@@ -217,8 +221,23 @@ struct TileInfo {
   int BM, BN, BK, threads;
   void (*launch[4])(const GemmDesc &, int64_t, int64_t, hipStream_t);  // [akc*2 + bkc]
   void (*launch_ladder)(const GemmDesc &, int64_t, int64_t, hipStream_t);  // both K-contiguous
+  void (*launch_ladder_tail)(const GemmDesc &, int64_t, int64_t, hipStream_t);
   void (*launch_grouped[4])(const GemmGroupEntry *, const int64_t *, int, int64_t, hipStream_t);
+  int (*occupancy[4])();  // resident workgroups per CU, [akc*2 + bkc]
 };
+
+// Workgroups of one configuration that fit on a CU at once (registers, LDS,
+// waves), as the runtime computes it for the compiled kernel; 0 if unknown.
+template <int BM, int BN, int BK, int WM, int WN, bool AKC, bool BKC>
+int occupancy_cfg() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gemm_f64_kernel<BM, BN, BK, WM, WN, AKC, BKC, 0>,
+                                                   WM * WN * kWave, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return nb;
+}
 
 template <int BM, int BN, int BK, int WM, int WN, bool AKC, bool BKC>
 void launch_grp(const GemmGroupEntry *e, const int64_t *off, int n, int64_t blocks, hipStream_t s) {
@@ -227,7 +246,8 @@ void launch_grp(const GemmGroupEntry *e, const int64_t *off, int n, int64_t bloc
 }
 
 // TAG only changes the kernel's symbol name: TAG 1 is the particle-particle
-// ladder, so that profilers report it on its own line.
+// ladder and TAG 2 the K-split tail of a cut ladder launch, so that profilers
+// report them on lines of their own.
 template <int BM, int BN, int BK, int WM, int WN, bool AKC, bool BKC, int TAG = 0>
 void launch_cfg(const GemmDesc &d, int64_t tm, int64_t tn, hipStream_t s) {
   hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, WM, WN, AKC, BKC, TAG>), dim3(tm * tn * d.split),
@@ -239,9 +259,11 @@ void launch_cfg(const GemmDesc &d, int64_t tm, int64_t tn, hipStream_t s) {
     #BM "x" #BN "x" #BK "_w" #WM "x" #WN, BM, BN, BK, WM *WN * kWave, {                      \
       &launch_cfg<BM, BN, BK, WM, WN, false, false>, &launch_cfg<BM, BN, BK, WM, WN, false, true>, \
           &launch_cfg<BM, BN, BK, WM, WN, true, false>, &launch_cfg<BM, BN, BK, WM, WN, true, true> \
-    }, &launch_cfg<BM, BN, BK, WM, WN, true, true, 1>,                                       \
+    }, &launch_cfg<BM, BN, BK, WM, WN, true, true, 1>, &launch_cfg<BM, BN, BK, WM, WN, true, true, 2>, \
     {&launch_grp<BM, BN, BK, WM, WN, false, false>, &launch_grp<BM, BN, BK, WM, WN, false, true>, \
-     &launch_grp<BM, BN, BK, WM, WN, true, false>, &launch_grp<BM, BN, BK, WM, WN, true, true>}   \
+     &launch_grp<BM, BN, BK, WM, WN, true, false>, &launch_grp<BM, BN, BK, WM, WN, true, true>},  \
+    {&occupancy_cfg<BM, BN, BK, WM, WN, false, false>, &occupancy_cfg<BM, BN, BK, WM, WN, false, true>, \
+     &occupancy_cfg<BM, BN, BK, WM, WN, true, false>, &occupancy_cfg<BM, BN, BK, WM, WN, true, true>} \
   }
 
 const TileInfo kTiles[] = {
@@ -264,7 +286,93 @@ const TileInfo kTiles[] = {
 };
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 
+// resident slots of a configuration on the whole device (cached; -1 = not yet asked)
+std::atomic<int64_t> g_slots[kNumTiles][4];
+std::once_flag g_slots_once;
+
+int64_t tile_slots(int tile_id, int variant) {
+  std::call_once(g_slots_once, [] {
+    for (auto &row : g_slots)
+      for (auto &x : row) x.store(-1);
+  });
+  int64_t v = g_slots[tile_id][variant].load();
+  if (v < 0) {
+    v = int64_t(kTiles[tile_id].occupancy[variant]()) * gpu_cu_count();
+    g_slots[tile_id][variant].store(v);
+  }
+  return v;
+}
+
+TailCut f64_cut(const GemmDesc &d, int tile_id) {
+  const bool akc = (d.sak == 1), bkc = (d.sbk == 1);
+  const TileInfo &ti = kTiles[tile_id];
+  if (d.split != 1 || d.K <= 0) return TailCut{};
+  return gemm_tail_cut(d.M, d.N, d.K, ti.BM, ti.BN, ti.BK, tile_slots(tile_id, (akc ? 2 : 0) + (bkc ? 1 : 0)));
+}
+
 }  // namespace
+
+int gpu_cu_count() {
+  static std::atomic<int> cus{0};
+  int c = cus.load();
+  if (c == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0) {
+      (void)hipGetLastError();
+      c = 256;
+    }
+    cus.store(c);
+  }
+  return c;
+}
+
+// A round must carry enough work to pay for the two extra launches (the tail
+// and its reduction), about 0.2 ms at the FP64 rate.
+constexpr double kTailMinRoundFlops = 1.2e10;
+
+TailCut gemm_tail_cut(int64_t M, int64_t N, int64_t K, int BM, int BN, int BK, int64_t slots) {
+  TailCut best;
+  if (slots <= 0 || M <= 0 || N <= 0 || K <= 0) return best;
+  const int64_t tm = (M + BM - 1) / BM, tn = (N + BN - 1) / BN, tiles = tm * tn;
+  if (tiles <= slots || 2.0 * double(slots) * BM * BN * double(K) < kTailMinRoundFlops) return best;
+  const int64_t full = tiles / slots, rem = tiles - full * slots;
+  if (rem == 0 || 2 * rem > slots) return best;  // the last round is full enough
+  double best_rounds = double(full + 1);
+  for (int axis = 1; axis <= 2; ++axis) {
+    const int64_t per = axis == 1 ? tm : tn;  // tiles per panel
+    const int64_t np = axis == 1 ? tn : tm;   // panels
+    const int64_t mainp = (full * slots) / per;
+    if (mainp <= 0 || mainp >= np) continue;
+    const int64_t tail_tiles = (np - mainp) * per;
+    int64_t split = std::min<int64_t>({slots / tail_tiles, 16, K / (8 * int64_t(BK))});
+    if (split < 2) continue;
+    const double rounds = std::ceil(double(mainp * per) / double(slots)) + 1.0 / double(split);
+    if (rounds < best_rounds) {
+      best_rounds = rounds;
+      best.axis = axis;
+      best.main = mainp * (axis == 1 ? BN : BM);
+      best.split = int(split);
+      const int64_t tr = axis == 1 ? M : M - best.main, tc = axis == 1 ? N - best.main : N;
+      best.ws_elems = split * tr * tc;
+    }
+  }
+  return best;
+}
+
+int64_t gemm_tail_ws_bound(int64_t M, int64_t N, int64_t K) {
+  if (M <= 0 || N <= 0 || K <= 0 || 2.0 * double(M) * double(N) * double(K) < kTailMinRoundFlops) return 0;
+  // split x tail elements <= slots x BM x BN = every resident workgroup's
+  // accumulators, bounded by the register file (256 CUs x 512 KiB of 4-byte
+  // accumulators); the launch checks the exact figure against ws_elems
+  return std::min<int64_t>(16 * M * N, int64_t(1) << 25);
+}
+
+int64_t gemm_f64_tail_ws(const GemmDesc &d, int tile_id) {
+  if (d.M <= 0 || d.N <= 0 || d.K <= 0) return 0;
+  if (tile_id < 0 || tile_id >= kNumTiles) tile_id = gemm_f64_pick(d.M, d.N, d.K, d.sak == 1, d.sbk == 1);
+  return f64_cut(d, tile_id).ws_elems;
+}
 
 int gemm_f64_num_tiles() { return kNumTiles; }
 const char *gemm_f64_tile_name(int id) { return (id >= 0 && id < kNumTiles) ? kTiles[id].name : "?"; }
@@ -336,11 +444,25 @@ void gemm_f64(const GemmDesc &d, hipStream_t s, int tile_id) {
   const int64_t tm = (d.M + ti.BM - 1) / ti.BM, tn = (d.N + ti.BN - 1) / ti.BN;
   CC_REQUIRE(d.split >= 1, -1, "gemm: split must be >= 1");
   CC_REQUIRE(d.split == 1 || d.ws != nullptr, -1, "gemm: split-K needs a workspace");
+  CC_REQUIRE(d.split == 1 || d.ws_elems == 0 || d.ws_elems >= d.split * d.M * d.N, -1,
+             "gemm: split-K workspace too small");
   CC_REQUIRE(tm * tn * d.split < (int64_t(1) << 31), -1, "gemm: too many tiles");
-  if (d.ladder && akc && bkc) ti.launch_ladder(d, tm, tn, s);
-  else ti.launch[(akc ? 2 : 0) + (bkc ? 1 : 0)](d, tm, tn, s);
-  CC_HIP_CHECK(hipGetLastError());
-  if (d.split > 1) splitk_reduce(false, d.ws, d.split, d.M, d.N, d.C, d.ldc, d.alpha, d.beta, s);
+  auto one = [&](const GemmDesc &g) {
+    const int64_t gm = (g.M + ti.BM - 1) / ti.BM, gn = (g.N + ti.BN - 1) / ti.BN;
+    if (g.ladder == 2 && akc && bkc) ti.launch_ladder_tail(g, gm, gn, s);
+    else if (g.ladder && akc && bkc) ti.launch_ladder(g, gm, gn, s);
+    else ti.launch[(akc ? 2 : 0) + (bkc ? 1 : 0)](g, gm, gn, s);
+    CC_HIP_CHECK(hipGetLastError());
+    if (g.split > 1) splitk_reduce(false, g.ws, g.split, g.M, g.N, g.C, g.ldc, g.alpha, g.beta, s);
+  };
+  if (d.ws && d.split == 1) {
+    const TailCut tc = f64_cut(d, tile_id);
+    if (tc.axis && tc.ws_elems <= d.ws_elems) {
+      gemm_run_cut(d, tc, sizeof(double), sizeof(double), one);
+      return;
+    }
+  }
+  one(d);
 }
 
 }  // namespace ccmi

@@ -16,7 +16,9 @@
 // the XCD-aware tile order follow the FP64 kernel.
 #include "common.hpp"
 
+#include <atomic>
 #include <cmath>
+#include <mutex>
 #include <type_traits>
 
 namespace ccmi {
@@ -340,7 +342,9 @@ struct LTile {
   int BM, BN, BK;
   void (*launch[4])(const GemmDesc &, int64_t, int64_t, hipStream_t);
   void (*launch_ladder)(const GemmDesc &, int64_t, int64_t, hipStream_t);
+  void (*launch_ladder_tail)(const GemmDesc &, int64_t, int64_t, hipStream_t);
   void (*launch_grouped[4])(const GemmGroupEntry *, const int64_t *, int, int64_t, hipStream_t);
+  int (*occupancy[8])();  // resident workgroups per CU, [lp_in*4 + akc*2 + bkc]
 };
 
 template <int MODE, int BM, int BN, int BK, int WM, int WN, bool AKC, bool BKC>
@@ -359,14 +363,29 @@ void launch_l(const GemmDesc &d, int64_t tm, int64_t tn, hipStream_t s) {
                        dim3(tm * tn * d.split), dim3(WM * WN * kWave), 0, s, d, tm, tn);
 }
 
+// workgroups of one configuration resident on a CU (0 if unknown)
+template <int MODE, int BM, int BN, int BK, int WM, int WN, bool AKC, bool BKC, bool LPIN>
+int occ_l() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gemm_lowp_kernel<MODE, BM, BN, BK, WM, WN, AKC, BKC, 0, LPIN>,
+                                                   WM * WN * kWave, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return nb;
+}
+#define CC_LOCC(MODE, BM, BN, BK, WM, WN, LPIN)                                                      \
+  &occ_l<MODE, BM, BN, BK, WM, WN, false, false, LPIN>, &occ_l<MODE, BM, BN, BK, WM, WN, false, true, LPIN>, \
+      &occ_l<MODE, BM, BN, BK, WM, WN, true, false, LPIN>, &occ_l<MODE, BM, BN, BK, WM, WN, true, true, LPIN>
 #define CC_LTILE(MODE, BM, BN, BK, WM, WN)                                                          \
   LTile {                                                                                           \
     #BM "x" #BN "x" #BK "_w" #WM "x" #WN, BM, BN, BK,                                               \
         {&launch_l<MODE, BM, BN, BK, WM, WN, false, false>, &launch_l<MODE, BM, BN, BK, WM, WN, false, true>, \
          &launch_l<MODE, BM, BN, BK, WM, WN, true, false>, &launch_l<MODE, BM, BN, BK, WM, WN, true, true>},  \
-        &launch_l<MODE, BM, BN, BK, WM, WN, true, true, 1>,                                         \
+        &launch_l<MODE, BM, BN, BK, WM, WN, true, true, 1>, &launch_l<MODE, BM, BN, BK, WM, WN, true, true, 2>, \
         {&launch_lg<MODE, BM, BN, BK, WM, WN, false, false>, &launch_lg<MODE, BM, BN, BK, WM, WN, false, true>, \
-         &launch_lg<MODE, BM, BN, BK, WM, WN, true, false>, &launch_lg<MODE, BM, BN, BK, WM, WN, true, true>}  \
+         &launch_lg<MODE, BM, BN, BK, WM, WN, true, false>, &launch_lg<MODE, BM, BN, BK, WM, WN, true, true>},  \
+        {CC_LOCC(MODE, BM, BN, BK, WM, WN, false), CC_LOCC(MODE, BM, BN, BK, WM, WN, true)}                  \
   }
 
 const LTile kF32Tiles[] = {
@@ -382,6 +401,28 @@ const LTile kB3Tiles[] = {
     CC_LTILE(PREC_BF16X3, 128, 128, 32, 4, 2), CC_LTILE(PREC_BF16X3, 256, 128, 32, 4, 2),
 };
 constexpr int kNumL = 8;
+
+// resident slots per (precision, configuration, variant) on the device; -1 = not yet asked
+std::atomic<int64_t> g_lslots[2][kNumL][8];
+std::once_flag g_lslots_once;
+
+TailCut lowp_cut(const GemmDesc &d, int prec, int tile_id) {
+  if (d.split != 1 || d.K <= 0) return TailCut{};
+  std::call_once(g_lslots_once, [] {
+    for (auto &a : g_lslots)
+      for (auto &b : a)
+        for (auto &x : b) x.store(-1);
+  });
+  const LTile &ti = (prec == PREC_F32 ? kF32Tiles : kB3Tiles)[tile_id];
+  const int var = (d.lp_in ? 4 : 0) + (d.sak == 1 ? 2 : 0) + (d.sbk == 1 ? 1 : 0);
+  std::atomic<int64_t> &cell = g_lslots[prec == PREC_F32 ? 0 : 1][tile_id][var];
+  int64_t slots = cell.load();
+  if (slots < 0) {
+    slots = int64_t(ti.occupancy[var]()) * gpu_cu_count();
+    cell.store(slots);
+  }
+  return gemm_tail_cut(d.M, d.N, d.K, ti.BM, ti.BN, ti.BK, slots);
+}
 
 int pick_l(const LTile *tiles, int64_t M, int64_t N) {
   int best = 0;
@@ -524,11 +565,34 @@ void gemm_lowp(const GemmDesc &d, int prec, hipStream_t s, int tile_id) {
   const LTile &ti = tiles[tile_id];
   const int64_t tm = (d.M + ti.BM - 1) / ti.BM, tn = (d.N + ti.BN - 1) / ti.BN;
   CC_REQUIRE(d.split >= 1 && (d.split == 1 || d.ws != nullptr), -1, "gemm: split-K workspace");
+  CC_REQUIRE(d.split == 1 || d.ws_elems == 0 || d.ws_elems >= d.split * d.M * d.N, -1,
+             "gemm: split-K workspace too small");
   CC_REQUIRE(tm * tn * d.split < (int64_t(1) << 31), -1, "gemm: too many tiles");
-  if (d.ladder && akc && bkc) ti.launch_ladder(d, tm, tn, s);
-  else ti.launch[(akc ? 2 : 0) + (bkc ? 1 : 0)](d, tm, tn, s);
-  CC_HIP_CHECK(hipGetLastError());
-  if (d.split > 1) splitk_reduce(false, d.ws, d.split, d.M, d.N, d.C, d.ldc, d.alpha, d.beta, s);
+  auto one = [&](const GemmDesc &g) {
+    const int64_t gm = (g.M + ti.BM - 1) / ti.BM, gn = (g.N + ti.BN - 1) / ti.BN;
+    if (g.ladder == 2 && akc && bkc) ti.launch_ladder_tail(g, gm, gn, s);
+    else if (g.ladder && akc && bkc) ti.launch_ladder(g, gm, gn, s);
+    else ti.launch[(akc ? 2 : 0) + (bkc ? 1 : 0)](g, gm, gn, s);
+    CC_HIP_CHECK(hipGetLastError());
+    if (g.split > 1) splitk_reduce(false, g.ws, g.split, g.M, g.N, g.C, g.ldc, g.alpha, g.beta, s);
+  };
+  if (d.ws && d.split == 1) {
+    const TailCut tc = lowp_cut(d, prec, tile_id);
+    if (tc.axis && tc.ws_elems <= d.ws_elems) {
+      // operand element size: converted copies (4-byte FP32, 2-byte bf16
+      // planes) or the FP64 tensors themselves
+      const size_t es = d.lp_in ? (prec == PREC_F32 ? 4 : 2) : sizeof(double);
+      gemm_run_cut(d, tc, es, es, one);
+      return;
+    }
+  }
+  one(d);
+}
+
+int64_t gemm_lowp_tail_ws(const GemmDesc &d, int prec, int tile_id) {
+  if (d.M <= 0 || d.N <= 0 || d.K <= 0 || (prec != PREC_F32 && prec != PREC_BF16X3)) return 0;
+  if (tile_id < 0 || tile_id >= kNumL) tile_id = pick_l(prec == PREC_F32 ? kF32Tiles : kB3Tiles, d.M, d.N);
+  return lowp_cut(d, prec, tile_id).ws_elems;
 }
 
 }  // namespace ccmi

@@ -124,6 +124,17 @@ struct Planner {
   int splitws = -1;        // split-K partial sums
   int64_t splitws_elems = 0;
 
+  // Split-K partial sums, or room for the K-split tail of a launch whose last
+  // round of workgroups would be mostly empty (real GEMMs only).
+  void reserve_ws(Step &g, int64_t M, int64_t N, int64_t K) {
+    const int64_t split = g.gemm.split > 1 ? int64_t(g.gemm.split) * M * N : 0;
+    const int64_t tail = p->cplx ? 0 : gemm_tail_ws_bound(M, N, K);
+    if (split > 0 || tail > 0) {
+      splitws_elems = std::max<int64_t>(splitws_elems, std::max(split, tail));
+      g.b2 = splitws;
+    }
+  }
+
   int slot(const std::string &name) {
     auto it = p->index.find(name);
     if (it == p->index.end()) throw CCError(CC_EINTERNAL, "unknown tensor " + name);
@@ -349,10 +360,7 @@ struct Planner {
     g.tag = op.tag;
     g.gemm.ladder = std::string(op.tag) == "ladder" ? 1 : 0;
     g.gemm.split = gemm_split_pick(M, N, Kd, -1);
-    if (g.gemm.split > 1) {
-      splitws_elems = std::max<int64_t>(splitws_elems, int64_t(g.gemm.split) * M * N);
-      g.b2 = splitws;
-    }
+    reserve_ws(g, M, N, Kd);
     g.tile = p->cplx ? -1 : gemm_f64_pick(M, N, Kd, xkc, ykc);
     if (best.cm) {
       g.c = c;
@@ -463,10 +471,7 @@ struct Planner {
     g.flops = (p->cplx ? 8.0 : 2.0) * double(M) * double(N) * double(K);
     g.tag = tag;
     g.gemm.split = gemm_split_pick(M, N, K, -1);
-    if (g.gemm.split > 1) {
-      splitws_elems = std::max<int64_t>(splitws_elems, int64_t(g.gemm.split) * M * N);
-      g.b2 = splitws;
-    }
+    reserve_ws(g, M, N, K);
     g.tile = p->cplx ? -1 : gemm_f64_pick(M, N, K, akc, bkc);
     p->flops_per_iter += g.flops;
     if (g.gemm.ladder) p->ladder_flops += g.flops;
@@ -877,6 +882,7 @@ void exec(cc_plan *p, Step &st, hipStream_t s) {
       d.B = ptr_of(p, st.b);
       d.C = ptr_of(p, st.c);
       d.ws = st.b2 >= 0 ? ptr_of(p, st.b2) : nullptr;
+      d.ws_elems = st.b2 >= 0 ? p->slots[st.b2].elems : 0;
       if (st.delta >= 0 && p->delta_mode != 0 && !cplx && p->cur_prec == PREC_F64) run_delta_gemm(p, d, st, s);
       else run_gemm(p, d, st, s);
       break;
@@ -1150,6 +1156,7 @@ void plan_autotune(cc_plan *p, int reps) {
       d.B = ptr_of(p, st->b);
       d.C = ptr_of(p, st->c);
       d.ws = st->b2 >= 0 ? ptr_of(p, st->b2) : nullptr;
+      d.ws_elems = st->b2 >= 0 ? p->slots[st->b2].elems : 0;
       if (!p->cplx && prec != PREC_F64) use_shadows(p, d, *st, s, false);
       int best = slot;
       float best_ms = 1e30f;

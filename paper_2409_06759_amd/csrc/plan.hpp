@@ -15,6 +15,8 @@ struct cc_ctx {
   bool own_stream = false;
   std::string last_error;
   double *pinned = nullptr;  // small pinned host buffer for scalar read-back
+  void *gemm_ws = nullptr;   // cc_gemm's tail workspace (grown on demand, freed by cc_destroy)
+  int64_t gemm_ws_elems = 0;
 };
 
 namespace ccmi {

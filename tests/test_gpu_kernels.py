@@ -158,3 +158,57 @@ def test_gemm_with_empty_contraction_scales_c(ctx, prec, cplx):
     B = torch.zeros((53, 0), dtype=dt, device="cuda")
     E.gemm(ctx, A, B, Cd, 0.5, -1.5, prec=E.PRECS[prec])
     assert torch.equal(Cd.cpu(), -1.5 * C0)
+
+
+# Forced tile configurations whose launches end in an almost empty round of
+# workgroups: 544 tiles = 2 x 256 + 32 (one workgroup per CU) or 512 + 32 (two).
+TAIL_CASES = [
+    ("f64", 4, 1024, 136 * 128, 2048, True, True, 1),     # 256x128 tiles, column panels cut
+    ("f64", 4, 1024, 136 * 128, 2048, False, False, 1),
+    ("f64", 4, 136 * 256, 512, 2048, True, True, 2),      # row panels cut
+    ("bf16x3", 7, 1024, 136 * 128, 2048, True, True, 1),  # 256x128x32
+    ("f32", 7, 1024, 68 * 128, 2048, True, True, 1),      # 128x128x32
+]
+
+
+@pytest.mark.parametrize("prec,tile,M,N,K,akc,bkc,axis", TAIL_CASES)
+def test_gemm_tail_cut(ctx, monkeypatch, prec, tile, M, N, K, akc, bkc, axis):
+    """A GEMM whose last round of workgroups would be nearly empty runs as whole
+    rounds plus a K-split tail: the result meets the same error bound as one
+    launch, the main panels are bitwise those of one launch, and exactly a
+    trailing block of whole panels differs (summed over K in another order)."""
+    from paper_2409_06759_amd import engine as E
+    print(f"tail cut {prec} tile {tile} M={M} N={N} K={K} akc={akc} bkc={bkc}", flush=True)
+    rng = np.random.default_rng(M + 3 * N + K)
+    A = rng.normal(size=(M, K))
+    B = rng.normal(size=(N, K))
+    C0 = rng.normal(size=(M, N))
+    alpha, beta = 0.75, -0.5
+    Ad = torch.from_numpy(A if akc else np.ascontiguousarray(A.T)).cuda()
+    Bd = torch.from_numpy(B if bkc else np.ascontiguousarray(B.T)).cuda()
+    monkeypatch.setenv("CC_GEMM_TILE", str(tile))
+    out = {}
+    for cut in ("0", "1"):
+        monkeypatch.setenv("CC_GEMM_TAIL", cut)
+        Cd = torch.from_numpy(C0).cuda()
+        E.gemm(ctx, Ad, Bd, Cd, alpha, beta, a_kcontig=akc, b_kcontig=bkc, prec=E.PRECS[prec])
+        out[cut] = Cd.cpu().numpy()
+    ref = alpha * (A @ B.T) + beta * C0
+    u = 2.0 ** -53 if prec == "f64" else 2.0 ** -24
+    eps = (K + 16) * u + (3 * 2.0 ** -17 if prec == "bf16x3" else 0.0)
+    bound = 2 * eps * abs(alpha) * (np.abs(A) @ np.abs(B).T) + 4 * np.finfo(float).eps * np.abs(beta * C0)
+    for cut in ("0", "1"):
+        err = np.abs(out[cut] - ref)
+        assert np.all(err <= bound), (cut, (err / bound).max())
+    diff = out["0"] != out["1"]
+    lines = np.nonzero(diff.any(axis=0 if axis == 1 else 1))[0]
+    assert lines.size > 0, "no tail cut happened"
+    first = int(lines[0])
+    panel = 128 if axis == 1 else 256
+    extent = N if axis == 1 else M
+    print(f"tail from {first} of {extent}", flush=True)
+    assert first % panel == 0 and first >= extent // 2
+    assert np.array_equal(lines, np.arange(first, extent))
+    main = out["0"][:, :first] if axis == 1 else out["0"][:first]
+    main1 = out["1"][:, :first] if axis == 1 else out["1"][:first]
+    assert np.array_equal(main, main1)

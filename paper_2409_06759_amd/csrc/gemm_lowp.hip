@@ -53,7 +53,7 @@ struct LCfg {
   static_assert((BM * BK) % NT == 0 && (BN * BK) % NT == 0, "load split");
 };
 
-template <int MODE, int BM, int BN, int BK, int WM, int WN, bool AKC, bool BKC, bool LPIN>
+template <int MODE, int BM, int BN, int BK, int WM, int WN, bool AKC, bool BKC, bool LPIN, int PF = 1>
 __device__ __forceinline__ void gemm_lowp_body(const GemmDesc &d, int64_t tilesM, int64_t tilesN, int64_t L0) {
   using C = LCfg<MODE, BM, BN, BK, WM, WN, AKC, BKC>;
   // F32: one float array per operand and buffer.  BF16X3: hi and lo arrays
@@ -118,24 +118,53 @@ __device__ __forceinline__ void gemm_lowp_body(const GemmDesc &d, int64_t tilesM
     }
   };
 
+  // converted operands: one register set of a chunk's vectors
+  auto gload_into = [&](int64_t k0, uint4 (&xa)[AVT][NPART], uint4 (&xb)[BVT][NPART]) {
+#pragma unroll
+    for (int i = 0; i < AVT; ++i) {
+      const int v = tid + i * C::NT;
+      if (v < ANV) {
+        if (AKC) vload(Al, d.a_plane, d.sam, M, K, m0, k0, vec_a, v, AC / VEC, xa[i]);
+        else vload(Al, d.a_plane, d.sak, K, M, k0, m0, vec_a, v, AC / VEC, xa[i]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < BVT; ++i) {
+      const int v = tid + i * C::NT;
+      if (v < BNV) {
+        if (BKC) vload(Bl, d.b_plane, d.sbn, N, K, n0, k0, vec_b, v, BC / VEC, xb[i]);
+        else vload(Bl, d.b_plane, d.sbk, K, N, k0, n0, vec_b, v, BC / VEC, xb[i]);
+      }
+    }
+  };
+  auto sstore_from = [&](int buf, const uint4 (&xa)[AVT][NPART], const uint4 (&xb)[BVT][NPART]) {
+#pragma unroll
+    for (int i = 0; i < AVT; ++i) {
+      const int v = tid + i * C::NT;
+      if (v < ANV) {
+        const int r = v / (AC / VEC), c = (v % (AC / VEC)) * VEC;
+        EL *dst = reinterpret_cast<EL *>(a_base(buf));
+#pragma unroll
+        for (int pl = 0; pl < NPART; ++pl)
+          *reinterpret_cast<uint4 *>(dst + pl * C::A_ELEMS + r * C::A_LD + c) = xa[i][pl];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < BVT; ++i) {
+      const int v = tid + i * C::NT;
+      if (v < BNV) {
+        const int r = v / (BC / VEC), c = (v % (BC / VEC)) * VEC;
+        EL *dst = reinterpret_cast<EL *>(b_base(buf));
+#pragma unroll
+        for (int pl = 0; pl < NPART; ++pl)
+          *reinterpret_cast<uint4 *>(dst + pl * C::B_ELEMS + r * C::B_LD + c) = xb[i][pl];
+      }
+    }
+  };
+
   auto gload = [&](int64_t k0) {
     if constexpr (LPIN) {
-#pragma unroll
-      for (int i = 0; i < AVT; ++i) {
-        const int v = tid + i * C::NT;
-        if (v < ANV) {
-          if (AKC) vload(Al, d.a_plane, d.sam, M, K, m0, k0, vec_a, v, AC / VEC, va[i]);
-          else vload(Al, d.a_plane, d.sak, K, M, k0, m0, vec_a, v, AC / VEC, va[i]);
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < BVT; ++i) {
-        const int v = tid + i * C::NT;
-        if (v < BNV) {
-          if (BKC) vload(Bl, d.b_plane, d.sbn, N, K, n0, k0, vec_b, v, BC / VEC, vb[i]);
-          else vload(Bl, d.b_plane, d.sbk, K, N, k0, n0, vec_b, v, BC / VEC, vb[i]);
-        }
-      }
+      gload_into(k0, va, vb);
     } else {
 #pragma unroll
       for (int i = 0; i < C::LA; ++i) {
@@ -157,28 +186,7 @@ __device__ __forceinline__ void gemm_lowp_body(const GemmDesc &d, int64_t tilesM
   };
   auto sstore = [&](int buf) {
     if constexpr (LPIN) {
-#pragma unroll
-      for (int i = 0; i < AVT; ++i) {
-        const int v = tid + i * C::NT;
-        if (v < ANV) {
-          const int r = v / (AC / VEC), c = (v % (AC / VEC)) * VEC;
-          EL *dst = reinterpret_cast<EL *>(a_base(buf));
-#pragma unroll
-          for (int pl = 0; pl < NPART; ++pl)
-            *reinterpret_cast<uint4 *>(dst + pl * C::A_ELEMS + r * C::A_LD + c) = va[i][pl];
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < BVT; ++i) {
-        const int v = tid + i * C::NT;
-        if (v < BNV) {
-          const int r = v / (BC / VEC), c = (v % (BC / VEC)) * VEC;
-          EL *dst = reinterpret_cast<EL *>(b_base(buf));
-#pragma unroll
-          for (int pl = 0; pl < NPART; ++pl)
-            *reinterpret_cast<uint4 *>(dst + pl * C::B_ELEMS + r * C::B_LD + c) = vb[i][pl];
-        }
-      }
+      sstore_from(buf, va, vb);
     } else {
 #pragma unroll
       for (int i = 0; i < C::LA; ++i) {
@@ -216,12 +224,8 @@ __device__ __forceinline__ void gemm_lowp_body(const GemmDesc &d, int64_t tilesM
     for (int j = 0; j < C::FN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
   const int64_t nk = (K + BK - 1) / BK;
-  gload(0);
-  sstore(0);
-  __syncthreads();
-  for (int64_t kt = 0; kt < nk; ++kt) {
-    const int buf = kt & 1;
-    if (kt + 1 < nk) gload((kt + 1) * BK);
+  // MFMAs over the chunk staged in LDS buffer buf
+  auto mma = [&](int buf) {
     if constexpr (MODE == PREC_F32) {
       const float *as = reinterpret_cast<const float *>(a_base(buf));
       const float *bs = reinterpret_cast<const float *>(b_base(buf));
@@ -288,8 +292,40 @@ __device__ __forceinline__ void gemm_lowp_body(const GemmDesc &d, int64_t tilesM
           }
       }
     }
-    if (kt + 1 < nk) sstore(buf ^ 1);
+  };
+
+  if constexpr (LPIN && PF == 2) {
+    // Two chunks in flight: while chunk kt is multiplied out of one LDS
+    // buffer, chunk kt+1 sits in registers (stored to the other buffer after
+    // the MFMAs) and chunk kt+2 is being loaded into the second register set.
+    // Unrolled by two so that each register set is named statically.
+    uint4 wa[AVT][NPART], wb[BVT][NPART];
+    gload_into(0, va, vb);
+    if (nk > 1) gload_into(BK, wa, wb);
+    sstore_from(0, va, vb);
     __syncthreads();
+    for (int64_t kt = 0; kt < nk; kt += 2) {
+      if (kt + 2 < nk) gload_into((kt + 2) * BK, va, vb);
+      mma(0);
+      if (kt + 1 < nk) sstore_from(1, wa, wb);
+      __syncthreads();
+      if (kt + 1 >= nk) break;
+      if (kt + 3 < nk) gload_into((kt + 3) * BK, wa, wb);
+      mma(1);
+      if (kt + 2 < nk) sstore_from(0, va, vb);
+      __syncthreads();
+    }
+  } else {
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    for (int64_t kt = 0; kt < nk; ++kt) {
+      const int buf = kt & 1;
+      if (kt + 1 < nk) gload((kt + 1) * BK);
+      mma(buf);
+      if (kt + 1 < nk) sstore(buf ^ 1);
+      __syncthreads();
+    }
   }
 
   // epilogue: accumulator t of lane l is C[4 (l >> 4) + t][l & 15] of its block
@@ -319,10 +355,10 @@ __device__ __forceinline__ void gemm_lowp_body(const GemmDesc &d, int64_t tilesM
     }
 }
 
-template <int MODE, int BM, int BN, int BK, int WM, int WN, bool AKC, bool BKC, int TAG, bool LPIN>
+template <int MODE, int BM, int BN, int BK, int WM, int WN, bool AKC, bool BKC, int TAG, bool LPIN, int PF>
 __global__ __launch_bounds__(WM *WN *kWave) void gemm_lowp_kernel(GemmDesc d, int64_t tilesM,
                                                                    int64_t tilesN) {
-  gemm_lowp_body<MODE, BM, BN, BK, WM, WN, AKC, BKC, LPIN>(d, tilesM, tilesN,
+  gemm_lowp_body<MODE, BM, BN, BK, WM, WN, AKC, BKC, LPIN, PF>(d, tilesM, tilesN,
                                                            xcd_remap(blockIdx.x, tilesM * tilesN * d.split));
 }
 
@@ -337,6 +373,24 @@ __global__ __launch_bounds__(WM *WN *kWave) void gemm_lowp_grouped(const GemmGro
                                                             int64_t(blockIdx.x) - off[b]);
 }
 
+template <int MODE, int BM, int BN, int BK, int WM, int WN, bool AKC, bool BKC>
+void launch_lg(const GemmGroupEntry *e, const int64_t *off, int n, int64_t blocks, hipStream_t s) {
+  hipLaunchKernelGGL((gemm_lowp_grouped<MODE, BM, BN, BK, WM, WN, AKC, BKC>), dim3(blocks),
+                     dim3(WM * WN * kWave), 0, s, e, off, n);
+}
+
+// PF: chunks of K in flight (1 or 2); only the converted-operand variant has
+// a deeper pipeline, the staging variant is shared by both.
+template <int MODE, int BM, int BN, int BK, int WM, int WN, bool AKC, bool BKC, int PF, int TAG = 0>
+void launch_l(const GemmDesc &d, int64_t tm, int64_t tn, hipStream_t s) {
+  if (d.lp_in)
+    hipLaunchKernelGGL((gemm_lowp_kernel<MODE, BM, BN, BK, WM, WN, AKC, BKC, TAG, true, PF>),
+                       dim3(tm * tn * d.split), dim3(WM * WN * kWave), 0, s, d, tm, tn);
+  else
+    hipLaunchKernelGGL((gemm_lowp_kernel<MODE, BM, BN, BK, WM, WN, AKC, BKC, TAG, false, 1>),
+                       dim3(tm * tn * d.split), dim3(WM * WN * kWave), 0, s, d, tm, tn);
+}
+
 struct LTile {
   const char *name;
   int BM, BN, BK;
@@ -347,60 +401,47 @@ struct LTile {
   int (*occupancy[8])();  // resident workgroups per CU, [lp_in*4 + akc*2 + bkc]
 };
 
-template <int MODE, int BM, int BN, int BK, int WM, int WN, bool AKC, bool BKC>
-void launch_lg(const GemmGroupEntry *e, const int64_t *off, int n, int64_t blocks, hipStream_t s) {
-  hipLaunchKernelGGL((gemm_lowp_grouped<MODE, BM, BN, BK, WM, WN, AKC, BKC>), dim3(blocks),
-                     dim3(WM * WN * kWave), 0, s, e, off, n);
-}
-
-template <int MODE, int BM, int BN, int BK, int WM, int WN, bool AKC, bool BKC, int TAG = 0>
-void launch_l(const GemmDesc &d, int64_t tm, int64_t tn, hipStream_t s) {
-  if (d.lp_in)
-    hipLaunchKernelGGL((gemm_lowp_kernel<MODE, BM, BN, BK, WM, WN, AKC, BKC, TAG, true>),
-                       dim3(tm * tn * d.split), dim3(WM * WN * kWave), 0, s, d, tm, tn);
-  else
-    hipLaunchKernelGGL((gemm_lowp_kernel<MODE, BM, BN, BK, WM, WN, AKC, BKC, TAG, false>),
-                       dim3(tm * tn * d.split), dim3(WM * WN * kWave), 0, s, d, tm, tn);
-}
-
 // workgroups of one configuration resident on a CU (0 if unknown)
-template <int MODE, int BM, int BN, int BK, int WM, int WN, bool AKC, bool BKC, bool LPIN>
+template <int MODE, int BM, int BN, int BK, int WM, int WN, bool AKC, bool BKC, bool LPIN, int PF>
 int occ_l() {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gemm_lowp_kernel<MODE, BM, BN, BK, WM, WN, AKC, BKC, 0, LPIN>,
-                                                   WM * WN * kWave, 0) != hipSuccess) {
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &nb, gemm_lowp_kernel<MODE, BM, BN, BK, WM, WN, AKC, BKC, 0, LPIN, LPIN ? PF : 1>, WM * WN * kWave, 0) !=
+      hipSuccess) {
     (void)hipGetLastError();
     return 0;
   }
   return nb;
 }
-#define CC_LOCC(MODE, BM, BN, BK, WM, WN, LPIN)                                                      \
-  &occ_l<MODE, BM, BN, BK, WM, WN, false, false, LPIN>, &occ_l<MODE, BM, BN, BK, WM, WN, false, true, LPIN>, \
-      &occ_l<MODE, BM, BN, BK, WM, WN, true, false, LPIN>, &occ_l<MODE, BM, BN, BK, WM, WN, true, true, LPIN>
-#define CC_LTILE(MODE, BM, BN, BK, WM, WN)                                                          \
-  LTile {                                                                                           \
-    #BM "x" #BN "x" #BK "_w" #WM "x" #WN, BM, BN, BK,                                               \
-        {&launch_l<MODE, BM, BN, BK, WM, WN, false, false>, &launch_l<MODE, BM, BN, BK, WM, WN, false, true>, \
-         &launch_l<MODE, BM, BN, BK, WM, WN, true, false>, &launch_l<MODE, BM, BN, BK, WM, WN, true, true>},  \
-        &launch_l<MODE, BM, BN, BK, WM, WN, true, true, 1>, &launch_l<MODE, BM, BN, BK, WM, WN, true, true, 2>, \
-        {&launch_lg<MODE, BM, BN, BK, WM, WN, false, false>, &launch_lg<MODE, BM, BN, BK, WM, WN, false, true>, \
-         &launch_lg<MODE, BM, BN, BK, WM, WN, true, false>, &launch_lg<MODE, BM, BN, BK, WM, WN, true, true>},  \
-        {CC_LOCC(MODE, BM, BN, BK, WM, WN, false), CC_LOCC(MODE, BM, BN, BK, WM, WN, true)}                  \
+#define CC_LOCC(MODE, BM, BN, BK, WM, WN, LPIN, PF)                                                            \
+  &occ_l<MODE, BM, BN, BK, WM, WN, false, false, LPIN, PF>, &occ_l<MODE, BM, BN, BK, WM, WN, false, true, LPIN, PF>, \
+      &occ_l<MODE, BM, BN, BK, WM, WN, true, false, LPIN, PF>, &occ_l<MODE, BM, BN, BK, WM, WN, true, true, LPIN, PF>
+#define CC_LTILE(MODE, BM, BN, BK, WM, WN, PF)                                                                   \
+  LTile {                                                                                                        \
+    #BM "x" #BN "x" #BK "_w" #WM "x" #WN "_p" #PF, BM, BN, BK,                                                   \
+        {&launch_l<MODE, BM, BN, BK, WM, WN, false, false, PF>, &launch_l<MODE, BM, BN, BK, WM, WN, false, true, PF>, \
+         &launch_l<MODE, BM, BN, BK, WM, WN, true, false, PF>, &launch_l<MODE, BM, BN, BK, WM, WN, true, true, PF>},  \
+        &launch_l<MODE, BM, BN, BK, WM, WN, true, true, PF, 1>, &launch_l<MODE, BM, BN, BK, WM, WN, true, true, PF, 2>, \
+        {&launch_lg<MODE, BM, BN, BK, WM, WN, false, false>, &launch_lg<MODE, BM, BN, BK, WM, WN, false, true>,     \
+         &launch_lg<MODE, BM, BN, BK, WM, WN, true, false>, &launch_lg<MODE, BM, BN, BK, WM, WN, true, true>},      \
+        {CC_LOCC(MODE, BM, BN, BK, WM, WN, false, PF), CC_LOCC(MODE, BM, BN, BK, WM, WN, true, PF)}              \
   }
-
 const LTile kF32Tiles[] = {
-    CC_LTILE(PREC_F32, 128, 128, 16, 2, 2), CC_LTILE(PREC_F32, 64, 64, 16, 2, 2),
-    CC_LTILE(PREC_F32, 32, 32, 16, 2, 2),   CC_LTILE(PREC_F32, 128, 64, 16, 2, 2),
-    CC_LTILE(PREC_F32, 64, 128, 16, 2, 2),  CC_LTILE(PREC_F32, 128, 128, 32, 2, 2),
-    CC_LTILE(PREC_F32, 128, 128, 16, 4, 2), CC_LTILE(PREC_F32, 128, 128, 32, 4, 2),
+    CC_LTILE(PREC_F32, 128, 128, 16, 2, 2, 1), CC_LTILE(PREC_F32, 64, 64, 16, 2, 2, 1),
+    CC_LTILE(PREC_F32, 32, 32, 16, 2, 2, 1),   CC_LTILE(PREC_F32, 128, 64, 16, 2, 2, 1),
+    CC_LTILE(PREC_F32, 64, 128, 16, 2, 2, 1),  CC_LTILE(PREC_F32, 128, 128, 32, 2, 2, 1),
+    CC_LTILE(PREC_F32, 128, 128, 16, 4, 2, 1), CC_LTILE(PREC_F32, 128, 128, 32, 4, 2, 1),
+    CC_LTILE(PREC_F32, 128, 128, 32, 4, 2, 2),
 };
 const LTile kB3Tiles[] = {
-    CC_LTILE(PREC_BF16X3, 128, 128, 32, 2, 2), CC_LTILE(PREC_BF16X3, 64, 64, 32, 2, 2),
-    CC_LTILE(PREC_BF16X3, 32, 32, 32, 2, 2),   CC_LTILE(PREC_BF16X3, 128, 64, 32, 2, 2),
-    CC_LTILE(PREC_BF16X3, 64, 128, 32, 2, 2),  CC_LTILE(PREC_BF16X3, 128, 128, 64, 2, 2),
-    CC_LTILE(PREC_BF16X3, 128, 128, 32, 4, 2), CC_LTILE(PREC_BF16X3, 256, 128, 32, 4, 2),
+    CC_LTILE(PREC_BF16X3, 128, 128, 32, 2, 2, 1), CC_LTILE(PREC_BF16X3, 64, 64, 32, 2, 2, 1),
+    CC_LTILE(PREC_BF16X3, 32, 32, 32, 2, 2, 1),   CC_LTILE(PREC_BF16X3, 128, 64, 32, 2, 2, 1),
+    CC_LTILE(PREC_BF16X3, 64, 128, 32, 2, 2, 1),  CC_LTILE(PREC_BF16X3, 128, 128, 64, 2, 2, 1),
+    CC_LTILE(PREC_BF16X3, 128, 128, 32, 4, 2, 1), CC_LTILE(PREC_BF16X3, 256, 128, 32, 4, 2, 1),
+    CC_LTILE(PREC_BF16X3, 128, 128, 32, 4, 2, 2),
 };
-constexpr int kNumL = 8;
+static_assert(sizeof(kF32Tiles) == sizeof(kB3Tiles), "one configuration count for both precisions");
+constexpr int kNumL = sizeof(kF32Tiles) / sizeof(kF32Tiles[0]);
 
 // resident slots per (precision, configuration, variant) on the device; -1 = not yet asked
 std::atomic<int64_t> g_lslots[2][kNumL][8];

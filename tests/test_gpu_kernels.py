@@ -212,3 +212,35 @@ def test_gemm_tail_cut(ctx, monkeypatch, prec, tile, M, N, K, akc, bkc, axis):
     main = out["0"][:, :first] if axis == 1 else out["0"][:first]
     main1 = out["1"][:, :first] if axis == 1 else out["1"][:first]
     assert np.array_equal(main, main1)
+
+
+# (precision, one-chunk-prefetch configuration, two-chunk configuration of the same tile)
+PF_PAIRS = [("f32", 7, 8), ("bf16x3", 6, 8)]
+
+
+@pytest.mark.parametrize("prec,t1,t2", PF_PAIRS)
+@pytest.mark.parametrize("K", [5, 32, 64, 133, 160, 1000])
+@pytest.mark.parametrize("akc,bkc", [(True, True), (False, False), (True, False), (False, True)])
+def test_gemm_lowp_two_chunk_prefetch_is_bitwise_one_chunk(ctx, monkeypatch, prec, t1, t2, K, akc, bkc):
+    """Keeping two K chunks in flight changes when operands arrive, not what
+    is multiplied or in which order: results are bit-identical for one, two,
+    odd and even chunk counts and every operand layout."""
+    from paper_2409_06759_amd import engine as E
+    M, N = 300, 270
+    print(f"prefetch {prec} tiles {t1}/{t2} K={K} akc={akc} bkc={bkc}", flush=True)
+    rng = np.random.default_rng(K + 17)
+    A = rng.normal(size=(M, K))
+    B = rng.normal(size=(N, K))
+    C0 = rng.normal(size=(M, N))
+    Ad = torch.from_numpy(A if akc else np.ascontiguousarray(A.T)).cuda()
+    Bd = torch.from_numpy(B if bkc else np.ascontiguousarray(B.T)).cuda()
+    out = []
+    for t in (t1, t2):
+        monkeypatch.setenv("CC_GEMM_TILE", str(t))
+        Cd = torch.from_numpy(C0).cuda()
+        E.gemm(ctx, Ad, Bd, Cd, 0.5, -1.25, a_kcontig=akc, b_kcontig=bkc, prec=E.PRECS[prec])
+        out.append(Cd.cpu().numpy())
+    assert np.array_equal(out[0], out[1])
+    ref = 0.5 * (A @ B.T) - 1.25 * C0
+    tol = 1e-4 if prec == "f32" else 1e-3
+    assert np.abs(out[1] - ref).max() <= tol * max(1.0, np.sqrt(K))

@@ -362,6 +362,163 @@ __global__ __launch_bounds__(WM *WN *kWave) void gemm_lowp_kernel(GemmDesc d, in
                                                            xcd_remap(blockIdx.x, tilesM * tilesN * d.split));
 }
 
+// ---- split bf16 with LDS-direct loads --------------------------------------
+// Full 256x128 tiles, K a multiple of 32, both operands K-contiguous
+// converted copies (bf16 hi plane + lo plane) with 16-byte aligned rows.
+// global_load_lds_dwordx4 writes each lane's 16 bytes straight into LDS, so
+// no registers stage the operands, and three LDS stages keep two chunks of K
+// in flight while the third is multiplied.  A 16-row block of a stage is 64
+// slots of 16 bytes: slot s holds row (s & 15), k-group (s >> 4), which is the
+// MFMA operand layout of lane s, so a fragment is one contiguous 1 KiB
+// ds_read_b128 per wave.  Products, their order and the epilogue are those of
+// the staged kernel of the same tile, so results are bitwise the same.
+//
+// The loads are issued from inline assembly, so the compiler neither knows
+// of them nor inserts waits for them; the waits are explicit.  Vector memory
+// operations of a wave complete in issue order, so "vmcnt <= 6" after the
+// six loads of chunk kt+1 means chunk kt has landed (more operations issued
+// in between only make that wait longer), and a barrier behind it makes the
+// chunk visible to every wave.  The same barrier, behind "lgkmcnt == 0",
+// guarantees that every wave has finished reading the stage the next loads
+// overwrite.  Nothing else in the kernel uses M0.
+namespace dma {
+constexpr int BM = 256, BN = 128, BK = 32, WM = 4, WN = 2, NT = WM * WN * kWave;
+constexpr int FM = BM / WM / 16, FN = BN / WN / 16;
+constexpr int A_EL = BM * BK, B_EL = BN * BK;  // bf16 elements per plane and stage
+constexpr int STAGE = 2 * A_EL + 2 * B_EL;     // [A hi | A lo | B hi | B lo]
+constexpr int NSTAGE = 3;
+constexpr int LOADS = (2 * (BM / 16) + 2 * (BN / 16)) / (WM * WN);  // per wave and chunk
+static_assert(LOADS == 6, "the explicit waits count six loads per chunk");
+}  // namespace dma
+
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Winline-asm"  // m0 is reserved: set here, used by nothing else
+// 16 bytes per lane from src into LDS at lds_base + 16 * lane (lds_base
+// wave-uniform); one wait state between the M0 write and the LDS-DMA load
+__device__ __forceinline__ void lds_load16(const void *src, uint32_t lds_base) {
+  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(src), "s"(lds_base)
+               : "memory", "m0");
+}
+#pragma clang diagnostic pop
+
+__device__ __forceinline__ void gemm_b3_dma_body(const GemmDesc &d, int64_t tilesM, int64_t tilesN, int64_t L0) {
+  using namespace dma;
+  __shared__ __attribute__((aligned(16))) unsigned short S[NSTAGE * STAGE];
+
+  const int64_t tiles = tilesM * tilesN;
+  const int64_t ks = L0 / tiles, L = L0 % tiles;
+  const int64_t m0 = (L % tilesM) * BM, n0 = (L / tilesM) * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm0 = (wave / WN) * (BM / WM), wn0 = (wave % WN) * (BN / WN);
+  const int q = lane >> 4, r = lane & 15;
+  const int64_t M = d.M, N = d.N;
+  const int64_t kchunk = ((d.K + d.split - 1) / d.split + BK - 1) / BK * BK;
+  const int64_t kb = ks * kchunk;
+  const int64_t K = std::max<int64_t>(0, std::min<int64_t>(d.K - kb, kchunk));
+  const int64_t nk = K / BK;
+
+  // this wave's loads: A blocks 2w and 2w+1, B block w, hi and lo planes of
+  // each; LDS addresses are byte offsets in the shared aperture (its low 32
+  // bits), made wave-uniform for M0
+  const uint32_t lds0 = static_cast<uint32_t>(reinterpret_cast<uintptr_t>(S));
+  const unsigned short *src[LOADS];
+  uint32_t dst[LOADS];
+  const unsigned short *Ag = static_cast<const unsigned short *>(d.A) + kb;
+  const unsigned short *Bg = static_cast<const unsigned short *>(d.B) + kb;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int blk = 2 * wave + (u >> 1), pl = u & 1;
+    src[u] = Ag + pl * d.a_plane + (m0 + blk * 16 + r) * d.sam + q * 8;
+    dst[u] = __builtin_amdgcn_readfirstlane(lds0 + 2u * uint32_t(pl * A_EL + blk * 512));
+  }
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    src[4 + u] = Bg + u * d.b_plane + (n0 + wave * 16 + r) * d.sbn + q * 8;
+    dst[4 + u] = __builtin_amdgcn_readfirstlane(lds0 + 2u * uint32_t(2 * A_EL + u * B_EL + wave * 512));
+  }
+  auto issue = [&](int stage, int64_t k0) {
+#pragma unroll
+    for (int u = 0; u < LOADS; ++u) lds_load16(src[u] + k0, dst[u] + uint32_t(stage) * uint32_t(2 * STAGE));
+  };
+
+  f4 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+
+  if (nk > 0) issue(0, 0);
+  if (nk > 1) issue(1, BK);
+  int cur = 0, nxt = 2;
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    if (kt + 1 < nk) asm volatile("s_waitcnt vmcnt(6) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    else asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    if (kt + 2 < nk) issue(nxt, (kt + 2) * BK);
+    const unsigned short *St = S + cur * STAGE;
+    bf8 fah[FM], fal[FM], fbh[FN], fbl[FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+      const int blk = (wm0 >> 4) + i;
+      fah[i] = *reinterpret_cast<const bf8 *>(St + blk * 512 + lane * 8);
+      fal[i] = *reinterpret_cast<const bf8 *>(St + A_EL + blk * 512 + lane * 8);
+    }
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int blk = (wn0 >> 4) + j;
+      fbh[j] = *reinterpret_cast<const bf8 *>(St + 2 * A_EL + blk * 512 + lane * 8);
+      fbl[j] = *reinterpret_cast<const bf8 *>(St + 2 * A_EL + B_EL + blk * 512 + lane * 8);
+    }
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fal[i], fbh[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fah[i], fbl[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fah[i], fbh[j], acc[i][j], 0, 0, 0);
+      }
+    cur = cur == NSTAGE - 1 ? 0 : cur + 1;
+    nxt = nxt == NSTAGE - 1 ? 0 : nxt + 1;
+  }
+
+  // epilogue (as the staged kernel): accumulator t of lane l is C[4 (l >> 4) + t][l & 15]
+  double *__restrict__ Cp = static_cast<double *>(d.C);
+  double alpha = d.alpha, beta = d.beta;
+  int64_t ldc = d.ldc;
+  if (d.split > 1) {
+    Cp = static_cast<double *>(d.ws) + ks * M * N;
+    alpha = 1.0;
+    beta = 0.0;
+    ldc = N;
+  }
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int64_t gn = n0 + wn0 + j * 16 + r;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int64_t gm = m0 + wm0 + i * 16 + 4 * q + t;
+        if (gm < M && gn < N) {
+          double *p = Cp + gm * ldc + gn;
+          const double v = alpha * static_cast<double>(acc[i][j][t]);
+          *p = (beta == 0.0) ? v : v + beta * *p;
+        }
+      }
+    }
+}
+
+template <int TAG>
+__global__ __launch_bounds__(dma::NT) void gemm_b3_dma_kernel(GemmDesc d, int64_t tilesM, int64_t tilesN) {
+  gemm_b3_dma_body(d, tilesM, tilesN, xcd_remap(blockIdx.x, tilesM * tilesN * d.split));
+}
+
+// the shapes and layouts the LDS-direct kernel handles
+bool b3_dma_ok(const GemmDesc &d) {
+  return d.lp_in && d.sak == 1 && d.sbk == 1 && d.M % dma::BM == 0 && d.N % dma::BN == 0 && d.K % dma::BK == 0 &&
+         d.sam % 8 == 0 && d.sbn % 8 == 0 && d.a_plane % 8 == 0 && d.b_plane % 8 == 0 &&
+         (reinterpret_cast<uintptr_t>(d.A) & 15) == 0 && (reinterpret_cast<uintptr_t>(d.B) & 15) == 0;
+}
+
 // Grouped launch over many systems (FP64 operands converted while staging):
 // system b owns logical tiles [off[b], off[b+1]).
 template <int MODE, int BM, int BN, int BK, int WM, int WN, bool AKC, bool BKC>
@@ -426,12 +583,27 @@ int occ_l() {
          &launch_lg<MODE, BM, BN, BK, WM, WN, true, false>, &launch_lg<MODE, BM, BN, BK, WM, WN, true, true>},      \
         {CC_LOCC(MODE, BM, BN, BK, WM, WN, false, PF), CC_LOCC(MODE, BM, BN, BK, WM, WN, true, PF)}              \
   }
+template <int TAG>
+void launch_b3_dma(const GemmDesc &d, int64_t tm, int64_t tn, hipStream_t s) {
+  if (b3_dma_ok(d))
+    hipLaunchKernelGGL((gemm_b3_dma_kernel<TAG>), dim3(tm * tn * d.split), dim3(dma::NT), 0, s, d, tm, tn);
+  else
+    launch_l<PREC_BF16X3, 256, 128, 32, 4, 2, true, true, 1, TAG>(d, tm, tn, s);
+}
+int occ_b3_dma() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gemm_b3_dma_kernel<0>, dma::NT, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return nb;
+}
 const LTile kF32Tiles[] = {
     CC_LTILE(PREC_F32, 128, 128, 16, 2, 2, 1), CC_LTILE(PREC_F32, 64, 64, 16, 2, 2, 1),
     CC_LTILE(PREC_F32, 32, 32, 16, 2, 2, 1),   CC_LTILE(PREC_F32, 128, 64, 16, 2, 2, 1),
     CC_LTILE(PREC_F32, 64, 128, 16, 2, 2, 1),  CC_LTILE(PREC_F32, 128, 128, 32, 2, 2, 1),
     CC_LTILE(PREC_F32, 128, 128, 16, 4, 2, 1), CC_LTILE(PREC_F32, 128, 128, 32, 4, 2, 1),
-    CC_LTILE(PREC_F32, 128, 128, 32, 4, 2, 2),
+    CC_LTILE(PREC_F32, 128, 128, 32, 4, 2, 2), CC_LTILE(PREC_F32, 256, 128, 32, 4, 2, 1),
 };
 const LTile kB3Tiles[] = {
     CC_LTILE(PREC_BF16X3, 128, 128, 32, 2, 2, 1), CC_LTILE(PREC_BF16X3, 64, 64, 32, 2, 2, 1),
@@ -439,6 +611,23 @@ const LTile kB3Tiles[] = {
     CC_LTILE(PREC_BF16X3, 64, 128, 32, 2, 2, 1),  CC_LTILE(PREC_BF16X3, 128, 128, 64, 2, 2, 1),
     CC_LTILE(PREC_BF16X3, 128, 128, 32, 4, 2, 1), CC_LTILE(PREC_BF16X3, 256, 128, 32, 4, 2, 1),
     CC_LTILE(PREC_BF16X3, 128, 128, 32, 4, 2, 2),
+    // 256x128x32 with LDS-direct loads where the shape allows, else staged
+    LTile{"256x128x32_w4x2_lds",
+          256,
+          128,
+          32,
+          {&launch_l<PREC_BF16X3, 256, 128, 32, 4, 2, false, false, 1>,
+           &launch_l<PREC_BF16X3, 256, 128, 32, 4, 2, false, true, 1>,
+           &launch_l<PREC_BF16X3, 256, 128, 32, 4, 2, true, false, 1>, &launch_b3_dma<0>},
+          &launch_b3_dma<1>,
+          &launch_b3_dma<2>,
+          {&launch_lg<PREC_BF16X3, 256, 128, 32, 4, 2, false, false>,
+           &launch_lg<PREC_BF16X3, 256, 128, 32, 4, 2, false, true>,
+           &launch_lg<PREC_BF16X3, 256, 128, 32, 4, 2, true, false>,
+           &launch_lg<PREC_BF16X3, 256, 128, 32, 4, 2, true, true>},
+          {CC_LOCC(PREC_BF16X3, 256, 128, 32, 4, 2, false, 1), &occ_l<PREC_BF16X3, 256, 128, 32, 4, 2, false, false, true, 1>,
+           &occ_l<PREC_BF16X3, 256, 128, 32, 4, 2, false, true, true, 1>,
+           &occ_l<PREC_BF16X3, 256, 128, 32, 4, 2, true, false, true, 1>, &occ_b3_dma}},
 };
 static_assert(sizeof(kF32Tiles) == sizeof(kB3Tiles), "one configuration count for both precisions");
 constexpr int kNumL = sizeof(kF32Tiles) / sizeof(kF32Tiles[0]);

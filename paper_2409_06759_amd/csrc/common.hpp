@@ -38,6 +38,21 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t total) {
   return (x < rem) ? x * (per + 1) + l : rem * (per + 1) + (x - rem) * per + l;
 }
 
+// ---- LDS-direct loads ----
+// 16 bytes per lane from src (global) into LDS at lds_base + 16 * lane, with
+// lds_base a wave-uniform byte offset in the shared aperture.  Issued from
+// inline assembly so that the compiler inserts no waits for it: the caller
+// waits with s_waitcnt vmcnt (vector memory operations of a wave complete in
+// issue order).  One wait state separates the M0 write from the load; the
+// kernels that use it use M0 for nothing else.
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Winline-asm"  // m0 is a reserved register
+__device__ __forceinline__ void lds_load16(const void *src, uint32_t lds_base) {
+  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(src), "s"(lds_base)
+               : "memory", "m0");
+}
+#pragma clang diagnostic pop
+
 // ---- GEMM descriptor: C[m][n] = alpha * sum_k A(m,k) B(n,k) + beta * C ----
 struct GemmDesc {
   int64_t M, N, K;

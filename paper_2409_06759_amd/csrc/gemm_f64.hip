@@ -216,6 +216,144 @@ __global__ __launch_bounds__(WM *WN *kWave) void gemm_f64_grouped(const GemmGrou
   gemm_f64_body<BM, BN, BK, WM, WN, AKC, BKC>(g.d, g.tilesM, g.tilesN, int64_t(blockIdx.x) - off[b]);
 }
 
+// ---- 256x128x16 with LDS-direct loads ---------------------------------------
+// Full tiles, K a multiple of 16, both operands K-contiguous with 16-byte
+// aligned rows (the particle-particle ladder's layout).  Each lane's 16
+// bytes go straight from HBM/L2 into LDS (global_load_lds_dwordx4): no
+// staging registers, three LDS stages, two chunks of K in flight.  A 16-row
+// block of a stage is 128 slots of 16 bytes; slot s holds row (L & 15),
+// k = 4 (L >> 4) + 2 (s & 1) + {0, 1} with L = s >> 1, so lane L finds the
+// four k values it feeds the f64 MFMA (k = 4q + s, as in the staged kernel)
+// in 32 contiguous bytes, and a wave's fragment reads are contiguous.  The
+// products and their order are those of the staged kernel of the same tile,
+// so results are bitwise the same.  Waits: "vmcnt <= 6" after the six loads
+// of chunk kt+1 means chunk kt has landed (in-order completion), the barrier
+// behind it makes that so for every wave, and "lgkmcnt == 0" before it
+// means every wave has finished reading the stage the next loads overwrite.
+namespace dma64 {
+constexpr int BM = 256, BN = 128, BK = 16, WM = 4, WN = 2, NT = WM * WN * kWave;
+constexpr int FM = BM / WM / 16, FN = BN / WN / 16;
+constexpr int A_EL = BM * BK, B_EL = BN * BK, STAGE = A_EL + B_EL;  // doubles
+constexpr int NSTAGE = 3;
+constexpr int LOADS = (2 * (BM / 16) + 2 * (BN / 16)) / (WM * WN);  // per wave and chunk
+static_assert(LOADS == 6, "the explicit waits count six loads per chunk");
+}  // namespace dma64
+
+__device__ __forceinline__ void gemm_f64_dma_body(const GemmDesc &d, int64_t tilesM, int64_t tilesN, int64_t L0) {
+  using namespace dma64;
+  __shared__ __attribute__((aligned(16))) double S[NSTAGE * STAGE];
+
+  const int64_t tiles = tilesM * tilesN;
+  const int64_t ks = L0 / tiles, L = L0 % tiles;
+  const int64_t m0 = (L % tilesM) * BM, n0 = (L / tilesM) * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm0 = (wave / WN) * (BM / WM), wn0 = (wave % WN) * (BN / WN);
+  const int q = lane >> 4, r = lane & 15;
+  const int64_t M = d.M, N = d.N;
+  const int64_t kchunk = ((d.K + d.split - 1) / d.split + BK - 1) / BK * BK;
+  const int64_t kb = ks * kchunk;
+  const int64_t K = std::max<int64_t>(0, std::min<int64_t>(d.K - kb, kchunk));
+  const int64_t nk = K / BK;
+
+  // this wave's loads: A blocks 2w and 2w+1, B block w, each as two halves
+  // of 64 slots; slot s = 64 h + lane holds row (L & 15), k pair 4 (L >> 4) + 2 (s & 1)
+  const uint32_t lds0 = static_cast<uint32_t>(reinterpret_cast<uintptr_t>(S));
+  const double *src[LOADS];
+  uint32_t dst[LOADS];
+  const double *Ag = static_cast<const double *>(d.A) + kb;
+  const double *Bg = static_cast<const double *>(d.B) + kb;
+  const int sl = lane >> 1;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int blk = 2 * wave + (u >> 1), h = u & 1;
+    // slot 64 h + lane belongs to lane L = 32 h + (lane >> 1) of the fragment reads
+    const int Ls = 32 * h + sl;
+    src[u] = Ag + (m0 + blk * 16 + (Ls & 15)) * d.sam + 4 * (Ls >> 4) + 2 * (lane & 1);
+    dst[u] = __builtin_amdgcn_readfirstlane(lds0 + 8u * uint32_t(blk * 256 + h * 128));
+  }
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int Ls = 32 * u + sl;
+    src[4 + u] = Bg + (n0 + wave * 16 + (Ls & 15)) * d.sbn + 4 * (Ls >> 4) + 2 * (lane & 1);
+    dst[4 + u] = __builtin_amdgcn_readfirstlane(lds0 + 8u * uint32_t(A_EL + wave * 256 + u * 128));
+  }
+  auto issue = [&](int stage, int64_t k0) {
+#pragma unroll
+    for (int u = 0; u < LOADS; ++u) lds_load16(src[u] + k0, dst[u] + uint32_t(stage) * uint32_t(8 * STAGE));
+  };
+
+  d4 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+  if (nk > 0) issue(0, 0);
+  if (nk > 1) issue(1, BK);
+  int cur = 0, nxt = 2;
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    if (kt + 1 < nk) asm volatile("s_waitcnt vmcnt(6) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    else asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    if (kt + 2 < nk) issue(nxt, (kt + 2) * BK);
+    const double *St = S + cur * STAGE;
+    d4 fa[FM], fb[FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+      fa[i] = *reinterpret_cast<const d4 *>(St + ((wm0 >> 4) + i) * 256 + lane * 4);
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+      fb[j] = *reinterpret_cast<const d4 *>(St + A_EL + ((wn0 >> 4) + j) * 256 + lane * 4);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i][s], fb[j][s], acc[i][j], 0, 0, 0);
+    cur = cur == NSTAGE - 1 ? 0 : cur + 1;
+    nxt = nxt == NSTAGE - 1 ? 0 : nxt + 1;
+  }
+
+  // epilogue (as the staged kernel): accumulator t of lane l holds row
+  // (l >> 4) + 4t, column l & 15 of its 16x16 block
+  double *__restrict__ Cp = static_cast<double *>(d.C);
+  double alpha = d.alpha, beta = d.beta;
+  int64_t ldc = d.ldc;
+  if (d.split > 1) {
+    Cp = static_cast<double *>(d.ws) + ks * M * N;
+    alpha = 1.0;
+    beta = 0.0;
+    ldc = N;
+  }
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int64_t gn = n0 + wn0 + j * 16 + r;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int64_t gm = m0 + wm0 + i * 16 + q + 4 * t;
+        if (gm < M && gn < N) {
+          double *p = Cp + gm * ldc + gn;
+          const double v = alpha * acc[i][j][t];
+          *p = (beta == 0.0) ? v : v + beta * *p;
+        }
+      }
+    }
+}
+
+template <int TAG>
+__global__ __launch_bounds__(dma64::NT) void gemm_f64_dma_kernel(GemmDesc d, int64_t tilesM, int64_t tilesN) {
+  gemm_f64_dma_body(d, tilesM, tilesN, xcd_remap(blockIdx.x, tilesM * tilesN * d.split));
+}
+
+// the shapes and layouts the LDS-direct kernel handles
+bool f64_dma_ok(const GemmDesc &d) {
+  return d.sak == 1 && d.sbk == 1 && d.M % dma64::BM == 0 && d.N % dma64::BN == 0 && d.K % dma64::BK == 0 &&
+         d.sam % 2 == 0 && d.sbn % 2 == 0 && (reinterpret_cast<uintptr_t>(d.A) & 15) == 0 &&
+         (reinterpret_cast<uintptr_t>(d.B) & 15) == 0;
+}
+
 struct TileInfo {
   const char *name;
   int BM, BN, BK, threads;
@@ -266,6 +404,22 @@ void launch_cfg(const GemmDesc &d, int64_t tm, int64_t tn, hipStream_t s) {
      &occupancy_cfg<BM, BN, BK, WM, WN, true, false>, &occupancy_cfg<BM, BN, BK, WM, WN, true, true>} \
   }
 
+template <int TAG>
+void launch_f64_dma(const GemmDesc &d, int64_t tm, int64_t tn, hipStream_t s) {
+  if (f64_dma_ok(d))
+    hipLaunchKernelGGL((gemm_f64_dma_kernel<TAG>), dim3(tm * tn * d.split), dim3(dma64::NT), 0, s, d, tm, tn);
+  else
+    launch_cfg<256, 128, 16, 4, 2, true, true, TAG>(d, tm, tn, s);
+}
+int occ_f64_dma() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gemm_f64_dma_kernel<0>, dma64::NT, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return nb;
+}
+
 const TileInfo kTiles[] = {
     CC_TILE(128, 128, 16, 2, 2),
     CC_TILE(128, 160, 16, 2, 2),
@@ -283,6 +437,20 @@ const TileInfo kTiles[] = {
     CC_TILE(64, 128, 16, 2, 4),
     CC_TILE(128, 128, 16, 4, 4),
     CC_TILE(256, 64, 16, 8, 2),
+    // 256x128x16 with LDS-direct loads where the shape allows, else staged
+    TileInfo{"256x128x16_w4x2_lds",
+             256,
+             128,
+             16,
+             4 * 2 * kWave,
+             {&launch_cfg<256, 128, 16, 4, 2, false, false>, &launch_cfg<256, 128, 16, 4, 2, false, true>,
+              &launch_cfg<256, 128, 16, 4, 2, true, false>, &launch_f64_dma<0>},
+             &launch_f64_dma<1>,
+             &launch_f64_dma<2>,
+             {&launch_grp<256, 128, 16, 4, 2, false, false>, &launch_grp<256, 128, 16, 4, 2, false, true>,
+              &launch_grp<256, 128, 16, 4, 2, true, false>, &launch_grp<256, 128, 16, 4, 2, true, true>},
+             {&occupancy_cfg<256, 128, 16, 4, 2, false, false>, &occupancy_cfg<256, 128, 16, 4, 2, false, true>,
+              &occupancy_cfg<256, 128, 16, 4, 2, true, false>, &occ_f64_dma}},
 };
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 

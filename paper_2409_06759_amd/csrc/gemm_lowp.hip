@@ -391,16 +391,6 @@ constexpr int LOADS = (2 * (BM / 16) + 2 * (BN / 16)) / (WM * WN);  // per wave 
 static_assert(LOADS == 6, "the explicit waits count six loads per chunk");
 }  // namespace dma
 
-#pragma clang diagnostic push
-#pragma clang diagnostic ignored "-Winline-asm"  // m0 is reserved: set here, used by nothing else
-// 16 bytes per lane from src into LDS at lds_base + 16 * lane (lds_base
-// wave-uniform); one wait state between the M0 write and the LDS-DMA load
-__device__ __forceinline__ void lds_load16(const void *src, uint32_t lds_base) {
-  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(src), "s"(lds_base)
-               : "memory", "m0");
-}
-#pragma clang diagnostic pop
-
 __device__ __forceinline__ void gemm_b3_dma_body(const GemmDesc &d, int64_t tilesM, int64_t tilesN, int64_t L0) {
   using namespace dma;
   __shared__ __attribute__((aligned(16))) unsigned short S[NSTAGE * STAGE];

@@ -274,3 +274,33 @@ def test_gemm_bf16x3_lds_direct_is_bitwise_staged(ctx, monkeypatch, M, N, K, akc
     assert np.array_equal(out[0], out[1])
     ref = 0.5 * (A @ B.T) - 1.25 * C0
     assert np.abs(out[1] - ref).max() <= 1e-3 * max(1.0, np.sqrt(K))
+
+
+@pytest.mark.parametrize("M,N,K,akc,bkc", [
+    (256, 128, 16, True, True), (256, 128, 32, True, True), (512, 256, 48, True, True),
+    (256, 384, 80, True, True), (768, 256, 1024, True, True),
+    (1024, 136 * 128, 2048, True, True),   # cut: whole rounds + a K-split tail, both on this kernel
+    (300, 270, 133, True, True), (256, 128, 64, True, False)])  # shapes it hands to the staged kernel
+def test_gemm_f64_lds_direct_is_bitwise_staged(ctx, monkeypatch, M, N, K, akc, bkc):
+    """The 256x128x16 FP64 configuration with LDS-direct loads feeds every
+    MFMA the operands of the register-staged kernel of that tile in the same
+    order: bit-identical results; shapes it does not take fall back."""
+    from paper_2409_06759_amd import engine as E
+    staged, direct = 4, 16
+    print(f"f64 lds-direct M={M} N={N} K={K} akc={akc} bkc={bkc}", flush=True)
+    rng = np.random.default_rng(M + 2 * N + K)
+    A = rng.normal(size=(M, K))
+    B = rng.normal(size=(N, K))
+    C0 = rng.normal(size=(M, N))
+    Ad = torch.from_numpy(A if akc else np.ascontiguousarray(A.T)).cuda()
+    Bd = torch.from_numpy(B if bkc else np.ascontiguousarray(B.T)).cuda()
+    out = []
+    for t in (staged, direct):
+        monkeypatch.setenv("CC_GEMM_TILE", str(t))
+        Cd = torch.from_numpy(C0).cuda()
+        E.gemm(ctx, Ad, Bd, Cd, 0.5, -1.25, a_kcontig=akc, b_kcontig=bkc)
+        out.append(Cd.cpu().numpy())
+    assert np.array_equal(out[0], out[1])
+    ref = 0.5 * (A @ B.T) - 1.25 * C0
+    bound = (K + 16) * 2.0 ** -52 * 0.5 * (np.abs(A) @ np.abs(B).T) + 4 * np.finfo(float).eps * np.abs(1.25 * C0)
+    assert np.all(np.abs(out[1] - ref) <= bound)

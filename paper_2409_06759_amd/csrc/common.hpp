@@ -141,6 +141,12 @@ struct TailCut {
   int64_t ws_elems = 0;  // split x tail rows x tail columns
 };
 TailCut gemm_tail_cut(int64_t M, int64_t N, int64_t K, int BM, int BN, int BK, int64_t slots);
+// Split-K factor for a launch the plan split along K (split > 1): the factor
+// in [1, 16] that minimises rounds per unit of K for this tile's resident
+// slots (within ws_elems, at least 8 chunks per split); the plan's factor
+// unless another is better.  Large GEMMs only, as for the tail cut.
+int gemm_split_refine(int64_t M, int64_t N, int64_t K, int BM, int BN, int BK, int64_t slots, int split,
+                      int64_t ws_elems);
 // Workspace that covers the tail cut of every tile configuration (0 when
 // the GEMM is too small for any cut); no device query needed.
 int64_t gemm_tail_ws_bound(int64_t M, int64_t N, int64_t K);

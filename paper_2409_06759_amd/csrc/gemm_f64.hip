@@ -528,6 +528,25 @@ TailCut gemm_tail_cut(int64_t M, int64_t N, int64_t K, int BM, int BN, int BK, i
   return best;
 }
 
+int gemm_split_refine(int64_t M, int64_t N, int64_t K, int BM, int BN, int BK, int64_t slots, int split,
+                      int64_t ws_elems) {
+  if (split <= 1 || slots <= 0 || M <= 0 || N <= 0 || K <= 0) return split;
+  const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+  if (2.0 * double(std::min(tiles, slots)) * BM * BN * double(K) < kTailMinRoundFlops) return split;
+  const int64_t smax = std::min<int64_t>({16, std::max<int64_t>(1, K / (8 * int64_t(BK))), ws_elems / (M * N)});
+  // full-K rounds the launch takes with s splits, plus a small charge per
+  // split for its partial sums (written once, read once by the reduction)
+  auto cost = [&](int64_t s) { return std::ceil(double(tiles * s) / double(slots)) / double(s) + 0.02 * double(s); };
+  int best = split <= smax ? split : 1;
+  double best_cost = cost(best);
+  for (int64_t s = 1; s <= smax; ++s)
+    if (cost(s) < best_cost - 1e-9) {
+      best_cost = cost(s);
+      best = int(s);
+    }
+  return best;
+}
+
 int64_t gemm_tail_ws_bound(int64_t M, int64_t N, int64_t K) {
   if (M <= 0 || N <= 0 || K <= 0 || 2.0 * double(M) * double(N) * double(K) < kTailMinRoundFlops) return 0;
   // split x tail elements <= slots x BM x BN = every resident workgroup's
@@ -629,6 +648,13 @@ void gemm_f64(const GemmDesc &d, hipStream_t s, int tile_id) {
       gemm_run_cut(d, tc, sizeof(double), sizeof(double), one);
       return;
     }
+  }
+  if (d.ws && d.split > 1 && d.ws_elems > 0) {
+    GemmDesc g = d;
+    g.split = gemm_split_refine(d.M, d.N, d.K, ti.BM, ti.BN, ti.BK,
+                                tile_slots(tile_id, (akc ? 2 : 0) + (bkc ? 1 : 0)), d.split, d.ws_elems);
+    one(g);
+    return;
   }
   one(d);
 }

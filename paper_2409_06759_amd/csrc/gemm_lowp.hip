@@ -626,8 +626,7 @@ constexpr int kNumL = sizeof(kF32Tiles) / sizeof(kF32Tiles[0]);
 std::atomic<int64_t> g_lslots[2][kNumL][8];
 std::once_flag g_lslots_once;
 
-TailCut lowp_cut(const GemmDesc &d, int prec, int tile_id) {
-  if (d.split != 1 || d.K <= 0) return TailCut{};
+int64_t lowp_slots(const GemmDesc &d, int prec, int tile_id) {
   std::call_once(g_lslots_once, [] {
     for (auto &a : g_lslots)
       for (auto &b : a)
@@ -641,7 +640,13 @@ TailCut lowp_cut(const GemmDesc &d, int prec, int tile_id) {
     slots = int64_t(ti.occupancy[var]()) * gpu_cu_count();
     cell.store(slots);
   }
-  return gemm_tail_cut(d.M, d.N, d.K, ti.BM, ti.BN, ti.BK, slots);
+  return slots;
+}
+
+TailCut lowp_cut(const GemmDesc &d, int prec, int tile_id) {
+  if (d.split != 1 || d.K <= 0) return TailCut{};
+  const LTile &ti = (prec == PREC_F32 ? kF32Tiles : kB3Tiles)[tile_id];
+  return gemm_tail_cut(d.M, d.N, d.K, ti.BM, ti.BN, ti.BK, lowp_slots(d, prec, tile_id));
 }
 
 int pick_l(const LTile *tiles, int64_t M, int64_t N) {
@@ -805,6 +810,13 @@ void gemm_lowp(const GemmDesc &d, int prec, hipStream_t s, int tile_id) {
       gemm_run_cut(d, tc, es, es, one);
       return;
     }
+  }
+  if (d.ws && d.split > 1 && d.ws_elems > 0) {
+    GemmDesc g = d;
+    g.split = gemm_split_refine(d.M, d.N, d.K, ti.BM, ti.BN, ti.BK, lowp_slots(d, prec, tile_id), d.split,
+                                d.ws_elems);
+    one(g);
+    return;
   }
   one(d);
 }

@@ -213,12 +213,14 @@ int cc_iterate(cc_ctx *ctx, const cc_system *sys, int method, const cc_iter_opts
  * MFMA path (F64: FP64 MFMA; F32: FP32 MFMA on FP64 data rounded to FP32;
  * BF16X3: split-bf16 MFMA), scalar CC_C128 the complex path.  Accumulation is
  * FP64 for F64, FP32 otherwise.
- * A real GEMM whose workgroups would end in a mostly empty last round (more
- * tiles than the device holds at once) runs as a main part of whole rounds
- * plus the remaining row or column panels split along K into one short
- * round; the partial sums of that tail sit in a device buffer the context
- * keeps (grown on demand, freed by cc_destroy; the tail then sums K in a
- * different order).  CC_GEMM_TAIL=0 in the environment turns this off. */
+ * A real GEMM is split along K as a plan would split it (few output tiles,
+ * long K; the factor refined for the tile's resident workgroups), and one
+ * whose workgroups would end in a mostly empty last round runs as a main part
+ * of whole rounds plus the remaining row or column panels split along K into
+ * one short round.  Partial sums sit in a device buffer the context keeps
+ * (grown on demand, freed by cc_destroy) and are reduced in a fixed order;
+ * split parts sum K in a different order than one launch would.
+ * CC_GEMM_TAIL=0 in the environment runs every GEMM as one launch. */
 int cc_gemm(cc_ctx *ctx, int prec, int scalar, int64_t M, int64_t N, int64_t K, double alpha,
             const void *A, int64_t sam, int64_t sak, const void *B, int64_t sbn, int64_t sbk,
             double beta, void *C, int64_t ldc);

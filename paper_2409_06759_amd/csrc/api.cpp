@@ -543,12 +543,14 @@ int cc_gemm(cc_ctx *ctx, int prec, int scalar, int64_t M, int64_t N, int64_t K, 
     ccmi::GemmDesc d{M, N, K, A, sam, sak, B, sbn, sbk, C, ldc, alpha, beta};
     const char *tv = std::getenv("CC_GEMM_TILE");  // tuning sweeps: force one tile configuration
     const int tile = tv ? std::atoi(tv) : -1;
-    // room for the K-split tail of a launch whose last round would be mostly
-    // empty; without it (or with CC_GEMM_TAIL=0) the GEMM runs as one launch
+    // Partial sums of split-K (as a plan would split this shape, the factor
+    // then refined for the tile) or of the K-split tail of a launch whose last
+    // round would be mostly empty, in a buffer the context keeps.  Without it
+    // (or with CC_GEMM_TAIL=0) the GEMM runs as one launch.
     const char *cv = std::getenv("CC_GEMM_TAIL");
-    const bool cut_ok = !(cv && cv[0] == '0');
-    auto tail_ws = [&](int64_t need) {
-      if (need <= 0 || !cut_ok) return;
+    const bool ws_ok = !(cv && cv[0] == '0');
+    auto with_ws = [&](int64_t need) -> bool {
+      if (need <= 0 || !ws_ok) return false;
       if (need > ctx->gemm_ws_elems) {
         CC_HIP_CHECK(hipStreamSynchronize(ctx->stream));
         if (ctx->gemm_ws) (void)hipFree(ctx->gemm_ws);
@@ -557,16 +559,25 @@ int cc_gemm(cc_ctx *ctx, int prec, int scalar, int64_t M, int64_t N, int64_t K, 
         if (hipMalloc(&ctx->gemm_ws, size_t(need) * sizeof(double)) != hipSuccess) {
           (void)hipGetLastError();
           ctx->gemm_ws = nullptr;
-          return;
+          return false;
         }
         ctx->gemm_ws_elems = need;
       }
       d.ws = ctx->gemm_ws;
       d.ws_elems = ctx->gemm_ws_elems;
+      return true;
+    };
+    auto plan_ws = [&](int64_t tail_need) {
+      d.split = ws_ok ? ccmi::gemm_split_pick(M, N, K, -1) : 1;
+      if (d.split > 1) {
+        if (!with_ws(std::max<int64_t>(int64_t(d.split) * M * N, ccmi::gemm_tail_ws_bound(M, N, K)))) d.split = 1;
+      } else {
+        with_ws(tail_need);
+      }
     };
     if (scalar == CC_C128) ccmi::gemm_c128(d, ctx->stream);
     else if (prec == CC_PREC_F64) {
-      tail_ws(ccmi::gemm_f64_tail_ws(d, tile));
+      plan_ws(ccmi::gemm_f64_tail_ws(d, tile));
       ccmi::gemm_f64(d, ctx->stream, tile);
     }
     else {
@@ -589,7 +600,7 @@ int cc_gemm(cc_ctx *ctx, int prec, int scalar, int64_t M, int64_t N, int64_t K, 
         d.b_plane = nb;
         d.lp_in = 1;
       }
-      tail_ws(ccmi::gemm_lowp_tail_ws(d, prec, tile));
+      plan_ws(ccmi::gemm_lowp_tail_ws(d, prec, tile));
       ccmi::gemm_lowp(d, prec, ctx->stream, tile);
       const hipError_t e = hipStreamSynchronize(ctx->stream);
       if (sa) (void)hipFree(sa);

@@ -615,7 +615,7 @@ int cc_gemm(cc_ctx *ctx, int prec, int scalar, int64_t M, int64_t N, int64_t K, 
 
 int cc_gemm_tile_count(int prec) {
   if (prec == CC_PREC_F64) return ccmi::gemm_f64_num_tiles();
-  if (prec == CC_PREC_F32 || prec == CC_PREC_BF16X3) return ccmi::gemm_lowp_num_tiles();
+  if (prec == CC_PREC_F32 || prec == CC_PREC_BF16X3) return ccmi::gemm_lowp_num_tiles(prec);
   return -1;
 }
 

@@ -341,7 +341,7 @@ void batch_run(cc_batch *B) {
 void batch_autotune(cc_batch *B, int reps) {
   if (B->cplx) return;
   const int prec = B->prec;
-  const int ntiles = prec == PREC_F64 ? gemm_f64_num_tiles() : gemm_lowp_num_tiles();
+  const int ntiles = prec == PREC_F64 ? gemm_f64_num_tiles() : gemm_lowp_num_tiles(prec);
   auto tile_of = [prec](Step &st) -> int & { return prec == PREC_F64 ? st.tile : st.tile_lp[prec]; };
   hipStream_t s = B->ctx->stream;
   hipEvent_t e0, e1;

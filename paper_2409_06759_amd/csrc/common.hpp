@@ -123,7 +123,7 @@ int gemm_lowp_pick(int prec, int64_t M, int64_t N);
 void gemm_lowp_tile_shape(int prec, int tile_id, int *bm, int *bn);
 void gemm_lowp_grouped_launch(const GemmGroupEntry *dev_entries, const int64_t *dev_off, int n, int64_t blocks,
                               bool akc, bool bkc, int prec, int tile_id, hipStream_t s);
-int gemm_lowp_num_tiles();
+int gemm_lowp_num_tiles(int prec);
 const char *gemm_lowp_tile_name(int prec, int id);
 void splitk_reduce(bool cplx, const void *ws, int split, int64_t M, int64_t N, void *C, int64_t ldc,
                    double alpha, double beta, hipStream_t s);

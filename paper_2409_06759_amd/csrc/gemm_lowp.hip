@@ -502,6 +502,124 @@ __global__ __launch_bounds__(dma::NT) void gemm_b3_dma_kernel(GemmDesc d, int64_
   gemm_b3_dma_body(d, tilesM, tilesN, xcd_remap(blockIdx.x, tilesM * tilesN * d.split));
 }
 
+// FP32 variant of the LDS-direct kernel (same tile, stages and waits): the
+// f32 MFMA takes one k per lane and step, lane group q feeding k = 4q + s at
+// step s of each 16-wide k half, so a 16-row block of a k half is 64 slots
+// of 16 bytes, slot L = row (L & 15), k = 4 (L >> 4) .. +3.  A chunk of 32 k
+// is two such halves: 16 + 16 A loads and 8 + 8 B loads, six per wave.
+__device__ __forceinline__ void gemm_f32_dma_body(const GemmDesc &d, int64_t tilesM, int64_t tilesN, int64_t L0) {
+  using namespace dma;
+  constexpr int FA_EL = BM * BK, FB_EL = BN * BK, FSTAGE = FA_EL + FB_EL;  // floats: [A | B]
+  static_assert(FSTAGE * 4 == STAGE * 2, "same stage size as the split-bf16 kernel");
+  __shared__ __attribute__((aligned(16))) float S[NSTAGE * FSTAGE];
+
+  const int64_t tiles = tilesM * tilesN;
+  const int64_t ks = L0 / tiles, L = L0 % tiles;
+  const int64_t m0 = (L % tilesM) * BM, n0 = (L / tilesM) * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm0 = (wave / WN) * (BM / WM), wn0 = (wave % WN) * (BN / WN);
+  const int q = lane >> 4, r = lane & 15;
+  const int64_t M = d.M, N = d.N;
+  const int64_t kchunk = ((d.K + d.split - 1) / d.split + BK - 1) / BK * BK;
+  const int64_t kb = ks * kchunk;
+  const int64_t K = std::max<int64_t>(0, std::min<int64_t>(d.K - kb, kchunk));
+  const int64_t nk = K / BK;
+
+  // loads: (block, k half) pairs; A: blocks 2w, 2w+1 x halves 0, 1; B: block w x halves 0, 1.
+  // A block b, half h sits at floats (h * (BM / 16) + b) * 256 of the stage.
+  const uint32_t lds0 = static_cast<uint32_t>(reinterpret_cast<uintptr_t>(S));
+  const float *src[LOADS];
+  uint32_t dst[LOADS];
+  const float *Ag = static_cast<const float *>(d.A) + kb;
+  const float *Bg = static_cast<const float *>(d.B) + kb;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int blk = 2 * wave + (u >> 1), h = u & 1;
+    src[u] = Ag + (m0 + blk * 16 + r) * d.sam + 16 * h + 4 * q;
+    dst[u] = __builtin_amdgcn_readfirstlane(lds0 + 4u * uint32_t((h * (BM / 16) + blk) * 256));
+  }
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    src[4 + u] = Bg + (n0 + wave * 16 + r) * d.sbn + 16 * u + 4 * q;
+    dst[4 + u] = __builtin_amdgcn_readfirstlane(lds0 + 4u * uint32_t(FA_EL + (u * (BN / 16) + wave) * 256));
+  }
+  auto issue = [&](int stage, int64_t k0) {
+#pragma unroll
+    for (int u = 0; u < LOADS; ++u) lds_load16(src[u] + k0, dst[u] + uint32_t(stage) * uint32_t(4 * FSTAGE));
+  };
+
+  f4 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+
+  if (nk > 0) issue(0, 0);
+  if (nk > 1) issue(1, BK);
+  int cur = 0, nxt = 2;
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    if (kt + 1 < nk) asm volatile("s_waitcnt vmcnt(6) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    else asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    if (kt + 2 < nk) issue(nxt, (kt + 2) * BK);
+    const float *St = S + cur * FSTAGE;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      f4 fa[FM], fb[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+        fa[i] = *reinterpret_cast<const f4 *>(St + (h * (BM / 16) + (wm0 >> 4) + i) * 256 + lane * 4);
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+        fb[j] = *reinterpret_cast<const f4 *>(St + FA_EL + (h * (BN / 16) + (wn0 >> 4) + j) * 256 + lane * 4);
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i][s], fb[j][s], acc[i][j], 0, 0, 0);
+    }
+    cur = cur == NSTAGE - 1 ? 0 : cur + 1;
+    nxt = nxt == NSTAGE - 1 ? 0 : nxt + 1;
+  }
+
+  double *__restrict__ Cp = static_cast<double *>(d.C);
+  double alpha = d.alpha, beta = d.beta;
+  int64_t ldc = d.ldc;
+  if (d.split > 1) {
+    Cp = static_cast<double *>(d.ws) + ks * M * N;
+    alpha = 1.0;
+    beta = 0.0;
+    ldc = N;
+  }
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int64_t gn = n0 + wn0 + j * 16 + r;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int64_t gm = m0 + wm0 + i * 16 + 4 * q + t;
+        if (gm < M && gn < N) {
+          double *p = Cp + gm * ldc + gn;
+          const double v = alpha * static_cast<double>(acc[i][j][t]);
+          *p = (beta == 0.0) ? v : v + beta * *p;
+        }
+      }
+    }
+}
+
+template <int TAG>
+__global__ __launch_bounds__(dma::NT) void gemm_f32_dma_kernel(GemmDesc d, int64_t tilesM, int64_t tilesN) {
+  gemm_f32_dma_body(d, tilesM, tilesN, xcd_remap(blockIdx.x, tilesM * tilesN * d.split));
+}
+
+bool f32_dma_ok(const GemmDesc &d) {
+  return d.lp_in && d.sak == 1 && d.sbk == 1 && d.M % dma::BM == 0 && d.N % dma::BN == 0 && d.K % dma::BK == 0 &&
+         d.sam % 4 == 0 && d.sbn % 4 == 0 && (reinterpret_cast<uintptr_t>(d.A) & 15) == 0 &&
+         (reinterpret_cast<uintptr_t>(d.B) & 15) == 0;
+}
+
 // the shapes and layouts the LDS-direct kernel handles
 bool b3_dma_ok(const GemmDesc &d) {
   return d.lp_in && d.sak == 1 && d.sbk == 1 && d.M % dma::BM == 0 && d.N % dma::BN == 0 && d.K % dma::BK == 0 &&
@@ -580,6 +698,21 @@ void launch_b3_dma(const GemmDesc &d, int64_t tm, int64_t tn, hipStream_t s) {
   else
     launch_l<PREC_BF16X3, 256, 128, 32, 4, 2, true, true, 1, TAG>(d, tm, tn, s);
 }
+template <int TAG>
+void launch_f32_dma(const GemmDesc &d, int64_t tm, int64_t tn, hipStream_t s) {
+  if (f32_dma_ok(d))
+    hipLaunchKernelGGL((gemm_f32_dma_kernel<TAG>), dim3(tm * tn * d.split), dim3(dma::NT), 0, s, d, tm, tn);
+  else
+    launch_l<PREC_F32, 256, 128, 32, 4, 2, true, true, 1, TAG>(d, tm, tn, s);
+}
+int occ_f32_dma() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gemm_f32_dma_kernel<0>, dma::NT, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return nb;
+}
 int occ_b3_dma() {
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gemm_b3_dma_kernel<0>, dma::NT, 0) != hipSuccess) {
@@ -594,6 +727,20 @@ const LTile kF32Tiles[] = {
     CC_LTILE(PREC_F32, 64, 128, 16, 2, 2, 1),  CC_LTILE(PREC_F32, 128, 128, 32, 2, 2, 1),
     CC_LTILE(PREC_F32, 128, 128, 16, 4, 2, 1), CC_LTILE(PREC_F32, 128, 128, 32, 4, 2, 1),
     CC_LTILE(PREC_F32, 128, 128, 32, 4, 2, 2), CC_LTILE(PREC_F32, 256, 128, 32, 4, 2, 1),
+    // 256x128x32 with LDS-direct loads where the shape allows, else staged
+    LTile{"256x128x32_w4x2_lds",
+          256,
+          128,
+          32,
+          {&launch_l<PREC_F32, 256, 128, 32, 4, 2, false, false, 1>, &launch_l<PREC_F32, 256, 128, 32, 4, 2, false, true, 1>,
+           &launch_l<PREC_F32, 256, 128, 32, 4, 2, true, false, 1>, &launch_f32_dma<0>},
+          &launch_f32_dma<1>,
+          &launch_f32_dma<2>,
+          {&launch_lg<PREC_F32, 256, 128, 32, 4, 2, false, false>, &launch_lg<PREC_F32, 256, 128, 32, 4, 2, false, true>,
+           &launch_lg<PREC_F32, 256, 128, 32, 4, 2, true, false>, &launch_lg<PREC_F32, 256, 128, 32, 4, 2, true, true>},
+          {CC_LOCC(PREC_F32, 256, 128, 32, 4, 2, false, 1), &occ_l<PREC_F32, 256, 128, 32, 4, 2, false, false, true, 1>,
+           &occ_l<PREC_F32, 256, 128, 32, 4, 2, false, true, true, 1>,
+           &occ_l<PREC_F32, 256, 128, 32, 4, 2, true, false, true, 1>, &occ_f32_dma}},
 };
 const LTile kB3Tiles[] = {
     CC_LTILE(PREC_BF16X3, 128, 128, 32, 2, 2, 1), CC_LTILE(PREC_BF16X3, 64, 64, 32, 2, 2, 1),
@@ -619,8 +766,10 @@ const LTile kB3Tiles[] = {
            &occ_l<PREC_BF16X3, 256, 128, 32, 4, 2, false, true, true, 1>,
            &occ_l<PREC_BF16X3, 256, 128, 32, 4, 2, true, false, true, 1>, &occ_b3_dma}},
 };
-static_assert(sizeof(kF32Tiles) == sizeof(kB3Tiles), "one configuration count for both precisions");
-constexpr int kNumL = sizeof(kF32Tiles) / sizeof(kF32Tiles[0]);
+constexpr int kNumF32 = sizeof(kF32Tiles) / sizeof(kF32Tiles[0]);
+constexpr int kNumB3 = sizeof(kB3Tiles) / sizeof(kB3Tiles[0]);
+constexpr int kNumL = kNumF32 > kNumB3 ? kNumF32 : kNumB3;  // slot cache extent
+int num_l(int prec) { return prec == PREC_F32 ? kNumF32 : kNumB3; }
 
 // resident slots per (precision, configuration, variant) on the device; -1 = not yet asked
 std::atomic<int64_t> g_lslots[2][kNumL][8];
@@ -650,9 +799,10 @@ TailCut lowp_cut(const GemmDesc &d, int prec, int tile_id) {
 }
 
 int pick_l(const LTile *tiles, int64_t M, int64_t N) {
+  const int count = tiles == kF32Tiles ? kNumF32 : kNumB3;
   int best = 0;
   double best_cost = 1e300;
-  for (int t = 0; t < kNumL; ++t) {
+  for (int t = 0; t < count; ++t) {
     const double n = double((M + tiles[t].BM - 1) / tiles[t].BM) * double((N + tiles[t].BN - 1) / tiles[t].BN);
     const double cost = std::ceil(n / 256.0) * (double(tiles[t].BM) * tiles[t].BN + 4096.0);
     if (cost < best_cost) {
@@ -750,7 +900,7 @@ void convert_shadow(int prec, const double *src, int64_t n, void *dst, hipStream
   CC_HIP_CHECK(hipGetLastError());
 }
 
-int gemm_lowp_num_tiles() { return kNumL; }
+int gemm_lowp_num_tiles(int prec) { return num_l(prec); }
 
 int gemm_lowp_pick(int prec, int64_t M, int64_t N) { return pick_l(prec == PREC_F32 ? kF32Tiles : kB3Tiles, M, N); }
 
@@ -764,14 +914,14 @@ void gemm_lowp_grouped_launch(const GemmGroupEntry *dev_entries, const int64_t *
                               bool akc, bool bkc, int prec, int tile_id, hipStream_t s) {
   if (blocks <= 0) return;
   CC_REQUIRE(prec == PREC_F32 || prec == PREC_BF16X3, -1, "grouped gemm: precision");
-  CC_REQUIRE(tile_id >= 0 && tile_id < kNumL, -7, "grouped gemm: tile");
+  CC_REQUIRE(tile_id >= 0 && tile_id < num_l(prec), -7, "grouped gemm: tile");
   CC_REQUIRE(blocks < (int64_t(1) << 31), -1, "grouped gemm: too many tiles");
   (prec == PREC_F32 ? kF32Tiles : kB3Tiles)[tile_id].launch_grouped[(akc ? 2 : 0) + (bkc ? 1 : 0)](
       dev_entries, dev_off, n, blocks, s);
   CC_HIP_CHECK(hipGetLastError());
 }
 const char *gemm_lowp_tile_name(int prec, int id) {
-  if (id < 0 || id >= kNumL) return "?";
+  if (id < 0 || id >= num_l(prec)) return "?";
   return prec == PREC_F32 ? kF32Tiles[id].name : kB3Tiles[id].name;
 }
 
@@ -786,7 +936,7 @@ void gemm_lowp(const GemmDesc &d, int prec, hipStream_t s, int tile_id) {
     return;
   }
   const LTile *tiles = prec == PREC_F32 ? kF32Tiles : kB3Tiles;
-  if (tile_id < 0 || tile_id >= kNumL) tile_id = pick_l(tiles, d.M, d.N);
+  if (tile_id < 0 || tile_id >= num_l(prec)) tile_id = pick_l(tiles, d.M, d.N);
   const LTile &ti = tiles[tile_id];
   const int64_t tm = (d.M + ti.BM - 1) / ti.BM, tn = (d.N + ti.BN - 1) / ti.BN;
   CC_REQUIRE(d.split >= 1 && (d.split == 1 || d.ws != nullptr), -1, "gemm: split-K workspace");
@@ -823,7 +973,7 @@ void gemm_lowp(const GemmDesc &d, int prec, hipStream_t s, int tile_id) {
 
 int64_t gemm_lowp_tail_ws(const GemmDesc &d, int prec, int tile_id) {
   if (d.M <= 0 || d.N <= 0 || d.K <= 0 || (prec != PREC_F32 && prec != PREC_BF16X3)) return 0;
-  if (tile_id < 0 || tile_id >= kNumL) tile_id = pick_l(prec == PREC_F32 ? kF32Tiles : kB3Tiles, d.M, d.N);
+  if (tile_id < 0 || tile_id >= num_l(prec)) tile_id = pick_l(prec == PREC_F32 ? kF32Tiles : kB3Tiles, d.M, d.N);
   return lowp_cut(d, prec, tile_id).ws_elems;
 }
 

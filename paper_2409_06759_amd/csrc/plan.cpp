@@ -1132,7 +1132,7 @@ void plan_autotune(cc_plan *p, int reps) {
   const int prec = p->cplx ? 9 : p->cur_prec;  // 9: complex128 tiles
   plan_prepare(p);
   const int ntiles = p->cplx ? gemm_c128_num_tiles()
-                             : (prec == PREC_F64 ? gemm_f64_num_tiles() : gemm_lowp_num_tiles());
+                             : (prec == PREC_F64 ? gemm_f64_num_tiles() : gemm_lowp_num_tiles(prec));
   hipStream_t s = p->ctx->stream;
   hipEvent_t e0, e1;
   CC_HIP_CHECK(hipEventCreate(&e0));

@@ -251,14 +251,14 @@ def test_gemm_lowp_two_chunk_prefetch_is_bitwise_one_chunk(ctx, monkeypatch, pre
     (256, 384, 160, True, True), (768, 256, 1024, True, True),
     (1024, 136 * 128, 2048, True, True),   # cut: whole rounds + a K-split tail, both on this kernel
     (300, 270, 133, True, True), (256, 128, 64, False, True)])  # shapes it hands to the staged kernel
-def test_gemm_bf16x3_lds_direct_is_bitwise_staged(ctx, monkeypatch, M, N, K, akc, bkc):
-    """The 256x128 split-bf16 configuration with LDS-direct loads multiplies
-    the same fragments in the same order as the register-staged kernel of
-    that tile: bit-identical results (and it falls back to that kernel on
-    shapes it does not take)."""
+@pytest.mark.parametrize("prec,staged,direct", [("bf16x3", 7, 9), ("f32", 9, 10)])
+def test_gemm_lowp_lds_direct_is_bitwise_staged(ctx, monkeypatch, prec, staged, direct, M, N, K, akc, bkc):
+    """The 256x128 reduced-precision configurations with LDS-direct loads
+    multiply the same fragments in the same order as the register-staged
+    kernel of that tile: bit-identical results (and they fall back to that
+    kernel on shapes they do not take)."""
     from paper_2409_06759_amd import engine as E
-    staged, direct = 7, 9
-    print(f"lds-direct M={M} N={N} K={K} akc={akc} bkc={bkc}", flush=True)
+    print(f"lds-direct {prec} M={M} N={N} K={K} akc={akc} bkc={bkc}", flush=True)
     rng = np.random.default_rng(M + N + K)
     A = rng.normal(size=(M, K))
     B = rng.normal(size=(N, K))
@@ -269,7 +269,7 @@ def test_gemm_bf16x3_lds_direct_is_bitwise_staged(ctx, monkeypatch, M, N, K, akc
     for t in (staged, direct):
         monkeypatch.setenv("CC_GEMM_TILE", str(t))
         Cd = torch.from_numpy(C0).cuda()
-        E.gemm(ctx, Ad, Bd, Cd, 0.5, -1.25, a_kcontig=akc, b_kcontig=bkc, prec=E.PRECS["bf16x3"])
+        E.gemm(ctx, Ad, Bd, Cd, 0.5, -1.25, a_kcontig=akc, b_kcontig=bkc, prec=E.PRECS[prec])
         out.append(Cd.cpu().numpy())
     assert np.array_equal(out[0], out[1])
     ref = 0.5 * (A @ B.T) - 1.25 * C0

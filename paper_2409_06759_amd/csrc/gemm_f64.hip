@@ -221,10 +221,10 @@ __global__ __launch_bounds__(WM *WN *kWave) void gemm_f64_grouped(const GemmGrou
 // aligned rows (the particle-particle ladder's layout).  Each lane's 16
 // bytes go straight from HBM/L2 into LDS (global_load_lds_dwordx4): no
 // staging registers, three LDS stages, two chunks of K in flight.  A 16-row
-// block of a stage is 128 slots of 16 bytes; slot s holds row (L & 15),
-// k = 4 (L >> 4) + 2 (s & 1) + {0, 1} with L = s >> 1, so lane L finds the
-// four k values it feeds the f64 MFMA (k = 4q + s, as in the staged kernel)
-// in 32 contiguous bytes, and a wave's fragment reads are contiguous.  The
+// block of a stage is two halves of 64 slots of 16 bytes; slot L of half h
+// holds row (L & 15), k = 4 (L >> 4) + 2h + {0, 1}, so lane L reads the four
+// k values it feeds the f64 MFMA (k = 4q + s, as in the staged kernel) as
+// two 16-byte reads, each contiguous across the wave (no bank conflicts).  The
 // products and their order are those of the staged kernel of the same tile,
 // so results are bitwise the same.  Waits: "vmcnt <= 6" after the six loads
 // of chunk kt+1 means chunk kt has landed (in-order completion), the barrier
@@ -255,26 +255,22 @@ __device__ __forceinline__ void gemm_f64_dma_body(const GemmDesc &d, int64_t til
   const int64_t K = std::max<int64_t>(0, std::min<int64_t>(d.K - kb, kchunk));
   const int64_t nk = K / BK;
 
-  // this wave's loads: A blocks 2w and 2w+1, B block w, each as two halves
-  // of 64 slots; slot s = 64 h + lane holds row (L & 15), k pair 4 (L >> 4) + 2 (s & 1)
+  // this wave's loads: A blocks 2w and 2w+1, B block w, each as two halves;
+  // lane l of half h loads row (l & 15), k = 4 (l >> 4) + 2h + {0, 1}
   const uint32_t lds0 = static_cast<uint32_t>(reinterpret_cast<uintptr_t>(S));
   const double *src[LOADS];
   uint32_t dst[LOADS];
   const double *Ag = static_cast<const double *>(d.A) + kb;
   const double *Bg = static_cast<const double *>(d.B) + kb;
-  const int sl = lane >> 1;
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int blk = 2 * wave + (u >> 1), h = u & 1;
-    // slot 64 h + lane belongs to lane L = 32 h + (lane >> 1) of the fragment reads
-    const int Ls = 32 * h + sl;
-    src[u] = Ag + (m0 + blk * 16 + (Ls & 15)) * d.sam + 4 * (Ls >> 4) + 2 * (lane & 1);
+    src[u] = Ag + (m0 + blk * 16 + r) * d.sam + 4 * q + 2 * h;
     dst[u] = __builtin_amdgcn_readfirstlane(lds0 + 8u * uint32_t(blk * 256 + h * 128));
   }
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
-    const int Ls = 32 * u + sl;
-    src[4 + u] = Bg + (n0 + wave * 16 + (Ls & 15)) * d.sbn + 4 * (Ls >> 4) + 2 * (lane & 1);
+    src[4 + u] = Bg + (n0 + wave * 16 + r) * d.sbn + 4 * q + 2 * u;
     dst[4 + u] = __builtin_amdgcn_readfirstlane(lds0 + 8u * uint32_t(A_EL + wave * 256 + u * 128));
   }
   auto issue = [&](int stage, int64_t k0) {
@@ -296,13 +292,20 @@ __device__ __forceinline__ void gemm_f64_dma_body(const GemmDesc &d, int64_t til
     else asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
     if (kt + 2 < nk) issue(nxt, (kt + 2) * BK);
     const double *St = S + cur * STAGE;
+    typedef double d2 __attribute__((ext_vector_type(2)));
     d4 fa[FM], fb[FN];
 #pragma unroll
-    for (int i = 0; i < FM; ++i)
-      fa[i] = *reinterpret_cast<const d4 *>(St + ((wm0 >> 4) + i) * 256 + lane * 4);
+    for (int i = 0; i < FM; ++i) {
+      const double *blk = St + ((wm0 >> 4) + i) * 256 + lane * 2;
+      const d2 lo = *reinterpret_cast<const d2 *>(blk), hi = *reinterpret_cast<const d2 *>(blk + 128);
+      fa[i] = d4{lo.x, lo.y, hi.x, hi.y};
+    }
 #pragma unroll
-    for (int j = 0; j < FN; ++j)
-      fb[j] = *reinterpret_cast<const d4 *>(St + A_EL + ((wn0 >> 4) + j) * 256 + lane * 4);
+    for (int j = 0; j < FN; ++j) {
+      const double *blk = St + A_EL + ((wn0 >> 4) + j) * 256 + lane * 2;
+      const d2 lo = *reinterpret_cast<const d2 *>(blk), hi = *reinterpret_cast<const d2 *>(blk + 128);
+      fb[j] = d4{lo.x, lo.y, hi.x, hi.y};
+    }
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll

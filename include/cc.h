@@ -226,7 +226,8 @@ int cc_gemm(cc_ctx *ctx, int prec, int scalar, int64_t M, int64_t N, int64_t K, 
             double beta, void *C, int64_t ldc);
 /* Number of tile configurations of the real GEMM of precision prec (cc_prec);
  * cc_gemm uses configuration i when the environment variable CC_GEMM_TILE=i
- * is set (tuning sweeps), its own choice otherwise.  -1 for an unknown prec. */
+ * is set (tuning sweeps; for complex operands i indexes the complex GEMM's
+ * own configurations), its own choice otherwise.  -1 for an unknown prec. */
 int cc_gemm_tile_count(int prec);
 /* out[I] = alpha * in[perm(I)] + beta * out[I] for a dense rank-r tensor
  * (r <= 6): out has dims out_dims[0..r-1]; out index d reads input dim

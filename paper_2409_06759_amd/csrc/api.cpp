@@ -575,7 +575,7 @@ int cc_gemm(cc_ctx *ctx, int prec, int scalar, int64_t M, int64_t N, int64_t K, 
         with_ws(tail_need);
       }
     };
-    if (scalar == CC_C128) ccmi::gemm_c128(d, ctx->stream);
+    if (scalar == CC_C128) ccmi::gemm_c128(d, ctx->stream, tile);
     else if (prec == CC_PREC_F64) {
       plan_ws(ccmi::gemm_f64_tail_ws(d, tile));
       ccmi::gemm_f64(d, ctx->stream, tile);

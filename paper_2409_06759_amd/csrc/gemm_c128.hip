@@ -11,6 +11,7 @@
 // conjugated views.
 #include "common.hpp"
 
+#include <algorithm>
 #include <cmath>
 
 namespace ccmi {
@@ -184,6 +185,146 @@ __global__ __launch_bounds__(WM *WN *kWave) void gemm_c128_kernel(GemmDesc d, in
     }
 }
 
+// ---- 64x128x16 with LDS-direct loads ----------------------------------------
+// Both operands K-contiguous, K a multiple of 16 (the complex ladder's
+// layout).  Each lane's 16 bytes (one complex element) go straight into LDS
+// with global_load_lds_dwordx4: three 48 KiB stages, two chunks of K in
+// flight, no staging registers.  A 16-row block of a stage is four quarters
+// of 64 slots; slot L of quarter s holds element (row L & 15, k = 4 (L >> 4)
+// + s), the value lane L feeds the f64 MFMAs at step s (as in the staged
+// kernel), so each quarter is read contiguously across the wave.  Rows past
+// M or N load the last valid row instead: they only reach outputs that are
+// never stored.  The products and their order are those of the staged
+// 64x128 kernel, so results are bitwise the same.  Waits as in the real
+// LDS-direct kernel: "vmcnt <= 6" after the next chunk's six loads, a
+// barrier, and "lgkmcnt == 0" before it for the stage being overwritten.
+namespace zdma {
+constexpr int BM = 64, BN = 128, BK = 16, WM = 2, WN = 4, NT = WM * WN * kWave;
+constexpr int FM = BM / WM / 16, FN = BN / WN / 16;      // 2 x 2 blocks of 16x16 per wave
+constexpr int A_EL = BM * BK, B_EL = BN * BK, STAGE = A_EL + B_EL;  // complex elements
+constexpr int NSTAGE = 3;
+constexpr int LOADS = (4 * (BM / 16) + 4 * (BN / 16)) / (WM * WN);
+static_assert(LOADS == 6, "the explicit waits count six loads per chunk");
+}  // namespace zdma
+
+__global__ __launch_bounds__(zdma::NT) void gemm_c128_dma_kernel(GemmDesc d, int64_t tilesM, int64_t tilesN) {
+  using namespace zdma;
+  __shared__ __attribute__((aligned(16))) double2 S[NSTAGE * STAGE];
+
+  const int64_t tiles = tilesM * tilesN, total = tiles * d.split;
+  const int64_t L0 = xcd_remap(blockIdx.x, total);
+  const int64_t ks = L0 / tiles, L = L0 % tiles;
+  const int64_t m0 = (L % tilesM) * BM, n0 = (L / tilesM) * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm0 = (wave / WN) * (BM / WM), wn0 = (wave % WN) * (BN / WN);
+  const int q = lane >> 4, r = lane & 15;
+  const int64_t M = d.M, N = d.N;
+  const int64_t kchunk = ((d.K + d.split - 1) / d.split + BK - 1) / BK * BK;
+  const int64_t kb = ks * kchunk;
+  const int64_t K = std::max<int64_t>(0, std::min<int64_t>(d.K - kb, kchunk));
+  const int64_t nk = K / BK;
+
+  // load j of this wave (j = 6 wave + u): A (block j >> 2, quarter j & 3) for
+  // j < 16, else B (block (j - 16) >> 2, quarter j & 3); a block-quarter of A
+  // sits at elements (blk * 4 + quarter) * 64 of the stage, of B at A_EL + ...
+  const uint32_t lds0 = static_cast<uint32_t>(reinterpret_cast<uintptr_t>(S));
+  const double2 *src[LOADS];
+  uint32_t dst[LOADS];
+  const double2 *Ag = static_cast<const double2 *>(d.A) + kb;
+  const double2 *Bg = static_cast<const double2 *>(d.B) + kb;
+  const int wv = __builtin_amdgcn_readfirstlane(wave);  // wave-uniform, so the choice below is too
+#pragma unroll
+  for (int u = 0; u < LOADS; ++u) {
+    const int j = LOADS * wv + u;
+    const bool isa = j < 4 * (BM / 16);
+    const int jj = isa ? j : j - 4 * (BM / 16), blk = jj >> 2, qt = jj & 3;
+    const int64_t row = isa ? std::min<int64_t>(m0 + blk * 16 + r, M - 1) : std::min<int64_t>(n0 + blk * 16 + r, N - 1);
+    src[u] = (isa ? Ag + row * d.sam : Bg + row * d.sbn) + 4 * q + qt;
+    dst[u] = __builtin_amdgcn_readfirstlane(lds0 + 16u * uint32_t((isa ? 0 : A_EL) + (blk * 4 + qt) * 64));
+  }
+  auto issue = [&](int stage, int64_t k0) {
+#pragma unroll
+    for (int u = 0; u < LOADS; ++u) lds_load16(src[u] + k0, dst[u] + uint32_t(stage) * uint32_t(16 * STAGE));
+  };
+
+  d4 acr[FM][FN], aci[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      acr[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+      aci[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+
+  if (nk > 0) issue(0, 0);
+  if (nk > 1) issue(1, BK);
+  int cur = 0, nxt = 2;
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    if (kt + 1 < nk) asm volatile("s_waitcnt vmcnt(6) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    else asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    if (kt + 2 < nk) issue(nxt, (kt + 2) * BK);
+    const double2 *St = S + cur * STAGE;
+    double2 fa[FM][4], fb[FN][4];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) fa[i][s] = St[(((wm0 >> 4) + i) * 4 + s) * 64 + lane];
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) fb[j][s] = St[A_EL + (((wn0 >> 4) + j) * 4 + s) * 64 + lane];
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          acr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i][s].x, fb[j][s].x, acr[i][j], 0, 0, 0);
+          acr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-fa[i][s].y, fb[j][s].y, acr[i][j], 0, 0, 0);
+          aci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i][s].x, fb[j][s].y, aci[i][j], 0, 0, 0);
+          aci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i][s].y, fb[j][s].x, aci[i][j], 0, 0, 0);
+        }
+    cur = cur == NSTAGE - 1 ? 0 : cur + 1;
+    nxt = nxt == NSTAGE - 1 ? 0 : nxt + 1;
+  }
+
+  // epilogue (as the staged kernel): accumulator t of lane l is row (l >> 4) + 4t, column l & 15
+  double2 *__restrict__ Cp = static_cast<double2 *>(d.C);
+  double alpha = d.alpha, beta = d.beta;
+  int64_t ldc = d.ldc;
+  if (d.split > 1) {
+    Cp = static_cast<double2 *>(d.ws) + ks * M * N;
+    alpha = 1.0;
+    beta = 0.0;
+    ldc = N;
+  }
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int64_t gn = n0 + wn0 + j * 16 + r;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int64_t gm = m0 + wm0 + i * 16 + q + 4 * t;
+        if (gm < M && gn < N) {
+          double2 *p = Cp + gm * ldc + gn;
+          double2 v = make_double2(alpha * acr[i][j][t], alpha * aci[i][j][t]);
+          if (beta != 0.0) {
+            const double2 o = *p;
+            v.x += beta * o.x;
+            v.y += beta * o.y;
+          }
+          *p = v;
+        }
+      }
+    }
+}
+
+bool c128_dma_ok(const GemmDesc &d) {
+  return d.sak == 1 && d.sbk == 1 && d.K % zdma::BK == 0 && (reinterpret_cast<uintptr_t>(d.A) & 15) == 0 &&
+         (reinterpret_cast<uintptr_t>(d.B) & 15) == 0;
+}
+
 struct ZTile {
   const char *name;
   int BM, BN, BK;
@@ -203,9 +344,23 @@ void launch_z(const GemmDesc &d, int64_t tm, int64_t tn, hipStream_t s) {
          &launch_z<BM, BN, BK, WM, WN, true, false>, &launch_z<BM, BN, BK, WM, WN, true, true>}   \
   }
 
+void launch_z_dma(const GemmDesc &d, int64_t tm, int64_t tn, hipStream_t s) {
+  if (c128_dma_ok(d))
+    hipLaunchKernelGGL(gemm_c128_dma_kernel, dim3(tm * tn * d.split), dim3(zdma::NT), 0, s, d, tm, tn);
+  else
+    launch_z<64, 128, 16, 2, 2, true, true>(d, tm, tn, s);
+}
+
 const ZTile kZTiles[] = {CC_ZTILE(64, 64, 16, 2, 2), CC_ZTILE(32, 32, 16, 2, 2), CC_ZTILE(128, 64, 16, 2, 2),
-                         CC_ZTILE(64, 128, 16, 2, 2)};
-constexpr int kNumZ = 4;
+                         CC_ZTILE(64, 128, 16, 2, 2),
+                         // 64x128x16 with LDS-direct loads where the layout allows, else staged
+                         ZTile{"64x128x16_w2x4_lds",
+                               64,
+                               128,
+                               16,
+                               {&launch_z<64, 128, 16, 2, 2, false, false>, &launch_z<64, 128, 16, 2, 2, false, true>,
+                                &launch_z<64, 128, 16, 2, 2, true, false>, &launch_z_dma}}};
+constexpr int kNumZ = sizeof(kZTiles) / sizeof(kZTiles[0]);
 
 }  // namespace
 

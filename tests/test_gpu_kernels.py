@@ -304,3 +304,31 @@ def test_gemm_f64_lds_direct_is_bitwise_staged(ctx, monkeypatch, M, N, K, akc, b
     ref = 0.5 * (A @ B.T) - 1.25 * C0
     bound = (K + 16) * 2.0 ** -52 * 0.5 * (np.abs(A) @ np.abs(B).T) + 4 * np.finfo(float).eps * np.abs(1.25 * C0)
     assert np.all(np.abs(out[1] - ref) <= bound)
+
+
+@pytest.mark.parametrize("M,N,K,akc,bkc", [
+    (64, 128, 16, True, True), (128, 256, 48, True, True), (100, 70, 48, True, True),   # ragged M and N
+    (130, 260, 160, True, True), (64, 128, 16, False, True), (64, 128, 24, True, True)])  # fallbacks
+def test_gemm_c128_lds_direct_is_bitwise_staged(ctx, monkeypatch, M, N, K, akc, bkc):
+    """The complex 64x128x16 configuration with LDS-direct loads feeds every
+    MFMA the staged kernel's operands in the same order: bit-identical
+    complex results, also with rows past M or N clamped, and fallbacks for
+    layouts and K it does not take."""
+    from paper_2409_06759_amd import engine as E
+    staged, direct = 3, 4
+    print(f"c128 lds-direct M={M} N={N} K={K} akc={akc} bkc={bkc}", flush=True)
+    rng = np.random.default_rng(M + 5 * N + K)
+    A = rng.normal(size=(M, K)) + 1j * rng.normal(size=(M, K))
+    B = rng.normal(size=(N, K)) + 1j * rng.normal(size=(N, K))
+    C0 = rng.normal(size=(M, N)) + 1j * rng.normal(size=(M, N))
+    Ad = torch.from_numpy(A if akc else np.ascontiguousarray(A.T)).cuda()
+    Bd = torch.from_numpy(B if bkc else np.ascontiguousarray(B.T)).cuda()
+    out = []
+    for t in (staged, direct):
+        monkeypatch.setenv("CC_GEMM_TILE", str(t))
+        Cd = torch.from_numpy(C0).cuda()
+        E.gemm(ctx, Ad, Bd, Cd, 0.5, -1.25, a_kcontig=akc, b_kcontig=bkc)
+        out.append(Cd.cpu().numpy())
+    assert np.array_equal(out[0], out[1])
+    ref = 0.5 * (A @ B.T) - 1.25 * C0
+    assert np.abs(out[1] - ref).max() <= 1e-12 * max(1.0, K)

@@ -217,8 +217,9 @@ __global__ __launch_bounds__(WM *WN *kWave) void gemm_f64_grouped(const GemmGrou
 }
 
 // ---- 256x128x16 with LDS-direct loads ---------------------------------------
-// Full tiles, K a multiple of 16, both operands K-contiguous with 16-byte
-// aligned rows (the particle-particle ladder's layout).  Each lane's 16
+// K a multiple of 16, both operands K-contiguous with 16-byte aligned rows
+// (the particle-particle ladder's layout); rows past M or N load the last
+// valid row instead, which only reaches outputs that are never stored.  Each lane's 16
 // bytes go straight from HBM/L2 into LDS (global_load_lds_dwordx4): no
 // staging registers, three LDS stages, two chunks of K in flight.  A 16-row
 // block of a stage is two halves of 64 slots of 16 bytes; slot L of half h
@@ -265,12 +266,12 @@ __device__ __forceinline__ void gemm_f64_dma_body(const GemmDesc &d, int64_t til
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int blk = 2 * wave + (u >> 1), h = u & 1;
-    src[u] = Ag + (m0 + blk * 16 + r) * d.sam + 4 * q + 2 * h;
+    src[u] = Ag + std::min<int64_t>(m0 + blk * 16 + r, M - 1) * d.sam + 4 * q + 2 * h;
     dst[u] = __builtin_amdgcn_readfirstlane(lds0 + 8u * uint32_t(blk * 256 + h * 128));
   }
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
-    src[4 + u] = Bg + (n0 + wave * 16 + r) * d.sbn + 4 * q + 2 * u;
+    src[4 + u] = Bg + std::min<int64_t>(n0 + wave * 16 + r, N - 1) * d.sbn + 4 * q + 2 * u;
     dst[4 + u] = __builtin_amdgcn_readfirstlane(lds0 + 8u * uint32_t(A_EL + wave * 256 + u * 128));
   }
   auto issue = [&](int stage, int64_t k0) {
@@ -352,7 +353,7 @@ __global__ __launch_bounds__(dma64::NT) void gemm_f64_dma_kernel(GemmDesc d, int
 
 // the shapes and layouts the LDS-direct kernel handles
 bool f64_dma_ok(const GemmDesc &d) {
-  return d.sak == 1 && d.sbk == 1 && d.M % dma64::BM == 0 && d.N % dma64::BN == 0 && d.K % dma64::BK == 0 &&
+  return d.sak == 1 && d.sbk == 1 && d.K % dma64::BK == 0 &&
          d.sam % 2 == 0 && d.sbn % 2 == 0 && (reinterpret_cast<uintptr_t>(d.A) & 15) == 0 &&
          (reinterpret_cast<uintptr_t>(d.B) & 15) == 0;
 }

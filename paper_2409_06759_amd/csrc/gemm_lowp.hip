@@ -363,8 +363,10 @@ __global__ __launch_bounds__(WM *WN *kWave) void gemm_lowp_kernel(GemmDesc d, in
 }
 
 // ---- split bf16 with LDS-direct loads --------------------------------------
-// Full 256x128 tiles, K a multiple of 32, both operands K-contiguous
-// converted copies (bf16 hi plane + lo plane) with 16-byte aligned rows.
+// 256x128 tiles, K a multiple of 32, both operands K-contiguous converted
+// copies (bf16 hi plane + lo plane) with 16-byte aligned rows.  Rows past M
+// or N load the last valid row instead: they only reach outputs that are
+// never stored.
 // global_load_lds_dwordx4 writes each lane's 16 bytes straight into LDS, so
 // no registers stage the operands, and three LDS stages keep two chunks of K
 // in flight while the third is multiplied.  A 16-row block of a stage is 64
@@ -418,12 +420,12 @@ __device__ __forceinline__ void gemm_b3_dma_body(const GemmDesc &d, int64_t tile
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int blk = 2 * wave + (u >> 1), pl = u & 1;
-    src[u] = Ag + pl * d.a_plane + (m0 + blk * 16 + r) * d.sam + q * 8;
+    src[u] = Ag + pl * d.a_plane + std::min<int64_t>(m0 + blk * 16 + r, M - 1) * d.sam + q * 8;
     dst[u] = __builtin_amdgcn_readfirstlane(lds0 + 2u * uint32_t(pl * A_EL + blk * 512));
   }
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
-    src[4 + u] = Bg + u * d.b_plane + (n0 + wave * 16 + r) * d.sbn + q * 8;
+    src[4 + u] = Bg + u * d.b_plane + std::min<int64_t>(n0 + wave * 16 + r, N - 1) * d.sbn + q * 8;
     dst[4 + u] = __builtin_amdgcn_readfirstlane(lds0 + 2u * uint32_t(2 * A_EL + u * B_EL + wave * 512));
   }
   auto issue = [&](int stage, int64_t k0) {
@@ -535,12 +537,12 @@ __device__ __forceinline__ void gemm_f32_dma_body(const GemmDesc &d, int64_t til
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int blk = 2 * wave + (u >> 1), h = u & 1;
-    src[u] = Ag + (m0 + blk * 16 + r) * d.sam + 16 * h + 4 * q;
+    src[u] = Ag + std::min<int64_t>(m0 + blk * 16 + r, M - 1) * d.sam + 16 * h + 4 * q;
     dst[u] = __builtin_amdgcn_readfirstlane(lds0 + 4u * uint32_t((h * (BM / 16) + blk) * 256));
   }
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
-    src[4 + u] = Bg + (n0 + wave * 16 + r) * d.sbn + 16 * u + 4 * q;
+    src[4 + u] = Bg + std::min<int64_t>(n0 + wave * 16 + r, N - 1) * d.sbn + 16 * u + 4 * q;
     dst[4 + u] = __builtin_amdgcn_readfirstlane(lds0 + 4u * uint32_t(FA_EL + (u * (BN / 16) + wave) * 256));
   }
   auto issue = [&](int stage, int64_t k0) {
@@ -615,14 +617,14 @@ __global__ __launch_bounds__(dma::NT) void gemm_f32_dma_kernel(GemmDesc d, int64
 }
 
 bool f32_dma_ok(const GemmDesc &d) {
-  return d.lp_in && d.sak == 1 && d.sbk == 1 && d.M % dma::BM == 0 && d.N % dma::BN == 0 && d.K % dma::BK == 0 &&
+  return d.lp_in && d.sak == 1 && d.sbk == 1 && d.K % dma::BK == 0 &&
          d.sam % 4 == 0 && d.sbn % 4 == 0 && (reinterpret_cast<uintptr_t>(d.A) & 15) == 0 &&
          (reinterpret_cast<uintptr_t>(d.B) & 15) == 0;
 }
 
 // the shapes and layouts the LDS-direct kernel handles
 bool b3_dma_ok(const GemmDesc &d) {
-  return d.lp_in && d.sak == 1 && d.sbk == 1 && d.M % dma::BM == 0 && d.N % dma::BN == 0 && d.K % dma::BK == 0 &&
+  return d.lp_in && d.sak == 1 && d.sbk == 1 && d.K % dma::BK == 0 &&
          d.sam % 8 == 0 && d.sbn % 8 == 0 && d.a_plane % 8 == 0 && d.b_plane % 8 == 0 &&
          (reinterpret_cast<uintptr_t>(d.A) & 15) == 0 && (reinterpret_cast<uintptr_t>(d.B) & 15) == 0;
 }

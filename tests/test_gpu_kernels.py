@@ -250,6 +250,7 @@ def test_gemm_lowp_two_chunk_prefetch_is_bitwise_one_chunk(ctx, monkeypatch, pre
     (256, 128, 32, True, True), (256, 128, 64, True, True), (512, 256, 96, True, True),
     (256, 384, 160, True, True), (768, 256, 1024, True, True),
     (1024, 136 * 128, 2048, True, True),   # cut: whole rounds + a K-split tail, both on this kernel
+    (300, 270, 160, True, True), (496, 1000, 96, True, True),   # ragged M and N: rows clamped
     (300, 270, 133, True, True), (256, 128, 64, False, True)])  # shapes it hands to the staged kernel
 @pytest.mark.parametrize("prec,staged,direct", [("bf16x3", 7, 9), ("f32", 9, 10)])
 def test_gemm_lowp_lds_direct_is_bitwise_staged(ctx, monkeypatch, prec, staged, direct, M, N, K, akc, bkc):
@@ -280,6 +281,7 @@ def test_gemm_lowp_lds_direct_is_bitwise_staged(ctx, monkeypatch, prec, staged, 
     (256, 128, 16, True, True), (256, 128, 32, True, True), (512, 256, 48, True, True),
     (256, 384, 80, True, True), (768, 256, 1024, True, True),
     (1024, 136 * 128, 2048, True, True),   # cut: whole rounds + a K-split tail, both on this kernel
+    (300, 270, 160, True, True), (496, 1000, 96, True, True),   # ragged M and N: rows clamped
     (300, 270, 133, True, True), (256, 128, 64, True, False)])  # shapes it hands to the staged kernel
 def test_gemm_f64_lds_direct_is_bitwise_staged(ctx, monkeypatch, M, N, K, akc, bkc):
     """The 256x128x16 FP64 configuration with LDS-direct loads feeds every

@@ -293,27 +293,36 @@ __device__ __forceinline__ void gemm_f64_dma_body(const GemmDesc &d, int64_t til
     else asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
     if (kt + 2 < nk) issue(nxt, (kt + 2) * BK);
     const double *St = S + cur * STAGE;
+    // the k pair of steps 0-1 of every fragment is read first; the pair of
+    // steps 2-3 is read behind the MFMAs of step 0, so it overlaps them (at
+    // most eight LDS reads in flight, within what lgkmcnt can count)
     typedef double d2 __attribute__((ext_vector_type(2)));
-    d4 fa[FM], fb[FN];
+    d2 fa[2][FM], fb[2][FN];
+    auto read_pair = [&](int h) {
 #pragma unroll
-    for (int i = 0; i < FM; ++i) {
-      const double *blk = St + ((wm0 >> 4) + i) * 256 + lane * 2;
-      const d2 lo = *reinterpret_cast<const d2 *>(blk), hi = *reinterpret_cast<const d2 *>(blk + 128);
-      fa[i] = d4{lo.x, lo.y, hi.x, hi.y};
-    }
+      for (int i = 0; i < FM; ++i)
+        fa[h][i] = *reinterpret_cast<const d2 *>(St + ((wm0 >> 4) + i) * 256 + h * 128 + lane * 2);
 #pragma unroll
-    for (int j = 0; j < FN; ++j) {
-      const double *blk = St + A_EL + ((wn0 >> 4) + j) * 256 + lane * 2;
-      const d2 lo = *reinterpret_cast<const d2 *>(blk), hi = *reinterpret_cast<const d2 *>(blk + 128);
-      fb[j] = d4{lo.x, lo.y, hi.x, hi.y};
-    }
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
+      for (int j = 0; j < FN; ++j)
+        fb[h][j] = *reinterpret_cast<const d2 *>(St + A_EL + ((wn0 >> 4) + j) * 256 + h * 128 + lane * 2);
+    };
+    auto mfma_step = [&](int s) {
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i][s], fb[j][s], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[s >> 1][i][s & 1], fb[s >> 1][j][s & 1], acc[i][j],
+                                                           0, 0, 0);
+    };
+    read_pair(0);
+    __builtin_amdgcn_sched_barrier(0);
+    mfma_step(0);
+    __builtin_amdgcn_sched_barrier(0);
+    read_pair(1);
+    __builtin_amdgcn_sched_barrier(0);
+    mfma_step(1);
+    mfma_step(2);
+    mfma_step(3);
     cur = cur == NSTAGE - 1 ? 0 : cur + 1;
     nxt = nxt == NSTAGE - 1 ? 0 : nxt + 1;
   }

@@ -564,23 +564,33 @@ __device__ __forceinline__ void gemm_f32_dma_body(const GemmDesc &d, int64_t til
     else asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
     if (kt + 2 < nk) issue(nxt, (kt + 2) * BK);
     const float *St = S + cur * FSTAGE;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      f4 fa[FM], fb[FN];
+    // the second k half is read behind the first half's first MFMA step
+    f4 fa[2][FM], fb[2][FN];
+    auto read_half = [&](int h) {
 #pragma unroll
       for (int i = 0; i < FM; ++i)
-        fa[i] = *reinterpret_cast<const f4 *>(St + (h * (BM / 16) + (wm0 >> 4) + i) * 256 + lane * 4);
+        fa[h][i] = *reinterpret_cast<const f4 *>(St + (h * (BM / 16) + (wm0 >> 4) + i) * 256 + lane * 4);
 #pragma unroll
       for (int j = 0; j < FN; ++j)
-        fb[j] = *reinterpret_cast<const f4 *>(St + FA_EL + (h * (BN / 16) + (wn0 >> 4) + j) * 256 + lane * 4);
+        fb[h][j] = *reinterpret_cast<const f4 *>(St + FA_EL + (h * (BN / 16) + (wn0 >> 4) + j) * 256 + lane * 4);
+    };
+    auto mfma_step = [&](int h, int s) {
 #pragma unroll
-      for (int s = 0; s < 4; ++s)
+      for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int i = 0; i < FM; ++i)
+        for (int j = 0; j < FN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[h][i][s], fb[h][j][s], acc[i][j], 0, 0, 0);
+    };
+    read_half(0);
+    __builtin_amdgcn_sched_barrier(0);
+    mfma_step(0, 0);
+    __builtin_amdgcn_sched_barrier(0);
+    read_half(1);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-          for (int j = 0; j < FN; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i][s], fb[j][s], acc[i][j], 0, 0, 0);
-    }
+    for (int s = 1; s < 4; ++s) mfma_step(0, s);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) mfma_step(1, s);
     cur = cur == NSTAGE - 1 ? 0 : cur + 1;
     nxt = nxt == NSTAGE - 1 ? 0 : nxt + 1;
   }

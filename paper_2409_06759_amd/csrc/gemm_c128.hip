@@ -238,7 +238,8 @@ __global__ __launch_bounds__(zdma::NT) void gemm_c128_dma_kernel(GemmDesc d, int
     const int j = LOADS * wv + u;
     const bool isa = j < 4 * (BM / 16);
     const int jj = isa ? j : j - 4 * (BM / 16), blk = jj >> 2, qt = jj & 3;
-    const int64_t row = isa ? std::min<int64_t>(m0 + blk * 16 + r, M - 1) : std::min<int64_t>(n0 + blk * 16 + r, N - 1);
+    const int64_t lim = isa ? M : N, want = (isa ? m0 : n0) + blk * 16 + r;
+    const int64_t row = want < lim ? want : lim - 1;
     src[u] = (isa ? Ag + row * d.sam : Bg + row * d.sbn) + 4 * q + qt;
     dst[u] = __builtin_amdgcn_readfirstlane(lds0 + 16u * uint32_t((isa ? 0 : A_EL) + (blk * 4 + qt) * 64));
   }
@@ -264,17 +265,22 @@ __global__ __launch_bounds__(zdma::NT) void gemm_c128_dma_kernel(GemmDesc d, int
     else asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
     if (kt + 2 < nk) issue(nxt, (kt + 2) * BK);
     const double2 *St = S + cur * STAGE;
+    // steps 0-1 are read first and steps 2-3 behind the MFMAs of step 0, so
+    // those reads overlap them (at most eight LDS reads in flight)
     double2 fa[FM][4], fb[FN][4];
 #pragma unroll
-    for (int i = 0; i < FM; ++i)
+    for (int s = 0; s < 4; ++s) {
+      if (s == 0 || s == 2) {
+        // the fragments of steps s and s + 1
 #pragma unroll
-      for (int s = 0; s < 4; ++s) fa[i][s] = St[(((wm0 >> 4) + i) * 4 + s) * 64 + lane];
+        for (int t = s; t < s + 2; ++t) {
 #pragma unroll
-    for (int j = 0; j < FN; ++j)
+          for (int i = 0; i < FM; ++i) fa[i][t] = St[(((wm0 >> 4) + i) * 4 + t) * 64 + lane];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) fb[j][s] = St[A_EL + (((wn0 >> 4) + j) * 4 + s) * 64 + lane];
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
+          for (int j = 0; j < FN; ++j) fb[j][t] = St[A_EL + (((wn0 >> 4) + j) * 4 + t) * 64 + lane];
+        }
+      }
+      if (s <= 1) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -284,6 +290,8 @@ __global__ __launch_bounds__(zdma::NT) void gemm_c128_dma_kernel(GemmDesc d, int
           aci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i][s].x, fb[j][s].y, aci[i][j], 0, 0, 0);
           aci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i][s].y, fb[j][s].x, aci[i][j], 0, 0, 0);
         }
+      if (s == 0) __builtin_amdgcn_sched_barrier(0);
+    }
     cur = cur == NSTAGE - 1 ? 0 : cur + 1;
     nxt = nxt == NSTAGE - 1 ? 0 : nxt + 1;
   }

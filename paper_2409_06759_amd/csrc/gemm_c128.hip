@@ -6,7 +6,9 @@
 // with separate real and imaginary accumulators (8 real flop per complex
 // multiply-add, the algorithmic count of the complex residual).  Tiles are
 // staged into planar real/imaginary LDS panels, double buffered; split-K and
-// the XCD-aware tile order follow the real FP64 kernel.  Conjugated operands
+// the XCD-aware tile order follow the real FP64 kernel.  The 64x128x16
+// LDS-direct configuration loads K-contiguous operands straight into three
+// interleaved (re, im) LDS stages.  Conjugated operands
 // never reach this kernel: the contraction planner materialises them as
 // conjugated views.
 #include "common.hpp"

@@ -8,17 +8,23 @@
 // Design (CDNA4):
 // * v_mfma_f64_16x16x4_f64: each lane holds one A and one B value and four
 //   accumulators.  Lane l covers row (l & 15) of A / column (l & 15) of B and
-//   k-slot (l >> 4); accumulator t of lane l is C[(l >> 4) + 4t][l & 15].  Four consecutive MFMAs consume 16 k values: in MFMA s
-//   lane group q = l >> 4 supplies logical k = 4q + s, identically for A and B,
-//   so each lane reads 4 consecutive k of its row (one 32-byte LDS read when
-//   the operand is K-contiguous).
-// * Block tile BM x BN, K chunk BK, staged through LDS with two buffers; the
-//   next chunk's global loads are in flight while the current one is
-//   multiplied.  Operands may be K-contiguous or M/N-contiguous; the LDS
-//   layout follows the global one so both the HBM reads and the LDS fragment
-//   reads stay unit-stride.
+//   k-slot (l >> 4); accumulator t of lane l is C[(l >> 4) + 4t][l & 15].
+//   Four consecutive MFMAs consume 16 k values: in MFMA s lane group
+//   q = l >> 4 supplies logical k = 4q + s, identically for A and B, so each
+//   lane reads 4 consecutive k of its row when the operand is K-contiguous.
+// * Staged configurations: block tile BM x BN, K chunk BK, staged through LDS
+//   with two buffers; the next chunk's global loads are in flight (in
+//   registers) while the current one is multiplied.  Operands may be
+//   K-contiguous or M/N-contiguous; the LDS layout follows the global one so
+//   both the HBM reads and the LDS fragment reads stay unit-stride.
+// * The LDS-direct configuration (256x128x16) takes K-contiguous operands
+//   with global_load_lds_dwordx4 into three LDS stages (see its kernel).
 // * Workgroup ids are remapped so that the M tiles sharing one N tile are
 //   dispatched to the same XCD (shared L2 for the B panel).
+// * A launch whose last round of resident workgroups would be at most half
+//   full runs as whole rounds plus a K-split tail (gemm_tail_cut), and the
+//   split-K factor of a plan is re-chosen for the tile's resident workgroups
+//   (gemm_split_refine).
 #include "common.hpp"
 
 #include <algorithm>

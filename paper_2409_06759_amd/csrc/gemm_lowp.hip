@@ -12,8 +12,11 @@
 //   read with 16-byte vector loads and stored to LDS unchanged.  The LDS
 //   contents, hence the results, are identical for both.
 // Everything outside the contractions (permutations, assembly, norms,
-// denominators, energy) stays FP64.  Tiling, double buffering, split-K and
-// the XCD-aware tile order follow the FP64 kernel.
+// denominators, energy) stays FP64.  Tiling, double buffering, split-K, the
+// tail cut and the XCD-aware tile order follow the FP64 kernel; the 128x128
+// 8-wave configurations also come with two chunks in flight (a second
+// register set), and the 256x128 configurations with LDS-direct loads into
+// three stages for K-contiguous converted operands.
 #include "common.hpp"
 
 #include <atomic>

@@ -399,9 +399,10 @@ __device__ __forceinline__ void pair_body(const PairEntry &E, int64_t bid) {
     const int64_t P = e / E.nQ, Q = e % E.nQ;
     const int r0 = E.rows[2 * P], r1 = E.rows[2 * P + 1], c0 = E.cols[2 * Q], c1 = E.cols[2 * Q + 1];
     const int64_t q = ((int64_t(r0) * E.n1 + r1) * E.n2 + c0) * E.n3 + c1;
-    if (E.mode == 0) dst[e] = src[q];
-    else if (E.mode == 1) dst[q] = add(dst[q], src[e]);
-    else dst[q] = src[e];
+    const int64_t pe = P * E.ldq + Q;  // packed side
+    if (E.mode == 0) dst[pe] = src[q];
+    else if (E.mode == 1) dst[q] = add(dst[q], src[pe]);
+    else dst[q] = src[pe];
   }
 }
 
@@ -597,8 +598,9 @@ TauEntry make_tau_entry(int o, int v, const void *t1, const void *t2, const void
 int64_t t3_units(int o, int v) { return chunks(int64_t(o) * o * o * v * v * v, CH_T3); }
 
 PairEntry make_pair_entry(const void *src, void *dst, const int *rows, const int *cols, int64_t nP, int64_t nQ,
-                          int64_t n1, int64_t n2, int64_t n3, int mode) {
-  return PairEntry{src, dst, rows, cols, nP, nQ, n1, n2, n3, mode, nP * nQ > 0 ? chunks(nP * nQ, CH) : 0};
+                          int64_t ldq, int64_t n1, int64_t n2, int64_t n3, int mode) {
+  CC_REQUIRE(ldq >= nQ, -1, "pair: row stride below the row length");
+  return PairEntry{src, dst, rows, cols, nP, nQ, ldq, n1, n2, n3, mode, nP * nQ > 0 ? chunks(nP * nQ, CH) : 0};
 }
 
 int64_t asm_units(int o, int v) {

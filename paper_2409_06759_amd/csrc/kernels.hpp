@@ -122,6 +122,7 @@ struct PairEntry {
   void *dst;
   const int *rows, *cols;  // rows[2P], rows[2P+1]; cols[2Q], cols[2Q+1]
   int64_t nP, nQ;
+  int64_t ldq;             // row stride of the packed side (>= nQ; padding columns untouched)
   int64_t n1, n2, n3;      // dims 1..3 of X (dim 0 is implied)
   int mode;
   int64_t units;
@@ -156,7 +157,7 @@ int64_t tau_units(int o, int v);
 int64_t asm_units(int o, int v);
 int64_t t3_units(int o, int v);
 PairEntry make_pair_entry(const void *src, void *dst, const int *rows, const int *cols, int64_t nP, int64_t nQ,
-                          int64_t n1, int64_t n2, int64_t n3, int mode);
+                          int64_t ldq, int64_t n1, int64_t n2, int64_t n3, int mode);
 
 // ---- single launches ---------------------------------------------------------
 void launch_perm(const PermEntry &e, bool cplx, hipStream_t s);

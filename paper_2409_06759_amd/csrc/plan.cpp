@@ -420,14 +420,21 @@ struct Planner {
   // ---- packed index pairs (i<j, m<n, a<b, e<f) ----------------------------
   int tau_packed_version = -1;
 
+  // Row length of a packed e<f dimension that a GEMM sums over: padded with
+  // zero columns to a multiple of 32, so that every GEMM configuration takes
+  // whole K chunks (the padding adds zero products).
+  static int64_t packed_ld(int64_t n) { return std::max<int64_t>(32, (n + 31) / 32 * 32); }
+
+  // ldq: row stride of the packed side (0: dense, nq)
   Step pair_step(int a, int c, int64_t np, int64_t nq, int64_t n1, int64_t n2, int64_t n3, int rows, int cols,
-                 int mode, const char *tag) {
+                 int mode, const char *tag, int64_t ldq = 0) {
     Step st;
     st.kind = Step::PAIR;
     st.a = a;
     st.c = c;
     st.pair_np = np;
     st.pair_nq = nq;
+    st.pair_ldq = ldq > 0 ? ldq : nq;
     st.pair_n[0] = n1;
     st.pair_n[1] = n2;
     st.pair_n[2] = n3;
@@ -443,15 +450,17 @@ struct Planner {
     const int tau = slot("tau"), tp = slot("taup");
     if (tau_packed_version != p->version[tau]) {
       const int64_t no = int64_t(p->o) * (p->o - 1) / 2, nv = int64_t(p->v) * (p->v - 1) / 2;
-      p->iter.push_back(pair_step(tau, tp, no, nv, p->o, p->v, p->v, 0, 1, 0, "pack_tau"));
+      p->iter.push_back(pair_step(tau, tp, no, nv, p->o, p->v, p->v, 0, 1, 0, "pack_tau", packed_ld(nv)));
       p->version[tp]++;
       tau_packed_version = p->version[tau];
     }
     return tp;
   }
 
+  // lda, ldb: row strides of the stored operands ([M][K] or [K][M], ...);
+  // K may include zero padding columns, Kalg is the summed pair count
   Step packed_gemm(int a, int b, int c, int64_t M, int64_t N, int64_t K, bool akc, bool bkc, double alpha,
-                   const char *tag) {
+                   const char *tag, int64_t lda, int64_t ldb, int64_t Kalg) {
     Step g;
     g.kind = Step::GEMM;
     g.a = a;
@@ -460,15 +469,15 @@ struct Planner {
     g.gemm.M = M;
     g.gemm.N = N;
     g.gemm.K = K;
-    g.gemm.sam = akc ? K : 1;
-    g.gemm.sak = akc ? 1 : M;
-    g.gemm.sbn = bkc ? K : 1;
-    g.gemm.sbk = bkc ? 1 : N;
+    g.gemm.sam = akc ? lda : 1;
+    g.gemm.sak = akc ? 1 : lda;
+    g.gemm.sbn = bkc ? ldb : 1;
+    g.gemm.sbk = bkc ? 1 : ldb;
     g.gemm.ldc = N;
     g.gemm.alpha = alpha;
     g.gemm.beta = 0.0;
     g.gemm.ladder = std::string(tag) == "ladder" ? 1 : 0;
-    g.flops = (p->cplx ? 8.0 : 2.0) * double(M) * double(N) * double(K);
+    g.flops = (p->cplx ? 8.0 : 2.0) * double(M) * double(N) * double(Kalg);
     g.tag = tag;
     g.gemm.split = gemm_split_pick(M, N, K, -1);
     reserve_ws(g, M, N, K);
@@ -507,20 +516,22 @@ struct Planner {
     }
     const int tp = ensure_taup();
     const int xp = slot("XPp");
+    const int64_t nvp = packed_ld(nv);  // e<f columns of taup, vvvvp, ovvvp (zero padded)
     if (tag == "ladder") {
-      p->iter.push_back(packed_gemm(tp, slot("vvvvp"), xp, no, nv, nv, true, true, 2.0 * op.alpha, "ladder"));
+      p->iter.push_back(
+          packed_gemm(tp, slot("vvvvp"), xp, no, nv, nvp, true, true, 2.0 * op.alpha, "ladder", nvp, nvp, nv));
       p->iter.push_back(pair_step(xp, c, no, nv, p->o, p->v, p->v, 0, 1, 1, "unpack_ladder"));
     } else if (tag == "hh_ladder") {
       const int wg = slot("Wp");
       p->iter.push_back(pair_step(slot("Wmnij"), wg, no, no, p->o, p->o, p->o, 0, 0, 0, "pack_Wmnij"));
       p->version[wg]++;
       // C(ij, ab) = sum_{m<n} Wp[mn][ij] taup[mn][ab]: both operands stored [K][...]
-      p->iter.push_back(packed_gemm(wg, tp, xp, no, nv, no, false, false, 2.0 * op.alpha, "hh_ladder"));
+      p->iter.push_back(packed_gemm(wg, tp, xp, no, nv, no, false, false, 2.0 * op.alpha, "hh_ladder", no, nvp, no));
       p->iter.push_back(pair_step(xp, c, no, nv, p->o, p->v, p->v, 0, 1, 1, "unpack_hh_ladder"));
     } else {
       const int zp = slot("Zp");
       const int64_t nov = int64_t(p->o) * p->v;
-      p->iter.push_back(packed_gemm(tp, slot("ovvvp"), zp, no, nov, nv, true, true, 2.0 * op.alpha, "Z"));
+      p->iter.push_back(packed_gemm(tp, slot("ovvvp"), zp, no, nov, nvp, true, true, 2.0 * op.alpha, "Z", nvp, nvp, nv));
       // Zs[i][j][a][m] (i<j) <- Zp[ij][m a]; rows i>j stay as set up (zero)
       p->iter.push_back(pair_step(zp, c, no, nov, p->o, p->v, p->o, 0, 3, 2, "unpack_Z"));
     }
@@ -592,17 +603,27 @@ struct Planner {
       const int64_t no0 = int64_t(p->o) * (p->o - 1) / 2, nv0 = int64_t(p->v) * (p->v - 1) / 2;
       const int64_t no = std::max<int64_t>(1, no0), nv = std::max<int64_t>(1, nv0);
       const int64_t nov = int64_t(p->o) * p->v;
-      add_work("taup", {no, nv});
+      const int64_t nvp = packed_ld(nv);
+      const int tpk = add_work("taup", {no, nvp});
       add_work("XPp", {no, nv});
       add_work("Wp", {no, no});
       add_work("Zp", {no, nov});
-      const int vp = add_work("vvvvp", {nv, nv});
-      const int op_ = add_work("ovvvp", {nov, nv});
+      const int vp = add_work("vvvvp", {nv, nvp});
+      const int op_ = add_work("ovvvp", {nov, nvp});
       p->slots[vp].constant = true;
       p->slots[op_].constant = true;
+      // padding columns start at zero and are never written afterwards
+      for (int z : {tpk, vp, op_}) {
+        Step f;
+        f.kind = Step::FILL;
+        f.c = z;
+        f.nelem = p->slots[z].elems;
+        f.tag = "zero packed padding";
+        p->setup.push_back(f);
+      }
       if (nv0 > 0) {
-        p->setup.push_back(pair_step(slot("vvvv"), vp, nv, nv, p->v, p->v, p->v, 1, 1, 0, "pack_vvvv"));
-        p->setup.push_back(pair_step(slot("ovvv"), op_, nov, nv, p->v, p->v, p->v, 2, 1, 0, "pack_ovvv"));
+        p->setup.push_back(pair_step(slot("vvvv"), vp, nv, nv, p->v, p->v, p->v, 1, 1, 0, "pack_vvvv", nvp));
+        p->setup.push_back(pair_step(slot("ovvv"), op_, nov, nv, p->v, p->v, p->v, 2, 1, 0, "pack_ovvv", nvp));
       }
       // rows i > j of Zs are never written by the packed Z: keep them zero
       Step f;
@@ -912,8 +933,8 @@ void exec(cc_plan *p, Step &st, hipStream_t s) {
       break;
     case Step::PAIR:
       launch_pair(make_pair_entry(ptr_of(p, st.a), ptr_of(p, st.c), p->pair_tab[st.pair_rows],
-                                  p->pair_tab[st.pair_cols], st.pair_np, st.pair_nq, st.pair_n[0], st.pair_n[1],
-                                  st.pair_n[2], st.pair_mode),
+                                  p->pair_tab[st.pair_cols], st.pair_np, st.pair_nq, st.pair_ldq, st.pair_n[0],
+                                  st.pair_n[1], st.pair_n[2], st.pair_mode),
                   cplx, s);
       break;
     case Step::TRIPLES:

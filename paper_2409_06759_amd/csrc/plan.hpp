@@ -58,7 +58,7 @@ struct Step {
   // PAIR: slot a -> slot c through index-pair tables (PairEntry): mode 0
   // gathers packed rows/columns, 1 scatter-adds, 2 scatter-sets; tables:
   // 0 occupied i<j, 1 virtual a<b, 2 (m,a) all, 3 (a,m) all (same order as 2)
-  int64_t pair_np = 0, pair_nq = 0, pair_n[3] = {0, 0, 0};
+  int64_t pair_np = 0, pair_nq = 0, pair_ldq = 0, pair_n[3] = {0, 0, 0};
   int pair_rows = 0, pair_cols = 0, pair_mode = 0;
   int64_t nelem = 0;
   double flops = 0.0;

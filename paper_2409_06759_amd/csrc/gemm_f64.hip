@@ -473,7 +473,8 @@ const TileInfo kTiles[] = {
 };
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 
-// resident slots of a configuration on the whole device (cached; -1 = not yet asked)
+// resident slots of a configuration on the whole device (cached per process,
+// which assumes every device it uses is the same GPU model; -1 = not yet asked)
 std::atomic<int64_t> g_slots[kNumTiles][4];
 std::once_flag g_slots_once;
 

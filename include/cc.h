@@ -146,7 +146,12 @@ enum {
    * 1/2 sum_mn W_mnij tau_mn^ab over m<n, i<j, a<b, and Z_ij^am over e<f,
    * i<j.  Packed copies of vvvv and ovvv are made at plan creation.  Flop
    * counts of such a plan count the packed operations. */
-  CC_PLAN_PACKED_LADDER = 1
+  CC_PLAN_PACKED_LADDER = 1,
+  /* Reduced-precision plans run the contractions under 1% of an iteration's
+   * flops in FP64 (they are bandwidth- or latency-bound, and FP64 is faster
+   * for them as well as exact).  With this flag every contraction runs in
+   * the plan's precision, as the batched launches do. */
+  CC_PLAN_LOWP_ALL = 2
 };
 /* cc_plan_create with option flags (0 = cc_plan_create). */
 int cc_plan_create2(cc_ctx *ctx, const cc_system *sys, int method, int prec, int flags, cc_plan **plan);

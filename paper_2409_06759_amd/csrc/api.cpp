@@ -128,13 +128,14 @@ void run_step(cc_plan *p, bool use_graph) {
 }
 
 cc_plan *make_plan(cc_ctx *ctx, const cc_system *sys, int method, int prec,
-                   std::shared_ptr<ccmi::OpList> custom = nullptr, bool packed = false) {
+                   std::shared_ptr<ccmi::OpList> custom = nullptr, bool packed = false, bool lowp_all = false) {
   validate_system(sys);
   validate_method(method, prec, sys->scalar);
   set_device(ctx);
   cc_plan *p = new cc_plan();
   p->custom = std::move(custom);
   p->packed = packed;
+  p->lowp_all = lowp_all;
   p->ctx = ctx;
   p->o = sys->o;
   p->v = sys->v;
@@ -156,8 +157,8 @@ cc_plan *make_plan(cc_ctx *ctx, const cc_system *sys, int method, int prec,
 }  // namespace
 
 namespace ccmi {
-cc_plan *make_plan_checked(cc_ctx *ctx, const cc_system *sys, int method, int prec) {
-  return make_plan(ctx, sys, method, prec);
+cc_plan *make_plan_checked(cc_ctx *ctx, const cc_system *sys, int method, int prec, bool lowp_all) {
+  return make_plan(ctx, sys, method, prec, nullptr, false, lowp_all);
 }
 void check_amps(const cc_amps *t, int method) { validate_amps(t, method, "t"); }
 }  // namespace ccmi
@@ -242,8 +243,9 @@ int cc_plan_create2(cc_ctx *ctx, const cc_system *sys, int method, int prec, int
   if (!plan) return fail(ctx, CC_EINVAL, "plan pointer is NULL");
   *plan = nullptr;
   return guarded(ctx, [&] {
-    if (flags & ~int(CC_PLAN_PACKED_LADDER)) throw CCError(CC_EINVAL, "unknown plan flags");
-    *plan = make_plan(ctx, sys, method, prec, nullptr, (flags & CC_PLAN_PACKED_LADDER) != 0);
+    if (flags & ~int(CC_PLAN_PACKED_LADDER | CC_PLAN_LOWP_ALL)) throw CCError(CC_EINVAL, "unknown plan flags");
+    *plan = make_plan(ctx, sys, method, prec, nullptr, (flags & CC_PLAN_PACKED_LADDER) != 0,
+                      (flags & CC_PLAN_LOWP_ALL) != 0);
     return CC_OK;
   });
 }

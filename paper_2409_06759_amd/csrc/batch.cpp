@@ -465,7 +465,8 @@ int cc_batch_create(cc_ctx *ctx, int n, const cc_system *systems, int method, in
     B->prec = prec;
     try {
       for (int b = 0; b < n; ++b) {
-        cc_plan *p = ccmi::make_plan_checked(ctx, &systems[b], method, prec);
+        // every contraction in the batch's precision: one grouped launch per step
+        cc_plan *p = ccmi::make_plan_checked(ctx, &systems[b], method, prec, true);
         ccmi::check_amps(&amps[b], method);
         p->t1 = amps[b].t1;
         p->t2 = amps[b].t2;

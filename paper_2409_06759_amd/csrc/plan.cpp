@@ -751,7 +751,7 @@ void use_shadows(cc_plan *p, GemmDesc &d, const Step &st, hipStream_t s, bool co
 
 void run_gemm(cc_plan *p, GemmDesc &d, const Step &st, hipStream_t s) {
   if (p->cplx) gemm_c128(d, s, st.tile_z);
-  else if (p->cur_prec == PREC_F64) gemm_f64(d, s, st.tile);
+  else if (p->cur_prec == PREC_F64 || !st.lowp_ok) gemm_f64(d, s, st.tile);
   else {
     use_shadows(p, d, st, s, true);
     gemm_lowp(d, p->cur_prec, s, st.tile_lp[p->cur_prec]);
@@ -824,7 +824,7 @@ void plan_prepare(cc_plan *p) {
   }
   hipStream_t s = p->ctx->stream;
   for (const Step &st : p->iter) {
-    if (st.kind != Step::GEMM || (!lowp && st.delta < 0)) continue;
+    if (st.kind != Step::GEMM || (!lowp && st.delta < 0) || (lowp && !st.lowp_ok)) continue;
     for (int sl : {st.a, st.b}) {
       if (!lowp && !p->slots[sl].constant) continue;  // the correction reads its own copy
       if (!p->shadow[sl]) {
@@ -1058,6 +1058,13 @@ void plan_build(cc_plan *p, const cc_system *sys) {
   CC_HIP_CHECK(hipStreamSynchronize(s));
   for (Step &st : p->iter)
     if (st.kind == Step::GEMM) p->gemm_steps.push_back(&st);
+  // Reduced precision pays for the contractions that carry the work; the
+  // ones under 1% of the iteration's flops are bandwidth- or latency-bound
+  // and run in FP64 (measured faster, and exact), unless the plan asks for
+  // every contraction in its precision (CC_PLAN_LOWP_ALL, batched plans).
+  if (!p->cplx)
+    for (Step &st : p->iter)
+      if (st.kind == Step::GEMM) st.lowp_ok = p->lowp_all || st.flops >= 0.01 * p->flops_per_iter;
   // contractions linear in the amplitudes worth a reference + correction
   // evaluation: one constant operand and at least 1% of the iteration's work
   if (!p->cplx) {
@@ -1150,10 +1157,8 @@ void plan_autotune(cc_plan *p, int reps) {
   // host threads): lookups and inserts are serialised
   static std::map<std::string, int> cache;
   static std::mutex cache_mutex;
-  const int prec = p->cplx ? 9 : p->cur_prec;  // 9: complex128 tiles
+  const int prec_plan = p->cplx ? 9 : p->cur_prec;  // 9: complex128 tiles
   plan_prepare(p);
-  const int ntiles = p->cplx ? gemm_c128_num_tiles()
-                             : (prec == PREC_F64 ? gemm_f64_num_tiles() : gemm_lowp_num_tiles(prec));
   hipStream_t s = p->ctx->stream;
   hipEvent_t e0, e1;
   CC_HIP_CHECK(hipEventCreate(&e0));
@@ -1162,6 +1167,10 @@ void plan_autotune(cc_plan *p, int reps) {
     for (Step *st : p->gemm_steps) {
       GemmDesc d = st->gemm;
       const bool akc = d.sak == 1, bkc = d.sbk == 1;
+      // this step's precision: contractions under 1% of the work run in FP64
+      const int prec = (prec_plan != PREC_F64 && prec_plan != 9 && !st->lowp_ok) ? PREC_F64 : prec_plan;
+      const int ntiles = p->cplx ? gemm_c128_num_tiles()
+                                 : (prec == PREC_F64 ? gemm_f64_num_tiles() : gemm_lowp_num_tiles(prec));
       const std::string key = std::to_string(prec) + ":" + std::to_string(d.M) + "x" +
                               std::to_string(d.N) + "x" + std::to_string(d.K) + (akc ? "k" : "m") +
                               (bkc ? "k" : "n");
@@ -1224,9 +1233,9 @@ std::string plan_profile_table(const cc_plan *p) {
     for (auto &c : tag)
       if (c == ' ') c = '_';
     if (st.kind == Step::GEMM)
-      tag += "@" + std::string(p->cplx ? gemm_c128_tile_name(st.tile_z)
-                               : p->cur_prec == PREC_F64 ? gemm_f64_tile_name(st.tile)
-                                                         : gemm_lowp_tile_name(p->cur_prec, st.tile_lp[p->cur_prec]));
+      tag += "@" + std::string(p->cplx                                    ? gemm_c128_tile_name(st.tile_z)
+                               : (p->cur_prec == PREC_F64 || !st.lowp_ok) ? gemm_f64_tile_name(st.tile)
+                                                                          : gemm_lowp_tile_name(p->cur_prec, st.tile_lp[p->cur_prec]));
     os << i << " " << kinds[st.kind] << " " << tag << " " << p->step_calls[i]
        << " " << p->step_ms[i] << " " << (p->step_calls[i] ? p->step_ms[i] / p->step_calls[i] : 0.0)
        << " " << st.flops << "\n";

@@ -55,6 +55,7 @@ struct Step {
   int tile_lp[3] = {-1, -1, -1};  // per reduced precision (index = cc_prec)
   int tile_z = -1;      // complex128 tile
   int delta = -1;       // index into cc_plan::deltas (GEMM linear in the amplitudes)
+  bool lowp_ok = true;  // runs in the plan's reduced precision (else FP64: under 1% of the work)
   // PAIR: slot a -> slot c through index-pair tables (PairEntry): mode 0
   // gathers packed rows/columns, 1 scatter-adds, 2 scatter-sets; tables:
   // 0 occupied i<j, 1 virtual a<b, 2 (m,a) all, 3 (a,m) all (same order as 2)
@@ -104,6 +105,7 @@ struct cc_plan {
   std::shared_ptr<ccmi::OpList> custom;  // null: the built-in contraction table
   // particle-particle ladder over packed pairs (i<j, e<f, a<b)
   bool packed = false;
+  bool lowp_all = false;  // every contraction in the reduced precision (else small ones in FP64)
   int *pair_tab[4] = {nullptr, nullptr, nullptr, nullptr};  // device index-pair tables
   // triples (op lists that read t3 or accumulate Y3): bound per plan
   bool triples = false;
@@ -168,6 +170,6 @@ AsmEntry asm_entry(cc_plan *p);
 R1Entry r1_entry(cc_plan *p);
 FinEntry fin_entry(cc_plan *p);
 void *ptr_of(cc_plan *p, int slot);
-cc_plan *make_plan_checked(cc_ctx *ctx, const cc_system *sys, int method, int prec);
+cc_plan *make_plan_checked(cc_ctx *ctx, const cc_system *sys, int method, int prec, bool lowp_all = false);
 void check_amps(const cc_amps *t, int method);
 }  // namespace ccmi

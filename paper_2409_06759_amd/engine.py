@@ -109,13 +109,13 @@ class Plan:
     contraction list such as `codegen.emit.op_list` (cc_plan_create_ops)."""
 
     def __init__(self, ctx: Context, dsys: DeviceSystem, method: int = CCSD, prec: int = F64,
-                 ops: Optional[str] = None, packed: bool = False):
+                 ops: Optional[str] = None, packed: bool = False, lowp_all: bool = False):
         self.ctx, self.dsys, self.method = ctx, dsys, method
         self.h = C.c_void_p()
         ctx.enter()
         if ops is None:
-            ctx.check(ctx.lib.cc_plan_create2(ctx.h, C.byref(dsys.struct), method, prec, 1 if packed else 0,
-                                              C.byref(self.h)))
+            flags = (1 if packed else 0) | (2 if lowp_all else 0)
+            ctx.check(ctx.lib.cc_plan_create2(ctx.h, C.byref(dsys.struct), method, prec, flags, C.byref(self.h)))
         else:
             ctx.check(ctx.lib.cc_plan_create_ops(ctx.h, C.byref(dsys.struct), method, prec, ops.encode(),
                                                  C.byref(self.h)))

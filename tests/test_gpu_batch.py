@@ -90,7 +90,7 @@ def test_batch_reduced_precision_equals_single_system(E, ctx, prec):
         amps_b = B.amps
         for b, d in enumerate(ds):
             t1, t2 = E.zeros_amps(d, E.CCSD)
-            with E.Plan(ctx, d, E.CCSD, prec=P) as p:
+            with E.Plan(ctx, d, E.CCSD, prec=P, lowp_all=True) as p:  # as the batch: all in prec
                 for _ in range(3):
                     p.step(t1, t2, 0.0, True)
                 rn, e, _ = p.scalars()

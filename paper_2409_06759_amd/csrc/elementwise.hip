@@ -65,13 +65,27 @@ __device__ __forceinline__ void perm_flat_body(const PermEntry &E, int64_t bid) 
   const T *__restrict__ in = static_cast<const T *>(E.in);
   T *__restrict__ out = static_cast<T *>(E.out);
   const int64_t e1 = std::min<int64_t>(p.total, (bid + 1) * CH);
+  // element index -> (input, output) offsets; 32-bit division when the
+  // whole tensor indexes in 32 bits (several times cheaper than 64-bit)
+  const bool narrow = p.total < (int64_t(1) << 31);
   for (int64_t e = bid * CH + threadIdx.x; e < e1; e += 256) {
-    int64_t rem = e, io = 0, oo = 0;
-    for (int d = p.rank - 1; d >= 0; --d) {
-      const int64_t x = rem % p.dims[d];
-      rem /= p.dims[d];
-      io += x * p.istr[d];
-      oo += x * p.ostr[d];
+    int64_t io = 0, oo = 0;
+    if (narrow) {
+      uint32_t rem = uint32_t(e);
+      for (int d = p.rank - 1; d >= 0; --d) {
+        const uint32_t n = uint32_t(p.dims[d]), x = rem % n;
+        rem /= n;
+        io += int64_t(x) * p.istr[d];
+        oo += int64_t(x) * p.ostr[d];
+      }
+    } else {
+      int64_t rem = e;
+      for (int d = p.rank - 1; d >= 0; --d) {
+        const int64_t x = rem % p.dims[d];
+        rem /= p.dims[d];
+        io += x * p.istr[d];
+        oo += x * p.ostr[d];
+      }
     }
     T v = in[io];
     if (p.conj) v = cj(v);

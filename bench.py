@@ -332,8 +332,8 @@ def main():
                     help="also run one plain 1 GiB copy (for HBM counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path has no "
-              "multi-GPU mode in this build.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the residual path has no "
+              "multi-GPU mode.", file=sys.stderr)
         sys.exit(2)
 
     import torch

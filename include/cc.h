@@ -234,6 +234,9 @@ int cc_gemm(cc_ctx *ctx, int prec, int scalar, int64_t M, int64_t N, int64_t K, 
  * is set (tuning sweeps; for complex operands i indexes the complex GEMM's
  * own configurations), its own choice otherwise.  -1 for an unknown prec. */
 int cc_gemm_tile_count(int prec);
+/* Number of tile configurations of the complex (CC_C128) GEMM, which runs in
+ * FP64 only; CC_GEMM_TILE=i selects configuration i of that set. */
+int cc_gemm_tile_count_c128(void);
 /* out[I] = alpha * in[perm(I)] + beta * out[I] for a dense rank-r tensor
  * (r <= 6): out has dims out_dims[0..r-1]; out index d reads input dim
  * perm[d]; in is dense row-major with dims in_dims. */

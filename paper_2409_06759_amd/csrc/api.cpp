@@ -621,6 +621,8 @@ int cc_gemm_tile_count(int prec) {
   return -1;
 }
 
+int cc_gemm_tile_count_c128(void) { return ccmi::gemm_c128_num_tiles(); }
+
 int cc_permute(cc_ctx *ctx, int scalar, int rank, const int64_t *in_dims, const int32_t *perm,
                double alpha, const void *in, double beta, void *out) {
   if (!ctx) return fail(nullptr, CC_EINVAL, "ctx is NULL");

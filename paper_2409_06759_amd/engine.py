@@ -253,10 +253,10 @@ def gemm(ctx, A, B, Cm, alpha=1.0, beta=0.0, a_kcontig=True, b_kcontig=True, pre
                               beta, _ptr(Cm), N))
 
 
-def gemm_tile_count(ctx, prec=F64) -> int:
-    """Number of GEMM tile configurations of a precision (for forced-tile
-    sweeps through the CC_GEMM_TILE environment variable)."""
-    return ctx.lib.cc_gemm_tile_count(prec)
+def gemm_tile_count(ctx, prec=F64, cplx=False) -> int:
+    """Number of GEMM tile configurations of a precision, or of the complex
+    GEMM (for forced-tile sweeps through the CC_GEMM_TILE environment variable)."""
+    return ctx.lib.cc_gemm_tile_count_c128() if cplx else ctx.lib.cc_gemm_tile_count(prec)
 
 
 def permute(ctx, x, perm, out=None, alpha=1.0, beta=0.0):

@@ -334,3 +334,43 @@ def test_gemm_c128_lds_direct_is_bitwise_staged(ctx, monkeypatch, M, N, K, akc, 
     assert np.array_equal(out[0], out[1])
     ref = 0.5 * (A @ B.T) - 1.25 * C0
     assert np.abs(out[1] - ref).max() <= 1e-12 * max(1.0, K)
+
+
+# Every tile configuration, forced through CC_GEMM_TILE, on a ragged shape
+# (staged loads, partial tiles on every side) and on one whose K and row
+# strides admit the LDS-direct and vector-load paths.
+EVERY_TILE_SHAPES = [(100, 129, 37), (257, 300, 64)]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3", "c128"])
+def test_gemm_every_tile_meets_bound(ctx, monkeypatch, prec):
+    from paper_2409_06759_amd import engine as E
+    cplx = prec == "c128"
+    p = E.PRECS["f64" if cplx else prec]
+    ntiles = E.gemm_tile_count(ctx, p, cplx=cplx)
+    assert ntiles > 0
+    u = {"f64": 2.0 ** -53, "c128": 2.0 ** -53, "f32": 2.0 ** -24, "bf16x3": 2.0 ** -24}[prec]
+    for M, N, K in EVERY_TILE_SHAPES:
+        rng = np.random.default_rng(M + N + K)
+        A = rng.normal(size=(M, K))
+        B = rng.normal(size=(N, K))
+        C0 = rng.normal(size=(M, N))
+        if cplx:
+            A = A + 1j * rng.normal(size=(M, K))
+            B = B + 1j * rng.normal(size=(N, K))
+            C0 = C0 + 1j * rng.normal(size=(M, N))
+        alpha, beta = 0.5, -1.25
+        ref = alpha * (A @ B.T) + beta * C0
+        eps = (4 if cplx else 2) * (K + 2) * u + (3 * 2.0 ** -17 if prec == "bf16x3" else 0.0)
+        bound = eps * abs(alpha) * (np.abs(A) @ np.abs(B).T) + 4 * (K + 2) * np.finfo(float).eps * np.abs(beta * C0)
+        for akc in (True, False):
+            for bkc in (True, False):
+                Ad = torch.from_numpy(A if akc else np.ascontiguousarray(A.T)).cuda()
+                Bd = torch.from_numpy(B if bkc else np.ascontiguousarray(B.T)).cuda()
+                for t in range(ntiles):
+                    print(f"every tile {prec} tile {t} M={M} N={N} K={K} akc={akc} bkc={bkc}", flush=True)
+                    monkeypatch.setenv("CC_GEMM_TILE", str(t))
+                    Cd = torch.from_numpy(C0).cuda()
+                    E.gemm(ctx, Ad, Bd, Cd, alpha, beta, a_kcontig=akc, b_kcontig=bkc, prec=p)
+                    err = np.abs(Cd.cpu().numpy() - ref)
+                    assert np.all(err <= bound), (t, akc, bkc, (err / bound).max())

@@ -33,6 +33,7 @@ struct OpSpec {
   const char *swap;    // nullptr or two labels of C
   bool needs_t1;       // skipped for CCD
   const char *tag;     // short name for profiling
+  bool kc = false;     // reduced-precision plans: both GEMM operands K-contiguous (permuted if need be)
 };
 
 struct Slot {

@@ -358,3 +358,14 @@ def test_batched_norm_readback_reports_the_same_convergence(E, ctx, prec):
     else:
         assert abs(out[5]["iters"] - out[1]["iters"]) <= 10
         assert abs(out[5]["energy"] - out[1]["energy"]) < 1e-10
+
+
+@pytest.mark.parametrize("prec,kc", [("f64", False), ("f32", True), ("bf16x3", True)])
+def test_hole_hole_ladder_layout_follows_plan_precision(E, ctx, prec, kc):
+    """Plans made for a reduced precision read both operands of the hole-hole
+    ladder K-contiguous (tau permuted to [ab][mn], W to [ij][mn]); FP64 plans
+    read the stored [mn][ij] and [mn][ab] layouts."""
+    d = E.DeviceSystem(make_system(4, 12))
+    with E.Plan(ctx, d, E.CCSD, E.PRECS[prec]) as p:
+        line = next(s for s in p.describe().splitlines() if s.startswith("GEMM hh_ladder "))
+    assert (" sak=1 " in line and " sbk=1 " in line) == kc, line

@@ -60,6 +60,15 @@ def test_null_arguments_rejected():
     assert lib.cc_destroy(None) == 0
 
 
+def test_tile_counts():
+    """Configuration counts for the forced-tile sweeps (no device needed)."""
+    L, lib = _lib()
+    for prec in (L.CC_PREC_F64, L.CC_PREC_F32, L.CC_PREC_BF16X3):
+        assert lib.cc_gemm_tile_count(prec) > 1
+    assert lib.cc_gemm_tile_count(7) == -1
+    assert lib.cc_gemm_tile_count_c128() > 1
+
+
 def test_dry_plan_rejects_bad_sizes():
     _, lib = _lib()
     assert lib.cc_plan_describe_dry(0, 5, 1, 0).startswith(b"error")

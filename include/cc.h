@@ -200,14 +200,27 @@ int cc_plan_step(cc_plan *plan, cc_amps *t, double level_shift, int dressed);
 int cc_plan_scalars(cc_plan *plan, double *rnorm, double *e_re, double *e_im);
 
 /* ---- one-shot conveniences ---------------------------------------------- */
+/* Residual of the amplitude equations (Eq. eq:amp: the singles and doubles
+ * projections of the similarity-transformed normal-ordered Hamiltonian,
+ * with T and H_N as in Sec. "Coupled cluster amplitude equations") at the
+ * amplitudes t (device, layouts as in cc_amps).  r (device, caller-owned,
+ * same layout) receives R1/R2 and may be NULL; rnorm_out (host, may be NULL)
+ * receives the Frobenius norm over every stored element of R1 and R2.  A
+ * temporary plan is built and freed inside the call.  Errors: CC_EINVAL
+ * for bad sizes or method, CC_ENOMEM, CC_EHIP. */
 int cc_residual(cc_ctx *ctx, const cc_system *sys, int method, int prec, const cc_amps *t,
                 cc_amps *r, double *rnorm_out);
 /* E - E_HF = sum f_ia t_i^a + 1/4 sum <ij||ab> tau_ij^ab (first line of Eq. eq:amp). */
 int cc_energy(cc_ctx *ctx, const cc_system *sys, int method, const cc_amps *t, double *e_re,
               double *e_im);
-/* Jacobi iteration from the amplitudes in t_inout (zeros = start from the
- * reference, whose first step yields the MP2 amplitudes).  Returns CC_OK,
- * CC_ENOTCONV or CC_EDIVERGED; t_inout holds the last finite iterate. */
+/* Solves the amplitude equations of Eq. eq:amp by Jacobi iteration until
+ * the residual norm is below opts->tol, the convergence test of Sec.
+ * "Correctness: H2O and LiH" (energies compared at a residual-norm
+ * threshold).  Starts from the amplitudes in t_inout (device, caller-owned;
+ * zeros = the reference, whose first step yields the MP2 amplitudes), or
+ * from the guess opts->guess selects.  Returns CC_OK, CC_ENOTCONV or
+ * CC_EDIVERGED; t_inout holds the last finite iterate, report (host, may be
+ * NULL) the per-iteration history. */
 int cc_iterate(cc_ctx *ctx, const cc_system *sys, int method, const cc_iter_opts *opts,
                cc_amps *t_inout, cc_iter_report *report);
 

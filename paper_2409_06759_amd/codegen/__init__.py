@@ -6,8 +6,7 @@ the spirit of the string representation of Kallay and Surjan (paper, Sec.
 directed line graphs, and interpreted into explicit tensor terms with the
 usual Goldstone rules (sign from hole lines and loops, weights from
 equivalent lines and vertices, antisymmetrisers over inequivalent external
-lines).  The derivation is host-side Python; `evaluate` computes the terms
-with NumPy for checking.
+lines).  The derivation is host-side Python.
 """
 from .diagrams import Diagram, HPiece, TVertex, diagram_count, enumerate_diagrams, method_diagrams
 from .terms import Term, interpret, equations

@@ -1,11 +1,15 @@
-"""NumPy evaluation of derived terms (for checking the derivation)."""
+"""NumPy evaluation of the diagram generator's derived terms.  TEST CODE.
+
+Used by the tests only, to check the derivation and the GPU execution of
+generated contraction lists against the terms they came from.
+"""
 from __future__ import annotations
 
 from typing import Callable, Dict, List
 
 import numpy as np
 
-from .terms import Term
+from paper_2409_06759_amd.codegen.terms import Term
 
 
 def evaluate(terms: List[Term], fock: Callable[[str], np.ndarray], ints: Callable[[str], np.ndarray],

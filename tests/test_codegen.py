@@ -13,7 +13,7 @@ from oracle.cc import Fock, energy, residual
 from oracle.integrals import Integrals
 from oracle.projection import Projector
 from paper_2409_06759_amd.codegen import diagram_count, equations, method_diagrams
-from paper_2409_06759_amd.codegen.evaluate import evaluate
+from derived_eval import evaluate
 
 
 def test_diagram_counts_of_table_gener():

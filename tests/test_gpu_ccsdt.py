@@ -70,7 +70,7 @@ def test_ccsdt_residual_matches_derived_terms_larger(E, ctx):
     """Several tiles in every dimension: against the NumPy evaluation of the
     derived CCSDT terms (themselves pinned to the projection on the CPU)."""
     from paper_2409_06759_amd.codegen import equations
-    from paper_2409_06759_amd.codegen.evaluate import evaluate
+    from derived_eval import evaluate
     o, v = 6, 21
     s = make_system(o, v, 10, sigma=0.05)
     rng = np.random.default_rng(5)

@@ -28,8 +28,15 @@ def sources():
     return sorted(list(CSRC.glob("*.hip")) + list(CSRC.glob("*.cpp")))
 
 
-def _compile(src: pathlib.Path) -> pathlib.Path:
+def _headers_mtime() -> float:
+    hs = list(CSRC.glob("*.hpp")) + list(INCLUDE.glob("*.h"))
+    return max((h.stat().st_mtime for h in hs), default=0.0)
+
+
+def _compile(src: pathlib.Path, incremental: bool = False) -> pathlib.Path:
     obj = OBJDIR / (src.name + ".o")
+    if incremental and obj.exists() and obj.stat().st_mtime > max(src.stat().st_mtime, _headers_mtime()):
+        return obj
     cmd = [HIPCC, *COMMON, "-c"]
     if src.suffix == ".hip":
         cmd += ["-x", "hip"]
@@ -40,12 +47,20 @@ def _compile(src: pathlib.Path) -> pathlib.Path:
     return obj
 
 
-def build(verbose: bool = False) -> pathlib.Path:
+def build(verbose: bool = False, incremental: bool = False) -> pathlib.Path:
+    """Compile and link.  incremental=True skips sources whose object is newer
+    than the source and every header (development builds); the default
+    recompiles everything."""
     OBJDIR.mkdir(exist_ok=True)
     srcs = sources()
     jobs = min(len(srcs), max(1, min(8, os.cpu_count() or 1)))
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
+        objs = list(ex.map(lambda f: _compile(f, incremental), srcs))
+    # the LDS-direct GEMM kernels' M0 handling, on the disassembly of the objects just built
+    from . import check_m0
+    nk = check_m0.check_objects(objs)
+    if verbose:
+        print(f"LDS-direct M0 check: {nk} kernels")
     tmp = OUT.with_suffix(".so.tmp")
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", str(tmp), *map(str, objs)]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -58,5 +73,5 @@ def build(verbose: bool = False) -> pathlib.Path:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, incremental="--incremental" in sys.argv)
     sys.exit(0)

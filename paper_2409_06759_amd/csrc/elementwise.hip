@@ -65,13 +65,17 @@ __device__ __forceinline__ void perm_flat_body(const PermEntry &E, int64_t bid) 
   const T *__restrict__ in = static_cast<const T *>(E.in);
   T *__restrict__ out = static_cast<T *>(E.out);
   const int64_t e1 = std::min<int64_t>(p.total, (bid + 1) * CH);
-  // Real tensors whose shared unit-stride dimension is even and whose bases
-  // are 16-byte aligned move pairs of elements with 16-byte accesses (the
-  // pair never straddles a row, so one offset computation serves both).
+  // Real tensors whose shared unit-stride dimension is even, whose other
+  // strides are even and whose bases are 16-byte aligned move pairs of
+  // elements with 16-byte accesses (every pair starts at an even offset and
+  // never straddles a row, so one offset computation serves both).
   if constexpr (sizeof(T) == 8) {
     const int r1 = p.rank - 1;
-    if (p.rank >= 1 && p.dims[r1] % 2 == 0 && p.istr[r1] == 1 && p.ostr[r1] == 1 && p.total < (int64_t(1) << 31) &&
-        (reinterpret_cast<uintptr_t>(in) & 15) == 0 && (reinterpret_cast<uintptr_t>(out) & 15) == 0 && !p.conj) {
+    bool even = true;
+    for (int d = 0; d < r1; ++d) even = even && (p.istr[d] % 2 == 0) && (p.ostr[d] % 2 == 0);
+    if (p.rank >= 1 && even && p.dims[r1] % 2 == 0 && p.istr[r1] == 1 && p.ostr[r1] == 1 &&
+        p.total < (int64_t(1) << 31) && (reinterpret_cast<uintptr_t>(in) & 15) == 0 &&
+        (reinterpret_cast<uintptr_t>(out) & 15) == 0 && !p.conj) {
       typedef double d2v __attribute__((ext_vector_type(2)));
       for (int64_t e = bid * CH + 2 * threadIdx.x; e < e1; e += 512) {
         uint32_t rem = uint32_t(e);

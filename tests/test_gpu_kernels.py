@@ -374,3 +374,35 @@ def test_gemm_every_tile_meets_bound(ctx, monkeypatch, prec):
                     E.gemm(ctx, Ad, Bd, Cd, alpha, beta, a_kcontig=akc, b_kcontig=bkc, prec=p)
                     err = np.abs(Cd.cpu().numpy() - ref)
                     assert np.all(err <= bound), (t, akc, bkc, (err / bound).max())
+
+
+def test_permute_pairs_accumulate(ctx):
+    """Shared even unit-stride dimension (16-byte pair path) with alpha/beta
+    accumulation; exact against numpy (alpha, beta powers of two)."""
+    from paper_2409_06759_amd import engine as E
+    rng = np.random.default_rng(11)
+    x = rng.normal(size=(6, 10, 4, 8))
+    y = rng.normal(size=(10, 6, 4, 8))
+    yd = torch.from_numpy(y).cuda()
+    E.permute(ctx, torch.from_numpy(x).cuda(), (1, 0, 2, 3), out=yd, alpha=0.5, beta=-2.0)
+    assert np.array_equal(yd.cpu().numpy(), 0.5 * x.transpose(1, 0, 2, 3) + (-2.0) * y)
+
+
+@pytest.mark.parametrize("ldc", [4, 5, 7])
+def test_gemm_empty_contraction_strided_c(ctx, ldc):
+    """K = 0 scales C in place, row stride ldc (odd ldc: rows start at odd
+    element offsets, so elements cannot move in aligned pairs); the columns
+    past N are left alone."""
+    import ctypes as C
+    from paper_2409_06759_amd import _lib as L
+    M, N = 3, 4
+    rng = np.random.default_rng(ldc)
+    c0 = rng.normal(size=(M, ldc))
+    Cd = torch.from_numpy(c0).cuda()
+    A = torch.zeros(16, dtype=torch.float64, device="cuda")
+    ctx.enter()
+    ctx.check(ctx.lib.cc_gemm(ctx.h, L.CC_PREC_F64, L.CC_R64, M, N, 0, 1.0, C.c_void_p(A.data_ptr()), 1, 1,
+                              C.c_void_p(A.data_ptr()), 1, 1, -0.5, C.c_void_p(Cd.data_ptr()), ldc))
+    want = c0.copy()
+    want[:, :N] *= -0.5
+    assert np.array_equal(Cd.cpu().numpy(), want)

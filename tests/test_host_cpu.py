@@ -105,3 +105,19 @@ def test_plan_listing_reproduces_oracle(method, cplx, ov):
     assert np.abs(R2 - r2_ref).max() < 1e-13
     if method == 1:
         assert np.abs(R1 - r1_ref).max() < 1e-13
+
+
+def test_m0_check_flags_violations():
+    """The build-time check of the LDS-direct loads accepts the inline
+    sequence and rejects a stray M0 write, an implicit M0 reader and a load
+    without its M0 write."""
+    from paper_2409_06759_amd.check_m0 import check_text
+    good = ("0000000000001000 <k>:\n  s_mov_b32 m0, s4 // x\n  s_nop 0\n  global_load_lds_dwordx4 v[0:1], off\n"
+            "  v_mfma_f64_16x16x4_f64 v[2:9], v[10:11], v[12:13], v[2:9]\n")
+    assert check_text(good) == (1, [])
+    for extra in ("  s_mov_b32 m0, -1\n", "  s_movrels_b32 s0, s1\n", "  global_load_lds_dwordx4 v[0:1], off\n",
+                  "  s_sendmsg sendmsg(MSG_INTERRUPT)\n"):
+        n, bad = check_text(good + extra)
+        assert n == 1 and len(bad) == 1, extra
+    # kernels without LDS-direct loads are not constrained
+    assert check_text("0000000000002000 <j>:\n  s_mov_b32 m0, -1\n  ds_read_b64 v[0:1], v2\n") == (0, [])

@@ -250,3 +250,23 @@ def batch_shapes(count: int, seed: int = BASE_SEED + 1000, o_range=(4, 16), v_ra
     os_ = rng.integers(o_range[0], o_range[1] + 1, size=count)
     vs_ = rng.integers(v_range[0], v_range[1] + 1, size=count)
     return [(int(a), int(b), seed + s) for s, (a, b) in enumerate(zip(os_, vs_))]
+
+
+def random_amplitudes(o: int, v: int, seed: int, scale: float = 0.01, is_complex: bool = False):
+    """Test amplitudes (not a coupled-cluster solution): t1[i][a] and
+    t2[i][j][a][b] with independent N(0, scale^2) entries (complex: real and
+    imaginary parts each N(0, scale^2)), t2 then made antisymmetric in (i, j)
+    and in (a, b) by t2 <- P(ij) P(ab) x.  Drawn from PCG64(seed)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+
+    def draw(shape):
+        x = rng.standard_normal(size=shape) * scale
+        if is_complex:
+            x = x + 1j * (rng.standard_normal(size=shape) * scale)
+        return x
+
+    t1 = draw((o, v))
+    t2 = draw((o, o, v, v))
+    t2 = t2 - t2.transpose(1, 0, 2, 3)
+    t2 = t2 - t2.transpose(0, 1, 3, 2)
+    return t1, t2

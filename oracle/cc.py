@@ -32,6 +32,8 @@ D_ij^ab = f_ii + f_jj - f_aa - f_bb.
 """
 from __future__ import annotations
 
+import itertools
+
 import numpy as np
 
 from .integrals import Integrals
@@ -113,65 +115,76 @@ def singles_terms(F: Fock, V: Integrals, t1, t2):
 
 # --------------------------------------------------------------- doubles --
 def doubles_terms_ccd(F: Fock, V: Integrals, t2):
-    """The ten doubles diagrams that survive when T1 = 0."""
+    """The ten doubles diagrams that survive when T1 = 0 (a list)."""
+    return list(_doubles_ccd(F, V, t2))
+
+
+def _doubles_ccd(F: Fock, V: Integrals, t2):
+    """The same diagrams, produced one at a time (a generator)."""
     oooo, vvvv, ovvo, oovv = V.get("oooo"), V.get("vvvv"), V.get("ovvo"), V.get("oovv")
-    return [
-        V.get("vvoo").transpose(2, 3, 0, 1).copy(),                # <ab||ij>
-        P_ab(_es("bc,ijac->ijab", F.vv, t2)),                      # P(ab) f_bc t_ij^ac
-        -P_ij(_es("kj,ikab->ijab", F.oo, t2)),                     # -P(ij) f_kj t_ik^ab
-        0.5 * _es("klij,klab->ijab", oooo, t2),                    # 1/2 <kl||ij> t_kl^ab
-        0.5 * _es("abcd,ijcd->ijab", vvvv, t2),                    # 1/2 <ab||cd> t_ij^cd
-        P_ijab(_es("kbcj,ikac->ijab", ovvo, t2)),                  # P(ij)P(ab) <kb||cj> t_ik^ac
-        0.25 * _es("klcd,ijcd,klab->ijab", oovv, t2, t2),          # 1/4 <kl||cd> t_ij^cd t_kl^ab
-        P_ij(_es("klcd,ikac,jlbd->ijab", oovv, t2, t2)),           # P(ij) <kl||cd> t_ik^ac t_jl^bd
-        -0.5 * P_ij(_es("klcd,ikdc,ljab->ijab", oovv, t2, t2)),    # -1/2 P(ij) <kl||cd> t_ik^dc t_lj^ab
-        -0.5 * P_ab(_es("klcd,lkac,ijdb->ijab", oovv, t2, t2)),    # -1/2 P(ab) <kl||cd> t_lk^ac t_ij^db
-    ]
+    yield V.get("vvoo").transpose(2, 3, 0, 1).copy()                                # <ab||ij>
+    yield P_ab(_es("bc,ijac->ijab", F.vv, t2))                                      # P(ab) f_bc t_ij^ac
+    yield -P_ij(_es("kj,ikab->ijab", F.oo, t2))                                     # -P(ij) f_kj t_ik^ab
+    yield 0.5 * _es("klij,klab->ijab", oooo, t2)                                    # 1/2 <kl||ij> t_kl^ab
+    yield 0.5 * _es("abcd,ijcd->ijab", vvvv, t2)                                    # 1/2 <ab||cd> t_ij^cd
+    yield P_ijab(_es("kbcj,ikac->ijab", ovvo, t2))                                  # P(ij)P(ab) <kb||cj> t_ik^ac
+    yield 0.25 * _es("klcd,ijcd,klab->ijab", oovv, t2, t2)                          # 1/4 <kl||cd> t_ij^cd t_kl^ab
+    yield P_ij(_es("klcd,ikac,jlbd->ijab", oovv, t2, t2))                           # P(ij) <kl||cd> t_ik^ac t_jl^bd
+    yield -0.5 * P_ij(_es("klcd,ikdc,ljab->ijab", oovv, t2, t2))                    # -1/2 P(ij) <kl||cd> t_ik^dc t_lj^ab
+    yield -0.5 * P_ab(_es("klcd,lkac,ijdb->ijab", oovv, t2, t2))                    # -1/2 P(ab) <kl||cd> t_lk^ac t_ij^db
 
 
 def doubles_terms_t1(F: Fock, V: Integrals, t1, t2):
-    """The twenty-one doubles diagrams that contain at least one t1."""
+    """The twenty-one doubles diagrams that contain at least one t1 (a list)."""
+    return list(_doubles_t1(F, V, t1, t2))
+
+
+def _doubles_t1(F: Fock, V: Integrals, t1, t2):
+    """The same diagrams, produced one at a time (a generator)."""
     oooo, vvvv, oovv = V.get("oooo"), V.get("vvvv"), V.get("oovv")
     ovvv, ooov, oovo = V.get("ovvv"), V.get("ooov"), V.get("oovo")
-    return [
-        P_ij(_es("abcj,ic->ijab", V.get("vvvo"), t1)),                        # P(ij) <ab||cj> t_i^c
-        -P_ab(_es("kbij,ka->ijab", V.get("ovoo"), t1)),                       # -P(ab) <kb||ij> t_k^a
-        0.5 * P_ab(_es("klij,ka,lb->ijab", oooo, t1, t1)),                    # 1/2 P(ab) <kl||ij> t_k^a t_l^b
-        0.5 * P_ij(_es("abcd,ic,jd->ijab", vvvv, t1, t1)),                    # 1/2 P(ij) <ab||cd> t_i^c t_j^d
-        -P_ijab(_es("kbic,ka,jc->ijab", V.get("ovov"), t1, t1)),              # -P(ij)P(ab) <kb||ic> t_k^a t_j^c
-        P_ab(_es("kc,ka,ijbc->ijab", F.ov, t1, t2)),                          # P(ab) f_kc t_k^a t_ij^bc
-        P_ij(_es("kc,ic,jkab->ijab", F.ov, t1, t2)),                          # P(ij) f_kc t_i^c t_jk^ab
-        -P_ij(_es("klci,kc,ljab->ijab", oovo, t1, t2)),                       # -P(ij) <kl||ci> t_k^c t_lj^ab
-        P_ab(_es("kacd,kc,ijdb->ijab", ovvv, t1, t2)),                        # P(ab) <ka||cd> t_k^c t_ij^db
-        P_ijab(_es("akdc,id,jkbc->ijab", V.get("vovv"), t1, t2)),             # P(ij)P(ab) <ak||dc> t_i^d t_jk^bc
-        P_ijab(_es("klic,la,jkbc->ijab", ooov, t1, t2)),                      # P(ij)P(ab) <kl||ic> t_l^a t_jk^bc
-        0.5 * P_ij(_es("klcj,ic,klab->ijab", oovo, t1, t2)),                  # 1/2 P(ij) <kl||cj> t_i^c t_kl^ab
-        -0.5 * P_ab(_es("kbcd,ka,ijcd->ijab", ovvv, t1, t2)),                 # -1/2 P(ab) <kb||cd> t_k^a t_ij^cd
-        -0.5 * P_ijab(_es("kbcd,ic,ka,jd->ijab", ovvv, t1, t1, t1)),          # -1/2 P(ij)P(ab) <kb||cd> t_i^c t_k^a t_j^d
-        0.5 * P_ijab(_es("klcj,ic,ka,lb->ijab", oovo, t1, t1, t1)),           # 1/2 P(ij)P(ab) <kl||cj> t_i^c t_k^a t_l^b
-        -P_ij(_es("klcd,kc,id,ljab->ijab", oovv, t1, t1, t2)),                # -P(ij) <kl||cd> t_k^c t_i^d t_lj^ab
-        -P_ab(_es("klcd,kc,la,ijdb->ijab", oovv, t1, t1, t2)),                # -P(ab) <kl||cd> t_k^c t_l^a t_ij^db
-        0.25 * P_ij(_es("klcd,ic,jd,klab->ijab", oovv, t1, t1, t2)),          # 1/4 P(ij) <kl||cd> t_i^c t_j^d t_kl^ab
-        0.25 * P_ab(_es("klcd,ka,lb,ijcd->ijab", oovv, t1, t1, t2)),          # 1/4 P(ab) <kl||cd> t_k^a t_l^b t_ij^cd
-        P_ijab(_es("klcd,ic,lb,kjad->ijab", oovv, t1, t1, t2)),               # P(ij)P(ab) <kl||cd> t_i^c t_l^b t_kj^ad
-        0.25 * P_ijab(_es("klcd,ic,ka,jd,lb->ijab", oovv, t1, t1, t1, t1)),   # 1/4 P(ij)P(ab) <kl||cd> t_i^c t_k^a t_j^d t_l^b
-    ]
+    yield P_ij(_es("abcj,ic->ijab", V.get("vvvo"), t1))                             # P(ij) <ab||cj> t_i^c
+    yield -P_ab(_es("kbij,ka->ijab", V.get("ovoo"), t1))                            # -P(ab) <kb||ij> t_k^a
+    yield 0.5 * P_ab(_es("klij,ka,lb->ijab", oooo, t1, t1))                         # 1/2 P(ab) <kl||ij> t_k^a t_l^b
+    # 1/2 P(ij) <ab||cd> t_i^c t_j^d, with t_i^c t_j^d formed first: contracting
+    # vvvv with one t1 at a time would transpose vvvv into a temporary as large
+    yield 0.5 * P_ij(_es("abcd,ijcd->ijab", vvvv, _es("ic,jd->ijcd", t1, t1)))
+    yield -P_ijab(_es("kbic,ka,jc->ijab", V.get("ovov"), t1, t1))                   # -P(ij)P(ab) <kb||ic> t_k^a t_j^c
+    yield P_ab(_es("kc,ka,ijbc->ijab", F.ov, t1, t2))                               # P(ab) f_kc t_k^a t_ij^bc
+    yield P_ij(_es("kc,ic,jkab->ijab", F.ov, t1, t2))                               # P(ij) f_kc t_i^c t_jk^ab
+    yield -P_ij(_es("klci,kc,ljab->ijab", oovo, t1, t2))                            # -P(ij) <kl||ci> t_k^c t_lj^ab
+    yield P_ab(_es("kacd,kc,ijdb->ijab", ovvv, t1, t2))                             # P(ab) <ka||cd> t_k^c t_ij^db
+    yield P_ijab(_es("akdc,id,jkbc->ijab", V.get("vovv"), t1, t2))                  # P(ij)P(ab) <ak||dc> t_i^d t_jk^bc
+    yield P_ijab(_es("klic,la,jkbc->ijab", ooov, t1, t2))                           # P(ij)P(ab) <kl||ic> t_l^a t_jk^bc
+    yield 0.5 * P_ij(_es("klcj,ic,klab->ijab", oovo, t1, t2))                       # 1/2 P(ij) <kl||cj> t_i^c t_kl^ab
+    yield -0.5 * P_ab(_es("kbcd,ka,ijcd->ijab", ovvv, t1, t2))                      # -1/2 P(ab) <kb||cd> t_k^a t_ij^cd
+    yield -0.5 * P_ijab(_es("kbcd,ic,ka,jd->ijab", ovvv, t1, t1, t1))               # -1/2 P(ij)P(ab) <kb||cd> t_i^c t_k^a t_j^d
+    yield 0.5 * P_ijab(_es("klcj,ic,ka,lb->ijab", oovo, t1, t1, t1))                # 1/2 P(ij)P(ab) <kl||cj> t_i^c t_k^a t_l^b
+    yield -P_ij(_es("klcd,kc,id,ljab->ijab", oovv, t1, t1, t2))                     # -P(ij) <kl||cd> t_k^c t_i^d t_lj^ab
+    yield -P_ab(_es("klcd,kc,la,ijdb->ijab", oovv, t1, t1, t2))                     # -P(ab) <kl||cd> t_k^c t_l^a t_ij^db
+    yield 0.25 * P_ij(_es("klcd,ic,jd,klab->ijab", oovv, t1, t1, t2))               # 1/4 P(ij) <kl||cd> t_i^c t_j^d t_kl^ab
+    yield 0.25 * P_ab(_es("klcd,ka,lb,ijcd->ijab", oovv, t1, t1, t2))               # 1/4 P(ab) <kl||cd> t_k^a t_l^b t_ij^cd
+    yield P_ijab(_es("klcd,ic,lb,kjad->ijab", oovv, t1, t1, t2))                    # P(ij)P(ab) <kl||cd> t_i^c t_l^b t_kj^ad
+    yield 0.25 * P_ijab(_es("klcd,ic,ka,jd,lb->ijab", oovv, t1, t1, t1, t1))        # 1/4 P(ij)P(ab) <kl||cd> t_i^c t_k^a t_j^d t_l^b
 
 
 def _sum(terms):
-    acc = terms[0].copy()
-    for x in terms[1:]:
+    """Sum of the terms in their order (a list or a generator: each term of
+    a generator is added before the next one is formed)."""
+    it = iter(terms)
+    acc = next(it).copy()
+    for x in it:
         acc += x
     return acc
 
 
 def residual(F: Fock, V: Integrals, t1, t2):
-    """(R1, R2) for CCSD, or (None, R2) for CCD when t1 is None."""
-    r2_terms = doubles_terms_ccd(F, V, t2)
+    """(R1, R2) for CCSD, or (None, R2) for CCD when t1 is None.  The doubles
+    diagrams are summed as they are formed, in the order listed."""
     if t1 is None:
-        return None, _sum(r2_terms)
-    r2_terms += doubles_terms_t1(F, V, t1, t2)
-    return _sum(singles_terms(F, V, t1, t2)), _sum(r2_terms)
+        return None, _sum(_doubles_ccd(F, V, t2))
+    r2 = _sum(itertools.chain(_doubles_ccd(F, V, t2), _doubles_t1(F, V, t1, t2)))
+    return _sum(singles_terms(F, V, t1, t2)), r2
 
 
 def diagram_count(method: str) -> int:

@@ -250,6 +250,28 @@ int cc_gemm_tile_count(int prec);
 /* Number of tile configurations of the complex (CC_C128) GEMM, which runs in
  * FP64 only; CC_GEMM_TILE=i selects configuration i of that set. */
 int cc_gemm_tile_count_c128(void);
+/* cc_gemm with FP64 arithmetic (real, or complex for scalar CC_C128) that
+ * allocates nothing, for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Arguments, layouts and results are those of cc_gemm with
+ * prec CC_PREC_F64 (the default tile choice; CC_GEMM_TILE and CC_GEMM_TAIL
+ * are not read).  Scratch: a real GEMM keeps its split-K partial sums (and
+ * those of the K-split tail of a launch whose last round would be mostly
+ * empty) in a static device buffer of 128 MiB (2^24 doubles) that the
+ * library holds on every device it runs on until the process ends; the
+ * complex GEMM runs as one launch and uses none.  The split-K factor is
+ * cc_gemm's (about 2048 workgroups of 64 x 64 outputs when the output has
+ * fewer tiles), so split x M x N stays below 4096 x 4096 < 2^24 doubles;
+ * a GEMM whose partial sums would still exceed the buffer is refused with
+ * CC_EINVAL and a message giving both sizes, and a tail cut whose partial
+ * sums would not fit is skipped (the GEMM then runs as one launch).  The work is only enqueued on the context's stream (no
+ * host synchronisation; launch errors are returned, faults surface at the
+ * caller's next synchronisation).  Every call on one device shares that
+ * device's buffer: calls that overlap in time on one GPU (other streams,
+ * contexts or threads) race, calls ordered on one stream do not. */
+int cc_gemm_noalloc(cc_ctx *ctx, int scalar, int64_t M, int64_t N, int64_t K, double alpha, const void *A,
+                    int64_t sam, int64_t sak, const void *B, int64_t sbn, int64_t sbk, double beta, void *C,
+                    int64_t ldc);
 /* out[I] = alpha * in[perm(I)] + beta * out[I] for a dense rank-r tensor
  * (r <= 6): out has dims out_dims[0..r-1]; out index d reads input dim
  * perm[d]; in is dense row-major with dims in_dims. */

@@ -25,7 +25,7 @@ EXPORTS = (
     "cc_plan_create", "cc_plan_destroy", "cc_plan_workspace_bytes", "cc_plan_residual",
     "cc_plan_step", "cc_plan_scalars", "cc_residual", "cc_energy", "cc_iterate", "cc_gemm",
     "cc_permute", "cc_plan_describe", "cc_plan_describe_dry", "cc_plan_flops", "cc_plan_profile",
-    "cc_plan_profile_table", "cc_plan_autotune", "cc_plan_set_precision", "cc_plan_set_correction", "cc_gemm_tile_count", "cc_gemm_tile_count_c128", "cc_plan_create_ops", "cc_plan_describe_ops_dry", "cc_plan_set_triples", "cc_plan_create2", "cc_batch_create",
+    "cc_plan_profile_table", "cc_plan_autotune", "cc_plan_set_precision", "cc_plan_set_correction", "cc_gemm_tile_count", "cc_gemm_tile_count_c128", "cc_gemm_noalloc", "cc_plan_create_ops", "cc_plan_describe_ops_dry", "cc_plan_set_triples", "cc_plan_create2", "cc_batch_create",
     "cc_batch_destroy", "cc_batch_step", "cc_batch_scalars", "cc_batch_autotune", "cc_batch_iterate",
     "cc_batch_profile", "cc_batch_profile_table", "cc_batch_flops", "cc_mlp_num_params",
     "cc_mlp_num_samples", "cc_mlp_features", "cc_mlp_targets", "cc_mlp_moments", "cc_mlp_forward",
@@ -106,6 +106,7 @@ def load() -> C.CDLL:
         "cc_plan_set_correction": (C.c_int, [vp, C.c_int, C.c_int]),
         "cc_gemm_tile_count": (C.c_int, [C.c_int]),
         "cc_gemm_tile_count_c128": (C.c_int, []),
+        "cc_gemm_noalloc": (C.c_int, [vp, C.c_int, i64, i64, i64, dbl, vp, i64, i64, vp, i64, i64, dbl, vp, i64]),
         "cc_plan_create_ops": (C.c_int, [vp, P(CCSystemStruct), C.c_int, C.c_int, C.c_char_p, P(vp)]),
         "cc_plan_describe_ops_dry": (C.c_char_p, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_char_p]),
         "cc_plan_set_triples": (C.c_int, [vp, vp, vp]),

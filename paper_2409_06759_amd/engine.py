@@ -253,6 +253,19 @@ def gemm(ctx, A, B, Cm, alpha=1.0, beta=0.0, a_kcontig=True, b_kcontig=True, pre
                               beta, _ptr(Cm), N))
 
 
+def gemm_noalloc(ctx, A, B, Cm, alpha=1.0, beta=0.0, a_kcontig=True, b_kcontig=True):
+    """gemm() in FP64 through the entry point that allocates nothing (split-K
+    partial sums in the library's static device buffer); enqueued only."""
+    M, N = Cm.shape
+    K = A.shape[1] if a_kcontig else A.shape[0]
+    sam, sak = (K, 1) if a_kcontig else (1, M)
+    sbn, sbk = (K, 1) if b_kcontig else (1, N)
+    scalar = L.CC_C128 if Cm.dtype == torch.complex128 else L.CC_R64
+    ctx.enter()
+    ctx.check(ctx.lib.cc_gemm_noalloc(ctx.h, scalar, M, N, K, alpha, _ptr(A), sam, sak, _ptr(B), sbn, sbk,
+                                      beta, _ptr(Cm), N))
+
+
 def gemm_tile_count(ctx, prec=F64, cplx=False) -> int:
     """Number of GEMM tile configurations of a precision, or of the complex
     GEMM (for forced-tile sweeps through the CC_GEMM_TILE environment variable)."""

@@ -77,3 +77,42 @@ def test_c3_zero_imaginary_equals_real_path(E, ctx):
     print(f"max |R_complex - R_real| = {err:.3e} (|R| {scale:.3e}), norms {zn:.12e} {rn:.12e}", flush=True)
     assert err < 1e-13 * max(1.0, scale)
     assert abs(zn - rn) < 1e-12 * rn
+
+
+def test_c3_complex_residual_matches_oracle_sample(E, ctx):
+    """R1, R2, the norm and the energy at seeded random complex amplitudes
+    (genuinely complex, every term of the residual contributing), against
+    the oracle's values stored by tests/golden/make_reference.py c3, after
+    the autotuner has picked the launch configurations the benchmark times."""
+    import json
+    import pathlib
+
+    from ccinputs.synth import random_amplitudes
+    g = json.loads((pathlib.Path(__file__).parent / "golden" / f"c3_complex_o{O}_v{V}_sample.json").read_text())
+    print(f"complex CCSD o={O} v={V}: residual against the oracle sample", flush=True)
+    s = make_system(O, V, is_complex=True)
+    assert complex(*g["fingerprint"]["vvvv_0123"]) == s.block("vvvv")[0, 1, 2, 3]
+    t1, t2 = random_amplitudes(O, V, g["amp_seed"], g["amp_scale"], is_complex=True)
+    assert abs(np.abs(t2).sum() - g["fingerprint"]["t2_sum_abs"]) <= 1e-12 * g["fingerprint"]["t2_sum_abs"]
+    d = E.DeviceSystem(s, drop_host=True)
+    T1, T2 = torch.from_numpy(t1).cuda(), torch.from_numpy(t2).cuda()
+    del t2
+    with E.Plan(ctx, d, E.CCSD) as plan:
+        plan.autotune(T1, T2, 1)
+        r1, r2, rn = plan.residual(T1, T2)
+        _, er, ei = plan.scalars()
+    i2 = torch.tensor(g["r2_index"], device="cuda")
+    i1 = torch.tensor(g["r1_index"], device="cuda")
+    got2 = r2.reshape(-1)[i2].cpu().numpy()
+    got1 = r1.reshape(-1)[i1].cpu().numpy()
+    want2 = np.array([complex(*z) for z in g["r2"]])
+    want1 = np.array([complex(*z) for z in g["r1"]])
+    e2 = np.abs(got2 - want2).max() / g["r2_max_abs"]
+    e1 = np.abs(got1 - want1).max() / g["r1_max_abs"]
+    ew = complex(*g["energy"])
+    print(f"max |dR2|/max|R2| {e2:.2e}, |dR1|/max|R1| {e1:.2e}, norm {rn:.15e} vs {g['rnorm']:.15e}, "
+          f"E {er:.15f}{ei:+.3e}i vs {ew:.15f}", flush=True)
+    assert np.abs(want2.imag).max() > 0.1 * np.abs(want2.real).max()  # genuinely complex
+    assert e2 < 1e-12 and e1 < 1e-12
+    assert abs(rn - g["rnorm"]) < 1e-12 * g["rnorm"]
+    assert abs(complex(er, ei) - ew) < 1e-12 * max(1.0, abs(ew))

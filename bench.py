@@ -245,64 +245,97 @@ def bench_ccsdt(ctx, E, torch, o=10, v=40, steps=3):
     return res
 
 
-def bench_complex(ctx, E, torch, steps, warmup, o=40, v=200):
-    """Complex128 Hermitian system: FP64 complex MFMA contraction steps."""
+def bench_complex(ctx, E, torch, steps, warmup, o=40, v=200, precs=("f64", "f32", "bf16x3")):
+    """Complex128 Hermitian system: step time and ladder rate per contraction
+    precision (FP64: complex MFMA GEMMs; FP32 / split bf16: real GEMMs of
+    M x 2N x 2K on realified operands)."""
     from ccinputs.synth import make_system
     t0 = time.time()
     d = E.DeviceSystem(make_system(o, v, is_complex=True), drop_host=True)
     log(f"[bench] complex o={o} v={v} resident ({time.time() - t0:.1f}s)")
-    with E.Plan(ctx, d, E.CCSD) as plan:
-        t1, t2 = E.zeros_amps(d, E.CCSD)
-        plan.step(t1, t2, 0.0, True)
-        torch.cuda.synchronize()
-        plan.autotune(t1, t2, 1)
-        for _ in range(warmup):
+    res = {"o": o, "v": v}
+    for pname in precs:
+        with E.Plan(ctx, d, E.CCSD, prec=E.PRECS[pname]) as plan:
+            t1, t2 = E.zeros_amps(d, E.CCSD)
             plan.step(t1, t2, 0.0, True)
-        plan.profile(True)
-        torch.cuda.synchronize()
-        ts = time.perf_counter()
-        for _ in range(steps):
-            plan.step(t1, t2, 0.0, True)
-        torch.cuda.synchronize()
-        el = (time.perf_counter() - ts) / steps
-        rows = plan.profile_table()
-        plan.profile(False)
-        lad = [r for r in rows if r[1] == "GEMM" and r[2].startswith("ladder@")]
-        lad_ms = lad[0][5]
-        lf = plan.flops(ladder_only=True)
-        rn, e, _ = plan.scalars()
-        res = {"o": o, "v": v, "ms_per_step": round(el * 1e3, 2), "tflops": round(plan.flops() / el / 1e12, 3),
-               "flops_per_step": plan.flops(), "ladder_ms": round(lad_ms, 3),
-               "ladder_tflops": round(lf / (lad_ms / 1e3) / 1e12, 3),
-               "ladder_frac_fp64_peak": round(lf / (lad_ms / 1e3) / 1e12 / PEAK_FP64_TFLOPS, 4),
-               "steps": steps, "rnorm_last": rn}
-    log(f"[bench] complex: {res}")
+            torch.cuda.synchronize()
+            plan.autotune(t1, t2, 1)
+            for _ in range(warmup):
+                plan.step(t1, t2, 0.0, True)
+            plan.profile(True)
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            for _ in range(steps):
+                plan.step(t1, t2, 0.0, True)
+            torch.cuda.synchronize()
+            el = (time.perf_counter() - ts) / steps
+            rows = plan.profile_table()
+            plan.profile(False)
+            lad = [r for r in rows if r[1] == "GEMM" and r[2].startswith("ladder@")]
+            lad_ms = lad[0][5]
+            lf = plan.flops(ladder_only=True)
+            rn, e, _ = plan.scalars()
+            r = {"ms_per_step": round(el * 1e3, 2), "tflops": round(plan.flops() / el / 1e12, 3),
+                 "flops_per_step": plan.flops(), "ladder_ms": round(lad_ms, 3),
+                 "ladder_tflops": round(lf / (lad_ms / 1e3) / 1e12, 3),
+                 "ladder_frac_peak": round(lf / (lad_ms / 1e3) / 1e12 / PEAKS[pname], 4), "steps": steps,
+                 "rnorm_last": rn}
+            if pname == "f64":
+                res.update(r)
+                res["ladder_frac_fp64_peak"] = r["ladder_frac_peak"]
+            else:
+                res[pname] = r
+        log(f"[bench] complex {pname}: {r}")
     return res
 
 
+def bench_complex_converge(ctx, E, torch, o=40, v=200, precs=("f64", "bf16x3", "f32")):
+    """Complex o=40 v=200 to ||R|| < 1e-8 (dressed Jacobi from t = 0): FP64,
+    and reduced-precision contractions with FP64 refinement (minutes)."""
+    from ccinputs.synth import make_system
+    d = E.DeviceSystem(make_system(o, v, is_complex=True), drop_host=True)
+    out = {"o": o, "v": v}
+    os.environ.setdefault("CC_ITERATE_PROGRESS", "50")
+    for pname in precs:
+        t1, t2 = E.zeros_amps(d, E.CCSD)
+        r = E.iterate(ctx, d, E.CCSD, t1, t2, tol=1e-8, max_iter=1500, dressed=True, autotune=True,
+                      prec=E.PRECS[pname])
+        rec = {"converged": r["converged"], "iterations": r["iters"], "reduced_precision_iterations": r["lowp_iters"],
+               "seconds": round(r["seconds"], 3), "setup_seconds": round(r["setup_seconds"], 3),
+               "energy_re": r["energy"].real, "energy_im": r["energy"].imag, "rnorm": r["rnorm"]}
+        if "f64" in out:
+            rec["abs_err_vs_f64"] = abs(r["energy"] - complex(out["f64"]["energy_re"], out["f64"]["energy_im"]))
+            rec["speedup_vs_f64"] = round(out["f64"]["seconds"] / r["seconds"], 3)
+        out[pname] = rec
+        log(f"[bench] complex {pname} to 1e-8: {rec}")
+    return out
+
+
 def bench_learned(ctx, E, torch, dsys, f64_seconds, precs=("f64", "bf16x3")):
-    """Time to ||R|| < 1e-8 from the trained network's t2 guess (t1 = 0),
-    inference included, against the FP64 run from t = 0."""
-    import numpy as np
+    """Time to ||R|| < 1e-8 from the network's start (cc_iterate's MLP guess:
+    inference and the MP2 fallback check included) and from the MP2 start,
+    against the FP64 run from t = 0."""
     f = ROOT / "paper_2409_06759_amd" / "data" / "mlp_guess.npz"
     if not f.exists():
         return None
     mlp = E.MLP.load(ctx, str(f))
     out = {"params": str(f.relative_to(ROOT))}
     for pname in precs:
-        a1, a2 = E.zeros_amps(dsys, E.CCSD)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        mlp.guess(dsys, a1, a2)
-        torch.cuda.synchronize()
-        t_inf = time.perf_counter() - t0
-        r = E.iterate(ctx, dsys, E.CCSD, a1, a2, tol=1e-8, max_iter=1500, dressed=True, autotune=True,
-                      prec=E.PRECS[pname])
-        tot = r["seconds"] + t_inf
-        out[pname] = {"converged": r["converged"], "iterations": r["iters"], "seconds": round(tot, 3),
-                      "inference_seconds": round(t_inf, 4), "energy": r["energy"],
-                      "speedup_vs_f64": round(f64_seconds / tot, 3) if f64_seconds else None}
-        log(f"[bench] learned guess + {pname}: {r['iters']} iterations, {tot:.2f}s (inference {t_inf * 1e3:.1f} ms)")
+        rec = {}
+        for start in ("mlp", "mp2"):
+            a1, a2 = E.zeros_amps(dsys, E.CCSD)
+            r = E.iterate(ctx, dsys, E.CCSD, a1, a2, tol=1e-8, max_iter=1500, dressed=True, autotune=True,
+                          prec=E.PRECS[pname], guess=start, mlp=mlp if start == "mlp" else None)
+            rec[start] = {"converged": r["converged"], "iterations": r["iters"], "seconds": round(r["seconds"], 3),
+                          "guess_seconds": round(r["guess_seconds"], 4), "guess_used": r["guess_used"],
+                          "energy": r["energy"],
+                          "speedup_vs_f64_from_zero": round(f64_seconds / r["seconds"], 3) if f64_seconds else None}
+            if start == "mlp":
+                rec["guess_rnorm"] = r["guess_rnorm"]
+            log(f"[bench] {start} start + {pname}: {r['iters']} iterations, {r['seconds']:.2f}s "
+                f"(guess {r['guess_seconds'] * 1e3:.1f} ms, used {r['guess_used']})")
+        rec["speedup_mlp_vs_mp2"] = round(rec["mp2"]["seconds"] / rec["mlp"]["seconds"], 3)
+        out[pname] = rec
     return out
 
 
@@ -327,7 +360,11 @@ def main():
                          "systems), learned (time to 1e-8 from the trained network's guess), share (the "
                          "one-GPU share of an 8-GPU ladder), generated (the residual from the diagram "
                          "generator's contraction list), ccsdt (CCSDT o=10 v=40 from the generated list), complex "
-                         "(complex128 o=40 v=200); 'none' for no extras")
+                         "(complex128 o=40 v=200 steps per precision), complex_converge (the same system to "
+                         "1e-8 per precision; minutes, not in the default list); 'none' for no extras")
+    ap.add_argument("--packed", action="store_true",
+                    help="time the plan whose ladder, hole-hole ladder and Z run over packed pairs (profiling; "
+                         "the flop counts are then the packed ones)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB copy (for HBM counter scaling)")
     args = ap.parse_args()
@@ -350,7 +387,7 @@ def main():
     ctx = E.Context(0)
     torch.cuda.synchronize()
     t_setup = time.perf_counter()
-    plan = E.Plan(ctx, dsys, m)
+    plan = E.Plan(ctx, dsys, m, packed=args.packed)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t_setup
     flops = plan.flops()
@@ -441,6 +478,10 @@ def main():
             plan.close()
             plan_closed = True
             extras["complex"] = bench_complex(ctx, E, torch, 3, 1)
+        elif name == "complex_converge":
+            plan.close()
+            plan_closed = True
+            extras["complex_converge"] = bench_complex_converge(ctx, E, torch)
         else:
             raise SystemExit(f"unknown extra workload {name}")
 
@@ -464,6 +505,7 @@ def main():
         "config": {"workload": f"{method} o={o} v={v} fp64 real, seeded antisymmetrised <pq||rs>~N(0,0.01^2), "
                                f"diagonal Fock", "o": o, "v": v, "method": method,
                    "update": ("dressed" if dressed else "bare") + f" Jacobi, shift {args.shift}",
+                   "pairs": "packed" if args.packed else "dense",
                    "flops_per_step": flops},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3) if achieved else None,
                      "peak": round(PEAKS[args.prec], 1), "unit": "TFLOP/s",

@@ -82,6 +82,19 @@ typedef struct {
   void *t2;
 } cc_amps;
 
+/* Standardisation of the amplitude-guess network's features (see the
+ * learned initial amplitudes below). */
+typedef struct {
+  double sx, mD, sD, me, se, st;
+} cc_mlp_stats;
+
+/* Starting amplitudes of cc_iterate. */
+typedef enum {
+  CC_GUESS_GIVEN = 0, /* the amplitudes in t_inout */
+  CC_GUESS_MP2 = 1,   /* one bare-denominator Jacobi step from t = 0: t2 = <ab||ij> / D_ij^ab, t1 = f_ai / D_i^a */
+  CC_GUESS_MLP = 2    /* the network's t2 (t1 = 0), or the MP2 amplitudes when their residual norm is smaller */
+} cc_guess;
+
 typedef struct {
   double tol;          /* stop when ||R(t_n)|| < tol (Frobenius norm over all stored R1, R2) */
   int32_t max_iter;    /* at most this many residual evaluations */
@@ -105,6 +118,11 @@ typedef struct {
                           reference is taken whenever ||R|| fell 1000-fold since the last one,
                           and convergence is confirmed by one plain FP64 step */
   int32_t packed;      /* 1: particle-particle ladder over packed pairs (see CC_PLAN_PACKED_LADDER) */
+  int32_t guess;       /* cc_guess: where the iteration starts (0 = t_inout as given); the guess is
+                          written to t_inout and its time is part of `seconds` */
+  int32_t mlp_prec;    /* CC_GUESS_MLP: CC_PREC_F64 or CC_PREC_F32 network layers */
+  const double *mlp_params;      /* CC_GUESS_MLP: device, cc_mlp_num_params() doubles */
+  const cc_mlp_stats *mlp_stats; /* CC_GUESS_MLP: host; real systems only (EUNSUPPORTED otherwise) */
 } cc_iter_opts;
 
 typedef struct {
@@ -119,6 +137,9 @@ typedef struct {
   double *hist_rnorm;  /* host arrays of capacity hist_cap, or NULL */
   double *hist_e;      /* E per iteration (real part) */
   int32_t hist_cap;
+  int32_t guess_used;  /* cc_guess of the start actually used (CC_GUESS_MLP may fall back to MP2) */
+  double guess_rnorm_mlp, guess_rnorm_mp2; /* CC_GUESS_MLP: ||R|| of the two candidate starts (FP64) */
+  double guess_seconds;/* time spent forming the start (included in seconds) */
 } cc_iter_report;
 
 /* ---- context ------------------------------------------------------------ */
@@ -218,7 +239,8 @@ int cc_energy(cc_ctx *ctx, const cc_system *sys, int method, const cc_amps *t, d
  * "Correctness: H2O and LiH" (energies compared at a residual-norm
  * threshold).  Starts from the amplitudes in t_inout (device, caller-owned;
  * zeros = the reference, whose first step yields the MP2 amplitudes), or
- * from the guess opts->guess selects.  Returns CC_OK, CC_ENOTCONV or
+ * from the guess opts->guess selects (MP2, or the network's t2 with the
+ * MP2 amplitudes as fallback: whichever has the smaller FP64 residual norm).  Returns CC_OK, CC_ENOTCONV or
  * CC_EDIVERGED; t_inout holds the last finite iterate, report (host, may be
  * NULL) the per-iteration history. */
 int cc_iterate(cc_ctx *ctx, const cc_system *sys, int method, const cc_iter_opts *opts,
@@ -229,8 +251,11 @@ int cc_iterate(cc_ctx *ctx, const cc_system *sys, int method, const cc_iter_opts
  * leading dimension ldc.  A(m,k) = A[m*sam + k*sak] with sam == 1 or sak == 1;
  * B(n,k) = B[n*sbn + k*sbk] with sbn == 1 or sbk == 1.  prec selects the
  * MFMA path (F64: FP64 MFMA; F32: FP32 MFMA on FP64 data rounded to FP32;
- * BF16X3: split-bf16 MFMA), scalar CC_C128 the complex path.  Accumulation is
- * FP64 for F64, FP32 otherwise.
+ * BF16X3: split-bf16 MFMA), scalar CC_C128 the complex path (F64: complex
+ * FP64 MFMA GEMM; F32 / BF16X3: the real GEMM of M x 2N x 2K on the realified
+ * operands A' = [Re A, Im A] and B' with rows [Re B, -Im B], [Im B, Re B],
+ * whose output is the interleaved complex C).  Accumulation is FP64 for F64,
+ * FP32 otherwise.
  * A real GEMM is split along K as a plan would split it (few output tiles,
  * long K; the factor refined for the tile's resident workgroups), and one
  * whose workgroups would end in a mostly empty last round runs as a main part
@@ -247,8 +272,9 @@ int cc_gemm(cc_ctx *ctx, int prec, int scalar, int64_t M, int64_t N, int64_t K, 
  * is set (tuning sweeps; for complex operands i indexes the complex GEMM's
  * own configurations), its own choice otherwise.  -1 for an unknown prec. */
 int cc_gemm_tile_count(int prec);
-/* Number of tile configurations of the complex (CC_C128) GEMM, which runs in
- * FP64 only; CC_GEMM_TILE=i selects configuration i of that set. */
+/* Number of tile configurations of the complex (CC_C128) FP64 GEMM;
+ * CC_GEMM_TILE=i selects configuration i of that set (reduced-precision
+ * complex GEMMs use the real configurations of their precision). */
 int cc_gemm_tile_count_c128(void);
 /* cc_gemm with FP64 arithmetic (real, or complex for scalar CC_C128) that
  * allocates nothing, for callers that cannot allocate device memory: code
@@ -284,7 +310,8 @@ int cc_permute(cc_ctx *ctx, int scalar, int rank, const int64_t *in_dims, const 
  * grouped launch over all systems; the whole iteration is replayed as one
  * HIP graph.  The amplitude buffers amps[b] are bound at creation (they are
  * updated in place by every step) and must stay valid until destruction.
- * The contraction precision is fixed at creation. */
+ * The contraction precision is fixed at creation; batches of complex
+ * systems take CC_PREC_F64 only (CC_EUNSUPPORTED otherwise). */
 int cc_batch_create(cc_ctx *ctx, int n, const cc_system *systems, int method, int prec, cc_amps *amps,
                     cc_batch **batch);
 int cc_batch_destroy(cc_batch *batch);
@@ -318,9 +345,6 @@ double cc_batch_flops(const cc_batch *batch);
  * Parameters: cc_mlp_num_params() doubles in device memory, in the order
  * W1[128][3], b1[128], W2[128][128], b2[128], W3[1][128], b3[1].
  * prec: CC_PREC_F64 or CC_PREC_F32 (the dense layers on FP32 MFMA). */
-typedef struct {
-  double sx, mD, sD, me, se, st;
-} cc_mlp_stats;
 int64_t cc_mlp_num_params(void);
 /* number of unique amplitudes, C(o,2) * C(v,2) */
 int64_t cc_mlp_num_samples(int o, int v);
@@ -372,7 +396,7 @@ int cc_plan_set_precision(cc_plan *plan, int prec);
  * FP64 steps (see cc_iter_opts.correction): mode 0 off; mode 1 takes a
  * reference at the next step's amplitudes and uses it from then on; prec
  * (CC_PREC_F32 or CC_PREC_BF16X3) is the precision of the correction
- * products.  Real systems only (EUNSUPPORTED for complex). */
+ * products (complex systems: realified products as in cc_gemm). */
 int cc_plan_set_correction(cc_plan *plan, int mode, int prec);
 /* Autotuner: times every instantiated GEMM tile configuration (of the
  * plan's current precision) for each distinct GEMM shape of the plan (reps launches each, on the plan's own

@@ -18,6 +18,7 @@ CC_OK, CC_EINVAL, CC_ENOMEM, CC_EDEVICE, CC_ENOTCONV, CC_EDIVERGED, CC_EUNSUPPOR
 CC_CCD, CC_CCSD = 0, 1
 CC_R64, CC_C128 = 0, 1
 CC_PREC_F64, CC_PREC_F32, CC_PREC_BF16X3 = 0, 1, 2
+CC_GUESS_GIVEN, CC_GUESS_MP2, CC_GUESS_MLP = 0, 1, 2
 
 # Every symbol declared in include/cc.h.
 EXPORTS = (
@@ -47,7 +48,9 @@ class CCIterOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("prec", C.c_int32),
                 ("level_shift", C.c_double), ("refine_tol", C.c_double), ("use_graph", C.c_int32),
                 ("check_every", C.c_int32), ("diverge_window", C.c_int32), ("dressed", C.c_int32),
-                ("autotune", C.c_int32), ("correction", C.c_int32), ("packed", C.c_int32)]
+                ("autotune", C.c_int32), ("correction", C.c_int32), ("packed", C.c_int32),
+                ("guess", C.c_int32), ("mlp_prec", C.c_int32), ("mlp_params", C.c_void_p),
+                ("mlp_stats", C.c_void_p)]
 
 
 class CCIterReport(C.Structure):
@@ -55,7 +58,8 @@ class CCIterReport(C.Structure):
                 ("e_re", C.c_double), ("e_im", C.c_double), ("seconds", C.c_double),
                 ("setup_seconds", C.c_double), ("lowp_iters", C.c_int32), ("corr_iters", C.c_int32),
                 ("hist_rnorm", C.POINTER(C.c_double)),
-                ("hist_e", C.POINTER(C.c_double)), ("hist_cap", C.c_int32)]
+                ("hist_e", C.POINTER(C.c_double)), ("hist_cap", C.c_int32), ("guess_used", C.c_int32),
+                ("guess_rnorm_mlp", C.c_double), ("guess_rnorm_mp2", C.c_double), ("guess_seconds", C.c_double)]
 
 
 class CCMlpStats(C.Structure):

@@ -1,6 +1,7 @@
 // C ABI of the engine: validation, error mapping and the Jacobi driver.
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <memory>
@@ -62,8 +63,6 @@ void validate_method(int method, int prec, int scalar) {
   if (method != CC_CCD && method != CC_CCSD) throw CCError(CC_EINVAL, "unknown method");
   if (prec != CC_PREC_F64 && prec != CC_PREC_F32 && prec != CC_PREC_BF16X3)
     throw CCError(CC_EINVAL, "unknown precision");
-  if (scalar == CC_C128 && prec != CC_PREC_F64)
-    throw CCError(CC_EUNSUPPORTED, "complex amplitudes support FP64 contractions only");
 }
 
 void validate_amps(const cc_amps *t, int method, const char *what) {
@@ -127,8 +126,87 @@ void run_step(cc_plan *p, bool use_graph) {
   CC_HIP_CHECK(hipGraphLaunch(p->graph, p->ctx->stream));
 }
 
+// Eager evaluation of the plan at (t1, t2) in FP64: a bare Jacobi update in
+// place (update) or only R and the scalars; the plan's per-call state is
+// restored afterwards.  Returns ||R(t)||.
+double eval_fp64(cc_plan *p, void *t1, void *t2, bool update) {
+  void *o1 = p->t1, *o2 = p->t2, *r1 = p->r1_out, *r2 = p->r2_out;
+  const bool ou = p->update;
+  const int od = p->dressed, op = p->cur_prec, om = p->delta_mode;
+  const double os = p->shift;
+  p->t1 = t1;
+  p->t2 = t2;
+  p->r1_out = p->r2_out = nullptr;
+  p->update = update;
+  p->dressed = 0;
+  p->shift = 0.0;
+  p->cur_prec = CC_PREC_F64;
+  p->delta_mode = 0;
+  double rn = NAN, er = NAN, ei = NAN;
+  try {
+    ccmi::plan_run(p);
+    read_scalars(p, &rn, &er, &ei);
+  } catch (...) {
+    p->t1 = o1; p->t2 = o2; p->r1_out = r1; p->r2_out = r2; p->update = ou;
+    p->dressed = od; p->shift = os; p->cur_prec = op; p->delta_mode = om;
+    throw;
+  }
+  p->t1 = o1; p->t2 = o2; p->r1_out = r1; p->r2_out = r2; p->update = ou;
+  p->dressed = od; p->shift = os; p->cur_prec = op; p->delta_mode = om;
+  return rn;
+}
+
+// The MP2 amplitudes: one bare-denominator Jacobi step from t = 0.
+void mp2_start(cc_plan *p, void *t1, void *t2) {
+  hipStream_t s = p->ctx->stream;
+  const size_t n1 = size_t(p->o) * p->v * p->esize, n2 = n1 * size_t(p->o) * p->v;
+  CC_HIP_CHECK(hipMemsetAsync(t2, 0, n2, s));
+  if (t1) CC_HIP_CHECK(hipMemsetAsync(t1, 0, n1, s));
+  (void)eval_fp64(p, t1, t2, true);
+}
+
+// Writes the start opts->guess selects into t; returns the cc_guess used.
+int form_guess(cc_ctx *ctx, const cc_system *sys, cc_plan *p, const cc_iter_opts *opts, cc_amps *t,
+               double *rn_mlp, double *rn_mp2) {
+  if (opts->guess == CC_GUESS_MP2) {
+    mp2_start(p, t->t1, t->t2);
+    return CC_GUESS_MP2;
+  }
+  cc_amps g{t->t1, t->t2};
+  const int st = cc_guess_mlp(ctx, sys, opts->mlp_prec, opts->mlp_params, opts->mlp_stats, &g);
+  if (st != CC_OK) throw CCError(st, ctx->last_error);
+  *rn_mlp = eval_fp64(p, t->t1, t->t2, false);
+  const size_t n1 = size_t(p->o) * p->v * p->esize, n2 = n1 * size_t(p->o) * p->v;
+  void *m1 = nullptr, *m2 = nullptr;
+  CC_HIP_CHECK(hipMalloc(&m2, n2));
+  if (t->t1 && hipMalloc(&m1, n1) != hipSuccess) {
+    (void)hipFree(m2);
+    throw CCError(CC_ENOMEM, "guess buffers");
+  }
+  int used = CC_GUESS_MLP;
+  try {
+    mp2_start(p, m1, m2);
+    *rn_mp2 = eval_fp64(p, m1, m2, false);
+    if (*rn_mp2 < *rn_mlp) {
+      CC_HIP_CHECK(hipMemcpyAsync(t->t2, m2, n2, hipMemcpyDeviceToDevice, p->ctx->stream));
+      if (t->t1) CC_HIP_CHECK(hipMemcpyAsync(t->t1, m1, n1, hipMemcpyDeviceToDevice, p->ctx->stream));
+      used = CC_GUESS_MP2;
+    }
+    CC_HIP_CHECK(hipStreamSynchronize(p->ctx->stream));
+  } catch (...) {
+    (void)hipStreamSynchronize(p->ctx->stream);
+    (void)hipFree(m2);
+    if (m1) (void)hipFree(m1);
+    throw;
+  }
+  (void)hipFree(m2);
+  if (m1) (void)hipFree(m1);
+  return used;
+}
+
 cc_plan *make_plan(cc_ctx *ctx, const cc_system *sys, int method, int prec,
-                   std::shared_ptr<ccmi::OpList> custom = nullptr, bool packed = false, bool lowp_all = false) {
+                   std::shared_ptr<ccmi::OpList> custom = nullptr, bool packed = false, bool lowp_all = false,
+                   bool private_work = false) {
   validate_system(sys);
   validate_method(method, prec, sys->scalar);
   set_device(ctx);
@@ -136,6 +214,7 @@ cc_plan *make_plan(cc_ctx *ctx, const cc_system *sys, int method, int prec,
   p->custom = std::move(custom);
   p->packed = packed;
   p->lowp_all = lowp_all;
+  p->private_work = private_work;
   p->ctx = ctx;
   p->o = sys->o;
   p->v = sys->v;
@@ -157,8 +236,9 @@ cc_plan *make_plan(cc_ctx *ctx, const cc_system *sys, int method, int prec,
 }  // namespace
 
 namespace ccmi {
-cc_plan *make_plan_checked(cc_ctx *ctx, const cc_system *sys, int method, int prec, bool lowp_all) {
-  return make_plan(ctx, sys, method, prec, nullptr, false, lowp_all);
+cc_plan *make_plan_checked(cc_ctx *ctx, const cc_system *sys, int method, int prec, bool lowp_all,
+                           bool private_work) {
+  return make_plan(ctx, sys, method, prec, nullptr, false, lowp_all, private_work);
 }
 void check_amps(const cc_amps *t, int method) { validate_amps(t, method, "t"); }
 }  // namespace ccmi
@@ -376,6 +456,11 @@ int cc_iterate(cc_ctx *ctx, const cc_system *sys, int method, const cc_iter_opts
     if (opts->max_iter < 1) throw CCError(CC_EINVAL, "max_iter must be >= 1");
     if (!(opts->tol > 0.0)) throw CCError(CC_EINVAL, "tol must be > 0");
     if (!(opts->level_shift >= 0.0)) throw CCError(CC_EINVAL, "level_shift must be >= 0");
+    if (opts->guess < CC_GUESS_GIVEN || opts->guess > CC_GUESS_MLP) throw CCError(CC_EINVAL, "unknown guess");
+    if (opts->guess == CC_GUESS_MLP) {
+      if (!opts->mlp_params || !opts->mlp_stats) throw CCError(CC_EINVAL, "MLP guess needs parameters and stats");
+      if (sys && sys->scalar != CC_R64) throw CCError(CC_EUNSUPPORTED, "the amplitude-guess network is real-valued");
+    }
     validate_amps(t, method, "t");
     const auto t0 = std::chrono::steady_clock::now();
     cc_plan *p = make_plan(ctx, sys, method, opts->prec, nullptr, opts->packed != 0);
@@ -388,10 +473,14 @@ int cc_iterate(cc_ctx *ctx, const cc_system *sys, int method, const cc_iter_opts
     int corr_iters = 0;
     double ref_rn = INFINITY;   // norm at the last reference (correction form)
     bool confirming = false;    // the next step is the plain FP64 confirmation
-    const bool use_corr = opts->correction != 0 && opts->prec != CC_PREC_F64 && !p->cplx &&
-                          !p->deltas.empty();
+    const bool use_corr = opts->correction != 0 && opts->prec != CC_PREC_F64 && !p->deltas.empty();
     if (use_corr) p->delta_prec = opts->prec;
     std::chrono::steady_clock::time_point t1c;
+    int guess_used = CC_GUESS_GIVEN;
+    double g_mlp = NAN, g_mp2 = NAN, guess_s = 0.0;
+    // CC_ITERATE_PROGRESS=n: one line on stderr every n iterations (long runs)
+    const char *pv = std::getenv("CC_ITERATE_PROGRESS");
+    const int progress = pv ? std::atoi(pv) : 0;
     try {
       p->t1 = t->t1;
       p->t2 = t->t2;
@@ -409,6 +498,10 @@ int cc_iterate(cc_ctx *ctx, const cc_system *sys, int method, const cc_iter_opts
       ccmi::plan_prepare(p);
       CC_HIP_CHECK(hipStreamSynchronize(p->ctx->stream));
       t1c = std::chrono::steady_clock::now();
+      if (opts->guess != CC_GUESS_GIVEN) {
+        guess_used = form_guess(ctx, sys, p, opts, t, &g_mlp, &g_mp2);
+        guess_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t1c).count();
+      }
       // Steps are launched in batches of check_every; each step's three
       // scalars are copied to pinned memory asynchronously and the batch is
       // examined after one synchronisation.  Decisions taken while examining
@@ -448,6 +541,9 @@ int cc_iterate(cc_ctx *ctx, const cc_system *sys, int method, const cc_iter_opts
             } else if (mode_now == 1 && rn < 1e-3 * ref_rn && p->delta_mode == 1) {
               p->delta_mode = 2;  // refresh the reference at the next step
             }
+            if (progress > 0 && iters % progress == 0)
+              std::fprintf(stderr, "cc_iterate: iteration %d ||R|| %.6e E %.12f%s\n", iters, rn, er,
+                           prec_now != CC_PREC_F64 ? " (reduced precision)" : mode_now ? " (corrected)" : "");
             if (rep && rep->hist_rnorm && it < rep->hist_cap) rep->hist_rnorm[it] = rn;
             if (rep && rep->hist_e && it < rep->hist_cap) rep->hist_e[it] = er;
             if (!std::isfinite(rn) || !std::isfinite(er)) {
@@ -515,6 +611,10 @@ int cc_iterate(cc_ctx *ctx, const cc_system *sys, int method, const cc_iter_opts
       rep->lowp_iters = switched_at < 0 ? (opts->prec == CC_PREC_F64 ? 0 : iters) : switched_at;
       rep->corr_iters = corr_iters;
       rep->setup_seconds = std::chrono::duration<double>(t1c - t0).count();
+      rep->guess_used = guess_used;
+      rep->guess_rnorm_mlp = g_mlp;
+      rep->guess_rnorm_mp2 = g_mp2;
+      rep->guess_seconds = guess_s;
     }
     cc_plan_destroy(p);
     if (status == CC_ENOTCONV) ctx->last_error = "max_iter reached before tolerance";
@@ -539,8 +639,8 @@ int cc_gemm(cc_ctx *ctx, int prec, int scalar, int64_t M, int64_t N, int64_t K, 
     if (!(sam == 1 || sak == 1) || !(sbn == 1 || sbk == 1))
       throw CCError(CC_EINVAL, "each operand needs one unit stride");
     if (ldc < N) throw CCError(CC_EINVAL, "ldc < N");
-    if (scalar == CC_C128 && prec != CC_PREC_F64)
-      throw CCError(CC_EUNSUPPORTED, "complex GEMM is FP64 only");
+    if (prec != CC_PREC_F64 && prec != CC_PREC_F32 && prec != CC_PREC_BF16X3)
+      throw CCError(CC_EINVAL, "unknown precision");
     set_device(ctx);
     ccmi::GemmDesc d{M, N, K, A, sam, sak, B, sbn, sbk, C, ldc, alpha, beta};
     const char *tv = std::getenv("CC_GEMM_TILE");  // tuning sweeps: force one tile configuration
@@ -577,6 +677,43 @@ int cc_gemm(cc_ctx *ctx, int prec, int scalar, int64_t M, int64_t N, int64_t K, 
         with_ws(tail_need);
       }
     };
+    if (scalar == CC_C128 && prec != CC_PREC_F64) {
+      // the real reduced-precision GEMM of M x 2N x 2K on realified copies
+      // of the operands (A' M x 2K, B' 2N x 2K; 4 bytes per real element)
+      if (K == 0) {
+        ccmi::gemm_c128(d, ctx->stream, tile);
+        CC_HIP_CHECK(hipStreamSynchronize(ctx->stream));
+        return CC_OK;
+      }
+      void *sa = nullptr, *sb = nullptr;
+      CC_HIP_CHECK(hipMalloc(&sa, size_t(2 * M * K) * 4));
+      if (hipMalloc(&sb, size_t(4 * N * K) * 4) != hipSuccess) {
+        (void)hipFree(sa);
+        throw CCError(CC_ENOMEM, "GEMM operand copy allocation failed");
+      }
+      ccmi::realify_complex(prec, 0, static_cast<const double *>(A), nullptr, M, K, sam, sak, sa, ctx->stream);
+      ccmi::realify_complex(prec, 1, static_cast<const double *>(B), nullptr, N, K, sbn, sbk, sb, ctx->stream);
+      ccmi::GemmDesc g = ccmi::realified_desc(d, sa, sb);
+      g.ws_elems = 0;
+      g.split = ws_ok ? ccmi::gemm_split_pick(g.M, g.N, g.K, -1) : 1;
+      if (g.split > 1) {
+        if (with_ws(std::max<int64_t>(int64_t(g.split) * g.M * g.N, ccmi::gemm_tail_ws_bound(g.M, g.N, g.K)))) {
+          g.ws = d.ws;
+          g.ws_elems = d.ws_elems;
+        } else {
+          g.split = 1;
+        }
+      } else if (with_ws(ccmi::gemm_lowp_tail_ws(g, prec, tile))) {
+        g.ws = d.ws;
+        g.ws_elems = d.ws_elems;
+      }
+      ccmi::gemm_lowp(g, prec, ctx->stream, tile);
+      const hipError_t e = hipStreamSynchronize(ctx->stream);
+      (void)hipFree(sa);
+      (void)hipFree(sb);
+      CC_HIP_CHECK(e);
+      return CC_OK;
+    }
     if (scalar == CC_C128) ccmi::gemm_c128(d, ctx->stream, tile);
     else if (prec == CC_PREC_F64) {
       plan_ws(ccmi::gemm_f64_tail_ws(d, tile));
@@ -727,7 +864,6 @@ int cc_plan_set_correction(cc_plan *p, int mode, int prec) {
     if (mode != 0 && mode != 1) throw CCError(CC_EINVAL, "mode must be 0 or 1");
     if (prec != CC_PREC_F32 && prec != CC_PREC_BF16X3)
       throw CCError(CC_EINVAL, "correction precision must be F32 or BF16X3");
-    if (p->cplx) throw CCError(CC_EUNSUPPORTED, "correction form is real-only");
     p->delta_prec = prec;
     p->delta_mode = mode ? 2 : 0;
     return CC_OK;

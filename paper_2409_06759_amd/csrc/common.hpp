@@ -80,6 +80,16 @@ void convert_shadow(int prec, const double *src, int64_t n, void *dst, hipStream
 // dst = reduced-precision (a - ref), same layout as convert_shadow.
 void convert_delta(int prec, const double *a, const double *ref, int64_t n, void *dst, hipStream_t s);
 void copy_f64(double *dst, const double *src, int64_t n, hipStream_t s);
+// Complex operands of a reduced-precision complex GEMM as real ones: side 0
+// writes A' = [Re A(r,k), Im A(r,k)] (R x 2K), side 1 writes B' (2R x 2K)
+// with rows [Re B, -Im B] and [Im B, Re B], from the complex tensor src
+// (element (r,k) at r*sr + k*sk) minus ref (or NULL) at the same indexing;
+// dense rows of 2K, FP32 or a bf16 hi plane followed by a lo plane.
+void realify_complex(int prec, int side, const double *src, const double *ref, int64_t R, int64_t K, int64_t sr,
+                     int64_t sk, void *dst, hipStream_t s);
+// The real reduced-precision GEMM (M x 2N x 2K) on realified operands that
+// computes the complex GEMM d in its interleaved output layout.
+GemmDesc realified_desc(const GemmDesc &d, const void *a_form, const void *b_form);
 // C = beta C + P with P dense M x N and C of leading dimension ldc.
 void add_product(double *C, int64_t ldc, double beta, const double *P, int64_t M, int64_t N, hipStream_t s);
 

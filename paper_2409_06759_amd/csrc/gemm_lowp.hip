@@ -881,7 +881,104 @@ __global__ __launch_bounds__(256) void add_product_kernel(double *__restrict__ C
 
 int64_t ew_blocks(int64_t n) { return std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 65536)); }
 
+// ---- complex operands as real ones -----------------------------------------
+// A complex product C(m,n) = sum_k A(m,k) B(n,k) is the real product of
+//   A' (M x 2K):  A'[m][2k] = Re A(m,k),   A'[m][2k+1] = Im A(m,k)
+//   B' (2N x 2K): B'[2n][2k]   = Re B(n,k), B'[2n][2k+1]   = -Im B(n,k)
+//                 B'[2n+1][2k] = Im B(n,k), B'[2n+1][2k+1] =  Re B(n,k)
+// since sum_k' A'(m,k') B'(2n+c,k') is the real (c = 0) or imaginary (c = 1)
+// part of C(m,n): exactly the interleaved layout of complex C, read as a real
+// M x 2N matrix.  The reduced-precision copies hold A', B' dense (rows of
+// 2K), rounded as convert_shadow rounds, optionally of X - X_ref.
+// Each value goes to dst (FP32) or to the bf16 hi plane at dst and the lo
+// plane `plane` elements further.
+template <int MODE>
+__device__ __forceinline__ void put_lp(void *dst, int64_t plane, int64_t i, double x) {
+  const float f = static_cast<float>(x);
+  if constexpr (MODE == PREC_F32) {
+    static_cast<float *>(dst)[i] = f;
+  } else {
+    unsigned short *hi = static_cast<unsigned short *>(dst);
+    const unsigned short h = bf16_bits(f);
+    hi[i] = h;
+    hi[plane + i] = bf16_bits(f - bf16_to_float(h));
+  }
+}
+
+// one thread per complex element (r, k), k fastest; SIDE 0 writes A', 1 B'
+template <int MODE, int SIDE, bool REF>
+__global__ __launch_bounds__(256) void realify_kernel(const double2 *__restrict__ src, const double2 *__restrict__ ref,
+                                                      int64_t R, int64_t K, int64_t sr, int64_t sk, void *dst) {
+  const int64_t total = R * K;
+  const int64_t plane = (SIDE == 0 ? 2 : 4) * total;
+  for (int64_t e = blockIdx.x * int64_t(256) + threadIdx.x; e < total; e += int64_t(gridDim.x) * 256) {
+    const int64_t r = e / K, k = e - r * K;
+    const int64_t q = r * sr + k * sk;
+    double re = src[q].x, im = src[q].y;
+    if constexpr (REF) {
+      re -= ref[q].x;
+      im -= ref[q].y;
+    }
+    if constexpr (SIDE == 0) {
+      const int64_t o = r * 2 * K + 2 * k;
+      put_lp<MODE>(dst, plane, o, re);
+      put_lp<MODE>(dst, plane, o + 1, im);
+    } else {
+      const int64_t o0 = (2 * r) * 2 * K + 2 * k, o1 = o0 + 2 * K;
+      put_lp<MODE>(dst, plane, o0, re);
+      put_lp<MODE>(dst, plane, o0 + 1, -im);
+      put_lp<MODE>(dst, plane, o1, im);
+      put_lp<MODE>(dst, plane, o1 + 1, re);
+    }
+  }
+}
+
+template <int MODE, int SIDE>
+void realify_launch(const double *src, const double *ref, int64_t R, int64_t K, int64_t sr, int64_t sk, void *dst,
+                    hipStream_t s) {
+  const auto *a = reinterpret_cast<const double2 *>(src);
+  const auto *b = reinterpret_cast<const double2 *>(ref);
+  if (ref)
+    hipLaunchKernelGGL((realify_kernel<MODE, SIDE, true>), dim3(ew_blocks(R * K)), dim3(256), 0, s, a, b, R, K, sr,
+                       sk, dst);
+  else
+    hipLaunchKernelGGL((realify_kernel<MODE, SIDE, false>), dim3(ew_blocks(R * K)), dim3(256), 0, s, a, b, R, K, sr,
+                       sk, dst);
+}
+
 }  // namespace
+
+void realify_complex(int prec, int side, const double *src, const double *ref, int64_t R, int64_t K, int64_t sr,
+                     int64_t sk, void *dst, hipStream_t s) {
+  if (R <= 0 || K <= 0) return;
+  CC_REQUIRE(prec == PREC_F32 || prec == PREC_BF16X3, -1, "realify: precision");
+  if (prec == PREC_F32) {
+    if (side == 0) realify_launch<PREC_F32, 0>(src, ref, R, K, sr, sk, dst, s);
+    else realify_launch<PREC_F32, 1>(src, ref, R, K, sr, sk, dst, s);
+  } else {
+    if (side == 0) realify_launch<PREC_BF16X3, 0>(src, ref, R, K, sr, sk, dst, s);
+    else realify_launch<PREC_BF16X3, 1>(src, ref, R, K, sr, sk, dst, s);
+  }
+  CC_HIP_CHECK(hipGetLastError());
+}
+
+GemmDesc realified_desc(const GemmDesc &d, const void *a_form, const void *b_form) {
+  GemmDesc g = d;
+  g.N = 2 * d.N;
+  g.K = 2 * d.K;
+  g.A = a_form;
+  g.sam = 2 * d.K;
+  g.sak = 1;
+  g.B = b_form;
+  g.sbn = 2 * d.K;
+  g.sbk = 1;
+  g.ldc = 2 * d.ldc;
+  g.a_plane = 2 * d.M * d.K;
+  g.b_plane = 4 * d.N * d.K;
+  g.lp_in = 1;
+  g.ws_elems = 2 * d.ws_elems;  // complex elements of the workspace, as doubles
+  return g;
+}
 
 void convert_delta(int prec, const double *a, const double *ref, int64_t n, void *dst, hipStream_t s) {
   if (n <= 0) return;

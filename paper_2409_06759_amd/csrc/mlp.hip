@@ -252,6 +252,109 @@ __global__ __launch_bounds__(256) void moments_kernel(const double *__restrict__
 
 int64_t grid_of(int64_t n) { return std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096)); }
 
+// ---- fused FP32 forward (inference) ----------------------------------------
+// f[u] = (g(z_u) - g(z~_u)) / 2 without writing activations anywhere: one
+// wave takes 16 samples at a time as two 16-row blocks (the + branch and the
+// branch with z0 negated) against all 128 hidden units.  Layer 1 is formed in
+// registers directly in the MFMA operand layout, layer 2 runs on
+// v_mfma_f32_16x16x4_f32 with W2 (rounded to FP32) staged once per workgroup
+// in LDS, and bias, ReLU and the 128 -> 1 layer are applied to the
+// accumulators, summed over the 16 lanes that share output rows.
+//   MFMA 16x16x4 operands: lane l = 16 q + r supplies A[row r][k q] and
+//   B[k q][col r] and holds D[4 q + t][r], t = 0..3.  Step s of chunk c uses
+//   hidden unit k = 16 c + 4 q + s for lane group q (a permutation of the
+//   128 units, the same on both operands).
+typedef float f4v __attribute__((ext_vector_type(4)));
+constexpr int FW_WAVES = 4;
+constexpr int W2_LD = HID + 4;  // padded LDS row: the 16 lanes of a read phase hit distinct banks
+
+__global__ __launch_bounds__(FW_WAVES * 64) void mlp_forward_fused_kernel(const double *__restrict__ P,
+                                                                          const double *__restrict__ z, int64_t n,
+                                                                          double *__restrict__ f) {
+  __shared__ __attribute__((aligned(16))) float sW2[HID * W2_LD];
+  __shared__ __attribute__((aligned(16))) float sW1[HID * 4];  // (w1 x, w1 y, w1 z, b1) per hidden unit
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int e = tid; e < HID * HID; e += FW_WAVES * 64) sW2[(e / HID) * W2_LD + e % HID] = float(P[OFF_W2 + e]);
+  for (int k = tid; k < HID; k += FW_WAVES * 64) {
+    sW1[4 * k] = float(P[OFF_W1 + 3 * k]);
+    sW1[4 * k + 1] = float(P[OFF_W1 + 3 * k + 1]);
+    sW1[4 * k + 2] = float(P[OFF_W1 + 3 * k + 2]);
+    sW1[4 * k + 3] = float(P[OFF_B1 + k]);
+  }
+  __syncthreads();
+  const int r = lane & 15, q = lane >> 4;
+  float b2r[8], w3r[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    b2r[j] = float(P[OFF_B2 + 16 * j + r]);
+    w3r[j] = float(P[OFF_W3 + 16 * j + r]);
+  }
+  const int64_t nblk = (n + 15) / 16;
+  for (int64_t blk = int64_t(blockIdx.x) * FW_WAVES + wave; blk < nblk; blk += int64_t(gridDim.x) * FW_WAVES) {
+    const int64_t u = std::min<int64_t>(blk * 16 + r, n - 1);
+    const float z0 = float(z[3 * u]), z1 = float(z[3 * u + 1]), z2 = float(z[3 * u + 2]);
+    f4v acc[2][8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[0][j] = acc[1][j] = f4v{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+    for (int c = 0; c < 8; ++c) {
+      float a0[4], a1[4];
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        const f4v w = *reinterpret_cast<const f4v *>(&sW1[4 * (16 * c + 4 * q + st)]);
+        const float common = w[1] * z1 + w[2] * z2 + w[3];
+        const float hp = common + w[0] * z0, hm = common - w[0] * z0;
+        a0[st] = hp > 0.f ? hp : 0.f;
+        a1[st] = hm > 0.f ? hm : 0.f;
+      }
+      f4v bf[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) bf[j] = *reinterpret_cast<const f4v *>(&sW2[(16 * j + r) * W2_LD + 16 * c + 4 * q]);
+#pragma unroll
+      for (int st = 0; st < 4; ++st)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          acc[0][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[st], bf[j][st], acc[0][j], 0, 0, 0);
+          acc[1][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[st], bf[j][st], acc[1][j], 0, 0, 0);
+        }
+    }
+    // g (without b3, which cancels in f) for rows 4 q + t of both branches
+    float g[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        float sum = 0.f;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const float h = acc[i][j][t] + b2r[j];
+          sum += (h > 0.f ? h : 0.f) * w3r[j];
+        }
+        g[i][t] = sum;
+      }
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) g[i][t] += __shfl_xor(g[i][t], off, 64);
+    if (r == 0) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int64_t uu = blk * 16 + 4 * q + t;
+        if (uu < n) f[uu] = 0.5 * (double(g[0][t]) - double(g[1][t]));
+      }
+    }
+  }
+}
+
+void forward_fused(const double *P, const double *z, int64_t n, double *f, hipStream_t s) {
+  if (n <= 0) return;
+  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((n + 16 * FW_WAVES - 1) / (16 * FW_WAVES), 512));
+  hipLaunchKernelGGL(mlp_forward_fused_kernel, dim3(blocks), dim3(FW_WAVES * 64), 0, s, P, z, n, f);
+  CC_HIP_CHECK(hipGetLastError());
+}
+
 // Dense layer helper: C[M][N] = alpha * A' B'^T + beta C (GemmDesc conventions)
 void dense(int prec, int64_t M, int64_t N, int64_t K, const double *A, int64_t sam, int64_t sak, const double *B,
            int64_t sbn, int64_t sbk, double *C, double beta, double *ws, int64_t ws_elems, hipStream_t s) {
@@ -458,6 +561,11 @@ int cc_mlp_forward(cc_ctx *ctx, int prec, const double *params, const double *z,
     check_prec(prec);
     if (!params || !z || !f_out || n < 1) throw CCError(CC_EINVAL, "bad arguments");
     CC_HIP_CHECK(hipSetDevice(ctx->device));
+    if (prec == CC_PREC_F32) {  // inference in one fused launch
+      ccmi::forward_fused(params, z, n, f_out, ctx->stream);
+      CC_HIP_CHECK(hipStreamSynchronize(ctx->stream));
+      return CC_OK;
+    }
     ccmi::MlpWork w;
     const int64_t cap = std::min<int64_t>(n, 1 << 18);
     w.alloc(cap);

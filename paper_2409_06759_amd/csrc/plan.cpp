@@ -131,8 +131,14 @@ struct Planner {
   // round of workgroups would be mostly empty (real GEMMs only).
   void reserve_ws(Step &g, int64_t M, int64_t N, int64_t K) {
     const int64_t split = g.gemm.split > 1 ? int64_t(g.gemm.split) * M * N : 0;
-    const int64_t tail = p->cplx ? 0 : gemm_tail_ws_bound(M, N, K);
+    // complex: room for the tail of the realified M x 2N x 2K reduced-precision
+    // GEMM, in complex elements
+    const int64_t tail = p->cplx ? (gemm_tail_ws_bound(M, 2 * N, 2 * K) + 1) / 2 : gemm_tail_ws_bound(M, N, K);
     if (split > 0 || tail > 0) {
+      if (p->private_work) {
+        g.b2 = add_work("splitk_ws_" + std::to_string(p->slots.size()), {std::max(split, tail)});
+        return;
+      }
       splitws_elems = std::max<int64_t>(splitws_elems, std::max(split, tail));
       g.b2 = splitws;
     }
@@ -378,13 +384,15 @@ struct Planner {
       p->iter.push_back(g);
     } else {
       const int64_t need = M * N;
-      if (need > scratch_elems) scratch_elems = need;
-      g.c = scratch;
+      int sc = scratch;
+      if (p->private_work) sc = add_work("scratch_" + std::to_string(p->slots.size()), {need});
+      else if (need > scratch_elems) scratch_elems = need;
+      g.c = sc;
       g.gemm.alpha = op.alpha;
       g.gemm.beta = 0.0;
       p->iter.push_back(g);
       const auto tdims = label_dims(best.rows + best.cols);
-      accumulate(scratch, best.rows + best.cols, false, c, cl, 1.0, op.swap, p->iter, false, &tdims);
+      accumulate(sc, best.rows + best.cols, false, c, cl, 1.0, op.swap, p->iter, false, &tdims);
     }
     p->flops_per_iter += g.flops;
     if (std::string(op.tag) == "ladder") p->ladder_flops += g.flops;
@@ -709,8 +717,8 @@ struct Planner {
     fin.kind = Step::FINALIZE;
     fin.tag = "finalize";
     p->iter.push_back(fin);
-    p->slots[scratch].dims = {scratch_elems};
-    p->slots[scratch].elems = scratch_elems;
+    p->slots[scratch].dims = {std::max<int64_t>(scratch_elems, 1)};
+    p->slots[scratch].elems = std::max<int64_t>(scratch_elems, 1);
     p->slots[splitws].dims = {std::max<int64_t>(splitws_elems, 1)};
     p->slots[splitws].elems = std::max<int64_t>(splitws_elems, 1);
   }
@@ -756,9 +764,42 @@ void use_shadows(cc_plan *p, GemmDesc &d, const Step &st, hipStream_t s, bool co
   d.lp_in = 1;
 }
 
+// The realified B' copy of a complex slot for rows of K complex elements.
+void convert_b_form(cc_plan *p, BForm &bf, int prec, hipStream_t s) {
+  const int64_t n = slot_elems(p, bf.slot);
+  CC_REQUIRE(bf.ptr && bf.K > 0 && n % bf.K == 0, CC_EINTERNAL, "complex B operand rows");
+  realify_complex(prec, 1, static_cast<const double *>(ptr_of(p, bf.slot)), nullptr, n / bf.K, bf.K, bf.K, 1, bf.ptr,
+                  s);
+}
+
+// Complex reduced precision: the realified real GEMM (M x 2N x 2K) on the
+// interleaved copy of A and the realified copy of B, converting a copy first
+// when its slot was written since the last conversion in this run.
+void use_shadows_c(cc_plan *p, GemmDesc &d, const Step &st, hipStream_t s, bool convert) {
+  const int prec = p->cur_prec;
+  const int64_t na = slot_elems(p, st.a), nb = slot_elems(p, st.b);
+  CC_REQUIRE(st.bform >= 0 && p->shadow[st.a] && p->bforms[st.bform].ptr, CC_EINTERNAL,
+             "complex operand copies not prepared");
+  BForm &bf = p->bforms[st.bform];
+  if (convert && !p->shadow_ok[st.a]) {
+    convert_shadow(prec, static_cast<const double *>(ptr_of(p, st.a)), 2 * na, p->shadow[st.a], s);
+    p->shadow_ok[st.a] = 1;
+  }
+  if (convert && !bf.ok) {
+    convert_b_form(p, bf, prec, s);
+    bf.ok = 1;
+  }
+  d = realified_desc(d, p->shadow[st.a], bf.ptr);
+  d.a_plane = 2 * na;
+  d.b_plane = 4 * nb;
+}
+
 void run_gemm(cc_plan *p, GemmDesc &d, const Step &st, hipStream_t s) {
-  if (p->cplx) gemm_c128(d, s, st.tile_z);
-  else if (p->cur_prec == PREC_F64 || !st.lowp_ok) gemm_f64(d, s, st.tile);
+  if (p->cplx && (p->cur_prec == PREC_F64 || !st.lowp_ok)) gemm_c128(d, s, st.tile_z);
+  else if (p->cplx) {
+    use_shadows_c(p, d, st, s, true);
+    gemm_lowp(d, p->cur_prec, s, st.tile_lp[p->cur_prec]);
+  } else if (p->cur_prec == PREC_F64 || !st.lowp_ok) gemm_f64(d, s, st.tile);
   else {
     use_shadows(p, d, st, s, true);
     gemm_lowp(d, p->cur_prec, s, st.tile_lp[p->cur_prec]);
@@ -767,6 +808,8 @@ void run_gemm(cc_plan *p, GemmDesc &d, const Step &st, hipStream_t s) {
 
 void invalidate(cc_plan *p, int sl) {
   if (sl >= 0 && !p->shadow_ok.empty()) p->shadow_ok[sl] = 0;
+  for (BForm &bf : p->bforms)
+    if (bf.slot == sl) bf.ok = 0;
 }
 
 // Mode 2: store X_ref and alpha X_ref Y (FP64), then C = beta C + that.
@@ -778,14 +821,33 @@ void run_delta_gemm(cc_plan *p, GemmDesc &d, const Step &st, hipStream_t s) {
   const int var_slot = r.var ? st.b : st.a, con_slot = r.var ? st.a : st.b;
   const double *X = static_cast<const double *>(ptr_of(p, var_slot));
   double *C = static_cast<double *>(d.C);
+  const int64_t w = p->cplx ? 2 : 1;  // doubles per element
   if (p->delta_mode == 2) {
-    copy_f64(r.ref_op, X, r.n_op, s);
+    copy_f64(r.ref_op, X, w * r.n_op, s);
     GemmDesc g = d;
     g.C = r.ref_out;
     g.ldc = d.N;
     g.beta = 0.0;
-    gemm_f64(g, s, st.tile);
-    add_product(C, d.ldc, d.beta, r.ref_out, d.M, d.N, s);
+    if (p->cplx) gemm_c128(g, s, st.tile_z);
+    else gemm_f64(g, s, st.tile);
+    add_product(C, w * d.ldc, d.beta, r.ref_out, d.M, w * d.N, s);
+    return;
+  }
+  if (p->cplx) {
+    // (X - X_ref) as the realified operand of its side; the constant operand's
+    // copy of the other side was made by plan_prepare
+    CC_REQUIRE(r.var ? (p->shadow[con_slot] && p->shadow_prec[con_slot] == p->delta_prec)
+                     : (st.bform >= 0 && p->bforms[st.bform].ptr && p->bforms[st.bform].prec == p->delta_prec),
+               CC_EINTERNAL, "constant operand copy not prepared");
+    if (r.var) realify_complex(p->delta_prec, 1, X, r.ref_op, r.n_op / d.K, d.K, d.K, 1, r.dshadow, s);
+    else convert_delta(p->delta_prec, X, r.ref_op, 2 * r.n_op, r.dshadow, s);
+    add_product(C, 2 * d.ldc, d.beta, r.ref_out, d.M, 2 * d.N, s);
+    GemmDesc g = realified_desc(d, r.var ? p->shadow[con_slot] : r.dshadow,
+                                r.var ? r.dshadow : p->bforms[st.bform].ptr);
+    g.a_plane = 2 * slot_elems(p, st.a);
+    g.b_plane = 4 * slot_elems(p, st.b);
+    g.beta = 1.0;
+    gemm_lowp(g, p->delta_prec, s, st.tile_lp[p->delta_prec]);
     return;
   }
   CC_REQUIRE(p->shadow.size() == p->slots.size() && p->shadow[con_slot] &&
@@ -817,13 +879,15 @@ void run_delta_gemm(cc_plan *p, GemmDesc &d, const Step &st, hipStream_t s) {
 // conversion pass: constant operands once per precision, the others once per
 // write.  Allocation and the constant conversions happen here, outside any
 // graph capture.
+// Complex slots: the interleaved copy (2 reals per element) serves the A
+// side; the B side reads the realified copy (4 reals per element).
 void plan_prepare(cc_plan *p) {
-  if (p->cplx) return;
   const bool lowp = p->cur_prec != PREC_F64;
   const bool delta = !lowp && p->delta_mode != 0 && !p->deltas.empty();
   if (!lowp && !delta) return;
   const int prec = lowp ? p->cur_prec : p->delta_prec;
   const size_t n = p->slots.size();
+  const int64_t w = p->cplx ? 2 : 1;  // reals per element
   if (p->shadow.size() != n) {
     p->shadow.assign(n, nullptr);
     p->shadow_prec.assign(n, -1);
@@ -832,14 +896,28 @@ void plan_prepare(cc_plan *p) {
   hipStream_t s = p->ctx->stream;
   for (const Step &st : p->iter) {
     if (st.kind != Step::GEMM || (!lowp && st.delta < 0) || (lowp && !st.lowp_ok)) continue;
-    for (int sl : {st.a, st.b}) {
+    for (int side = 0; side < 2; ++side) {
+      const int sl = side ? st.b : st.a;
       if (!lowp && !p->slots[sl].constant) continue;  // the correction reads its own copy
+      if (p->cplx && side == 1) {
+        CC_REQUIRE(st.bform >= 0, CC_EINTERNAL, "complex B operand copy not planned");
+        BForm &bf = p->bforms[st.bform];
+        if (!bf.ptr) {
+          CC_HIP_CHECK(hipMalloc(&bf.ptr, size_t(slot_elems(p, sl)) * 16));
+          bf.prec = -1;
+        }
+        if (p->slots[sl].constant && bf.prec != prec) {
+          convert_b_form(p, bf, prec, s);
+          bf.prec = prec;
+        }
+        continue;
+      }
       if (!p->shadow[sl]) {
-        CC_HIP_CHECK(hipMalloc(&p->shadow[sl], size_t(slot_elems(p, sl)) * 4));
+        CC_HIP_CHECK(hipMalloc(&p->shadow[sl], size_t(slot_elems(p, sl)) * w * 4));
         p->shadow_prec[sl] = -1;
       }
       if (p->slots[sl].constant && p->shadow_prec[sl] != prec) {
-        convert_shadow(prec, static_cast<const double *>(ptr_of(p, sl)), slot_elems(p, sl), p->shadow[sl], s);
+        convert_shadow(prec, static_cast<const double *>(ptr_of(p, sl)), w * slot_elems(p, sl), p->shadow[sl], s);
         p->shadow_prec[sl] = prec;
       }
     }
@@ -847,9 +925,10 @@ void plan_prepare(cc_plan *p) {
   if (delta) {
     for (DeltaRef &d : p->deltas) {
       const GemmDesc &g = p->iter[d.step].gemm;
-      if (!d.ref_op) CC_HIP_CHECK(hipMalloc(reinterpret_cast<void **>(&d.ref_op), size_t(d.n_op) * 8));
-      if (!d.ref_out) CC_HIP_CHECK(hipMalloc(reinterpret_cast<void **>(&d.ref_out), size_t(g.M) * g.N * 8));
-      if (!d.dshadow) CC_HIP_CHECK(hipMalloc(&d.dshadow, size_t(d.n_op) * 4));
+      const int64_t wd = p->cplx ? (d.var ? 4 : 2) : 1;  // reals per element of the varying operand's copy
+      if (!d.ref_op) CC_HIP_CHECK(hipMalloc(reinterpret_cast<void **>(&d.ref_op), size_t(d.n_op) * w * 8));
+      if (!d.ref_out) CC_HIP_CHECK(hipMalloc(reinterpret_cast<void **>(&d.ref_out), size_t(g.M) * g.N * w * 8));
+      if (!d.dshadow) CC_HIP_CHECK(hipMalloc(&d.dshadow, size_t(d.n_op) * wd * 4));
     }
   }
 }
@@ -911,7 +990,7 @@ void exec(cc_plan *p, Step &st, hipStream_t s) {
       d.C = ptr_of(p, st.c);
       d.ws = st.b2 >= 0 ? ptr_of(p, st.b2) : nullptr;
       d.ws_elems = st.b2 >= 0 ? p->slots[st.b2].elems : 0;
-      if (st.delta >= 0 && p->delta_mode != 0 && !cplx && p->cur_prec == PREC_F64) run_delta_gemm(p, d, st, s);
+      if (st.delta >= 0 && p->delta_mode != 0 && p->cur_prec == PREC_F64) run_delta_gemm(p, d, st, s);
       else run_gemm(p, d, st, s);
       break;
     }
@@ -1069,15 +1148,21 @@ void plan_build(cc_plan *p, const cc_system *sys) {
   // ones under 1% of the iteration's flops are bandwidth- or latency-bound
   // and run in FP64 (measured faster, and exact), unless the plan asks for
   // every contraction in its precision (CC_PLAN_LOWP_ALL, batched plans).
-  if (!p->cplx)
-    for (Step &st : p->iter)
-      if (st.kind == Step::GEMM) st.lowp_ok = p->lowp_all || st.flops >= 0.01 * p->flops_per_iter;
+  // Complex contractions run in reduced precision as real GEMMs on realified
+  // operands, which needs both operands in dense K-contiguous rows.
+  auto shape_ok = [p](const Step &st) {
+    const GemmDesc &g = st.gemm;
+    return !p->cplx || (g.K > 0 && g.sak == 1 && g.sbk == 1 && g.sam == g.K && g.sbn == g.K &&
+                        slot_elems(p, st.b) % g.K == 0);
+  };
+  for (Step &st : p->iter)
+    if (st.kind == Step::GEMM) st.lowp_ok = (p->lowp_all || st.flops >= 0.01 * p->flops_per_iter) && shape_ok(st);
   // contractions linear in the amplitudes worth a reference + correction
   // evaluation: one constant operand and at least 1% of the iteration's work
-  if (!p->cplx) {
+  {
     for (size_t k = 0; k < p->iter.size(); ++k) {
       Step &st = p->iter[k];
-      if (st.kind != Step::GEMM || st.flops < 0.01 * p->flops_per_iter) continue;
+      if (st.kind != Step::GEMM || st.flops < 0.01 * p->flops_per_iter || !shape_ok(st)) continue;
       const bool ca = p->slots[st.a].constant, cb = p->slots[st.b].constant;
       if (ca == cb) continue;
       DeltaRef d;
@@ -1088,6 +1173,22 @@ void plan_build(cc_plan *p, const cc_system *sys) {
       p->deltas.push_back(d);
     }
   }
+  // complex: one realified copy per (B slot, row length K) of those GEMMs
+  if (p->cplx)
+    for (Step &st : p->iter) {
+      if (st.kind != Step::GEMM || (!st.lowp_ok && st.delta < 0)) continue;
+      int idx = -1;
+      for (size_t i = 0; i < p->bforms.size(); ++i)
+        if (p->bforms[i].slot == st.b && p->bforms[i].K == st.gemm.K) idx = int(i);
+      if (idx < 0) {
+        BForm bf;
+        bf.slot = st.b;
+        bf.K = st.gemm.K;
+        p->bforms.push_back(bf);
+        idx = int(p->bforms.size()) - 1;
+      }
+      st.bform = idx;
+    }
 }
 
 void plan_free(cc_plan *p) {
@@ -1100,6 +1201,9 @@ void plan_free(cc_plan *p) {
   for (void *q : p->shadow)
     if (q) (void)hipFree(q);
   p->shadow.clear();
+  for (BForm &bf : p->bforms)
+    if (bf.ptr) (void)hipFree(bf.ptr);
+  p->bforms.clear();
   for (DeltaRef &d : p->deltas) {
     for (void *q : {static_cast<void *>(d.ref_op), static_cast<void *>(d.ref_out), d.dshadow})
       if (q) (void)hipFree(q);
@@ -1114,17 +1218,18 @@ void plan_free(cc_plan *p) {
 
 void plan_run(cc_plan *p) {
   hipStream_t s = p->ctx->stream;
-  if (!p->cplx) {
+  {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     CC_HIP_CHECK(hipStreamIsCapturing(s, &cs));
     if (cs == hipStreamCaptureStatusNone) plan_prepare(p);
   }
-  if (!p->cplx && p->cur_prec != PREC_F64) {
+  if (p->cur_prec != PREC_F64) {
     CC_REQUIRE(p->shadow.size() == p->slots.size(), CC_EINTERNAL, "operand copies not prepared");
     for (size_t i = 0; i < p->slots.size(); ++i)
       p->shadow_ok[i] = p->slots[i].constant && p->shadow_prec[i] == p->cur_prec;
+    for (BForm &bf : p->bforms) bf.ok = p->slots[bf.slot].constant && bf.prec == p->cur_prec;
   }
-  if (p->delta_mode == 2 && !p->cplx && p->cur_prec == PREC_F64 && !p->deltas.empty()) {
+  if (p->delta_mode == 2 && p->cur_prec == PREC_F64 && !p->deltas.empty()) {
     // this run stores the reference; the following ones correct it
     for (Step &st : p->iter) exec(p, st, s);
     p->delta_mode = 1;
@@ -1174,14 +1279,18 @@ void plan_autotune(cc_plan *p, int reps) {
     for (Step *st : p->gemm_steps) {
       GemmDesc d = st->gemm;
       const bool akc = d.sak == 1, bkc = d.sbk == 1;
-      // this step's precision: contractions under 1% of the work run in FP64
-      const int prec = (prec_plan != PREC_F64 && prec_plan != 9 && !st->lowp_ok) ? PREC_F64 : prec_plan;
-      const int ntiles = p->cplx ? gemm_c128_num_tiles()
-                                 : (prec == PREC_F64 ? gemm_f64_num_tiles() : gemm_lowp_num_tiles(prec));
+      // this step's precision: contractions under 1% of the work run in FP64;
+      // complex ones in reduced precision are real GEMMs of M x 2N x 2K
+      const bool lowp = p->cur_prec != PREC_F64 && st->lowp_ok;
+      const int prec = lowp ? p->cur_prec : prec_plan == 9 ? 9 : PREC_F64;
+      const bool cz = prec == 9;
+      const int ntiles = cz ? gemm_c128_num_tiles()
+                            : (prec == PREC_F64 ? gemm_f64_num_tiles() : gemm_lowp_num_tiles(prec));
+      const int64_t rN = (p->cplx && lowp) ? 2 * d.N : d.N, rK = (p->cplx && lowp) ? 2 * d.K : d.K;
       const std::string key = std::to_string(prec) + ":" + std::to_string(d.M) + "x" +
-                              std::to_string(d.N) + "x" + std::to_string(d.K) + (akc ? "k" : "m") +
+                              std::to_string(rN) + "x" + std::to_string(rK) + (akc ? "k" : "m") +
                               (bkc ? "k" : "n");
-      int &slot = p->cplx ? st->tile_z : (prec == PREC_F64 ? st->tile : st->tile_lp[prec]);
+      int &slot = cz ? st->tile_z : (prec == PREC_F64 ? st->tile : st->tile_lp[prec]);
       std::unique_lock<std::mutex> lk(cache_mutex);
       auto it = cache.find(key);
       if (it != cache.end()) {
@@ -1194,11 +1303,12 @@ void plan_autotune(cc_plan *p, int reps) {
       d.C = ptr_of(p, st->c);
       d.ws = st->b2 >= 0 ? ptr_of(p, st->b2) : nullptr;
       d.ws_elems = st->b2 >= 0 ? p->slots[st->b2].elems : 0;
-      if (!p->cplx && prec != PREC_F64) use_shadows(p, d, *st, s, false);
+      if (lowp && p->cplx) use_shadows_c(p, d, *st, s, false);
+      else if (lowp) use_shadows(p, d, *st, s, false);
       int best = slot;
       float best_ms = 1e30f;
       auto launch = [&](int t) {
-        if (p->cplx) gemm_c128(d, s, t);
+        if (cz) gemm_c128(d, s, t);
         else if (prec == PREC_F64) gemm_f64(d, s, t);
         else gemm_lowp(d, prec, s, t);
       };
@@ -1240,9 +1350,9 @@ std::string plan_profile_table(const cc_plan *p) {
     for (auto &c : tag)
       if (c == ' ') c = '_';
     if (st.kind == Step::GEMM)
-      tag += "@" + std::string(p->cplx                                    ? gemm_c128_tile_name(st.tile_z)
-                               : (p->cur_prec == PREC_F64 || !st.lowp_ok) ? gemm_f64_tile_name(st.tile)
-                                                                          : gemm_lowp_tile_name(p->cur_prec, st.tile_lp[p->cur_prec]));
+      tag += "@" + std::string((p->cur_prec != PREC_F64 && st.lowp_ok) ? gemm_lowp_tile_name(p->cur_prec, st.tile_lp[p->cur_prec])
+                               : p->cplx                                  ? gemm_c128_tile_name(st.tile_z)
+                                                                          : gemm_f64_tile_name(st.tile));
     os << i << " " << kinds[st.kind] << " " << tag << " " << p->step_calls[i]
        << " " << p->step_ms[i] << " " << (p->step_calls[i] ? p->step_ms[i] / p->step_calls[i] : 0.0)
        << " " << st.flops << "\n";

@@ -36,6 +36,16 @@ struct OpSpec {
   bool kc = false;     // reduced-precision plans: both GEMM operands K-contiguous (permuted if need be)
 };
 
+// Realified copy of a complex slot read as the B operand of reduced-precision
+// GEMMs with rows of K complex elements (the layout depends on K).
+struct BForm {
+  int slot = -1;
+  int64_t K = 0;
+  void *ptr = nullptr;
+  int prec = -1;  // precision held (constant slots)
+  char ok = 0;    // matches the slot in the current run
+};
+
 struct Slot {
   std::string name, spaces;
   std::vector<int64_t> dims;
@@ -56,6 +66,7 @@ struct Step {
   int tile_lp[3] = {-1, -1, -1};  // per reduced precision (index = cc_prec)
   int tile_z = -1;      // complex128 tile
   int delta = -1;       // index into cc_plan::deltas (GEMM linear in the amplitudes)
+  int bform = -1;       // complex reduced precision: index into cc_plan::bforms of the B operand
   bool lowp_ok = true;  // runs in the plan's reduced precision (else FP64: under 1% of the work)
   // PAIR: slot a -> slot c through index-pair tables (PairEntry): mode 0
   // gathers packed rows/columns, 1 scatter-adds, 2 scatter-sets; tables:
@@ -107,6 +118,9 @@ struct cc_plan {
   // particle-particle ladder over packed pairs (i<j, e<f, a<b)
   bool packed = false;
   bool lowp_all = false;  // every contraction in the reduced precision (else small ones in FP64)
+  // every GEMM gets its own output scratch and split-K workspace (batched
+  // plans, whose steps may run concurrently), instead of one shared buffer each
+  bool private_work = false;
   int *pair_tab[4] = {nullptr, nullptr, nullptr, nullptr};  // device index-pair tables
   // triples (op lists that read t3 or accumulate Y3): bound per plan
   bool triples = false;
@@ -143,10 +157,15 @@ struct cc_plan {
   std::vector<hipEvent_t> events;
   std::vector<double> step_ms;   // accumulated per iteration step
   std::vector<int64_t> step_calls;
-  // reduced-precision operand copies (4 bytes per element), per slot
+  // reduced-precision operand copies (4 bytes per real element), per slot:
+  // the slot's elements in their own order (complex: re, im interleaved,
+  // which is also the realified A' of a dense K-contiguous complex operand)
   std::vector<void *> shadow;
   std::vector<int> shadow_prec;   // precision held by a constant slot's copy
   std::vector<char> shadow_ok;    // copy matches the slot in the current run
+  // complex slots read as the B operand of a reduced-precision GEMM: the
+  // realified B' (rows [Re, -Im] and [Im, Re]), one copy per (slot, K)
+  std::vector<ccmi::BForm> bforms;
   // reference + correction mode of the FP64 contractions (0 off, 1 use the
   // stored reference, 2 take a new reference in the next run)
   int delta_mode = 0;
@@ -171,6 +190,7 @@ AsmEntry asm_entry(cc_plan *p);
 R1Entry r1_entry(cc_plan *p);
 FinEntry fin_entry(cc_plan *p);
 void *ptr_of(cc_plan *p, int slot);
-cc_plan *make_plan_checked(cc_ctx *ctx, const cc_system *sys, int method, int prec, bool lowp_all = false);
+cc_plan *make_plan_checked(cc_ctx *ctx, const cc_system *sys, int method, int prec, bool lowp_all = false,
+                           bool private_work = false);
 void check_amps(const cc_amps *t, int method);
 }  // namespace ccmi

@@ -213,21 +213,29 @@ def energy(ctx, dsys, method, t1, t2):
     return complex(er.value, ei.value) if dsys.is_complex else er.value
 
 
+GUESSES = {"given": L.CC_GUESS_GIVEN, "mp2": L.CC_GUESS_MP2, "mlp": L.CC_GUESS_MLP}
+
+
 def iterate(ctx, dsys, method, t1, t2, tol=1e-8, max_iter=100, level_shift=0.0, prec=F64,
             use_graph=True, refine_tol=0.0, diverge_window=0, hist_cap=None, dressed=False,
-            autotune=False, correction=True, packed=False, check_every=1):
+            autotune=False, correction=True, packed=False, check_every=1, guess="given", mlp=None):
     """Jacobi iteration (cc_iterate).  Reduced `prec` runs its contractions in
     that precision until the norm stagnates, then finishes with FP64 steps
     (with `correction`, in reference + reduced-precision-correction form for
-    the contractions linear in the amplitudes)."""
+    the contractions linear in the amplitudes).  `guess` selects the start:
+    the amplitudes given, "mp2", or "mlp" (the network `mlp`, with the MP2
+    amplitudes as fallback), formed inside the library and timed with it."""
     cap = hist_cap or max_iter
     hr = (C.c_double * cap)()
     he = (C.c_double * cap)()
+    stats = mlp._st() if mlp is not None else None
     opts = L.CCIterOpts(tol, max_iter, prec, level_shift, refine_tol, 1 if use_graph else 0, check_every,
                         diverge_window, 1 if dressed else 0, 1 if autotune else 0, 1 if correction else 0,
-                        1 if packed else 0)
+                        1 if packed else 0, GUESSES[guess], mlp.prec if mlp is not None else F64,
+                        _ptr(mlp.params) if mlp is not None else None,
+                        C.cast(C.pointer(stats), C.c_void_p) if stats is not None else None)
     rep = L.CCIterReport(0, 0, 0.0, 0.0, 0.0, 0.0, 0.0, 0, 0, C.cast(hr, C.POINTER(C.c_double)),
-                         C.cast(he, C.POINTER(C.c_double)), cap)
+                         C.cast(he, C.POINTER(C.c_double)), cap, 0, 0.0, 0.0, 0.0)
     ctx.enter()
     rc = ctx.lib.cc_iterate(ctx.h, C.byref(dsys.struct), method, C.byref(opts), C.byref(_amps(t1, t2)),
                             C.byref(rep))
@@ -236,7 +244,9 @@ def iterate(ctx, dsys, method, t1, t2, tol=1e-8, max_iter=100, level_shift=0.0, 
     return {"status": rc, "iters": rep.iters, "converged": bool(rep.converged), "rnorm": rep.rnorm,
             "energy": complex(rep.e_re, rep.e_im) if dsys.is_complex else rep.e_re,
             "seconds": rep.seconds, "setup_seconds": rep.setup_seconds, "lowp_iters": rep.lowp_iters,
-            "corr_iters": rep.corr_iters,
+            "corr_iters": rep.corr_iters, "guess_used": {v: k for k, v in GUESSES.items()}[rep.guess_used],
+            "guess_rnorm": {"mlp": rep.guess_rnorm_mlp, "mp2": rep.guess_rnorm_mp2},
+            "guess_seconds": rep.guess_seconds,
             "hist_rnorm": list(hr[:n]), "hist_e": list(he[:n])}
 
 

@@ -142,6 +142,8 @@ def main(argv=None):
     tr.add_argument("--epochs", type=int, default=4)
     tr.add_argument("--batch", type=int, default=65536)
     tr.add_argument("--lr", type=float, default=1e-3)
+    tr.add_argument("--group", type=int, default=64, help="systems solved together in one batch")
+    tr.add_argument("--tol", type=float, default=1e-8, help="residual norm of the training solutions")
     tr.add_argument("--out", required=True)
     tr.add_argument("--eval", action="store_true", help="evaluate on o=32 v=160 after training")
     tr.add_argument("--precs", default="f64", help="contraction precisions of the evaluation")
@@ -155,7 +157,7 @@ def main(argv=None):
     ctx = E.Context(0)
     if args.cmd == "train":
         t0 = time.perf_counter()
-        raw, y = generate(ctx, training_shapes(args.systems), log=log)
+        raw, y = generate(ctx, training_shapes(args.systems), tol=args.tol, group=args.group, log=log)
         t_gen = time.perf_counter() - t0
         mlp, hist = train(ctx, raw, y, epochs=args.epochs, batch=args.batch, lr=args.lr, log=log)
         mlp.save(args.out)

@@ -147,7 +147,37 @@ def test_gemm_c128_matches_numpy(ctx, shape, akc, bkc):
     assert np.all(np.abs(Cd.cpu().numpy() - ref) <= bound)
 
 
-@pytest.mark.parametrize("prec,cplx", [("f64", False), ("f32", False), ("bf16x3", False), ("f64", True)])
+@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
+@pytest.mark.parametrize("shape", [(1, 1, 1), (17, 33, 65), (64, 100, 300), (130, 70, 33), (70, 200, 512)])
+@pytest.mark.parametrize("akc,bkc", [(True, True), (False, False), (False, True)])
+def test_gemm_c128_lowp_error_bound(ctx, prec, shape, akc, bkc):
+    """Complex reduced precision as the real GEMM of M x 2N x 2K on realified
+    operands: the real and imaginary parts each carry the real bound with
+    K' = 2K terms of |Re a| + |Im a| times |Re b| + |Im b| per k."""
+    from paper_2409_06759_amd import engine as E
+    M, N, K = shape
+    print(f"gemm c128 {prec} M={M} N={N} K={K} akc={akc} bkc={bkc}", flush=True)
+    rng = np.random.default_rng(M * 3 + N + 11 * K)
+    A = rng.normal(size=(M, K)) + 1j * rng.normal(size=(M, K))
+    B = rng.normal(size=(N, K)) + 1j * rng.normal(size=(N, K))
+    C0 = rng.normal(size=(M, N)) + 1j * rng.normal(size=(M, N))
+    alpha, beta = 0.5, -1.25
+    ref = alpha * (A @ B.T) + beta * C0
+    Ad = torch.from_numpy(A if akc else np.ascontiguousarray(A.T)).cuda()
+    Bd = torch.from_numpy(B if bkc else np.ascontiguousarray(B.T)).cuda()
+    Cd = torch.from_numpy(C0).cuda()
+    E.gemm(ctx, Ad, Bd, Cd, alpha, beta, a_kcontig=akc, b_kcontig=bkc, prec=E.PRECS[prec])
+    got = Cd.cpu().numpy()
+    eps = (2 * K + 2) * 2.0 ** -24 + (3 * 2.0 ** -17 if prec == "bf16x3" else 0.0)
+    mag = (np.abs(A.real) + np.abs(A.imag)) @ (np.abs(B.real) + np.abs(B.imag)).T
+    bound = 2 * eps * abs(alpha) * mag + 4 * np.finfo(float).eps * np.abs(beta * C0)
+    for part in (np.real, np.imag):
+        err = np.abs(part(got) - part(ref))
+        assert np.all(err <= bound), (err / bound).max()
+
+
+@pytest.mark.parametrize("prec,cplx", [("f64", False), ("f32", False), ("bf16x3", False), ("f64", True),
+                                       ("f32", True)])
 def test_gemm_with_empty_contraction_scales_c(ctx, prec, cplx):
     """K = 0: C = beta C (no products)."""
     from paper_2409_06759_amd import engine as E

@@ -119,3 +119,72 @@ def test_trained_network_gains_over_mp2(E, ctx):
     # ring sums that per-amplitude features cannot see, so the gain in
     # iterations is small; it must not be a loss
     assert res["mlp"]["iterations"] <= res["mp2"]["iterations"]
+
+
+def test_iterate_guess_option(E, ctx):
+    """cc_iterate's guess option.  MP2: the start is the zero start's first
+    iterate, so the run is the zero-start run shifted by one iteration.  MLP:
+    the network's amplitudes unless the MP2 ones have the smaller FP64
+    residual norm; both candidate norms are reported and the first iteration
+    evaluates the chosen one."""
+    o, v = 8, 24
+    s = make_system(o, v)
+    d = E.DeviceSystem(s)
+    z1, z2 = E.zeros_amps(d, E.CCSD)
+    ref_run = E.iterate(ctx, d, E.CCSD, z1, z2, tol=1e-10, max_iter=200, dressed=True)
+    g1, g2 = E.zeros_amps(d, E.CCSD)
+    g2.fill_(1.0)  # overwritten by the guess
+    mp = E.iterate(ctx, d, E.CCSD, g1, g2, tol=1e-10, max_iter=200, dressed=True, guess="mp2")
+    assert mp["guess_used"] == "mp2"
+    assert abs(mp["hist_rnorm"][0] - ref_run["hist_rnorm"][1]) < 1e-12 * ref_run["hist_rnorm"][1]
+    assert mp["iters"] == ref_run["iters"] - 1
+    assert abs(mp["energy"] - ref_run["energy"]) < 1e-12
+    params = E.MLP.init_params(3, "cuda")
+    # output scale 0: the network's t2 is exactly zero, whose norm is the zero start's
+    zero_net = E.MLP(ctx, params, dict(_stats(), st=0.0), E.F64)
+    a1, a2 = E.zeros_amps(d, E.CCSD)
+    r = E.iterate(ctx, d, E.CCSD, a1, a2, tol=1e-10, max_iter=200, dressed=True, guess="mlp", mlp=zero_net)
+    assert abs(r["guess_rnorm"]["mlp"] - ref_run["hist_rnorm"][0]) < 1e-12 * ref_run["hist_rnorm"][0]
+    assert abs(r["guess_rnorm"]["mp2"] - ref_run["hist_rnorm"][1]) < 1e-12 * ref_run["hist_rnorm"][1]
+    want = "mlp" if r["guess_rnorm"]["mlp"] <= r["guess_rnorm"]["mp2"] else "mp2"
+    assert r["guess_used"] == want
+    assert abs(r["hist_rnorm"][0] - min(r["guess_rnorm"].values())) < 1e-12 * r["hist_rnorm"][0]
+    assert abs(r["energy"] - ref_run["energy"]) < 1e-12
+    # an output scale far beyond the amplitudes: the MP2 start is kept
+    wild = E.MLP(ctx, params, dict(_stats(), st=1e3), E.F32)
+    b1, b2 = E.zeros_amps(d, E.CCSD)
+    w = E.iterate(ctx, d, E.CCSD, b1, b2, tol=1e-10, max_iter=200, dressed=True, guess="mlp", mlp=wild)
+    assert w["guess_used"] == "mp2" and w["guess_rnorm"]["mlp"] > w["guess_rnorm"]["mp2"]
+    assert w["iters"] == mp["iters"] and abs(w["energy"] - ref_run["energy"]) < 1e-12
+    assert w["guess_seconds"] > 0
+
+
+@pytest.mark.parametrize("n", [1, 17, 50017])
+def test_fused_fp32_forward_matches_oracle(E, ctx, n):
+    """FP32 inference is one fused launch (layer 1 in registers, layer 2 on
+    FP32 MFMA with W2 in LDS, bias, ReLU and the output layer on the
+    accumulators): against the FP64 oracle network to ~K 2^-24, for sample
+    counts that leave a ragged last group of 16 and span many workgroups."""
+    rng = np.random.default_rng(n)
+    p = ref.init_params(8)
+    z = rng.normal(size=(n, 3))
+    net = E.MLP(ctx, torch.from_numpy(ref.flatten(p)).cuda(), _stats(), E.F32)
+    f = net.forward(torch.from_numpy(z).cuda()).cpu().numpy()
+    f_ref = ref.forward(p, z)
+    assert f.shape == f_ref.shape
+    assert np.abs(f - f_ref).max() < 2e-5 * max(1.0, np.abs(f_ref).max())
+
+
+def test_fp32_guess_matches_oracle(E, ctx):
+    o, v = 7, 19
+    s = make_system(o, v, 33)
+    d = E.DeviceSystem(s)
+    p = ref.init_params(9)
+    net = E.MLP(ctx, torch.from_numpy(ref.flatten(p)).cuda(), _stats(), E.F32)
+    t1, t2 = E.zeros_amps(d, E.CCSD)
+    net.guess(d, t1, t2)
+    g = t2.cpu().numpy()
+    _, d2 = denominators(Fock.from_system(s))
+    want = ref.predict_t2(p, _stats(), Integrals.from_system(s).get("oovv"), d2)
+    assert np.abs(g - want).max() < 2e-5 * np.abs(want).max()
+    assert np.array_equal(g, -g.transpose(1, 0, 2, 3)) and np.array_equal(g, -g.transpose(0, 1, 3, 2))

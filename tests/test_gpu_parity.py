@@ -72,15 +72,41 @@ def test_residual_matches_oracle(E, ctx, method, ov):
     assert abs(e - energy(F, V, t1, t2)) < 1e-13
 
 
-def test_complex_reduced_precision_rejected(E, ctx):
+def test_complex_batch_reduced_precision_rejected(E, ctx):
+    """Batches of complex systems keep FP64 contractions (their grouped
+    launches have no realified complex path)."""
     from paper_2409_06759_amd import _lib as L
     s = make_system(3, 5, 9, is_complex=True)
     d = E.DeviceSystem(s)
-    t1 = torch.zeros((3, 5), dtype=torch.complex128, device="cuda")
-    t2 = torch.zeros((3, 3, 5, 5), dtype=torch.complex128, device="cuda")
     with pytest.raises(L.CCError) as ei:
-        E.residual(ctx, d, E.CCSD, t1, t2, prec=E.F32)
+        E.Batch(ctx, [d], E.CCSD, prec=E.F32)
     assert ei.value.status == L.CC_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("prec,tol", [("f32", 2e-6), ("bf16x3", 5e-5)])
+@pytest.mark.parametrize("ov", [(3, 5), (8, 24), (6, 40)])
+def test_complex_reduced_precision_residual(E, ctx, prec, tol, ov):
+    """Complex residual with the large contractions as real reduced-precision
+    GEMMs on realified operands, against the FP64 oracle.  As for real
+    systems, terms are O(1e-2) with at most 2 v^2 real products each (the
+    realified sum has twice the length), so FP32 gives about
+    2 * 1600 * 2^-24 * 1e-2 ~ 2e-6 at v = 40 in the worst case, split bf16 adds
+    3 * 2^-17 * 1e-2; the plan's flags show which contractions took that path."""
+    o, v = ov
+    s = make_system(o, v, 2100 + o * v, is_complex=True)
+    t1, t2 = _amps(o, v, o * v + 1, cplx=True)
+    F, V = Fock.from_system(s), Integrals.from_system(s)
+    r1_ref, r2_ref = residual(F, V, t1, t2)
+    d = E.DeviceSystem(s)
+    T1, T2 = torch.from_numpy(t1).cuda(), torch.from_numpy(t2).cuda()
+    with E.Plan(ctx, d, E.CCSD, prec=E.PRECS[prec]) as p:
+        r1, r2, rn = p.residual(T1, T2)
+    r2 = r2.cpu().numpy()
+    err = max(np.abs(r2 - r2_ref).max(), np.abs(r1.cpu().numpy() - r1_ref).max())
+    print(f"complex {prec} o={o} v={v}: max err {err:.2e} (tol {tol:.0e})", flush=True)
+    assert err < tol
+    assert err > 1e-11  # reduced-precision rounding, far above FP64's (1e-12 tests above)
+    assert np.array_equal(r2, -r2.transpose(1, 0, 2, 3))
 
 
 @pytest.mark.parametrize("method", ["ccd", "ccsd"])
@@ -369,3 +395,58 @@ def test_hole_hole_ladder_layout_follows_plan_precision(E, ctx, prec, kc):
     with E.Plan(ctx, d, E.CCSD, E.PRECS[prec]) as p:
         line = next(s for s in p.describe().splitlines() if s.startswith("GEMM hh_ladder "))
     assert (" sak=1 " in line and " sbk=1 " in line) == kc, line
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
+def test_complex_mixed_precision_refines_to_fp64_solution(E, ctx, prec):
+    """Complex CCSD with reduced-precision contractions, then the FP64 phase
+    (plain and in reference + correction form): the converged energy equals
+    the FP64 solve's."""
+    o, v = 6, 20
+    s = make_system(o, v, 77, is_complex=True)
+    d = E.DeviceSystem(s)
+    t1, t2 = E.zeros_amps(d, E.CCSD)
+    ref = E.iterate(ctx, d, E.CCSD, t1, t2, tol=1e-11, max_iter=200, dressed=True)
+    assert ref["converged"]
+    for corr in (False, True):
+        t1, t2 = E.zeros_amps(d, E.CCSD)
+        out = E.iterate(ctx, d, E.CCSD, t1, t2, tol=1e-10, max_iter=200, prec=E.PRECS[prec], dressed=True,
+                        correction=corr)
+        print(f"complex {prec} correction={corr}: {out['iters']} it, {out['lowp_iters']} reduced, "
+              f"{out['corr_iters']} corrected, dE={abs(out['energy'] - ref['energy']):.2e}", flush=True)
+        assert out["converged"]
+        assert 0 < out["lowp_iters"] < out["iters"]
+        assert (out["corr_iters"] > 0) == corr
+        assert abs(out["energy"] - ref["energy"]) < 1e-10
+
+
+@pytest.mark.parametrize("prec,eps", [("f32", 2.0 ** -24), ("bf16x3", 2.0 ** -16)])
+def test_complex_correction_form_error_scales_with_the_change(E, ctx, prec, eps):
+    """Complex reference + correction: exact at the reference; at t_ref + delta
+    the error is about eps * |delta| terms, far below the plain error."""
+    o, v = 6, 28
+    s = make_system(o, v, 43, is_complex=True)
+    d = E.DeviceSystem(s)
+    r1, r2 = _amps(o, v, 11, scale=0.05, cplx=True)
+    d1, d2 = _amps(o, v, 12, scale=1e-6, cplx=True)
+    t_ref = [torch.from_numpy(x).cuda() for x in (r1, r2)]
+    t_new = [torch.from_numpy(x).cuda() for x in (r1 + d1, r2 + d2)]
+
+    def res(plan, t):
+        q1, q2, _ = plan.residual(t[0], t[1])
+        return torch.cat([q1.flatten(), q2.flatten()]).cpu().numpy()
+
+    with E.Plan(ctx, d, E.CCSD) as p64:
+        exact_ref, exact_new = res(p64, t_ref), res(p64, t_new)
+    with E.Plan(ctx, d, E.CCSD, prec=E.PRECS[prec]) as p:
+        plain_err = np.abs(res(p, t_new) - exact_new).max()
+        p.set_precision(E.F64)
+        p.set_correction(1, E.PRECS[prec])
+        at_ref = res(p, t_ref)
+        corrected = res(p, t_new)
+    scale = np.abs(exact_new).max()
+    print(f"complex {prec}: plain {plain_err:.2e}, at ref {np.abs(at_ref - exact_ref).max():.2e}, "
+          f"corrected {np.abs(corrected - exact_new).max():.2e} (|R| {scale:.2e})", flush=True)
+    assert np.abs(at_ref - exact_ref).max() < 1e-13 * max(1.0, scale)
+    assert np.abs(corrected - exact_new).max() < 1e-3 * plain_err
+    assert np.abs(corrected - exact_new).max() < 1e3 * eps * 1e-6 * max(1.0, scale)

@@ -20,11 +20,6 @@
 
 #include "plan.hpp"
 
-namespace {
-// iteration graph of a batch: explicit dependencies between the steps
-// (CC_BATCH_GRAPH=dag / serial overrides)
-constexpr bool kBatchDag = false;
-}  // namespace
 
 namespace ccmi {
 namespace {
@@ -43,8 +38,6 @@ struct GStep {
   int64_t sk_blocks = 0;
   size_t sk_entry_off = 0, sk_off_off = 0;
   double flops = 0.0;
-  // earlier steps this one must follow (transitively reduced)
-  std::vector<int> deps;
 };
 
 }  // namespace
@@ -65,9 +58,6 @@ struct cc_batch {
   bool built_for_update = false;
   hipGraphExec_t graph = nullptr;
   bool profiling = false;
-  // the iteration graph: steps as child graphs with explicit dependencies
-  // (independent steps run concurrently), or one serial capture
-  bool dag = false;
   std::vector<hipEvent_t> events;
   std::vector<double> step_ms;
   int64_t prof_calls = 0;
@@ -91,8 +81,6 @@ size_t push_offsets(cc_batch *B, const std::vector<int64_t> &units, int64_t *tot
   *total = off.back();
   return push_entries(B, off);
 }
-
-void plan_deps(cc_batch *B);
 
 // (Re)build the device tables of every grouped step from the plans' current
 // per-call state (amplitude pointers, shift, denominator mode).
@@ -242,7 +230,6 @@ void build_tables(cc_batch *B) {
     }
     B->gsteps.push_back(g);
   }
-  plan_deps(B);
   const size_t bytes = std::max<size_t>(B->host_arena.size(), 256);
   if (bytes > B->arena_bytes) {
     if (B->dev_arena) (void)hipFree(B->dev_arena);
@@ -255,101 +242,6 @@ void build_tables(cc_batch *B) {
   CC_HIP_CHECK(hipStreamSynchronize(B->ctx->stream));
   if (B->graph) (void)hipGraphExecDestroy(B->graph);
   B->graph = nullptr;
-}
-
-// Slots a step reads and writes (slot indices of the plan; the scalar
-// partial sums as pseudo-slots past the last one).  Every plan of a batch
-// has the same slots and steps, so the first plan stands for all.
-void step_rw(const cc_plan *p, const Step &st, std::vector<int> &R, std::vector<int> &W) {
-  const int ns = int(p->slots.size());
-  const int EPART = ns, N2 = ns + 1, N1 = ns + 2, SCAL = ns + 3;
-  auto id = [p](const char *name) {
-    auto it = p->index.find(name);
-    return it == p->index.end() ? -1 : it->second;
-  };
-  auto add = [](std::vector<int> &v, int x) {
-    if (x >= 0) v.push_back(x);
-  };
-  switch (st.kind) {
-    case Step::PERMUTE:
-      add(R, st.a);
-      if (st.perm.beta != 0.0) add(R, st.c);
-      add(W, st.c);
-      break;
-    case Step::GEMM:
-      add(R, st.a);
-      add(R, st.b);
-      if (st.gemm.beta != 0.0) add(R, st.c);
-      add(W, st.c);
-      add(W, st.b2);
-      break;
-    case Step::OUTER:
-      add(R, st.a);
-      add(R, st.b);
-      add(R, st.c);
-      add(W, st.c);
-      break;
-    case Step::FILL:
-      add(W, st.c);
-      break;
-    case Step::TAU_E:
-      for (const char *n : {"t1", "t2", "oovv", "fov"}) add(R, id(n));
-      for (const char *n : {"tau", "taut"}) add(W, id(n));
-      add(W, EPART);
-      break;
-    case Step::ASSEMBLE:
-      for (const char *n : {"XP", "Xij", "Xab", "Xr", "GG", "FF", "t2"}) add(R, id(n));
-      add(W, id("t2"));
-      add(W, N2);
-      break;
-    case Step::R1UPD:
-      for (const char *n : {"R1", "Fmi", "Fae", "t1"}) add(R, id(n));
-      add(W, id("t1"));
-      add(W, N1);
-      break;
-    case Step::FINALIZE:
-      for (int x : {EPART, N2, N1}) add(R, x);
-      add(W, SCAL);
-      break;
-    default:
-      throw CCError(CC_EINTERNAL, "batch: step without read/write sets");
-  }
-}
-
-// Dependencies between the batch's steps (read after write, write after
-// read, write after write), reduced to the steps not already implied through
-// another dependency.
-void plan_deps(cc_batch *B) {
-  const cc_plan *p = B->plans[0];
-  const size_t n = B->gsteps.size();
-  std::vector<std::vector<int>> R(n), W(n);
-  for (size_t k = 0; k < n; ++k) step_rw(p, p->iter[k], R[k], W[k]);
-  auto meets = [](const std::vector<int> &x, const std::vector<int> &y) {
-    for (int a : x)
-      for (int b : y)
-        if (a == b) return true;
-    return false;
-  };
-  // anc[k][j]: step j precedes step k through the dependencies
-  std::vector<std::vector<char>> anc(n, std::vector<char>(n, 0));
-  for (size_t k = 0; k < n; ++k) {
-    std::vector<int> direct;
-    for (size_t j = 0; j < k; ++j)
-      if (meets(W[j], R[k]) || meets(W[j], W[k]) || meets(R[j], W[k])) direct.push_back(int(j));
-    for (int j : direct) {
-      anc[k][j] = 1;
-      for (size_t i = 0; i < n; ++i)
-        if (anc[j][i]) anc[k][i] = 1;
-    }
-    GStep &g = B->gsteps[k];
-    g.deps.clear();
-    for (int j : direct) {  // keep j unless another direct dependency already follows it
-      bool implied = false;
-      for (int i : direct)
-        if (i != j && anc[i][j]) implied = true;
-      if (!implied) g.deps.push_back(j);
-    }
-  }
 }
 
 template <class E>
@@ -447,46 +339,6 @@ void batch_run(cc_batch *B) {
   ++B->prof_calls;
 }
 
-// The iteration as a graph of child graphs, one per step (each captured on
-// its own from the context stream), with the step dependencies as edges:
-// independent steps run concurrently when the graph is replayed.
-void build_dag_graph(cc_batch *B) {
-  hipStream_t s = B->ctx->stream;
-  const size_t n = B->gsteps.size();
-  hipGraph_t parent = nullptr;
-  CC_HIP_CHECK(hipGraphCreate(&parent, 0));
-  try {
-    std::vector<hipGraphNode_t> nodes(n, nullptr);
-    for (size_t k = 0; k < n; ++k) {
-      hipGraph_t child = nullptr;
-      CC_HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-      try {
-        run_gstep(B, k, s);
-      } catch (...) {
-        hipGraph_t dummy;
-        if (hipStreamEndCapture(s, &dummy) == hipSuccess && dummy) (void)hipGraphDestroy(dummy);
-        throw;
-      }
-      CC_HIP_CHECK(hipStreamEndCapture(s, &child));
-      std::vector<hipGraphNode_t> deps;
-      for (int j : B->gsteps[k].deps) deps.push_back(nodes[j]);
-      size_t nchild = 0;
-      hipError_t e = hipGraphGetNodes(child, nullptr, &nchild);
-      if (e == hipSuccess && nchild > 0)
-        e = hipGraphAddChildGraphNode(&nodes[k], parent, deps.empty() ? nullptr : deps.data(), deps.size(), child);
-      else if (e == hipSuccess)
-        e = hipGraphAddEmptyNode(&nodes[k], parent, deps.empty() ? nullptr : deps.data(), deps.size());
-      (void)hipGraphDestroy(child);
-      CC_HIP_CHECK(e);
-    }
-    CC_HIP_CHECK(hipGraphInstantiate(&B->graph, parent, nullptr, nullptr, 0));
-  } catch (...) {
-    (void)hipGraphDestroy(parent);
-    throw;
-  }
-  (void)hipGraphDestroy(parent);
-}
-
 // Time every FP64 tile configuration of each grouped GEMM (a contraction
 // class across the batch) and keep the fastest.
 void batch_autotune(cc_batch *B, int reps) {
@@ -582,9 +434,7 @@ void batch_launch(cc_batch *B, bool use_graph) {
     ccmi::batch_run(B);
     return;
   }
-  if (!B->graph && B->dag) {
-    ccmi::build_dag_graph(B);
-  } else if (!B->graph) {
+  if (!B->graph) {
     hipGraph_t g;
     CC_HIP_CHECK(hipStreamBeginCapture(B->ctx->stream, hipStreamCaptureModeThreadLocal));
     try {
@@ -632,9 +482,6 @@ int cc_batch_create(cc_ctx *ctx, int n, const cc_system *systems, int method, in
       for (cc_plan *p : B->plans)
         if (p->cplx != B->cplx) throw ccmi::CCError(CC_EINVAL, "batch mixes real and complex systems");
       CC_HIP_CHECK(hipMalloc(reinterpret_cast<void **>(&B->scalars), sizeof(double) * 4 * n));
-      // CC_BATCH_GRAPH=serial: the iteration as one serial capture instead of the dependency graph
-      const char *gv = std::getenv("CC_BATCH_GRAPH");
-      B->dag = gv ? std::string(gv) == "dag" : kBatchDag;
       batch_prepare(B, 0.0, 0);
     } catch (...) {
       batch_free(B);

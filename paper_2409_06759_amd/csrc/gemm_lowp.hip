@@ -502,9 +502,153 @@ __device__ __forceinline__ void gemm_b3_dma_body(const GemmDesc &d, int64_t tile
     }
 }
 
+// The same tile with the fragments of the next chunk read from LDS into a
+// second register set while the current chunk's MFMAs run, so that the
+// waves do not all read their fragments at once behind each barrier.  A
+// stage is free for new loads once every wave holds its fragments, so the
+// loads of chunk kt+3 go to the stage of chunk kt right after the barrier
+// that ends its reads; chunks still land two iterations ahead of their
+// reads.  The products and their order are those of gemm_b3_dma_body.
+template <bool HAVE_NEXT>
+__device__ __forceinline__ void b3_read(const unsigned short *St, int wm0, int wn0, int lane, bf8 (&ah)[dma::FM],
+                                        bf8 (&al)[dma::FM], bf8 (&bh)[dma::FN], bf8 (&bl)[dma::FN]) {
+  using namespace dma;
+#pragma unroll
+  for (int i = 0; i < FM; ++i) {
+    const int blk = (wm0 >> 4) + i;
+    ah[i] = *reinterpret_cast<const bf8 *>(St + blk * 512 + lane * 8);
+    al[i] = *reinterpret_cast<const bf8 *>(St + A_EL + blk * 512 + lane * 8);
+  }
+#pragma unroll
+  for (int j = 0; j < FN; ++j) {
+    const int blk = (wn0 >> 4) + j;
+    bh[j] = *reinterpret_cast<const bf8 *>(St + 2 * A_EL + blk * 512 + lane * 8);
+    bl[j] = *reinterpret_cast<const bf8 *>(St + 2 * A_EL + B_EL + blk * 512 + lane * 8);
+  }
+}
+
+// the three products of output block (i, j), in the staged kernel's order
+__device__ __forceinline__ void b3_block(f4 &acc, const bf8 &ah, const bf8 &al, const bf8 &bh, const bf8 &bl) {
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
+}
+
+__device__ __forceinline__ void gemm_b3_dmap_body(const GemmDesc &d, int64_t tilesM, int64_t tilesN, int64_t L0) {
+  using namespace dma;
+  __shared__ __attribute__((aligned(16))) unsigned short S[NSTAGE * STAGE];
+
+  const int64_t tiles = tilesM * tilesN;
+  const int64_t ks = L0 / tiles, L = L0 % tiles;
+  const int64_t m0 = (L % tilesM) * BM, n0 = (L / tilesM) * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm0 = (wave / WN) * (BM / WM), wn0 = (wave % WN) * (BN / WN);
+  const int q = lane >> 4, r = lane & 15;
+  const int64_t M = d.M, N = d.N;
+  const int64_t kchunk = ((d.K + d.split - 1) / d.split + BK - 1) / BK * BK;
+  const int64_t kb = ks * kchunk;
+  const int64_t K = std::max<int64_t>(0, std::min<int64_t>(d.K - kb, kchunk));
+  const int64_t nk = K / BK;
+
+  const uint32_t lds0 = static_cast<uint32_t>(reinterpret_cast<uintptr_t>(S));
+  const unsigned short *src[LOADS];
+  uint32_t dst[LOADS];
+  const unsigned short *Ag = static_cast<const unsigned short *>(d.A) + kb;
+  const unsigned short *Bg = static_cast<const unsigned short *>(d.B) + kb;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int blk = 2 * wave + (u >> 1), pl = u & 1;
+    src[u] = Ag + pl * d.a_plane + std::min<int64_t>(m0 + blk * 16 + r, M - 1) * d.sam + q * 8;
+    dst[u] = __builtin_amdgcn_readfirstlane(lds0 + 2u * uint32_t(pl * A_EL + blk * 512));
+  }
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    src[4 + u] = Bg + u * d.b_plane + std::min<int64_t>(n0 + wave * 16 + r, N - 1) * d.sbn + q * 8;
+    dst[4 + u] = __builtin_amdgcn_readfirstlane(lds0 + 2u * uint32_t(2 * A_EL + u * B_EL + wave * 512));
+  }
+  auto issue = [&](int stage, int64_t k0) {
+#pragma unroll
+    for (int u = 0; u < LOADS; ++u) lds_load16(src[u] + k0, dst[u] + uint32_t(stage) * uint32_t(2 * STAGE));
+  };
+
+  f4 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+
+  bf8 ah0[FM], al0[FM], bh0[FN], bl0[FN], ah1[FM], al1[FM], bh1[FN], bl1[FN];
+  if (nk > 0) {
+    issue(0, 0);
+    if (nk > 1) issue(1, BK);
+    if (nk > 2) issue(2, 2 * BK);
+    // chunk 0 landed: the loads of chunks 1 and 2 may still be in flight
+    if (nk > 2) asm volatile("s_waitcnt vmcnt(12)\n\ts_barrier" ::: "memory");
+    else if (nk > 1) asm volatile("s_waitcnt vmcnt(6)\n\ts_barrier" ::: "memory");
+    else asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
+    b3_read<true>(S, wm0, wn0, lane, ah0, al0, bh0, bl0);
+  }
+  // one step: wait for chunk kt+1 to land and for this wave's reads of chunk
+  // kt; the barrier then frees chunk kt's stage for the loads of chunk kt+3
+  auto step = [&](int64_t kt, bf8 (&ah)[FM], bf8 (&al)[FM], bf8 (&bh)[FN], bf8 (&bl)[FN], bf8 (&nah)[FM],
+                  bf8 (&nal)[FM], bf8 (&nbh)[FN], bf8 (&nbl)[FN]) {
+    if (kt + 2 < nk) asm volatile("s_waitcnt vmcnt(6) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    else if (kt + 1 < nk) asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    else asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    if (kt + 3 < nk) issue(int(kt % NSTAGE), (kt + 3) * BK);
+    // the first block's products wait for this chunk's fragments; the next
+    // chunk's reads go out behind them, so the compiler, which cannot count
+    // sixteen reads in flight, does not make the remaining products wait
+    // for those reads too
+    b3_block(acc[0][0], ah[0], al[0], bh[0], bl[0]);
+    __builtin_amdgcn_sched_barrier(0);
+    if (kt + 1 < nk) b3_read<true>(S + int((kt + 1) % NSTAGE) * STAGE, wm0, wn0, lane, nah, nal, nbh, nbl);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+        if (i + j > 0) b3_block(acc[i][j], ah[i], al[i], bh[j], bl[j]);
+  };
+  for (int64_t kt = 0; kt < nk; kt += 2) {
+    step(kt, ah0, al0, bh0, bl0, ah1, al1, bh1, bl1);
+    if (kt + 1 < nk) step(kt + 1, ah1, al1, bh1, bl1, ah0, al0, bh0, bl0);
+  }
+
+  double *__restrict__ Cp = static_cast<double *>(d.C);
+  double alpha = d.alpha, beta = d.beta;
+  int64_t ldc = d.ldc;
+  if (d.split > 1) {
+    Cp = static_cast<double *>(d.ws) + ks * M * N;
+    alpha = 1.0;
+    beta = 0.0;
+    ldc = N;
+  }
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int64_t gn = n0 + wn0 + j * 16 + r;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int64_t gm = m0 + wm0 + i * 16 + 4 * q + t;
+        if (gm < M && gn < N) {
+          double *p = Cp + gm * ldc + gn;
+          const double v = alpha * static_cast<double>(acc[i][j][t]);
+          *p = (beta == 0.0) ? v : v + beta * *p;
+        }
+      }
+    }
+}
+
 template <int TAG>
 __global__ __launch_bounds__(dma::NT) void gemm_b3_dma_kernel(GemmDesc d, int64_t tilesM, int64_t tilesN) {
   gemm_b3_dma_body(d, tilesM, tilesN, xcd_remap(blockIdx.x, tilesM * tilesN * d.split));
+}
+
+template <int TAG>
+__global__ __launch_bounds__(dma::NT) void gemm_b3_dmap_kernel(GemmDesc d, int64_t tilesM, int64_t tilesN) {
+  gemm_b3_dmap_body(d, tilesM, tilesN, xcd_remap(blockIdx.x, tilesM * tilesN * d.split));
 }
 
 // FP32 variant of the LDS-direct kernel (same tile, stages and waits): the
@@ -728,6 +872,21 @@ int occ_f32_dma() {
   }
   return nb;
 }
+template <int TAG>
+void launch_b3_dmap(const GemmDesc &d, int64_t tm, int64_t tn, hipStream_t s) {
+  if (b3_dma_ok(d))
+    hipLaunchKernelGGL((gemm_b3_dmap_kernel<TAG>), dim3(tm * tn * d.split), dim3(dma::NT), 0, s, d, tm, tn);
+  else
+    launch_l<PREC_BF16X3, 256, 128, 32, 4, 2, true, true, 1, TAG>(d, tm, tn, s);
+}
+int occ_b3_dmap() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gemm_b3_dmap_kernel<0>, dma::NT, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return nb;
+}
 int occ_b3_dma() {
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gemm_b3_dma_kernel<0>, dma::NT, 0) != hipSuccess) {
@@ -780,6 +939,23 @@ const LTile kB3Tiles[] = {
           {CC_LOCC(PREC_BF16X3, 256, 128, 32, 4, 2, false, 1), &occ_l<PREC_BF16X3, 256, 128, 32, 4, 2, false, false, true, 1>,
            &occ_l<PREC_BF16X3, 256, 128, 32, 4, 2, false, true, true, 1>,
            &occ_l<PREC_BF16X3, 256, 128, 32, 4, 2, true, false, true, 1>, &occ_b3_dma}},
+    // the same with the next chunk's fragments read behind the current MFMAs
+    LTile{"256x128x32_w4x2_ldsp",
+          256,
+          128,
+          32,
+          {&launch_l<PREC_BF16X3, 256, 128, 32, 4, 2, false, false, 1>,
+           &launch_l<PREC_BF16X3, 256, 128, 32, 4, 2, false, true, 1>,
+           &launch_l<PREC_BF16X3, 256, 128, 32, 4, 2, true, false, 1>, &launch_b3_dmap<0>},
+          &launch_b3_dmap<1>,
+          &launch_b3_dmap<2>,
+          {&launch_lg<PREC_BF16X3, 256, 128, 32, 4, 2, false, false>,
+           &launch_lg<PREC_BF16X3, 256, 128, 32, 4, 2, false, true>,
+           &launch_lg<PREC_BF16X3, 256, 128, 32, 4, 2, true, false>,
+           &launch_lg<PREC_BF16X3, 256, 128, 32, 4, 2, true, true>},
+          {CC_LOCC(PREC_BF16X3, 256, 128, 32, 4, 2, false, 1), &occ_l<PREC_BF16X3, 256, 128, 32, 4, 2, false, false, true, 1>,
+           &occ_l<PREC_BF16X3, 256, 128, 32, 4, 2, false, true, true, 1>,
+           &occ_l<PREC_BF16X3, 256, 128, 32, 4, 2, true, false, true, 1>, &occ_b3_dmap}},
 };
 constexpr int kNumF32 = sizeof(kF32Tiles) / sizeof(kF32Tiles[0]);
 constexpr int kNumB3 = sizeof(kB3Tiles) / sizeof(kB3Tiles[0]);

@@ -449,12 +449,22 @@ class MLP:
         self.ctx.check(self.ctx.lib.cc_guess_mlp(self.ctx.h, C.byref(dsys.struct), self.prec, _ptr(self.params),
                                                  C.byref(st), C.byref(_amps(t1, t2))))
 
-    def save(self, path):
+    def save(self, path, with_state: bool = False):
+        """Parameters and standardisation; with_state also Adam's moments and
+        step count (to continue training on more data)."""
+        extra = {}
+        if with_state:
+            extra = dict(adam_m=self.m.cpu().numpy(), adam_v=self.v.cpu().numpy(), adam_t=np.array([self.t.value]))
         np.savez(path, params=self.params.cpu().numpy(),
-                 stats=np.array([self.stats[k] for k in ("sx", "mD", "sD", "me", "se", "st")]))
+                 stats=np.array([self.stats[k] for k in ("sx", "mD", "sD", "me", "se", "st")]), **extra)
 
     @classmethod
     def load(cls, ctx: Context, path, prec: int = F32, device="cuda"):
         d = np.load(path, allow_pickle=False)
         keys = ("sx", "mD", "sD", "me", "se", "st")
-        return cls(ctx, torch.from_numpy(d["params"]).to(device), dict(zip(keys, d["stats"].tolist())), prec)
+        net = cls(ctx, torch.from_numpy(d["params"]).to(device), dict(zip(keys, d["stats"].tolist())), prec)
+        if "adam_m" in d:
+            net.m = torch.from_numpy(d["adam_m"]).to(device)
+            net.v = torch.from_numpy(d["adam_v"]).to(device)
+            net.t = C.c_int64(int(d["adam_t"][0]))
+        return net

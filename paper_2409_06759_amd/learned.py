@@ -3,9 +3,9 @@
 Training data are the converged CCSD doubles of generated systems, solved
 on the GPU in batches (dressed-denominator Jacobi to ||R|| < tol); the
 network (``include/cc.h``, cc_mlp_*) is trained with the library's own
-forward/backward kernels and Adam.  For a new system the guess is the
-network's t2 (t1 = 0) unless its residual norm exceeds that of the MP2
-amplitudes t2 = <ab||ij> / D_ij^ab, which are then used instead.
+forward/backward kernels and Adam.  For a new system cc_iterate's MLP guess
+takes the network's t2 (t1 = 0) unless its residual norm exceeds that of the
+MP2 amplitudes t2 = <ab||ij> / D_ij^ab, which are then used instead.
 
     python -m paper_2409_06759_amd.learned train --systems 200 --out mlp.npz
     python -m paper_2409_06759_amd.learned eval --params mlp.npz --o 32 --v 160
@@ -52,9 +52,12 @@ def generate(ctx, shapes, tol=1e-8, group=16, max_iter=400, log=None):
     return torch.cat(raws), torch.cat(ys)
 
 
-def train(ctx, raw, y, epochs=4, batch=65536, lr=1e-3, seed=0, prec=E.F32, log=None):
-    stats = E.MLP.fit_stats(ctx, raw, y)
-    mlp = E.MLP(ctx, E.MLP.init_params(seed, raw.device), stats, prec)
+def train(ctx, raw, y, epochs=4, batch=65536, lr=1e-3, seed=0, prec=E.F32, log=None, mlp=None):
+    """Adam on (raw, y); a fresh network with statistics fitted to this data,
+    or `mlp` (parameters, statistics and Adam state kept) trained further."""
+    if mlp is None:
+        stats = E.MLP.fit_stats(ctx, raw, y)
+        mlp = E.MLP(ctx, E.MLP.init_params(seed, raw.device), stats, prec)
     z, ys = mlp.standardise(raw, y)
     order = torch.from_numpy(np.random.default_rng(seed).permutation(z.shape[0])).to(raw.device)
     t0 = time.perf_counter()
@@ -66,71 +69,35 @@ def train(ctx, raw, y, epochs=4, batch=65536, lr=1e-3, seed=0, prec=E.F32, log=N
     return mlp, hist
 
 
-def mp2_guess(plan, dsys):
-    """t2 = <ab||ij> / D (one Jacobi step from t = 0), t1 = 0."""
-    t1, t2 = E.zeros_amps(dsys, plan.method)
-    plan.step(t1, t2, 0.0, False)
-    if t1 is not None:
-        t1.zero_()
-    return t1, t2
-
-
-def guess_with_fallback(ctx, plan, dsys, mlp):
-    """(t1, t2, source, ||R(mlp)||, ||R(mp2)||, inference seconds)."""
-    t1, t2 = E.zeros_amps(dsys, plan.method)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    mlp.guess(dsys, t1, t2)
-    torch.cuda.synchronize()
-    t_inf = time.perf_counter() - t0
-    _, _, rn_mlp = plan.residual(t1, t2, want_r=False)
-    m1, m2 = mp2_guess(plan, dsys)
-    _, _, rn_mp2 = plan.residual(m1, m2, want_r=False)
-    if rn_mlp <= rn_mp2:
-        return t1, t2, "mlp", rn_mlp, rn_mp2, t_inf
-    return m1, m2, "mp2", rn_mlp, rn_mp2, t_inf
-
-
 def evaluate(ctx, mlp, o=32, v=160, seed=BASE_SEED, tol=1e-8, max_iter=1000, precs=("f64",), log=None):
-    """Iterations and time to ||R|| < tol from the network's guess and from
-    MP2, for each contraction precision in `precs` (reduced ones finish in
-    FP64).  Times include the guess (network inference, or the MP2 step)."""
-    s = make_system(o, v, seed)
-    d = E.DeviceSystem(s, drop_host=True)
+    """Iterations and time to ||R|| < tol from the network's start (cc_iterate's
+    MLP guess with its MP2 fallback), from the MP2 start and from t = 0, for
+    each contraction precision in `precs` (reduced ones finish in FP64).
+    Times include forming the start."""
+    d = E.DeviceSystem(make_system(o, v, seed), drop_host=True)
     res = {"o": o, "v": v}
-    with E.Plan(ctx, d, E.CCSD) as plan:
-        t1, t2, src, rn_mlp, rn_mp2, t_inf = guess_with_fallback(ctx, plan, d, mlp)
-        del t1, t2
-        for pname in precs:
-            for name in ("mlp", "mp2"):
-                a1, a2 = E.zeros_amps(d, E.CCSD)
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                if name == "mlp":
-                    mlp.guess(d, a1, a2)
-                else:
-                    plan.step(a1, a2, 0.0, False)
-                    a1.zero_()
-                torch.cuda.synchronize()
-                t_guess = time.perf_counter() - t0
-                out = E.iterate(ctx, d, E.CCSD, a1, a2, tol=tol, max_iter=max_iter, dressed=True,
-                                prec=E.PRECS[pname], autotune=True)
-                res.setdefault(pname, {})[name] = {
-                    "iterations": out["iters"], "reduced_precision_iterations": out["lowp_iters"],
-                    "seconds": out["seconds"] + t_guess, "guess_seconds": t_guess, "energy": out["energy"],
-                    "converged": out["converged"]}
-                if log:
-                    log(f"[learned] o={o} v={v} {pname} from {name} guess: {out['iters']} it, "
-                        f"{out['seconds'] + t_guess:.2f}s (guess {t_guess * 1e3:.1f} ms), E={out['energy']:.10f}")
-    res["inference_seconds"] = t_inf
-    res["rnorm_guess"] = {"mlp": rn_mlp, "mp2": rn_mp2}
-    res["chosen"] = src
+    for pname in precs:
+        for start in ("mlp", "mp2", "given"):
+            a1, a2 = E.zeros_amps(d, E.CCSD)
+            out = E.iterate(ctx, d, E.CCSD, a1, a2, tol=tol, max_iter=max_iter, dressed=True, prec=E.PRECS[pname],
+                            autotune=True, guess=start, mlp=mlp if start == "mlp" else None)
+            name = "zero" if start == "given" else start
+            res.setdefault(pname, {})[name] = {
+                "iterations": out["iters"], "reduced_precision_iterations": out["lowp_iters"],
+                "seconds": out["seconds"], "guess_seconds": out["guess_seconds"], "guess_used": out["guess_used"],
+                "energy": out["energy"], "converged": out["converged"]}
+            if start == "mlp":
+                res["rnorm_guess"] = out["guess_rnorm"]
+            if log:
+                log(f"[learned] o={o} v={v} {pname} from {name}: {out['iters']} it, {out['seconds']:.2f}s "
+                    f"(guess {out['guess_seconds'] * 1e3:.1f} ms, used {out['guess_used']}), E={out['energy']:.10f}")
     base = res[precs[0]]
     res["mlp"], res["mp2"] = base["mlp"], base["mp2"]
     res["iterations_saved"] = base["mp2"]["iterations"] - base["mlp"]["iterations"]
     res["speedup_vs_mp2"] = base["mp2"]["seconds"] / base["mlp"]["seconds"]
+    res["speedup_vs_zero"] = base["zero"]["seconds"] / base["mlp"]["seconds"]
     if log:
-        log(f"[learned] ||R|| of the guess: mlp {rn_mlp:.3e}, mp2 {rn_mp2:.3e}; inference {t_inf * 1e3:.1f} ms")
+        log(f"[learned] ||R|| of the starts: {res['rnorm_guess']}")
     return res
 
 
@@ -144,6 +111,8 @@ def main(argv=None):
     tr.add_argument("--lr", type=float, default=1e-3)
     tr.add_argument("--group", type=int, default=64, help="systems solved together in one batch")
     tr.add_argument("--tol", type=float, default=1e-8, help="residual norm of the training solutions")
+    tr.add_argument("--shard", default="0/1", help="k/n: train on systems k, k+n, k+2n, ... of the list")
+    tr.add_argument("--resume", help="network (with Adam state) to train further")
     tr.add_argument("--out", required=True)
     tr.add_argument("--eval", action="store_true", help="evaluate on o=32 v=160 after training")
     tr.add_argument("--precs", default="f64", help="contraction precisions of the evaluation")
@@ -157,12 +126,16 @@ def main(argv=None):
     ctx = E.Context(0)
     if args.cmd == "train":
         t0 = time.perf_counter()
-        raw, y = generate(ctx, training_shapes(args.systems), tol=args.tol, group=args.group, log=log)
+        k, n = (int(x) for x in args.shard.split("/"))
+        shapes = training_shapes(args.systems)[k::n]
+        raw, y = generate(ctx, shapes, tol=args.tol, group=args.group, log=log)
         t_gen = time.perf_counter() - t0
-        mlp, hist = train(ctx, raw, y, epochs=args.epochs, batch=args.batch, lr=args.lr, log=log)
-        mlp.save(args.out)
-        summary = {"systems": args.systems, "samples": int(raw.shape[0]), "data_seconds": t_gen,
-                   "loss_per_epoch": hist, "stats": mlp.stats}
+        prev = E.MLP.load(ctx, args.resume) if args.resume else None
+        mlp, hist = train(ctx, raw, y, epochs=args.epochs, batch=args.batch, lr=args.lr, log=log, mlp=prev)
+        mlp.save(args.out, with_state=True)
+        summary = {"systems": args.systems, "shard": args.shard, "shard_systems": len(shapes),
+                   "samples": int(raw.shape[0]), "data_seconds": t_gen, "loss_per_epoch": hist, "stats": mlp.stats,
+                   "adam_steps": mlp.t.value}
         if args.eval:
             summary["eval"] = evaluate(ctx, mlp, precs=tuple(args.precs.split(",")), log=log)
         print(json.dumps(summary))

@@ -282,7 +282,7 @@ def test_gemm_lowp_two_chunk_prefetch_is_bitwise_one_chunk(ctx, monkeypatch, pre
     (1024, 136 * 128, 2048, True, True),   # cut: whole rounds + a K-split tail, both on this kernel
     (300, 270, 160, True, True), (496, 1000, 96, True, True),   # ragged M and N: rows clamped
     (300, 270, 133, True, True), (256, 128, 64, False, True)])  # shapes it hands to the staged kernel
-@pytest.mark.parametrize("prec,staged,direct", [("bf16x3", 7, 9), ("f32", 9, 10)])
+@pytest.mark.parametrize("prec,staged,direct", [("bf16x3", 7, 9), ("bf16x3", 7, 10), ("f32", 9, 10)])
 def test_gemm_lowp_lds_direct_is_bitwise_staged(ctx, monkeypatch, prec, staged, direct, M, N, K, akc, bkc):
     """The 256x128 reduced-precision configurations with LDS-direct loads
     multiply the same fragments in the same order as the register-staged

@@ -336,7 +336,47 @@ def bench_learned(ctx, E, torch, dsys, f64_seconds, precs=("f64", "bf16x3")):
                 f"(guess {r['guess_seconds'] * 1e3:.1f} ms, used {r['guess_used']})")
         rec["speedup_mlp_vs_mp2"] = round(rec["mp2"]["seconds"] / rec["mlp"]["seconds"], 3)
         out[pname] = rec
+    out["network"] = bench_network(ctx, E, torch, dsys, mlp)
     return out
+
+
+# Network flops per sample: two branches (z and z with the integral negated)
+# of Linear 3 -> 128, 128 -> 128, 128 -> 1.  Forward: 2 x 2 x 16,896 MACs.
+# Training adds per branch the gradients of W3, W2, W1 and the layer-2 input
+# (128 + 16,384 + 384 + 16,384 MACs).
+NET_FWD_FLOP = 2 * 2 * (3 * 128 + 128 * 128 + 128)
+NET_TRAIN_FLOP = NET_FWD_FLOP + 2 * 2 * (128 + 128 * 128 + 3 * 128 + 128 * 128)
+FP32_MFMA_PEAK = 157.3e12
+
+
+def bench_network(ctx, E, torch, dsys, mlp, reps=5):
+    """Throughput of the network's kernels on the features of the evaluation
+    system: the fused FP32 forward (inference) and one Adam epoch (minibatches
+    of 65,536) on a copy of the network."""
+    raw = E.MLP.raw_features(ctx, dsys)
+    z, _ = mlp.standardise(raw)
+    n = z.shape[0]
+    mlp.forward(z)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        y = mlp.forward(z)
+    torch.cuda.synchronize()
+    fwd = (time.perf_counter() - t) / reps
+    net = E.MLP(ctx, mlp.params.clone(), mlp.stats, mlp.prec)
+    net.train(z, y, epochs=1)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    net.train(z, y, epochs=1)
+    torch.cuda.synchronize()
+    tr = time.perf_counter() - t
+    rec = {"samples": n, "forward_ms": round(fwd * 1e3, 3),
+           "forward_tflops": round(n * NET_FWD_FLOP / fwd / 1e12, 2),
+           "forward_frac_fp32_mfma_peak": round(n * NET_FWD_FLOP / fwd / FP32_MFMA_PEAK, 3),
+           "train_epoch_ms": round(tr * 1e3, 2), "train_msamples_per_s": round(n / tr / 1e6, 2),
+           "train_tflops": round(n * NET_TRAIN_FLOP / tr / 1e12, 2)}
+    log(f"[bench] network: {rec}")
+    return rec
 
 
 def main():

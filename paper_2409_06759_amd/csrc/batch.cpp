@@ -133,8 +133,9 @@ void build_tables(cc_batch *B) {
             if (B->prec == PREC_F64)
               g.tile = st.tile >= 0 ? st.tile : gemm_f64_pick(st.gemm.M, st.gemm.N, st.gemm.K, g.akc, g.bkc);
             else
-              g.tile = st.tile_lp[B->prec] >= 0 ? st.tile_lp[B->prec]
-                                                 : gemm_lowp_pick(B->prec, st.gemm.M, st.gemm.N);
+              g.tile = st.tile_lp[B->prec] >= 0 && gemm_lowp_tile_grouped(B->prec, st.tile_lp[B->prec])
+                           ? st.tile_lp[B->prec]
+                           : gemm_lowp_pick(B->prec, st.gemm.M, st.gemm.N);
           }
         }
         int bm, bn;
@@ -356,6 +357,7 @@ void batch_autotune(cc_batch *B, int reps) {
       int best = B->gsteps[k].tile;
       float best_ms = 1e30f;
       for (int t = 0; t < ntiles; ++t) {
+        if (prec != PREC_F64 && !gemm_lowp_tile_grouped(prec, t)) continue;
         for (cc_plan *p : B->plans) tile_of(p->iter[k]) = t;
         build_tables(B);
         run_gstep(B, k, s);

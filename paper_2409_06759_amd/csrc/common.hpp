@@ -131,6 +131,7 @@ int gemm_f64_pick(int64_t M, int64_t N, int64_t K, bool a_kc, bool b_kc);
 int gemm_split_pick(int64_t M, int64_t N, int64_t K, int tile_id);
 int gemm_lowp_pick(int prec, int64_t M, int64_t N);
 void gemm_lowp_tile_shape(int prec, int tile_id, int *bm, int *bn);
+bool gemm_lowp_tile_grouped(int prec, int tile_id);  // has a grouped launch
 void gemm_lowp_grouped_launch(const GemmGroupEntry *dev_entries, const int64_t *dev_off, int n, int64_t blocks,
                               bool akc, bool bkc, int prec, int tile_id, hipStream_t s);
 int gemm_lowp_num_tiles(int prec);

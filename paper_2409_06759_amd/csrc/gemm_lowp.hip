@@ -651,6 +651,120 @@ __global__ __launch_bounds__(dma::NT) void gemm_b3_dmap_kernel(GemmDesc d, int64
   gemm_b3_dmap_body(d, tilesM, tilesN, xcd_remap(blockIdx.x, tilesM * tilesN * d.split));
 }
 
+// ---- split bf16, 256x256 tiles with LDS-direct loads -----------------------
+// Eight waves of 128x64 outputs: each fragment read from LDS feeds twice the
+// products it feeds in a 64x64 wave tile along one axis, so LDS reads per
+// product fall by a quarter, and the operand bytes a tile fetches per product
+// fall by a third.  A 32-deep stage is 64 KiB, so two stages fit: chunk kt+1
+// loads while chunk kt is multiplied.  Slot layout, the products of a block
+// and their order, and the epilogue are those of the 256x128 kernel: results
+// are bitwise the same.
+namespace dmw {
+constexpr int BM = 256, BN = 256, BK = 32, WM = 2, WN = 4, NT = WM * WN * kWave;
+constexpr int FM = BM / WM / 16, FN = BN / WN / 16;
+constexpr int A_EL = BM * BK, B_EL = BN * BK;
+constexpr int STAGE = 2 * A_EL + 2 * B_EL;  // [A hi | A lo | B hi | B lo]
+constexpr int NSTAGE = 2;
+constexpr int LOADS = (2 * (BM / 16) + 2 * (BN / 16)) / (WM * WN);  // per wave and chunk
+static_assert(LOADS == 8 && FM == 8 && FN == 4, "wave tiling");
+}  // namespace dmw
+
+__device__ __forceinline__ void gemm_b3_dmw_body(const GemmDesc &d, int64_t tilesM, int64_t tilesN, int64_t L0) {
+  using namespace dmw;
+  __shared__ __attribute__((aligned(16))) unsigned short S[NSTAGE * STAGE];
+
+  const int64_t tiles = tilesM * tilesN;
+  const int64_t ks = L0 / tiles, L = L0 % tiles;
+  const int64_t m0 = (L % tilesM) * BM, n0 = (L / tilesM) * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm0 = (wave / WN) * (BM / WM), wn0 = (wave % WN) * (BN / WN);
+  const int q = lane >> 4, r = lane & 15;
+  const int64_t M = d.M, N = d.N;
+  const int64_t kchunk = ((d.K + d.split - 1) / d.split + BK - 1) / BK * BK;
+  const int64_t kb = ks * kchunk;
+  const int64_t K = std::max<int64_t>(0, std::min<int64_t>(d.K - kb, kchunk));
+  const int64_t nk = K / BK;
+
+  // this wave's loads: blocks 2w and 2w+1 of A and of B, hi and lo planes
+  const uint32_t lds0 = static_cast<uint32_t>(reinterpret_cast<uintptr_t>(S));
+  const unsigned short *src[LOADS];
+  uint32_t dst[LOADS];
+  const unsigned short *Ag = static_cast<const unsigned short *>(d.A) + kb;
+  const unsigned short *Bg = static_cast<const unsigned short *>(d.B) + kb;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int blk = 2 * wave + (u >> 1), pl = u & 1;
+    src[u] = Ag + pl * d.a_plane + std::min<int64_t>(m0 + blk * 16 + r, M - 1) * d.sam + q * 8;
+    dst[u] = __builtin_amdgcn_readfirstlane(lds0 + 2u * uint32_t(pl * A_EL + blk * 512));
+    src[4 + u] = Bg + pl * d.b_plane + std::min<int64_t>(n0 + blk * 16 + r, N - 1) * d.sbn + q * 8;
+    dst[4 + u] = __builtin_amdgcn_readfirstlane(lds0 + 2u * uint32_t(2 * A_EL + pl * B_EL + blk * 512));
+  }
+  auto issue = [&](int stage, int64_t k0) {
+#pragma unroll
+    for (int u = 0; u < LOADS; ++u) lds_load16(src[u] + k0, dst[u] + uint32_t(stage) * uint32_t(2 * STAGE));
+  };
+
+  f4 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+
+  if (nk > 0) issue(0, 0);
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    // chunk kt has landed (the only loads in flight) and this wave has read
+    // chunk kt-1; after the barrier every wave has, so its stage takes kt+1
+    asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    if (kt + 1 < nk) issue(int((kt + 1) & 1), (kt + 1) * BK);
+    const unsigned short *St = S + int(kt & 1) * STAGE;
+    bf8 bh[FN], bl[FN];
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int blk = (wn0 >> 4) + j;
+      bh[j] = *reinterpret_cast<const bf8 *>(St + 2 * A_EL + blk * 512 + lane * 8);
+      bl[j] = *reinterpret_cast<const bf8 *>(St + 2 * A_EL + B_EL + blk * 512 + lane * 8);
+    }
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+      const int blk = (wm0 >> 4) + i;
+      const bf8 ah = *reinterpret_cast<const bf8 *>(St + blk * 512 + lane * 8);
+      const bf8 al = *reinterpret_cast<const bf8 *>(St + A_EL + blk * 512 + lane * 8);
+#pragma unroll
+      for (int j = 0; j < FN; ++j) b3_block(acc[i][j], ah, al, bh[j], bl[j]);
+    }
+  }
+
+  double *__restrict__ Cp = static_cast<double *>(d.C);
+  double alpha = d.alpha, beta = d.beta;
+  int64_t ldc = d.ldc;
+  if (d.split > 1) {
+    Cp = static_cast<double *>(d.ws) + ks * M * N;
+    alpha = 1.0;
+    beta = 0.0;
+    ldc = N;
+  }
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int64_t gn = n0 + wn0 + j * 16 + r;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int64_t gm = m0 + wm0 + i * 16 + 4 * q + t;
+        if (gm < M && gn < N) {
+          double *p = Cp + gm * ldc + gn;
+          const double v = alpha * static_cast<double>(acc[i][j][t]);
+          *p = (beta == 0.0) ? v : v + beta * *p;
+        }
+      }
+    }
+}
+
+template <int TAG>
+__global__ __launch_bounds__(dmw::NT) void gemm_b3_dmw_kernel(GemmDesc d, int64_t tilesM, int64_t tilesN) {
+  gemm_b3_dmw_body(d, tilesM, tilesN, xcd_remap(blockIdx.x, tilesM * tilesN * d.split));
+}
+
 // FP32 variant of the LDS-direct kernel (same tile, stages and waits): the
 // f32 MFMA takes one k per lane and step, lane group q feeding k = 4q + s at
 // step s of each 16-wide k half, so a 16-row block of a k half is 64 slots
@@ -895,6 +1009,25 @@ int occ_b3_dma() {
   }
   return nb;
 }
+template <int TAG>
+void launch_b3_dmw(const GemmDesc &d, int64_t tm, int64_t tn, hipStream_t s) {
+  if (b3_dma_ok(d))
+    hipLaunchKernelGGL((gemm_b3_dmw_kernel<TAG>), dim3(tm * tn * d.split), dim3(dmw::NT), 0, s, d, tm, tn);
+  else  // shapes it does not take: the staged 256x128 kernel over its own tiles
+    launch_l<PREC_BF16X3, 256, 128, 32, 4, 2, true, true, 1, TAG>(d, (d.M + 255) / 256, (d.N + 127) / 128, s);
+}
+template <bool AKC, bool BKC>
+void launch_b3_w_staged(const GemmDesc &d, int64_t, int64_t, hipStream_t s) {
+  launch_l<PREC_BF16X3, 256, 128, 32, 4, 2, AKC, BKC, 1>(d, (d.M + 255) / 256, (d.N + 127) / 128, s);
+}
+int occ_b3_dmw() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gemm_b3_dmw_kernel<0>, dmw::NT, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return nb;
+}
 const LTile kF32Tiles[] = {
     CC_LTILE(PREC_F32, 128, 128, 16, 2, 2, 1), CC_LTILE(PREC_F32, 64, 64, 16, 2, 2, 1),
     CC_LTILE(PREC_F32, 32, 32, 16, 2, 2, 1),   CC_LTILE(PREC_F32, 128, 64, 16, 2, 2, 1),
@@ -956,6 +1089,21 @@ const LTile kB3Tiles[] = {
           {CC_LOCC(PREC_BF16X3, 256, 128, 32, 4, 2, false, 1), &occ_l<PREC_BF16X3, 256, 128, 32, 4, 2, false, false, true, 1>,
            &occ_l<PREC_BF16X3, 256, 128, 32, 4, 2, false, true, true, 1>,
            &occ_l<PREC_BF16X3, 256, 128, 32, 4, 2, true, false, true, 1>, &occ_b3_dmap}},
+    // 256x256 with LDS-direct loads where the shape allows, else the staged
+    // 256x128 kernel over its own tiles; no grouped launches (batches use
+    // per-system tile tables of one tile shape)
+    LTile{"256x256x32_w2x4_lds",
+          256,
+          256,
+          32,
+          {&launch_b3_w_staged<false, false>, &launch_b3_w_staged<false, true>, &launch_b3_w_staged<true, false>,
+           &launch_b3_dmw<0>},
+          &launch_b3_dmw<1>,
+          &launch_b3_dmw<2>,
+          {nullptr, nullptr, nullptr, nullptr},
+          {CC_LOCC(PREC_BF16X3, 256, 128, 32, 4, 2, false, 1), &occ_l<PREC_BF16X3, 256, 128, 32, 4, 2, false, false, true, 1>,
+           &occ_l<PREC_BF16X3, 256, 128, 32, 4, 2, false, true, true, 1>,
+           &occ_l<PREC_BF16X3, 256, 128, 32, 4, 2, true, false, true, 1>, &occ_b3_dmw}},
 };
 constexpr int kNumF32 = sizeof(kF32Tiles) / sizeof(kF32Tiles[0]);
 constexpr int kNumB3 = sizeof(kB3Tiles) / sizeof(kB3Tiles[0]);
@@ -994,6 +1142,7 @@ int pick_l(const LTile *tiles, int64_t M, int64_t N) {
   int best = 0;
   double best_cost = 1e300;
   for (int t = 0; t < count; ++t) {
+    if (!tiles[t].launch_grouped[0]) continue;  // chosen by timing only
     const double n = double((M + tiles[t].BM - 1) / tiles[t].BM) * double((N + tiles[t].BN - 1) / tiles[t].BN);
     const double cost = std::ceil(n / 256.0) * (double(tiles[t].BM) * tiles[t].BN + 4096.0);
     if (cost < best_cost) {
@@ -1192,6 +1341,11 @@ int gemm_lowp_num_tiles(int prec) { return num_l(prec); }
 
 int gemm_lowp_pick(int prec, int64_t M, int64_t N) { return pick_l(prec == PREC_F32 ? kF32Tiles : kB3Tiles, M, N); }
 
+bool gemm_lowp_tile_grouped(int prec, int tile_id) {
+  return tile_id >= 0 && tile_id < num_l(prec) &&
+         (prec == PREC_F32 ? kF32Tiles : kB3Tiles)[tile_id].launch_grouped[0] != nullptr;
+}
+
 void gemm_lowp_tile_shape(int prec, int tile_id, int *bm, int *bn) {
   const LTile &t = (prec == PREC_F32 ? kF32Tiles : kB3Tiles)[tile_id];
   *bm = t.BM;
@@ -1204,6 +1358,7 @@ void gemm_lowp_grouped_launch(const GemmGroupEntry *dev_entries, const int64_t *
   CC_REQUIRE(prec == PREC_F32 || prec == PREC_BF16X3, -1, "grouped gemm: precision");
   CC_REQUIRE(tile_id >= 0 && tile_id < num_l(prec), -7, "grouped gemm: tile");
   CC_REQUIRE(blocks < (int64_t(1) << 31), -1, "grouped gemm: too many tiles");
+  CC_REQUIRE(gemm_lowp_tile_grouped(prec, tile_id), -7, "grouped gemm: tile has no grouped launch");
   (prec == PREC_F32 ? kF32Tiles : kB3Tiles)[tile_id].launch_grouped[(akc ? 2 : 0) + (bkc ? 1 : 0)](
       dev_entries, dev_off, n, blocks, s);
   CC_HIP_CHECK(hipGetLastError());

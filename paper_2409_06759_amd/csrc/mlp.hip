@@ -359,9 +359,13 @@ void forward_fused(const double *P, const double *z, int64_t n, double *f, hipSt
 void dense(int prec, int64_t M, int64_t N, int64_t K, const double *A, int64_t sam, int64_t sak, const double *B,
            int64_t sbn, int64_t sbk, double *C, double beta, double *ws, int64_t ws_elems, hipStream_t s) {
   GemmDesc d{M, N, K, A, sam, sak, B, sbn, sbk, C, N, 1.0, beta};
-  const int split = gemm_split_pick(M, N, K, -1);
-  if (split > 1 && ws && int64_t(split) * M * N <= ws_elems) {
-    d.split = split;
+  // the split-K factor the library picks, down to what the workspace holds
+  // (the weight gradients, K = rows of a minibatch, run on a handful of
+  // output tiles and need the split)
+  int64_t split = gemm_split_pick(M, N, K, -1);
+  if (ws) split = std::min<int64_t>(split, ws_elems / (M * N));
+  if (split > 1 && ws) {
+    d.split = int(split);
     d.ws = ws;
   }
   if (prec == PREC_F64) gemm_f64(d, s, -1);

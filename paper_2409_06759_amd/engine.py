@@ -436,10 +436,15 @@ class MLP:
 
     def train(self, z: torch.Tensor, y: torch.Tensor, epochs: int = 1, batch: int = 65536, lr: float = 1e-3,
               order: Optional[torch.Tensor] = None):
+        """Adam over the rows of z, y in the order given (all rows when None;
+        else the rows `order` lists, which may be a subset)."""
+        n = z.shape[0] if order is None else order.shape[0]
+        if order is not None:
+            assert order.dtype == torch.int64 and order.is_contiguous() and n <= z.shape[0]
         hist = (C.c_double * epochs)()
         self.ctx.enter()
         self.ctx.check(self.ctx.lib.cc_mlp_train(self.ctx.h, self.prec, _ptr(self.params), _ptr(self.m),
-                                                 _ptr(self.v), _ptr(z), _ptr(y), z.shape[0], _ptr(order), batch,
+                                                 _ptr(self.v), _ptr(z), _ptr(y), n, _ptr(order), batch,
                                                  epochs, lr, C.byref(self.t), hist, epochs))
         return list(hist)
 

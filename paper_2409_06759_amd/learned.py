@@ -49,19 +49,48 @@ def generate(ctx, shapes, tol=1e-8, group=16, max_iter=400, log=None):
                 f"({out['n_converged']}/{len(chunk)} converged in this group)")
         del ds
         torch.cuda.empty_cache()
-    return torch.cat(raws), torch.cat(ys)
+    raw, y = torch.cat(raws), torch.cat(ys)
+    if log:
+        log(f"[learned] data: {raw.shape[0]} samples")
+    return raw, y
 
 
 def train(ctx, raw, y, epochs=4, batch=65536, lr=1e-3, seed=0, prec=E.F32, log=None, mlp=None):
     """Adam on (raw, y); a fresh network with statistics fitted to this data,
     or `mlp` (parameters, statistics and Adam state kept) trained further."""
+    t0 = time.perf_counter()
     if mlp is None:
         stats = E.MLP.fit_stats(ctx, raw, y)
         mlp = E.MLP(ctx, E.MLP.init_params(seed, raw.device), stats, prec)
     z, ys = mlp.standardise(raw, y)
-    order = torch.from_numpy(np.random.default_rng(seed).permutation(z.shape[0])).to(raw.device)
+    n = z.shape[0]
+    if log:
+        log(f"[learned] standardised {n} samples ({time.perf_counter() - t0:.1f}s)")
+    gen = torch.Generator(device=raw.device)
+    gen.manual_seed(seed)
+    order = torch.randperm(n, generator=gen, device=raw.device)
+    # the rows are gathered into the shuffled order once: minibatches that
+    # gather single rows from all over a table of 1e8+ rows run several times
+    # slower than contiguous ones
+    z, ys = z[order], ys[order]
+    del order
+    torch.cuda.synchronize()
+    if log:
+        log(f"[learned] shuffled ({time.perf_counter() - t0:.1f}s)")
     t0 = time.perf_counter()
-    hist = mlp.train(z, ys, epochs=epochs, batch=batch, lr=lr, order=order)
+    # every epoch visits the rows in the same shuffled order, in pieces of
+    # whole minibatches so that progress can be reported
+    piece = max(batch, (n // 8) // batch * batch)
+    hist = []
+    for ep in range(epochs):
+        losses, counts = [], []
+        for a in range(0, n, piece):
+            b = min(a + piece, n)
+            losses.append(mlp.train(z[a:b], ys[a:b], epochs=1, batch=batch, lr=lr)[0])
+            counts.append((b - a + batch - 1) // batch)
+            if log:
+                log(f"[learned] epoch {ep}: {min(a + piece, n)}/{n} samples, loss {losses[-1]:.5f}")
+        hist.append(float(np.dot(losses, counts) / sum(counts)))
     torch.cuda.synchronize()
     if log:
         log(f"[learned] trained {epochs} epochs on {z.shape[0]} samples in {time.perf_counter() - t0:.1f}s; "

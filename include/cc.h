@@ -401,8 +401,11 @@ int cc_plan_set_correction(cc_plan *plan, int mode, int prec);
 /* Autotuner: times every instantiated GEMM tile configuration (of the
  * plan's current precision) for each distinct GEMM shape of the plan (reps launches each, on the plan's own
  * buffers, with t as the amplitude operand) and keeps the fastest.  Choices
- * are cached per shape for the life of the process.  Workspace contents are
- * clobbered; the next step recomputes them.  t is only read. */
+ * are cached per shape for the life of the process; if the environment
+ * variable CC_AUTOTUNE_CACHE names a file, choices are also read from it at
+ * the process's first autotune and new ones appended to it (lines
+ * "key tile"), so that separate processes take the same choices.  Workspace
+ * contents are clobbered; the next step recomputes them.  t is only read. */
 int cc_plan_autotune(cc_plan *plan, const cc_amps *t, int reps);
 /* Per-step timing: with enable != 0 every later cc_plan_step /
  * cc_plan_residual records a HIP event after each of its steps on the

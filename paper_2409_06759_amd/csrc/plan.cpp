@@ -21,6 +21,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <mutex>
 #include <set>
 #include <sstream>
@@ -1263,12 +1264,27 @@ void plan_run(cc_plan *p) {
 
 // Time every tile configuration for each distinct GEMM shape of the
 // iteration (on the plan's own buffers) and keep the fastest.  Results are
-// cached per (M, N, K, layouts) for the life of the process.
+// cached per (M, N, K, layouts) for the life of the process; with
+// CC_AUTOTUNE_CACHE naming a file they are also read from it (lines "key
+// tile", at the first autotune of the process) and appended to it, so that
+// another process (a profiler pass, say) takes the same choices.
 void plan_autotune(cc_plan *p, int reps) {
   // shared by every context of the process (contexts may live on different
   // host threads): lookups and inserts are serialised
   static std::map<std::string, int> cache;
   static std::mutex cache_mutex;
+  static bool file_read = false;
+  const char *cache_file = std::getenv("CC_AUTOTUNE_CACHE");
+  if (cache_file && *cache_file) {
+    std::lock_guard<std::mutex> lk(cache_mutex);
+    if (!file_read) {
+      file_read = true;
+      std::ifstream in(cache_file);
+      std::string k;
+      int t;
+      while (in >> k >> t) cache.emplace(k, t);
+    }
+  }
   const int prec_plan = p->cplx ? 9 : p->cur_prec;  // 9: complex128 tiles
   plan_prepare(p);
   hipStream_t s = p->ctx->stream;
@@ -1328,6 +1344,10 @@ void plan_autotune(cc_plan *p, int reps) {
       slot = best;
       lk.lock();
       cache[key] = best;
+      if (cache_file && *cache_file) {
+        std::ofstream out(cache_file, std::ios::app);
+        out << key << " " << best << "\n";
+      }
     }
   } catch (...) {
     (void)hipEventDestroy(e0);

@@ -721,10 +721,30 @@ int cc_gemm(cc_ctx *ctx, int prec, int scalar, int64_t M, int64_t N, int64_t K, 
     }
     else {
       // operands converted once into temporary 4-byte copies (CC_GEMM_LPIN=0:
-      // convert while staging instead)
+      // convert while staging instead); split bf16 on dense K-contiguous rows
+      // with an LDS-direct configuration: copies in 16 x 32 blocks, which
+      // those kernels load whole (CC_GEMM_BLOCKED=0: row-major copies)
       const char *lv = std::getenv("CC_GEMM_LPIN");
+      const char *bv = std::getenv("CC_GEMM_BLOCKED");
       void *sa = nullptr, *sb = nullptr;
-      if (K > 0 && !(lv && lv[0] == '0')) {
+      const bool blocked = K > 0 && !(lv && lv[0] == '0') && !(bv && bv[0] == '0') && prec == CC_PREC_BF16X3 &&
+                           K % 32 == 0 && sak == 1 && sbk == 1 && sam == K && sbn == K &&
+                           ccmi::gemm_lowp_tile_blocked(prec, tile >= 0 ? tile : ccmi::gemm_lowp_pick(prec, M, N));
+      if (blocked) {
+        const int64_t pa = ccmi::blocked_plane(M, K), pb = ccmi::blocked_plane(N, K);
+        CC_HIP_CHECK(hipMalloc(&sa, size_t(pa) * 4));
+        if (hipMalloc(&sb, size_t(pb) * 4) != hipSuccess) {
+          (void)hipFree(sa);
+          throw CCError(CC_ENOMEM, "GEMM operand copy allocation failed");
+        }
+        ccmi::convert_blocked(static_cast<const double *>(A), M, K, sa, ctx->stream);
+        ccmi::convert_blocked(static_cast<const double *>(B), N, K, sb, ctx->stream);
+        d.A = sa;
+        d.B = sb;
+        d.a_plane = pa;
+        d.b_plane = pb;
+        d.lp_in = 2;
+      } else if (K > 0 && !(lv && lv[0] == '0')) {
         const int64_t na = (M - 1) * sam + (K - 1) * sak + 1, nb = (N - 1) * sbn + (K - 1) * sbk + 1;
         CC_HIP_CHECK(hipMalloc(&sa, size_t(na) * 4));
         if (hipMalloc(&sb, size_t(nb) * 4) != hipSuccess) {

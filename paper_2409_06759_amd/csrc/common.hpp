@@ -70,13 +70,22 @@ struct GemmDesc {
   int64_t ws_elems = 0;        // capacity of ws in elements (the tail cut checks it)
   // reduced precision with converted operands ("shadows"): A and B point to
   // FP32 (F32) or to bf16 hi planes whose lo planes follow at +a_plane /
-  // +b_plane elements (BF16X3), indexed exactly like the FP64 tensors.
+  // +b_plane elements (BF16X3), indexed exactly like the FP64 tensors
+  // (lp_in 1), or, split bf16 only, in the 16 x 32 blocks of
+  // convert_blocked (lp_in 2: K-contiguous rows of K, K a multiple of 32;
+  // only the LDS-direct configurations read them).
   int lp_in = 0;
   int64_t a_plane = 0, b_plane = 0;
 };
 
 // FP64 tensor -> reduced-precision shadow with the same element indexing.
 void convert_shadow(int prec, const double *src, int64_t n, void *dst, hipStream_t s);
+// Row-major R x K FP64 operand -> split-bf16 copy in 16-row x 32-k blocks
+// (rows padded to a multiple of 16); each plane holds blocked_plane(R, K)
+// elements, lo after hi.
+int64_t blocked_plane(int64_t R, int64_t K);
+void convert_blocked(const double *src, int64_t R, int64_t K, void *dst, hipStream_t s);
+bool gemm_lowp_tile_blocked(int prec, int tile_id);  // its LDS-direct kernel reads blocked copies
 // dst = reduced-precision (a - ref), same layout as convert_shadow.
 void convert_delta(int prec, const double *a, const double *ref, int64_t n, void *dst, hipStream_t s);
 void copy_f64(double *dst, const double *src, int64_t n, hipStream_t s);

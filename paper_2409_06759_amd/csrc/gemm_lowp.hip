@@ -418,22 +418,30 @@ __device__ __forceinline__ void gemm_b3_dma_body(const GemmDesc &d, int64_t tile
   const uint32_t lds0 = static_cast<uint32_t>(reinterpret_cast<uintptr_t>(S));
   const unsigned short *src[LOADS];
   uint32_t dst[LOADS];
-  const unsigned short *Ag = static_cast<const unsigned short *>(d.A) + kb;
-  const unsigned short *Bg = static_cast<const unsigned short *>(d.B) + kb;
+  // lp_in == 2: operands in 16-row x 32-k blocks of 1 KiB (convert_blocked),
+  // a chunk of a 16-row block one contiguous wave load; 16 elements of a
+  // block per element of k
+  const int64_t kx = d.lp_in == 2 ? 16 : 1;
+  const unsigned short *Ag = static_cast<const unsigned short *>(d.A) + kb * kx;
+  const unsigned short *Bg = static_cast<const unsigned short *>(d.B) + kb * kx;
+  auto row_src = [&](const unsigned short *g, int64_t r0, int64_t lim, int64_t stride) {
+    return kx == 16 ? g + std::min<int64_t>(r0 >> 4, (lim - 1) >> 4) * (d.K * 16) + lane * 8
+                    : g + std::min<int64_t>(r0 + r, lim - 1) * stride + q * 8;
+  };
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int blk = 2 * wave + (u >> 1), pl = u & 1;
-    src[u] = Ag + pl * d.a_plane + std::min<int64_t>(m0 + blk * 16 + r, M - 1) * d.sam + q * 8;
+    src[u] = row_src(Ag + pl * d.a_plane, m0 + blk * 16, M, d.sam);
     dst[u] = __builtin_amdgcn_readfirstlane(lds0 + 2u * uint32_t(pl * A_EL + blk * 512));
   }
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
-    src[4 + u] = Bg + u * d.b_plane + std::min<int64_t>(n0 + wave * 16 + r, N - 1) * d.sbn + q * 8;
+    src[4 + u] = row_src(Bg + u * d.b_plane, n0 + wave * 16, N, d.sbn);
     dst[4 + u] = __builtin_amdgcn_readfirstlane(lds0 + 2u * uint32_t(2 * A_EL + u * B_EL + wave * 512));
   }
   auto issue = [&](int stage, int64_t k0) {
 #pragma unroll
-    for (int u = 0; u < LOADS; ++u) lds_load16(src[u] + k0, dst[u] + uint32_t(stage) * uint32_t(2 * STAGE));
+    for (int u = 0; u < LOADS; ++u) lds_load16(src[u] + k0 * kx, dst[u] + uint32_t(stage) * uint32_t(2 * STAGE));
   };
 
   f4 acc[FM][FN];
@@ -553,22 +561,30 @@ __device__ __forceinline__ void gemm_b3_dmap_body(const GemmDesc &d, int64_t til
   const uint32_t lds0 = static_cast<uint32_t>(reinterpret_cast<uintptr_t>(S));
   const unsigned short *src[LOADS];
   uint32_t dst[LOADS];
-  const unsigned short *Ag = static_cast<const unsigned short *>(d.A) + kb;
-  const unsigned short *Bg = static_cast<const unsigned short *>(d.B) + kb;
+  // lp_in == 2: operands in 16-row x 32-k blocks of 1 KiB (convert_blocked),
+  // a chunk of a 16-row block one contiguous wave load; 16 elements of a
+  // block per element of k
+  const int64_t kx = d.lp_in == 2 ? 16 : 1;
+  const unsigned short *Ag = static_cast<const unsigned short *>(d.A) + kb * kx;
+  const unsigned short *Bg = static_cast<const unsigned short *>(d.B) + kb * kx;
+  auto row_src = [&](const unsigned short *g, int64_t r0, int64_t lim, int64_t stride) {
+    return kx == 16 ? g + std::min<int64_t>(r0 >> 4, (lim - 1) >> 4) * (d.K * 16) + lane * 8
+                    : g + std::min<int64_t>(r0 + r, lim - 1) * stride + q * 8;
+  };
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int blk = 2 * wave + (u >> 1), pl = u & 1;
-    src[u] = Ag + pl * d.a_plane + std::min<int64_t>(m0 + blk * 16 + r, M - 1) * d.sam + q * 8;
+    src[u] = row_src(Ag + pl * d.a_plane, m0 + blk * 16, M, d.sam);
     dst[u] = __builtin_amdgcn_readfirstlane(lds0 + 2u * uint32_t(pl * A_EL + blk * 512));
   }
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
-    src[4 + u] = Bg + u * d.b_plane + std::min<int64_t>(n0 + wave * 16 + r, N - 1) * d.sbn + q * 8;
+    src[4 + u] = row_src(Bg + u * d.b_plane, n0 + wave * 16, N, d.sbn);
     dst[4 + u] = __builtin_amdgcn_readfirstlane(lds0 + 2u * uint32_t(2 * A_EL + u * B_EL + wave * 512));
   }
   auto issue = [&](int stage, int64_t k0) {
 #pragma unroll
-    for (int u = 0; u < LOADS; ++u) lds_load16(src[u] + k0, dst[u] + uint32_t(stage) * uint32_t(2 * STAGE));
+    for (int u = 0; u < LOADS; ++u) lds_load16(src[u] + k0 * kx, dst[u] + uint32_t(stage) * uint32_t(2 * STAGE));
   };
 
   f4 acc[FM][FN];
@@ -689,19 +705,27 @@ __device__ __forceinline__ void gemm_b3_dmw_body(const GemmDesc &d, int64_t tile
   const uint32_t lds0 = static_cast<uint32_t>(reinterpret_cast<uintptr_t>(S));
   const unsigned short *src[LOADS];
   uint32_t dst[LOADS];
-  const unsigned short *Ag = static_cast<const unsigned short *>(d.A) + kb;
-  const unsigned short *Bg = static_cast<const unsigned short *>(d.B) + kb;
+  // lp_in == 2: operands in 16-row x 32-k blocks of 1 KiB (convert_blocked),
+  // a chunk of a 16-row block one contiguous wave load; 16 elements of a
+  // block per element of k
+  const int64_t kx = d.lp_in == 2 ? 16 : 1;
+  const unsigned short *Ag = static_cast<const unsigned short *>(d.A) + kb * kx;
+  const unsigned short *Bg = static_cast<const unsigned short *>(d.B) + kb * kx;
+  auto row_src = [&](const unsigned short *g, int64_t r0, int64_t lim, int64_t stride) {
+    return kx == 16 ? g + std::min<int64_t>(r0 >> 4, (lim - 1) >> 4) * (d.K * 16) + lane * 8
+                    : g + std::min<int64_t>(r0 + r, lim - 1) * stride + q * 8;
+  };
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int blk = 2 * wave + (u >> 1), pl = u & 1;
-    src[u] = Ag + pl * d.a_plane + std::min<int64_t>(m0 + blk * 16 + r, M - 1) * d.sam + q * 8;
+    src[u] = row_src(Ag + pl * d.a_plane, m0 + blk * 16, M, d.sam);
     dst[u] = __builtin_amdgcn_readfirstlane(lds0 + 2u * uint32_t(pl * A_EL + blk * 512));
-    src[4 + u] = Bg + pl * d.b_plane + std::min<int64_t>(n0 + blk * 16 + r, N - 1) * d.sbn + q * 8;
+    src[4 + u] = row_src(Bg + pl * d.b_plane, n0 + blk * 16, N, d.sbn);
     dst[4 + u] = __builtin_amdgcn_readfirstlane(lds0 + 2u * uint32_t(2 * A_EL + pl * B_EL + blk * 512));
   }
   auto issue = [&](int stage, int64_t k0) {
 #pragma unroll
-    for (int u = 0; u < LOADS; ++u) lds_load16(src[u] + k0, dst[u] + uint32_t(stage) * uint32_t(2 * STAGE));
+    for (int u = 0; u < LOADS; ++u) lds_load16(src[u] + k0 * kx, dst[u] + uint32_t(stage) * uint32_t(2 * STAGE));
   };
 
   f4 acc[FM][FN];
@@ -921,6 +945,7 @@ void launch_lg(const GemmGroupEntry *e, const int64_t *off, int n, int64_t block
 // a deeper pipeline, the staging variant is shared by both.
 template <int MODE, int BM, int BN, int BK, int WM, int WN, bool AKC, bool BKC, int PF, int TAG = 0>
 void launch_l(const GemmDesc &d, int64_t tm, int64_t tn, hipStream_t s) {
+  CC_REQUIRE(d.lp_in != 2, -1, "gemm: blocked operand copies need an LDS-direct configuration and shape");
   if (d.lp_in)
     hipLaunchKernelGGL((gemm_lowp_kernel<MODE, BM, BN, BK, WM, WN, AKC, BKC, TAG, true, PF>),
                        dim3(tm * tn * d.split), dim3(WM * WN * kWave), 0, s, d, tm, tn);
@@ -937,6 +962,7 @@ struct LTile {
   void (*launch_ladder_tail)(const GemmDesc &, int64_t, int64_t, hipStream_t);
   void (*launch_grouped[4])(const GemmGroupEntry *, const int64_t *, int, int64_t, hipStream_t);
   int (*occupancy[8])();  // resident workgroups per CU, [lp_in*4 + akc*2 + bkc]
+  bool blocked = false;   // its LDS-direct kernel also reads blocked copies (lp_in == 2)
 };
 
 // workgroups of one configuration resident on a CU (0 if unknown)
@@ -1071,7 +1097,8 @@ const LTile kB3Tiles[] = {
            &launch_lg<PREC_BF16X3, 256, 128, 32, 4, 2, true, true>},
           {CC_LOCC(PREC_BF16X3, 256, 128, 32, 4, 2, false, 1), &occ_l<PREC_BF16X3, 256, 128, 32, 4, 2, false, false, true, 1>,
            &occ_l<PREC_BF16X3, 256, 128, 32, 4, 2, false, true, true, 1>,
-           &occ_l<PREC_BF16X3, 256, 128, 32, 4, 2, true, false, true, 1>, &occ_b3_dma}},
+           &occ_l<PREC_BF16X3, 256, 128, 32, 4, 2, true, false, true, 1>, &occ_b3_dma},
+          true},
     // the same with the next chunk's fragments read behind the current MFMAs
     LTile{"256x128x32_w4x2_ldsp",
           256,
@@ -1088,7 +1115,8 @@ const LTile kB3Tiles[] = {
            &launch_lg<PREC_BF16X3, 256, 128, 32, 4, 2, true, true>},
           {CC_LOCC(PREC_BF16X3, 256, 128, 32, 4, 2, false, 1), &occ_l<PREC_BF16X3, 256, 128, 32, 4, 2, false, false, true, 1>,
            &occ_l<PREC_BF16X3, 256, 128, 32, 4, 2, false, true, true, 1>,
-           &occ_l<PREC_BF16X3, 256, 128, 32, 4, 2, true, false, true, 1>, &occ_b3_dmap}},
+           &occ_l<PREC_BF16X3, 256, 128, 32, 4, 2, true, false, true, 1>, &occ_b3_dmap},
+          true},
     // 256x256 with LDS-direct loads where the shape allows, else the staged
     // 256x128 kernel over its own tiles; no grouped launches (batches use
     // per-system tile tables of one tile shape)
@@ -1103,7 +1131,8 @@ const LTile kB3Tiles[] = {
           {nullptr, nullptr, nullptr, nullptr},
           {CC_LOCC(PREC_BF16X3, 256, 128, 32, 4, 2, false, 1), &occ_l<PREC_BF16X3, 256, 128, 32, 4, 2, false, false, true, 1>,
            &occ_l<PREC_BF16X3, 256, 128, 32, 4, 2, false, true, true, 1>,
-           &occ_l<PREC_BF16X3, 256, 128, 32, 4, 2, true, false, true, 1>, &occ_b3_dmw}},
+           &occ_l<PREC_BF16X3, 256, 128, 32, 4, 2, true, false, true, 1>, &occ_b3_dmw},
+          true},
 };
 constexpr int kNumF32 = sizeof(kF32Tiles) / sizeof(kF32Tiles[0]);
 constexpr int kNumB3 = sizeof(kB3Tiles) / sizeof(kB3Tiles[0]);
@@ -1167,6 +1196,35 @@ __global__ __launch_bounds__(256) void to_bf16x2_kernel(const double *__restrict
     const unsigned short h = bf16_bits(x);
     hi[e] = h;
     lo[e] = bf16_bits(x - bf16_to_float(h));
+  }
+}
+
+// The same split of a row-major R x K operand (K a multiple of 32) into
+// 16-row x 32-k blocks of 512 elements: block (rb, kb) at (rb K/32 + kb) 512,
+// slot s = (row & 15) + 16 ((k & 31) >> 3) holding k & 7 = 0..7 at 8 s (the
+// LDS slot order of the LDS-direct kernels), rows padded with zeros to a
+// multiple of 16; hi plane, then the lo plane `plane` elements further.
+// One thread per slot: eight elements, one 16-byte store per plane.
+__global__ __launch_bounds__(256) void to_bf16x2_blocked_kernel(const double *__restrict__ src, int64_t R, int64_t K,
+                                                                int64_t nslot, int64_t plane,
+                                                                unsigned short *__restrict__ hi) {
+  const int64_t kblocks = K >> 5;
+  for (int64_t t = blockIdx.x * int64_t(256) + threadIdx.x; t < nslot; t += int64_t(gridDim.x) * 256) {
+    const int64_t blk = t >> 6;
+    const int sl = int(t & 63);
+    const int64_t row = (blk / kblocks) * 16 + (sl & 15), k = (blk % kblocks) * 32 + (sl >> 4) * 8;
+    union {
+      uint4 u;
+      unsigned short e[8];
+    } h, l;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const float x = row < R ? static_cast<float>(src[row * K + k + e]) : 0.f;
+      h.e[e] = bf16_bits(x);
+      l.e[e] = bf16_bits(x - bf16_to_float(h.e[e]));
+    }
+    *reinterpret_cast<uint4 *>(hi + 8 * t) = h.u;
+    *reinterpret_cast<uint4 *>(hi + plane + 8 * t) = l.u;
   }
 }
 
@@ -1335,6 +1393,22 @@ void convert_shadow(int prec, const double *src, int64_t n, void *dst, hipStream
   else
     hipLaunchKernelGGL(to_bf16x2_kernel, dim3(blocks), dim3(256), 0, s, src, n, static_cast<unsigned short *>(dst));
   CC_HIP_CHECK(hipGetLastError());
+}
+
+int64_t blocked_plane(int64_t R, int64_t K) { return (R + 15) / 16 * 16 * K; }
+
+void convert_blocked(const double *src, int64_t R, int64_t K, void *dst, hipStream_t s) {
+  CC_REQUIRE(R > 0 && K > 0 && K % 32 == 0, -1, "blocked split-bf16 copy: K must be a multiple of 32");
+  CC_REQUIRE((reinterpret_cast<uintptr_t>(dst) & 15) == 0, -1, "blocked split-bf16 copy: alignment");
+  const int64_t plane = blocked_plane(R, K), nslot = plane / 8;
+  const int64_t blocks = std::min<int64_t>((nslot + 255) / 256, 65536);
+  hipLaunchKernelGGL(to_bf16x2_blocked_kernel, dim3(blocks), dim3(256), 0, s, src, R, K, nslot, plane,
+                     static_cast<unsigned short *>(dst));
+  CC_HIP_CHECK(hipGetLastError());
+}
+
+bool gemm_lowp_tile_blocked(int prec, int tile_id) {
+  return prec == PREC_BF16X3 && tile_id >= 0 && tile_id < num_l(prec) && kB3Tiles[tile_id].blocked;
 }
 
 int gemm_lowp_num_tiles(int prec) { return num_l(prec); }

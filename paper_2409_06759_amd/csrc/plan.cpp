@@ -795,6 +795,37 @@ void use_shadows_c(cc_plan *p, GemmDesc &d, const Step &st, hipStream_t s, bool 
   d.b_plane = 4 * nb;
 }
 
+// The blocked split-bf16 copies serve a contraction when the plan runs in
+// split bf16 and the configuration (the autotuner's, else the default)
+// is an LDS-direct one that reads them, unless the autotuner timed that
+// configuration faster on the row-major copies.
+bool blocked_for(const cc_plan *p, const Step &st, int tile) {
+  if (p->cplx || p->cur_prec != PREC_BF16X3 || st.blk_a < 0 || st.blk_b < 0 || st.blk_use == 0) return false;
+  if (!p->bforms[st.blk_a].ptr || !p->bforms[st.blk_b].ptr) return false;
+  if (tile < 0) tile = gemm_lowp_pick(PREC_BF16X3, st.gemm.M, st.gemm.N);
+  return gemm_lowp_tile_blocked(PREC_BF16X3, tile);
+}
+
+void convert_blocked_form(cc_plan *p, BForm &bf, hipStream_t s) {
+  convert_blocked(static_cast<const double *>(ptr_of(p, bf.slot)), slot_elems(p, bf.slot) / bf.K, bf.K, bf.ptr, s);
+}
+
+// Point a split-bf16 GEMM at the blocked copies of its operands, converting
+// a copy first when its slot was written since the last conversion.
+void use_blocked(cc_plan *p, GemmDesc &d, const Step &st, hipStream_t s, bool convert) {
+  BForm &fa = p->bforms[st.blk_a], &fb = p->bforms[st.blk_b];
+  for (BForm *f : {&fa, &fb})
+    if (convert && !f->ok) {
+      convert_blocked_form(p, *f, s);
+      f->ok = 1;
+    }
+  d.A = fa.ptr;
+  d.B = fb.ptr;
+  d.a_plane = blocked_plane(slot_elems(p, fa.slot) / fa.K, fa.K);
+  d.b_plane = blocked_plane(slot_elems(p, fb.slot) / fb.K, fb.K);
+  d.lp_in = 2;
+}
+
 void run_gemm(cc_plan *p, GemmDesc &d, const Step &st, hipStream_t s) {
   if (p->cplx && (p->cur_prec == PREC_F64 || !st.lowp_ok)) gemm_c128(d, s, st.tile_z);
   else if (p->cplx) {
@@ -802,8 +833,10 @@ void run_gemm(cc_plan *p, GemmDesc &d, const Step &st, hipStream_t s) {
     gemm_lowp(d, p->cur_prec, s, st.tile_lp[p->cur_prec]);
   } else if (p->cur_prec == PREC_F64 || !st.lowp_ok) gemm_f64(d, s, st.tile);
   else {
-    use_shadows(p, d, st, s, true);
-    gemm_lowp(d, p->cur_prec, s, st.tile_lp[p->cur_prec]);
+    const int tile = st.tile_lp[p->cur_prec];
+    if (blocked_for(p, st, tile)) use_blocked(p, d, st, s, true);
+    else use_shadows(p, d, st, s, true);
+    gemm_lowp(d, p->cur_prec, s, tile);
   }
 }
 
@@ -900,6 +933,18 @@ void plan_prepare(cc_plan *p) {
     for (int side = 0; side < 2; ++side) {
       const int sl = side ? st.b : st.a;
       if (!lowp && !p->slots[sl].constant) continue;  // the correction reads its own copy
+      if (lowp && prec == PREC_BF16X3 && (side ? st.blk_b : st.blk_a) >= 0) {
+        BForm &bf = p->bforms[side ? st.blk_b : st.blk_a];
+        if (!bf.ptr) {
+          const int64_t plane = blocked_plane(slot_elems(p, sl) / bf.K, bf.K);
+          CC_HIP_CHECK(hipMalloc(&bf.ptr, size_t(plane) * 2 * sizeof(uint16_t)));
+          bf.prec = -1;
+        }
+        if (p->slots[sl].constant && bf.prec != prec) {
+          convert_blocked_form(p, bf, s);
+          bf.prec = prec;
+        }
+      }
       if (p->cplx && side == 1) {
         CC_REQUIRE(st.bform >= 0, CC_EINTERNAL, "complex B operand copy not planned");
         BForm &bf = p->bforms[st.bform];
@@ -1180,7 +1225,7 @@ void plan_build(cc_plan *p, const cc_system *sys) {
       if (st.kind != Step::GEMM || (!st.lowp_ok && st.delta < 0)) continue;
       int idx = -1;
       for (size_t i = 0; i < p->bforms.size(); ++i)
-        if (p->bforms[i].slot == st.b && p->bforms[i].K == st.gemm.K) idx = int(i);
+        if (p->bforms[i].kind == 0 && p->bforms[i].slot == st.b && p->bforms[i].K == st.gemm.K) idx = int(i);
       if (idx < 0) {
         BForm bf;
         bf.slot = st.b;
@@ -1189,6 +1234,30 @@ void plan_build(cc_plan *p, const cc_system *sys) {
         idx = int(p->bforms.size()) - 1;
       }
       st.bform = idx;
+    }
+  // real split bf16: the large contractions on dense K-contiguous rows (K a
+  // multiple of 32) also get copies of both operands in the 16 x 32 blocks
+  // the LDS-direct kernels load whole (one per slot and row length K);
+  // batched plans run grouped launches on FP64 operands instead
+  if (!p->cplx && !p->lowp_all)
+    for (Step &st : p->iter) {
+      const GemmDesc &g = st.gemm;
+      if (st.kind != Step::GEMM || !st.lowp_ok || g.K <= 0 || g.K % 32 != 0 || g.sak != 1 || g.sbk != 1 ||
+          g.sam != g.K || g.sbn != g.K || g.M < 256 || g.N < 128 || slot_elems(p, st.a) % g.K != 0 ||
+          slot_elems(p, st.b) % g.K != 0)
+        continue;
+      auto form = [p](int slot, int64_t K) {
+        for (size_t i = 0; i < p->bforms.size(); ++i)
+          if (p->bforms[i].kind == 1 && p->bforms[i].slot == slot && p->bforms[i].K == K) return int(i);
+        BForm bf;
+        bf.kind = 1;
+        bf.slot = slot;
+        bf.K = K;
+        p->bforms.push_back(bf);
+        return int(p->bforms.size()) - 1;
+      };
+      st.blk_a = form(st.a, g.K);
+      st.blk_b = form(st.b, g.K);
     }
 }
 
@@ -1303,14 +1372,21 @@ void plan_autotune(cc_plan *p, int reps) {
       const int ntiles = cz ? gemm_c128_num_tiles()
                             : (prec == PREC_F64 ? gemm_f64_num_tiles() : gemm_lowp_num_tiles(prec));
       const int64_t rN = (p->cplx && lowp) ? 2 * d.N : d.N, rK = (p->cplx && lowp) ? 2 * d.K : d.K;
+      // blocked split-bf16 copies available: the LDS-direct configurations
+      // are timed on them (a choice of its own in the cache)
+      const bool blk = lowp && !p->cplx && prec == PREC_BF16X3 && st->blk_a >= 0 && st->blk_b >= 0 &&
+                       p->bforms[st->blk_a].ptr && p->bforms[st->blk_b].ptr;
       const std::string key = std::to_string(prec) + ":" + std::to_string(d.M) + "x" +
                               std::to_string(rN) + "x" + std::to_string(rK) + (akc ? "k" : "m") +
-                              (bkc ? "k" : "n");
+                              (bkc ? "k" : "n") + (blk ? "b" : "");
       int &slot = cz ? st->tile_z : (prec == PREC_F64 ? st->tile : st->tile_lp[prec]);
       std::unique_lock<std::mutex> lk(cache_mutex);
       auto it = cache.find(key);
+      // cached value: the tile, plus kBlockedChoice when it runs on the blocked copies
+      constexpr int kBlockedChoice = 1000;
       if (it != cache.end()) {
-        slot = it->second;
+        slot = it->second % kBlockedChoice;
+        if (blk) st->blk_use = it->second >= kBlockedChoice ? 1 : 0;
         continue;
       }
       lk.unlock();
@@ -1319,34 +1395,42 @@ void plan_autotune(cc_plan *p, int reps) {
       d.C = ptr_of(p, st->c);
       d.ws = st->b2 >= 0 ? ptr_of(p, st->b2) : nullptr;
       d.ws_elems = st->b2 >= 0 ? p->slots[st->b2].elems : 0;
+      GemmDesc db = d;
       if (lowp && p->cplx) use_shadows_c(p, d, *st, s, false);
       else if (lowp) use_shadows(p, d, *st, s, false);
-      int best = slot;
+      if (blk) use_blocked(p, db, *st, s, false);
+      int best = slot, best_blk = 0;
       float best_ms = 1e30f;
-      auto launch = [&](int t) {
+      auto launch = [&](int t, int b) {
         if (cz) gemm_c128(d, s, t);
         else if (prec == PREC_F64) gemm_f64(d, s, t);
-        else gemm_lowp(d, prec, s, t);
+        else gemm_lowp(b ? db : d, prec, s, t);
       };
-      for (int t = 0; t < ntiles; ++t) {
-        launch(t);
-        CC_HIP_CHECK(hipEventRecord(e0, s));
-        for (int r = 0; r < reps; ++r) launch(t);
-        CC_HIP_CHECK(hipEventRecord(e1, s));
-        CC_HIP_CHECK(hipEventSynchronize(e1));
-        float ms = 0.f;
-        CC_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best_ms) {
-          best_ms = ms;
-          best = t;
+      // every configuration on the row-major copies, and the LDS-direct
+      // ones also on the blocked copies
+      for (int t = 0; t < ntiles; ++t)
+        for (int b = 0; b < ((blk && gemm_lowp_tile_blocked(prec, t)) ? 2 : 1); ++b) {
+          launch(t, b);
+          CC_HIP_CHECK(hipEventRecord(e0, s));
+          for (int r = 0; r < reps; ++r) launch(t, b);
+          CC_HIP_CHECK(hipEventRecord(e1, s));
+          CC_HIP_CHECK(hipEventSynchronize(e1));
+          float ms = 0.f;
+          CC_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+          if (ms < best_ms) {
+            best_ms = ms;
+            best = t;
+            best_blk = b;
+          }
         }
-      }
       slot = best;
+      if (blk) st->blk_use = best_blk;
+      const int value = best + (best_blk ? kBlockedChoice : 0);
       lk.lock();
-      cache[key] = best;
+      cache[key] = value;
       if (cache_file && *cache_file) {
         std::ofstream out(cache_file, std::ios::app);
-        out << key << " " << best << "\n";
+        out << key << " " << value << "\n";
       }
     }
   } catch (...) {

@@ -39,6 +39,7 @@ struct OpSpec {
 // Realified copy of a complex slot read as the B operand of reduced-precision
 // GEMMs with rows of K complex elements (the layout depends on K).
 struct BForm {
+  int kind = 0;   // 0: complex realified B' copy; 1: real split-bf16 copy in 16 x 32 blocks (A or B side)
   int slot = -1;
   int64_t K = 0;
   void *ptr = nullptr;
@@ -67,6 +68,8 @@ struct Step {
   int tile_z = -1;      // complex128 tile
   int delta = -1;       // index into cc_plan::deltas (GEMM linear in the amplitudes)
   int bform = -1;       // complex reduced precision: index into cc_plan::bforms of the B operand
+  int blk_a = -1, blk_b = -1;  // real split bf16: blocked copies (cc_plan::bforms) of A and B, or -1
+  int blk_use = -1;            // autotuner: 1 blocked copies, 0 row-major copies, -1 blocked if the tile reads them
   bool lowp_ok = true;  // runs in the plan's reduced precision (else FP64: under 1% of the work)
   // PAIR: slot a -> slot c through index-pair tables (PairEntry): mode 0
   // gathers packed rows/columns, 1 scatter-adds, 2 scatter-sets; tables:

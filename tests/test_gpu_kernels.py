@@ -276,6 +276,34 @@ def test_gemm_lowp_two_chunk_prefetch_is_bitwise_one_chunk(ctx, monkeypatch, pre
     assert np.abs(out[1] - ref).max() <= tol * max(1.0, np.sqrt(K))
 
 
+@pytest.mark.parametrize("M,N,K", [
+    (256, 128, 32), (512, 256, 96), (300, 270, 160), (496, 1000, 96), (37, 300, 64),
+    (1024, 136 * 128, 2048)])  # cut: whole rounds + a K-split tail
+@pytest.mark.parametrize("tile", [9, 10, 11])
+def test_gemm_bf16x3_blocked_copies_are_bitwise_row_major(ctx, monkeypatch, tile, M, N, K):
+    """Split-bf16 operand copies in 16-row x 32-k blocks (rows padded to a
+    multiple of 16) put the same values in the same LDS slots as the
+    row-major copies: every LDS-direct configuration gives bit-identical
+    results with either, on ragged M and N, padded rows and the K-split tail."""
+    from paper_2409_06759_amd import engine as E
+    print(f"blocked tile {tile} M={M} N={N} K={K}", flush=True)
+    rng = np.random.default_rng(M + 7 * N + K)
+    A = rng.normal(size=(M, K))
+    B = rng.normal(size=(N, K))
+    C0 = rng.normal(size=(M, N))
+    Ad, Bd = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    monkeypatch.setenv("CC_GEMM_TILE", str(tile))
+    out = []
+    for blocked in ("0", "1"):
+        monkeypatch.setenv("CC_GEMM_BLOCKED", blocked)
+        Cd = torch.from_numpy(C0).cuda()
+        E.gemm(ctx, Ad, Bd, Cd, 0.5, -1.25, prec=E.PRECS["bf16x3"])
+        out.append(Cd.cpu().numpy())
+    assert np.array_equal(out[0], out[1])
+    ref = 0.5 * (A @ B.T) - 1.25 * C0
+    assert np.abs(out[1] - ref).max() <= 1e-3 * max(1.0, np.sqrt(K))
+
+
 @pytest.mark.parametrize("M,N,K,akc,bkc", [
     (256, 128, 32, True, True), (256, 128, 64, True, True), (512, 256, 96, True, True),
     (256, 384, 160, True, True), (768, 256, 1024, True, True),

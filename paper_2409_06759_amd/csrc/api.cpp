@@ -737,8 +737,8 @@ int cc_gemm(cc_ctx *ctx, int prec, int scalar, int64_t M, int64_t N, int64_t K, 
           (void)hipFree(sa);
           throw CCError(CC_ENOMEM, "GEMM operand copy allocation failed");
         }
-        ccmi::convert_blocked(static_cast<const double *>(A), M, K, sa, ctx->stream);
-        ccmi::convert_blocked(static_cast<const double *>(B), N, K, sb, ctx->stream);
+        ccmi::convert_blocked(static_cast<const double *>(A), nullptr, M, K, sa, ctx->stream);
+        ccmi::convert_blocked(static_cast<const double *>(B), nullptr, N, K, sb, ctx->stream);
         d.A = sa;
         d.B = sb;
         d.a_plane = pa;

@@ -80,11 +80,11 @@ struct GemmDesc {
 
 // FP64 tensor -> reduced-precision shadow with the same element indexing.
 void convert_shadow(int prec, const double *src, int64_t n, void *dst, hipStream_t s);
-// Row-major R x K FP64 operand -> split-bf16 copy in 16-row x 32-k blocks
-// (rows padded to a multiple of 16); each plane holds blocked_plane(R, K)
-// elements, lo after hi.
+// Row-major R x K FP64 operand (minus ref, if not NULL) -> split-bf16 copy
+// in 16-row x 32-k blocks (rows padded to a multiple of 16); each plane
+// holds blocked_plane(R, K) elements, lo after hi.
 int64_t blocked_plane(int64_t R, int64_t K);
-void convert_blocked(const double *src, int64_t R, int64_t K, void *dst, hipStream_t s);
+void convert_blocked(const double *src, const double *ref, int64_t R, int64_t K, void *dst, hipStream_t s);
 bool gemm_lowp_tile_blocked(int prec, int tile_id);  // its LDS-direct kernel reads blocked copies
 // dst = reduced-precision (a - ref), same layout as convert_shadow.
 void convert_delta(int prec, const double *a, const double *ref, int64_t n, void *dst, hipStream_t s);

@@ -1205,7 +1205,9 @@ __global__ __launch_bounds__(256) void to_bf16x2_kernel(const double *__restrict
 // LDS slot order of the LDS-direct kernels), rows padded with zeros to a
 // multiple of 16; hi plane, then the lo plane `plane` elements further.
 // One thread per slot: eight elements, one 16-byte store per plane.
-__global__ __launch_bounds__(256) void to_bf16x2_blocked_kernel(const double *__restrict__ src, int64_t R, int64_t K,
+// With ref, the copy is of src - ref (the correction form's varying operand).
+__global__ __launch_bounds__(256) void to_bf16x2_blocked_kernel(const double *__restrict__ src,
+                                                                const double *__restrict__ ref, int64_t R, int64_t K,
                                                                 int64_t nslot, int64_t plane,
                                                                 unsigned short *__restrict__ hi) {
   const int64_t kblocks = K >> 5;
@@ -1219,7 +1221,8 @@ __global__ __launch_bounds__(256) void to_bf16x2_blocked_kernel(const double *__
     } h, l;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      const float x = row < R ? static_cast<float>(src[row * K + k + e]) : 0.f;
+      const int64_t at = row * K + k + e;
+      const float x = row < R ? static_cast<float>(ref ? src[at] - ref[at] : src[at]) : 0.f;
       h.e[e] = bf16_bits(x);
       l.e[e] = bf16_bits(x - bf16_to_float(h.e[e]));
     }
@@ -1397,12 +1400,12 @@ void convert_shadow(int prec, const double *src, int64_t n, void *dst, hipStream
 
 int64_t blocked_plane(int64_t R, int64_t K) { return (R + 15) / 16 * 16 * K; }
 
-void convert_blocked(const double *src, int64_t R, int64_t K, void *dst, hipStream_t s) {
+void convert_blocked(const double *src, const double *ref, int64_t R, int64_t K, void *dst, hipStream_t s) {
   CC_REQUIRE(R > 0 && K > 0 && K % 32 == 0, -1, "blocked split-bf16 copy: K must be a multiple of 32");
   CC_REQUIRE((reinterpret_cast<uintptr_t>(dst) & 15) == 0, -1, "blocked split-bf16 copy: alignment");
   const int64_t plane = blocked_plane(R, K), nslot = plane / 8;
   const int64_t blocks = std::min<int64_t>((nslot + 255) / 256, 65536);
-  hipLaunchKernelGGL(to_bf16x2_blocked_kernel, dim3(blocks), dim3(256), 0, s, src, R, K, nslot, plane,
+  hipLaunchKernelGGL(to_bf16x2_blocked_kernel, dim3(blocks), dim3(256), 0, s, src, ref, R, K, nslot, plane,
                      static_cast<unsigned short *>(dst));
   CC_HIP_CHECK(hipGetLastError());
 }

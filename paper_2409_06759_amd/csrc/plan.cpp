@@ -807,7 +807,8 @@ bool blocked_for(const cc_plan *p, const Step &st, int tile) {
 }
 
 void convert_blocked_form(cc_plan *p, BForm &bf, hipStream_t s) {
-  convert_blocked(static_cast<const double *>(ptr_of(p, bf.slot)), slot_elems(p, bf.slot) / bf.K, bf.K, bf.ptr, s);
+  convert_blocked(static_cast<const double *>(ptr_of(p, bf.slot)), nullptr, slot_elems(p, bf.slot) / bf.K, bf.K,
+                  bf.ptr, s);
 }
 
 // Point a split-bf16 GEMM at the blocked copies of its operands, converting
@@ -882,6 +883,35 @@ void run_delta_gemm(cc_plan *p, GemmDesc &d, const Step &st, hipStream_t s) {
     g.b_plane = 4 * slot_elems(p, st.b);
     g.beta = 1.0;
     gemm_lowp(g, p->delta_prec, s, st.tile_lp[p->delta_prec]);
+    return;
+  }
+  // split bf16 with blocked copies (prepared by an earlier split-bf16 run)
+  // and an LDS-direct configuration: (X - X_ref) blocked as well
+  const int con_blk = r.var ? st.blk_a : st.blk_b;
+  const int tile = st.tile_lp[p->delta_prec];
+  if (p->delta_prec == PREC_BF16X3 && r.dblk && con_blk >= 0 && st.blk_use != 0 && p->bforms[con_blk].ptr &&
+      p->bforms[con_blk].prec == PREC_BF16X3 &&
+      gemm_lowp_tile_blocked(PREC_BF16X3, tile >= 0 ? tile : gemm_lowp_pick(PREC_BF16X3, d.M, d.N))) {
+    const BForm &cf = p->bforms[con_blk];
+    const int64_t rows = r.n_op / d.K;
+    convert_blocked(X, r.ref_op, rows, d.K, r.dblk, s);
+    add_product(C, d.ldc, d.beta, r.ref_out, d.M, d.N, s);
+    GemmDesc g = d;
+    const int64_t vplane = blocked_plane(rows, d.K), cplane = blocked_plane(slot_elems(p, cf.slot) / cf.K, cf.K);
+    if (r.var) {
+      g.A = cf.ptr;
+      g.a_plane = cplane;
+      g.B = r.dblk;
+      g.b_plane = vplane;
+    } else {
+      g.A = r.dblk;
+      g.a_plane = vplane;
+      g.B = cf.ptr;
+      g.b_plane = cplane;
+    }
+    g.lp_in = 2;
+    g.beta = 1.0;
+    gemm_lowp(g, PREC_BF16X3, s, tile);
     return;
   }
   CC_REQUIRE(p->shadow.size() == p->slots.size() && p->shadow[con_slot] &&
@@ -975,6 +1005,9 @@ void plan_prepare(cc_plan *p) {
       if (!d.ref_op) CC_HIP_CHECK(hipMalloc(reinterpret_cast<void **>(&d.ref_op), size_t(d.n_op) * w * 8));
       if (!d.ref_out) CC_HIP_CHECK(hipMalloc(reinterpret_cast<void **>(&d.ref_out), size_t(g.M) * g.N * w * 8));
       if (!d.dshadow) CC_HIP_CHECK(hipMalloc(&d.dshadow, size_t(d.n_op) * wd * 4));
+      const Step &ds = p->iter[d.step];
+      if (!p->cplx && prec == PREC_BF16X3 && ds.blk_a >= 0 && ds.blk_b >= 0 && !d.dblk)
+        CC_HIP_CHECK(hipMalloc(&d.dblk, size_t(blocked_plane(d.n_op / g.K, g.K)) * 4));
     }
   }
 }
@@ -1275,10 +1308,10 @@ void plan_free(cc_plan *p) {
     if (bf.ptr) (void)hipFree(bf.ptr);
   p->bforms.clear();
   for (DeltaRef &d : p->deltas) {
-    for (void *q : {static_cast<void *>(d.ref_op), static_cast<void *>(d.ref_out), d.dshadow})
+    for (void *q : {static_cast<void *>(d.ref_op), static_cast<void *>(d.ref_out), d.dshadow, d.dblk})
       if (q) (void)hipFree(q);
     d.ref_op = d.ref_out = nullptr;
-    d.dshadow = nullptr;
+    d.dshadow = d.dblk = nullptr;
   }
   for (double *q : {p->d_oo, p->d_vv, p->epart, p->n2part, p->n1part, p->scalars, p->n3part})
     if (q) (void)hipFree(q);
@@ -1453,10 +1486,12 @@ std::string plan_profile_table(const cc_plan *p) {
     std::string tag = st.tag.empty() ? "-" : st.tag;
     for (auto &c : tag)
       if (c == ' ') c = '_';
-    if (st.kind == Step::GEMM)
+    if (st.kind == Step::GEMM) {
       tag += "@" + std::string((p->cur_prec != PREC_F64 && st.lowp_ok) ? gemm_lowp_tile_name(p->cur_prec, st.tile_lp[p->cur_prec])
                                : p->cplx                                  ? gemm_c128_tile_name(st.tile_z)
                                                                           : gemm_f64_tile_name(st.tile));
+      if (st.lowp_ok && blocked_for(p, st, st.tile_lp[PREC_BF16X3])) tag += "/blk";  // blocked copies
+    }
     os << i << " " << kinds[st.kind] << " " << tag << " " << p->step_calls[i]
        << " " << p->step_ms[i] << " " << (p->step_calls[i] ? p->step_ms[i] / p->step_calls[i] : 0.0)
        << " " << st.flops << "\n";

@@ -91,6 +91,7 @@ struct DeltaRef {
   double *ref_op = nullptr;       // FP64 copy of the varying operand at the reference
   double *ref_out = nullptr;      // alpha * X_ref Y, dense M x N
   void *dshadow = nullptr;        // reduced-precision (X - X_ref)
+  void *dblk = nullptr;           // split bf16 (X - X_ref) in 16 x 32 blocks (steps with blocked copies)
 };
 
 // A caller-supplied contraction list (e.g. emitted by the diagram

@@ -320,6 +320,55 @@ def test_mixed_precision_refines_to_fp64_solution(E, ctx, prec):
         assert abs(out["energy"] - ref["energy"]) < 1e-10
 
 
+def test_blocked_split_bf16_copies_in_plans(E, ctx):
+    """At o=16, v=64 the ladder, Z, the ring terms and W_mnij's tau term are
+    large enough for the split-bf16 copies in 16 x 32 blocks; after
+    autotuning, the plain split-bf16 residual and the reference + correction
+    one keep the errors they have with row-major copies (a wrong block
+    layout would make them of the order of the residual itself)."""
+    o, v = 16, 64
+    s = make_system(o, v, 43)
+    d = E.DeviceSystem(s)
+    rng = np.random.default_rng(10)
+
+    def amps(scale):
+        a1 = rng.normal(size=(o, v)) * scale
+        a2 = rng.normal(size=(o, o, v, v)) * scale
+        a2 = a2 - a2.transpose(1, 0, 2, 3)
+        a2 = a2 - a2.transpose(0, 1, 3, 2)
+        return a1, a2
+
+    r1, r2 = amps(0.02)
+    d1, d2 = amps(1e-6)
+    t_ref = [torch.from_numpy(x).cuda() for x in (r1, r2)]
+    t_new = [torch.from_numpy(x).cuda() for x in (r1 + d1, r2 + d2)]
+
+    def res(plan, t):
+        q1, q2, _ = plan.residual(t[0], t[1])
+        return torch.cat([q1.flatten(), q2.flatten()]).cpu().numpy()
+
+    with E.Plan(ctx, d, E.CCSD) as p64:
+        exact_ref, exact_new = res(p64, t_ref), res(p64, t_new)
+    scale = np.abs(exact_new).max()
+    with E.Plan(ctx, d, E.CCSD, prec=E.PRECS["bf16x3"]) as p:
+        p.autotune(t_ref[0], t_ref[1])
+        p.profile(True)
+        plain = res(p, t_new)
+        tags = [row[2] for row in p.profile_table() if row[1] == "GEMM"]
+        p.profile(False)
+        plain_err = np.abs(plain - exact_new).max()
+        p.set_precision(E.F64)
+        p.set_correction(1, E.PRECS["bf16x3"])
+        at_ref = res(p, t_ref)
+        corrected = res(p, t_new)
+    print(f"blocked tags {[t for t in tags if t.endswith('/blk')]}; plain {plain_err:.2e}, "
+          f"corrected {np.abs(corrected - exact_new).max():.2e} (|R| {scale:.2e})", flush=True)
+    assert any(t.endswith("/blk") for t in tags)
+    assert plain_err < 1e-4 * scale
+    assert np.abs(at_ref - exact_ref).max() < 1e-13 * max(1.0, scale)
+    assert np.abs(corrected - exact_new).max() < 1e-3 * plain_err
+
+
 @pytest.mark.parametrize("prec,eps", [("f32", 2.0 ** -24), ("bf16x3", 2.0 ** -16)])
 def test_correction_form_error_scales_with_the_change(E, ctx, prec, eps):
     """Reference + correction: at the reference amplitudes the residual is

@@ -96,6 +96,11 @@ void copy_f64(double *dst, const double *src, int64_t n, hipStream_t s);
 // dense rows of 2K, FP32 or a bf16 hi plane followed by a lo plane.
 void realify_complex(int prec, int side, const double *src, const double *ref, int64_t R, int64_t K, int64_t sr,
                      int64_t sk, void *dst, hipStream_t s);
+// The same split-bf16 copies of dense rows (sr = K, sk = 1) in the 16 x 32
+// blocks of convert_blocked (rows of 2K, K a multiple of 16): planes of
+// blocked_plane(R, 2K) (side 0) or blocked_plane(2R, 2K) (side 1) elements;
+// rows past the copy's are left as they are.
+void realify_complex_blocked(int side, const double *src, int64_t R, int64_t K, void *dst, hipStream_t s);
 // The real reduced-precision GEMM (M x 2N x 2K) on realified operands that
 // computes the complex GEMM d in its interleaved output layout.
 GemmDesc realified_desc(const GemmDesc &d, const void *a_form, const void *b_form);

@@ -1291,12 +1291,20 @@ __device__ __forceinline__ void put_lp(void *dst, int64_t plane, int64_t i, doub
   }
 }
 
-// one thread per complex element (r, k), k fastest; SIDE 0 writes A', 1 B'
-template <int MODE, int SIDE, bool REF>
+// element (row, k) of a real operand with rows of Kr (a multiple of 32) in
+// the 16 x 32 blocks of convert_blocked
+__device__ __forceinline__ int64_t blocked_at(int64_t row, int64_t k, int64_t Kr) {
+  return ((row >> 4) * (Kr >> 5) + (k >> 5)) * 512 + ((row & 15) + 16 * ((k & 31) >> 3)) * 8 + (k & 7);
+}
+
+// one thread per complex element (r, k), k fastest; SIDE 0 writes A', 1 B';
+// BLK: in 16 x 32 blocks (split bf16; rows of 2K, planes padded to 16 rows)
+template <int MODE, int SIDE, bool REF, bool BLK>
 __global__ __launch_bounds__(256) void realify_kernel(const double2 *__restrict__ src, const double2 *__restrict__ ref,
                                                       int64_t R, int64_t K, int64_t sr, int64_t sk, void *dst) {
   const int64_t total = R * K;
-  const int64_t plane = (SIDE == 0 ? 2 : 4) * total;
+  const int64_t plane = BLK ? (((SIDE == 0 ? R : 2 * R) + 15) / 16 * 16) * 2 * K : (SIDE == 0 ? 2 : 4) * total;
+  auto at = [K](int64_t row, int64_t kk) { return BLK ? blocked_at(row, kk, 2 * K) : row * 2 * K + kk; };
   for (int64_t e = blockIdx.x * int64_t(256) + threadIdx.x; e < total; e += int64_t(gridDim.x) * 256) {
     const int64_t r = e / K, k = e - r * K;
     const int64_t q = r * sr + k * sk;
@@ -1306,15 +1314,13 @@ __global__ __launch_bounds__(256) void realify_kernel(const double2 *__restrict_
       im -= ref[q].y;
     }
     if constexpr (SIDE == 0) {
-      const int64_t o = r * 2 * K + 2 * k;
-      put_lp<MODE>(dst, plane, o, re);
-      put_lp<MODE>(dst, plane, o + 1, im);
+      put_lp<MODE>(dst, plane, at(r, 2 * k), re);
+      put_lp<MODE>(dst, plane, at(r, 2 * k + 1), im);
     } else {
-      const int64_t o0 = (2 * r) * 2 * K + 2 * k, o1 = o0 + 2 * K;
-      put_lp<MODE>(dst, plane, o0, re);
-      put_lp<MODE>(dst, plane, o0 + 1, -im);
-      put_lp<MODE>(dst, plane, o1, im);
-      put_lp<MODE>(dst, plane, o1 + 1, re);
+      put_lp<MODE>(dst, plane, at(2 * r, 2 * k), re);
+      put_lp<MODE>(dst, plane, at(2 * r, 2 * k + 1), -im);
+      put_lp<MODE>(dst, plane, at(2 * r + 1, 2 * k), im);
+      put_lp<MODE>(dst, plane, at(2 * r + 1, 2 * k + 1), re);
     }
   }
 }
@@ -1325,11 +1331,11 @@ void realify_launch(const double *src, const double *ref, int64_t R, int64_t K, 
   const auto *a = reinterpret_cast<const double2 *>(src);
   const auto *b = reinterpret_cast<const double2 *>(ref);
   if (ref)
-    hipLaunchKernelGGL((realify_kernel<MODE, SIDE, true>), dim3(ew_blocks(R * K)), dim3(256), 0, s, a, b, R, K, sr,
-                       sk, dst);
+    hipLaunchKernelGGL((realify_kernel<MODE, SIDE, true, false>), dim3(ew_blocks(R * K)), dim3(256), 0, s, a, b, R, K,
+                       sr, sk, dst);
   else
-    hipLaunchKernelGGL((realify_kernel<MODE, SIDE, false>), dim3(ew_blocks(R * K)), dim3(256), 0, s, a, b, R, K, sr,
-                       sk, dst);
+    hipLaunchKernelGGL((realify_kernel<MODE, SIDE, false, false>), dim3(ew_blocks(R * K)), dim3(256), 0, s, a, b, R,
+                       K, sr, sk, dst);
 }
 
 }  // namespace
@@ -1345,6 +1351,20 @@ void realify_complex(int prec, int side, const double *src, const double *ref, i
     if (side == 0) realify_launch<PREC_BF16X3, 0>(src, ref, R, K, sr, sk, dst, s);
     else realify_launch<PREC_BF16X3, 1>(src, ref, R, K, sr, sk, dst, s);
   }
+  CC_HIP_CHECK(hipGetLastError());
+}
+
+void realify_complex_blocked(int side, const double *src, int64_t R, int64_t K, void *dst, hipStream_t s) {
+  if (R <= 0 || K <= 0) return;
+  CC_REQUIRE(K % 16 == 0, -1, "blocked realified copy: K must be a multiple of 16");
+  CC_REQUIRE((reinterpret_cast<uintptr_t>(dst) & 15) == 0, -1, "blocked realified copy: alignment");
+  const auto *a = reinterpret_cast<const double2 *>(src);
+  if (side == 0)
+    hipLaunchKernelGGL((realify_kernel<PREC_BF16X3, 0, false, true>), dim3(ew_blocks(R * K)), dim3(256), 0, s, a,
+                       nullptr, R, K, K, int64_t(1), dst);
+  else
+    hipLaunchKernelGGL((realify_kernel<PREC_BF16X3, 1, false, true>), dim3(ew_blocks(R * K)), dim3(256), 0, s, a,
+                       nullptr, R, K, K, int64_t(1), dst);
   CC_HIP_CHECK(hipGetLastError());
 }
 

@@ -800,15 +800,25 @@ void use_shadows_c(cc_plan *p, GemmDesc &d, const Step &st, hipStream_t s, bool 
 // is an LDS-direct one that reads them, unless the autotuner timed that
 // configuration faster on the row-major copies.
 bool blocked_for(const cc_plan *p, const Step &st, int tile) {
-  if (p->cplx || p->cur_prec != PREC_BF16X3 || st.blk_a < 0 || st.blk_b < 0 || st.blk_use == 0) return false;
+  if (p->cur_prec != PREC_BF16X3 || st.blk_a < 0 || st.blk_b < 0 || st.blk_use == 0) return false;
   if (!p->bforms[st.blk_a].ptr || !p->bforms[st.blk_b].ptr) return false;
-  if (tile < 0) tile = gemm_lowp_pick(PREC_BF16X3, st.gemm.M, st.gemm.N);
+  if (tile < 0) tile = gemm_lowp_pick(PREC_BF16X3, st.gemm.M, p->cplx ? 2 * st.gemm.N : st.gemm.N);
   return gemm_lowp_tile_blocked(PREC_BF16X3, tile);
 }
 
+// rows of a blocked copy: the slot's rows of K (twice that for a realified B')
+int64_t blocked_rows(const cc_plan *p, const BForm &bf) {
+  return slot_elems(p, bf.slot) / bf.K * (bf.kind == 3 ? 2 : 1);
+}
+
+int64_t blocked_bytes(const cc_plan *p, const BForm &bf) {
+  return blocked_plane(blocked_rows(p, bf), bf.kind >= 2 ? 2 * bf.K : bf.K) * 2 * int64_t(sizeof(uint16_t));
+}
+
 void convert_blocked_form(cc_plan *p, BForm &bf, hipStream_t s) {
-  convert_blocked(static_cast<const double *>(ptr_of(p, bf.slot)), nullptr, slot_elems(p, bf.slot) / bf.K, bf.K,
-                  bf.ptr, s);
+  const double *src = static_cast<const double *>(ptr_of(p, bf.slot));
+  if (bf.kind == 1) convert_blocked(src, nullptr, blocked_rows(p, bf), bf.K, bf.ptr, s);
+  else realify_complex_blocked(bf.kind == 2 ? 0 : 1, src, slot_elems(p, bf.slot) / bf.K, bf.K, bf.ptr, s);
 }
 
 // Point a split-bf16 GEMM at the blocked copies of its operands, converting
@@ -820,18 +830,26 @@ void use_blocked(cc_plan *p, GemmDesc &d, const Step &st, hipStream_t s, bool co
       convert_blocked_form(p, *f, s);
       f->ok = 1;
     }
-  d.A = fa.ptr;
-  d.B = fb.ptr;
-  d.a_plane = blocked_plane(slot_elems(p, fa.slot) / fa.K, fa.K);
-  d.b_plane = blocked_plane(slot_elems(p, fb.slot) / fb.K, fb.K);
+  if (p->cplx) {
+    d = realified_desc(d, fa.ptr, fb.ptr);
+    d.a_plane = blocked_plane(blocked_rows(p, fa), 2 * fa.K);
+    d.b_plane = blocked_plane(blocked_rows(p, fb), 2 * fb.K);
+  } else {
+    d.A = fa.ptr;
+    d.B = fb.ptr;
+    d.a_plane = blocked_plane(blocked_rows(p, fa), fa.K);
+    d.b_plane = blocked_plane(blocked_rows(p, fb), fb.K);
+  }
   d.lp_in = 2;
 }
 
 void run_gemm(cc_plan *p, GemmDesc &d, const Step &st, hipStream_t s) {
   if (p->cplx && (p->cur_prec == PREC_F64 || !st.lowp_ok)) gemm_c128(d, s, st.tile_z);
   else if (p->cplx) {
-    use_shadows_c(p, d, st, s, true);
-    gemm_lowp(d, p->cur_prec, s, st.tile_lp[p->cur_prec]);
+    const int tile = st.tile_lp[p->cur_prec];
+    if (blocked_for(p, st, tile)) use_blocked(p, d, st, s, true);
+    else use_shadows_c(p, d, st, s, true);
+    gemm_lowp(d, p->cur_prec, s, tile);
   } else if (p->cur_prec == PREC_F64 || !st.lowp_ok) gemm_f64(d, s, st.tile);
   else {
     const int tile = st.tile_lp[p->cur_prec];
@@ -966,8 +984,10 @@ void plan_prepare(cc_plan *p) {
       if (lowp && prec == PREC_BF16X3 && (side ? st.blk_b : st.blk_a) >= 0) {
         BForm &bf = p->bforms[side ? st.blk_b : st.blk_a];
         if (!bf.ptr) {
-          const int64_t plane = blocked_plane(slot_elems(p, sl) / bf.K, bf.K);
-          CC_HIP_CHECK(hipMalloc(&bf.ptr, size_t(plane) * 2 * sizeof(uint16_t)));
+          // the padding rows are never written: zero once (outside any capture)
+          const size_t bytes = size_t(blocked_bytes(p, bf));
+          CC_HIP_CHECK(hipMalloc(&bf.ptr, bytes));
+          CC_HIP_CHECK(hipMemsetAsync(bf.ptr, 0, bytes, s));
           bf.prec = -1;
         }
         if (p->slots[sl].constant && bf.prec != prec) {
@@ -1272,25 +1292,27 @@ void plan_build(cc_plan *p, const cc_system *sys) {
   // multiple of 32) also get copies of both operands in the 16 x 32 blocks
   // the LDS-direct kernels load whole (one per slot and row length K);
   // batched plans run grouped launches on FP64 operands instead
-  if (!p->cplx && !p->lowp_all)
+  // (complex: of the realified A' and B', rows of 2K, so K a multiple of 16)
+  if (!p->lowp_all)
     for (Step &st : p->iter) {
       const GemmDesc &g = st.gemm;
-      if (st.kind != Step::GEMM || !st.lowp_ok || g.K <= 0 || g.K % 32 != 0 || g.sak != 1 || g.sbk != 1 ||
-          g.sam != g.K || g.sbn != g.K || g.M < 256 || g.N < 128 || slot_elems(p, st.a) % g.K != 0 ||
+      const int64_t rk = p->cplx ? 2 * g.K : g.K, rn = p->cplx ? 2 * g.N : g.N;
+      if (st.kind != Step::GEMM || !st.lowp_ok || g.K <= 0 || rk % 32 != 0 || g.sak != 1 || g.sbk != 1 ||
+          g.sam != g.K || g.sbn != g.K || g.M < 256 || rn < 128 || slot_elems(p, st.a) % g.K != 0 ||
           slot_elems(p, st.b) % g.K != 0)
         continue;
-      auto form = [p](int slot, int64_t K) {
+      auto form = [p](int kind, int slot, int64_t K) {
         for (size_t i = 0; i < p->bforms.size(); ++i)
-          if (p->bforms[i].kind == 1 && p->bforms[i].slot == slot && p->bforms[i].K == K) return int(i);
+          if (p->bforms[i].kind == kind && p->bforms[i].slot == slot && p->bforms[i].K == K) return int(i);
         BForm bf;
-        bf.kind = 1;
+        bf.kind = kind;
         bf.slot = slot;
         bf.K = K;
         p->bforms.push_back(bf);
         return int(p->bforms.size()) - 1;
       };
-      st.blk_a = form(st.a, g.K);
-      st.blk_b = form(st.b, g.K);
+      st.blk_a = form(p->cplx ? 2 : 1, st.a, g.K);
+      st.blk_b = form(p->cplx ? 3 : 1, st.b, g.K);
     }
 }
 
@@ -1407,7 +1429,7 @@ void plan_autotune(cc_plan *p, int reps) {
       const int64_t rN = (p->cplx && lowp) ? 2 * d.N : d.N, rK = (p->cplx && lowp) ? 2 * d.K : d.K;
       // blocked split-bf16 copies available: the LDS-direct configurations
       // are timed on them (a choice of its own in the cache)
-      const bool blk = lowp && !p->cplx && prec == PREC_BF16X3 && st->blk_a >= 0 && st->blk_b >= 0 &&
+      const bool blk = lowp && prec == PREC_BF16X3 && st->blk_a >= 0 && st->blk_b >= 0 &&
                        p->bforms[st->blk_a].ptr && p->bforms[st->blk_b].ptr;
       const std::string key = std::to_string(prec) + ":" + std::to_string(d.M) + "x" +
                               std::to_string(rN) + "x" + std::to_string(rK) + (akc ? "k" : "m") +

@@ -39,7 +39,8 @@ struct OpSpec {
 // Realified copy of a complex slot read as the B operand of reduced-precision
 // GEMMs with rows of K complex elements (the layout depends on K).
 struct BForm {
-  int kind = 0;   // 0: complex realified B' copy; 1: real split-bf16 copy in 16 x 32 blocks (A or B side)
+  int kind = 0;   // 0: complex realified B' copy; 1: real split-bf16 copy in 16 x 32 blocks (A or B side);
+                  // 2, 3: complex realified A', B' split-bf16 copies in 16 x 32 blocks
   int slot = -1;
   int64_t K = 0;
   void *ptr = nullptr;

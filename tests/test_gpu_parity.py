@@ -320,20 +320,25 @@ def test_mixed_precision_refines_to_fp64_solution(E, ctx, prec):
         assert abs(out["energy"] - ref["energy"]) < 1e-10
 
 
-def test_blocked_split_bf16_copies_in_plans(E, ctx):
+@pytest.mark.parametrize("cplx", [False, True])
+def test_blocked_split_bf16_copies_in_plans(E, ctx, cplx):
     """At o=16, v=64 the ladder, Z, the ring terms and W_mnij's tau term are
-    large enough for the split-bf16 copies in 16 x 32 blocks; after
-    autotuning, the plain split-bf16 residual and the reference + correction
-    one keep the errors they have with row-major copies (a wrong block
-    layout would make them of the order of the residual itself)."""
+    large enough for the split-bf16 copies in 16 x 32 blocks (complex: of
+    the realified operands); after autotuning, the plain split-bf16 residual
+    and the reference + correction one keep the errors they have with
+    row-major copies (a wrong block layout would make them of the order of
+    the residual itself)."""
     o, v = 16, 64
-    s = make_system(o, v, 43)
+    s = make_system(o, v, 43, is_complex=cplx)
     d = E.DeviceSystem(s)
     rng = np.random.default_rng(10)
 
     def amps(scale):
         a1 = rng.normal(size=(o, v)) * scale
         a2 = rng.normal(size=(o, o, v, v)) * scale
+        if cplx:
+            a1 = a1 + 1j * rng.normal(size=(o, v)) * scale
+            a2 = a2 + 1j * rng.normal(size=(o, o, v, v)) * scale
         a2 = a2 - a2.transpose(1, 0, 2, 3)
         a2 = a2 - a2.transpose(0, 1, 3, 2)
         return a1, a2
@@ -361,7 +366,7 @@ def test_blocked_split_bf16_copies_in_plans(E, ctx):
         p.set_correction(1, E.PRECS["bf16x3"])
         at_ref = res(p, t_ref)
         corrected = res(p, t_new)
-    print(f"blocked tags {[t for t in tags if t.endswith('/blk')]}; plain {plain_err:.2e}, "
+    print(f"complex {cplx}: blocked tags {[t for t in tags if t.endswith('/blk')]}; plain {plain_err:.2e}, "
           f"corrected {np.abs(corrected - exact_new).max():.2e} (|R| {scale:.2e})", flush=True)
     assert any(t.endswith("/blk") for t in tags)
     assert plain_err < 1e-4 * scale

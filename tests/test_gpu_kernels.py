@@ -277,7 +277,7 @@ def test_gemm_lowp_two_chunk_prefetch_is_bitwise_one_chunk(ctx, monkeypatch, pre
 
 
 @pytest.mark.parametrize("M,N,K", [
-    (256, 128, 32), (512, 256, 96), (300, 270, 160), (496, 1000, 96), (37, 300, 64),
+    (256, 128, 32), (512, 256, 96), (300, 270, 160), (496, 1000, 96), (37, 300, 64), (1, 17, 32),
     (1024, 136 * 128, 2048)])  # cut: whole rounds + a K-split tail
 @pytest.mark.parametrize("tile", [9, 10, 11])
 def test_gemm_bf16x3_blocked_copies_are_bitwise_row_major(ctx, monkeypatch, tile, M, N, K):

@@ -111,10 +111,13 @@ typedef struct {
   int32_t dressed;     /* 0: D from the bare Fock diagonal; 1: from the diagonals of the
                           T-dressed one-body intermediates of the current iterate */
   int32_t autotune;    /* 1: run the GEMM tile autotuner before iterating (counted as setup) */
-  int32_t correction;  /* reduced prec only, 1: in the FP64 phase, evaluate each contraction that
-                          is linear in the amplitudes (one constant operand, >= 1% of the work) as
-                          a stored FP64 product at reference amplitudes plus a reduced-precision
-                          product of the change since the reference (defect correction); a new
+  int32_t correction;  /* reduced prec only, 1: in the FP64 phase, evaluate each contraction with
+                          >= 1% of the work that is linear in the amplitudes (one constant operand)
+                          as a stored FP64 product at reference amplitudes plus a reduced-precision
+                          product of the change since the reference (defect correction), and for
+                          real systems in split bf16 each product A B of two varying operands as
+                          A_ref B_ref + (A - A_ref) B + A_ref (B - B_ref), the last two products
+                          in split bf16; a new
                           reference is taken whenever ||R|| fell 1000-fold since the last one,
                           and convergence is confirmed by one plain FP64 step */
   int32_t packed;      /* 1: particle-particle ladder over packed pairs (see CC_PLAN_PACKED_LADDER) */
@@ -392,8 +395,9 @@ const char *cc_plan_describe_ops_dry(int o, int v, int method, int scalar, const
 /* Precision of the contractions of the following steps (cc_prec); the
  * plan's creation precision is the initial value. */
 int cc_plan_set_precision(cc_plan *plan, int prec);
-/* Reference + correction form of the linear contractions for the following
- * FP64 steps (see cc_iter_opts.correction): mode 0 off; mode 1 takes a
+/* Reference + correction form of the linear (and, real systems with split-bf16
+ * corrections, bilinear) contractions for the following FP64 steps (see cc_iter_opts.correction):
+ * mode 0 off; mode 1 takes a
  * reference at the next step's amplitudes and uses it from then on; prec
  * (CC_PREC_F32 or CC_PREC_BF16X3) is the precision of the correction
  * products (complex systems: realified products as in cc_gemm). */

@@ -870,11 +870,52 @@ void invalidate(cc_plan *p, int sl) {
 // in reduced precision; its rounding error scales with |X - X_ref|.
 void run_delta_gemm(cc_plan *p, GemmDesc &d, const Step &st, hipStream_t s) {
   DeltaRef &r = p->deltas[st.delta];
+  // products of two varying operands are corrected in split bf16 only: two
+  // FP32 products take as long as the FP64 one
+  if (r.var == 2 && p->delta_prec != PREC_BF16X3) {
+    gemm_f64(d, s, st.tile);
+    return;
+  }
   CC_REQUIRE(r.ref_op && r.ref_out && r.dshadow, CC_EINTERNAL, "reference buffers not prepared");
   const int var_slot = r.var ? st.b : st.a, con_slot = r.var ? st.a : st.b;
   const double *X = static_cast<const double *>(ptr_of(p, var_slot));
   double *C = static_cast<double *>(d.C);
   const int64_t w = p->cplx ? 2 : 1;  // doubles per element
+  if (r.var == 2) {
+    // A B = A_ref B_ref (FP64, stored) + (A - A_ref) B + A_ref (B - B_ref),
+    // the two corrections in reduced precision: their error scales with the
+    // change since the reference
+    const double *A = static_cast<const double *>(ptr_of(p, st.a));
+    const double *Bv = static_cast<const double *>(ptr_of(p, st.b));
+    if (p->delta_mode == 2) {
+      copy_f64(r.ref_op, A, r.n_op, s);
+      copy_f64(r.ref_b, Bv, r.n_b, s);
+      convert_shadow(p->delta_prec, A, r.n_op, r.ref_a_lp, s);
+      GemmDesc g = d;
+      g.C = r.ref_out;
+      g.ldc = d.N;
+      g.beta = 0.0;
+      gemm_f64(g, s, st.tile);
+      add_product(C, d.ldc, d.beta, r.ref_out, d.M, d.N, s);
+      return;
+    }
+    add_product(C, d.ldc, d.beta, r.ref_out, d.M, d.N, s);
+    convert_delta(p->delta_prec, A, r.ref_op, r.n_op, r.dshadow, s);
+    convert_shadow(p->delta_prec, Bv, r.n_b, r.cur_b_lp, s);
+    convert_delta(p->delta_prec, Bv, r.ref_b, r.n_b, r.dshadow_b, s);
+    GemmDesc g = d;
+    g.lp_in = 1;
+    g.beta = 1.0;
+    g.A = r.dshadow;
+    g.a_plane = r.n_op;
+    g.B = r.cur_b_lp;
+    g.b_plane = r.n_b;
+    gemm_lowp(g, p->delta_prec, s, st.tile_lp[p->delta_prec]);
+    g.A = r.ref_a_lp;
+    g.B = r.dshadow_b;
+    gemm_lowp(g, p->delta_prec, s, st.tile_lp[p->delta_prec]);
+    return;
+  }
   if (p->delta_mode == 2) {
     copy_f64(r.ref_op, X, w * r.n_op, s);
     GemmDesc g = d;
@@ -1020,12 +1061,20 @@ void plan_prepare(cc_plan *p) {
   }
   if (delta) {
     for (DeltaRef &d : p->deltas) {
+      if (d.var == 2 && prec != PREC_BF16X3) continue;  // such products stay plain FP64
       const GemmDesc &g = p->iter[d.step].gemm;
       const int64_t wd = p->cplx ? (d.var ? 4 : 2) : 1;  // reals per element of the varying operand's copy
       if (!d.ref_op) CC_HIP_CHECK(hipMalloc(reinterpret_cast<void **>(&d.ref_op), size_t(d.n_op) * w * 8));
       if (!d.ref_out) CC_HIP_CHECK(hipMalloc(reinterpret_cast<void **>(&d.ref_out), size_t(g.M) * g.N * w * 8));
       if (!d.dshadow) CC_HIP_CHECK(hipMalloc(&d.dshadow, size_t(d.n_op) * wd * 4));
       const Step &ds = p->iter[d.step];
+      if (d.var == 2) {
+        if (!d.ref_b) CC_HIP_CHECK(hipMalloc(reinterpret_cast<void **>(&d.ref_b), size_t(d.n_b) * 8));
+        if (!d.ref_a_lp) CC_HIP_CHECK(hipMalloc(&d.ref_a_lp, size_t(d.n_op) * 4));
+        if (!d.cur_b_lp) CC_HIP_CHECK(hipMalloc(&d.cur_b_lp, size_t(d.n_b) * 4));
+        if (!d.dshadow_b) CC_HIP_CHECK(hipMalloc(&d.dshadow_b, size_t(d.n_b) * 4));
+        continue;
+      }
       if (!p->cplx && prec == PREC_BF16X3 && ds.blk_a >= 0 && ds.blk_b >= 0 && !d.dblk)
         CC_HIP_CHECK(hipMalloc(&d.dblk, size_t(blocked_plane(d.n_op / g.K, g.K)) * 4));
     }
@@ -1256,18 +1305,22 @@ void plan_build(cc_plan *p, const cc_system *sys) {
   };
   for (Step &st : p->iter)
     if (st.kind == Step::GEMM) st.lowp_ok = (p->lowp_all || st.flops >= 0.01 * p->flops_per_iter) && shape_ok(st);
-  // contractions linear in the amplitudes worth a reference + correction
-  // evaluation: one constant operand and at least 1% of the iteration's work
+  // contractions worth a reference + correction evaluation (at least 1% of
+  // the iteration's work): linear in the amplitudes (one constant operand),
+  // and, for real systems, products of two varying operands, corrected as
+  // A B = A_ref B_ref + (A - A_ref) B + A_ref (B - B_ref)
   {
     for (size_t k = 0; k < p->iter.size(); ++k) {
       Step &st = p->iter[k];
       if (st.kind != Step::GEMM || st.flops < 0.01 * p->flops_per_iter || !shape_ok(st)) continue;
       const bool ca = p->slots[st.a].constant, cb = p->slots[st.b].constant;
-      if (ca == cb) continue;
+      if (ca && cb) continue;
+      if (!ca && !cb && p->cplx) continue;
       DeltaRef d;
       d.step = int(k);
-      d.var = ca ? 1 : 0;
+      d.var = (!ca && !cb) ? 2 : ca ? 1 : 0;
       d.n_op = slot_elems(p, ca ? st.b : st.a);
+      if (d.var == 2) d.n_b = slot_elems(p, st.b);
       st.delta = int(p->deltas.size());
       p->deltas.push_back(d);
     }
@@ -1330,10 +1383,11 @@ void plan_free(cc_plan *p) {
     if (bf.ptr) (void)hipFree(bf.ptr);
   p->bforms.clear();
   for (DeltaRef &d : p->deltas) {
-    for (void *q : {static_cast<void *>(d.ref_op), static_cast<void *>(d.ref_out), d.dshadow, d.dblk})
+    for (void *q : {static_cast<void *>(d.ref_op), static_cast<void *>(d.ref_out), d.dshadow, d.dblk,
+                    static_cast<void *>(d.ref_b), d.ref_a_lp, d.cur_b_lp, d.dshadow_b})
       if (q) (void)hipFree(q);
-    d.ref_op = d.ref_out = nullptr;
-    d.dshadow = d.dblk = nullptr;
+    d.ref_op = d.ref_out = d.ref_b = nullptr;
+    d.dshadow = d.dblk = d.ref_a_lp = d.cur_b_lp = d.dshadow_b = nullptr;
   }
   for (double *q : {p->d_oo, p->d_vv, p->epart, p->n2part, p->n1part, p->scalars, p->n3part})
     if (q) (void)hipFree(q);

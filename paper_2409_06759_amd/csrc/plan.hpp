@@ -87,12 +87,18 @@ struct Step {
 // change since the reference: C = beta C + alpha X_ref Y + alpha (X - X_ref) Y.
 struct DeltaRef {
   int step = -1;
-  int var = 0;                    // 0: A varies, 1: B varies
-  int64_t n_op = 0;               // elements of the varying operand's slot
-  double *ref_op = nullptr;       // FP64 copy of the varying operand at the reference
-  double *ref_out = nullptr;      // alpha * X_ref Y, dense M x N
-  void *dshadow = nullptr;        // reduced-precision (X - X_ref)
+  int var = 0;                    // 0: A varies, 1: B varies, 2: both vary (real systems)
+  int64_t n_op = 0;               // elements of the varying operand's slot (var 2: A's)
+  double *ref_op = nullptr;       // FP64 copy of the varying operand at the reference (var 2: A_ref)
+  double *ref_out = nullptr;      // alpha * X_ref Y, dense M x N (var 2: alpha * A_ref B_ref)
+  void *dshadow = nullptr;        // reduced-precision (X - X_ref) (var 2: A - A_ref)
   void *dblk = nullptr;           // split bf16 (X - X_ref) in 16 x 32 blocks (steps with blocked copies)
+  // var 2: A B = A_ref B_ref + (A - A_ref) B + A_ref (B - B_ref)
+  int64_t n_b = 0;                // elements of B's slot
+  double *ref_b = nullptr;        // FP64 B_ref
+  void *ref_a_lp = nullptr;       // reduced-precision A_ref (made at the reference)
+  void *cur_b_lp = nullptr;       // reduced-precision B
+  void *dshadow_b = nullptr;      // reduced-precision (B - B_ref)
 };
 
 // A caller-supplied contraction list (e.g. emitted by the diagram

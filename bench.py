@@ -427,7 +427,9 @@ def main():
     ctx = E.Context(0)
     torch.cuda.synchronize()
     t_setup = time.perf_counter()
-    plan = E.Plan(ctx, dsys, m, packed=args.packed)
+    # created in the timed precision, as cc_iterate creates its plans (the
+    # hole-hole ladder's operand layout follows the creation precision)
+    plan = E.Plan(ctx, dsys, m, prec=E.PRECS[args.prec], packed=args.packed)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t_setup
     flops = plan.flops()

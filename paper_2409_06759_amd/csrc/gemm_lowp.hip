@@ -471,6 +471,9 @@ __device__ __forceinline__ void gemm_b3_dma_body(const GemmDesc &d, int64_t tile
       fbh[j] = *reinterpret_cast<const bf8 *>(St + 2 * A_EL + blk * 512 + lane * 8);
       fbl[j] = *reinterpret_cast<const bf8 *>(St + 2 * A_EL + B_EL + blk * 512 + lane * 8);
     }
+    // the products at raised wave priority, so that the SIMD's other wave
+    // issues its loads and fragment reads around them rather than between
+    __builtin_amdgcn_s_setprio(1);
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -479,6 +482,7 @@ __device__ __forceinline__ void gemm_b3_dma_body(const GemmDesc &d, int64_t tile
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fah[i], fbl[j], acc[i][j], 0, 0, 0);
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fah[i], fbh[j], acc[i][j], 0, 0, 0);
       }
+    __builtin_amdgcn_s_setprio(0);
     cur = cur == NSTAGE - 1 ? 0 : cur + 1;
     nxt = nxt == NSTAGE - 1 ? 0 : nxt + 1;
   }

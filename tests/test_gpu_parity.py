@@ -223,6 +223,29 @@ def test_graph_replay_is_bitwise_eager(E, ctx):
     assert torch.equal(a2, b2) and torch.equal(a1, b1)
 
 
+def test_autotune_choices_written_to_the_cache_file(E, ctx, tmp_path, monkeypatch):
+    """With CC_AUTOTUNE_CACHE set, each new per-shape choice is appended to
+    the file as "key tile" (a split-bf16 choice on blocked copies as tile +
+    1000), and a second plan of the same shapes takes the same tiles."""
+    f = tmp_path / "tune.txt"
+    monkeypatch.setenv("CC_AUTOTUNE_CACHE", str(f))
+    o, v = 7, 29  # shapes no other test tunes, so the choices are new
+    d = E.DeviceSystem(make_system(o, v, 12))
+    t1, t2 = E.zeros_amps(d, E.CCSD)
+    tags = []
+    for _ in range(2):
+        with E.Plan(ctx, d, E.CCSD) as p:
+            p.autotune(t1, t2)
+            p.profile(True)
+            p.residual(t1, t2)
+            tags.append([r[2] for r in p.profile_table() if r[1] == "GEMM"])
+    lines = f.read_text().split("\n")
+    entries = [ln.split() for ln in lines if ln.strip()]
+    assert entries and all(len(e) == 2 and ":" in e[0] and 0 <= int(e[1]) < 1000 for e in entries)
+    assert len({e[0] for e in entries}) == len(entries)  # each shape tuned once
+    assert tags[0] == tags[1]
+
+
 def test_plan_step_matches_iterate(E, ctx):
     o, v = 5, 19
     s = make_system(o, v, 8)

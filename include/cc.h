@@ -266,7 +266,11 @@ int cc_iterate(cc_ctx *ctx, const cc_system *sys, int method, const cc_iter_opts
  * one short round.  Partial sums sit in a device buffer the context keeps
  * (grown on demand, freed by cc_destroy) and are reduced in a fixed order;
  * split parts sum K in a different order than one launch would.
- * CC_GEMM_TAIL=0 in the environment runs every GEMM as one launch. */
+ * CC_GEMM_TAIL=0 in the environment runs every GEMM as one launch.
+ * Reduced precision converts A and B once into temporary 4-byte copies; a
+ * split-bf16 GEMM on dense K-contiguous rows (sam = sbn = K, K a multiple of
+ * 32) whose configuration is LDS-direct takes copies in 16-row x 32-k blocks
+ * instead, with identical results (CC_GEMM_BLOCKED=0: row-major copies). */
 int cc_gemm(cc_ctx *ctx, int prec, int scalar, int64_t M, int64_t N, int64_t K, double alpha,
             const void *A, int64_t sam, int64_t sak, const void *B, int64_t sbn, int64_t sbk,
             double beta, void *C, int64_t ldc);

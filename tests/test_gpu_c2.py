@@ -65,3 +65,35 @@ def test_c2_mixed_precision_converged_energy(E, setup, ref, prec):
           f"{out['seconds']:.2f}s, |dE|={abs(out['energy'] - ref['energy']):.2e}", flush=True)
     assert out["converged"]
     assert abs(out["energy"] - ref["energy"]) < 1e-6
+
+
+def test_c2_split_bf16_residual_on_blocked_copies(E, setup):
+    """One split-bf16 residual at o=32, v=160 in the configuration the bench
+    times (plan created in split bf16, autotuned, so the ladder, Z and the
+    ring terms run on the blocked copies with the full-size tail cut),
+    against the FP64 residual at the same random amplitudes. Terms are
+    O(1e-2) with up to v^2 = 25,600 products: split bf16 (hi*hi + hi*lo +
+    lo*hi, FP32 accumulation) stays within 1e-4 of the largest |R|."""
+    ctx, d = setup
+    o, v = 32, 160
+    g = torch.Generator(device="cuda")
+    g.manual_seed(21)
+    t1 = torch.randn(o, v, dtype=torch.float64, device="cuda", generator=g) * 0.01
+    t2 = torch.randn(o, o, v, v, dtype=torch.float64, device="cuda", generator=g) * 0.01
+    t2 = t2 - t2.transpose(0, 1)
+    t2 = (t2 - t2.transpose(2, 3)).contiguous()
+    with E.Plan(ctx, d, E.CCSD) as p64:
+        e1, e2, _ = p64.residual(t1, t2)
+        e1, e2 = e1.clone(), e2.clone()
+    with E.Plan(ctx, d, E.CCSD, prec=E.PRECS["bf16x3"]) as p:
+        p.autotune(t1, t2)
+        p.profile(True)
+        r1, r2, _ = p.residual(t1, t2)
+        tags = [row[2] for row in p.profile_table() if row[1] == "GEMM"]
+    scale = max(float(e2.abs().max()), float(e1.abs().max()))
+    err = max(float((r2 - e2).abs().max()), float((r1 - e1).abs().max()))
+    blk = [t for t in tags if t.endswith("/blk")]
+    print(f"split bf16 at C2: max err {err:.2e} (|R| {scale:.2e}); blocked: {blk}", flush=True)
+    assert any(t.startswith("ladder@") for t in blk)
+    assert err < 1e-4 * scale
+    assert err > 1e-12 * scale  # reduced-precision rounding is there

@@ -38,6 +38,14 @@ struct GStep {
   int64_t sk_blocks = 0;
   size_t sk_entry_off = 0, sk_off_off = 0;
   double flops = 0.0;
+  // reduced precision: the GEMM reads operand copies (lp), made by the
+  // grouped conversions listed here for the slots written since their last one
+  bool lp = false;
+  struct Conv {
+    size_t entry_off, off_off;
+    int64_t blocks;
+  };
+  std::vector<Conv> conv;
 };
 
 }  // namespace
@@ -82,6 +90,12 @@ size_t push_offsets(cc_batch *B, const std::vector<int64_t> &units, int64_t *tot
   return push_entries(B, off);
 }
 
+int64_t batch_slot_elems(const cc_plan *p, int s) {
+  const Slot &sl = p->slots[s];
+  if (!sl.external) return sl.elems;
+  return sl.name == "t1" ? int64_t(p->o) * p->v : int64_t(p->o) * p->o * p->v * p->v;
+}
+
 // (Re)build the device tables of every grouped step from the plans' current
 // per-call state (amplitude pointers, shift, denominator mode).
 void build_tables(cc_batch *B) {
@@ -90,6 +104,34 @@ void build_tables(cc_batch *B) {
   const size_t nsteps = B->plans[0]->iter.size();
   for (cc_plan *p : B->plans)
     CC_REQUIRE(p->iter.size() == nsteps, CC_EINTERNAL, "batch: plans differ in step count");
+  // Reduced precision (real systems): the grouped GEMMs on K-contiguous
+  // operands read 4-byte copies made by grouped conversions, each slot
+  // converted once after every write (constant slots once, here).
+  const bool lowp = B->prec != PREC_F64 && !B->cplx;
+  if (lowp)
+    for (cc_plan *p : B->plans) {
+      p->cur_prec = B->prec;
+      plan_prepare(p);
+    }
+  // per plan and slot: the copy matches the slot at this point of the step list
+  std::vector<std::vector<char>> fresh;
+  for (cc_plan *p : B->plans) fresh.emplace_back(p->slots.size(), 0);
+  auto written = [&](size_t k) {
+    for (size_t b = 0; b < B->plans.size(); ++b) {
+      const Step &st = B->plans[b]->iter[k];
+      switch (st.kind) {
+        case Step::PERMUTE:
+        case Step::GEMM:
+        case Step::OUTER:
+        case Step::FILL:
+        case Step::PAIR:
+          if (st.c >= 0) fresh[b][st.c] = 0;
+          break;
+        default:  // tau, the assembly, the updates: conservatively every slot
+          std::fill(fresh[b].begin(), fresh[b].end(), 0);
+      }
+    }
+  };
   for (size_t k = 0; k < nsteps; ++k) {
     GStep g;
     const Step &s0 = B->plans[0]->iter[k];
@@ -162,6 +204,48 @@ void build_tables(cc_batch *B) {
           }
           skunits.push_back(e.d.split > 1 ? sk.back().units : 0);
         }
+        if (lowp && g.grouped && g.akc && g.bkc) {
+          g.lp = true;
+          for (cc_plan *p : B->plans) {
+            const Step &st = p->iter[k];
+            if (p->shadow.size() != p->slots.size() || !p->shadow[st.a] || !p->shadow[st.b]) g.lp = false;
+          }
+        }
+        if (g.lp) {
+          for (size_t b = 0; b < es.size(); ++b) {
+            cc_plan *p = B->plans[b];
+            const Step &st = p->iter[k];
+            es[b].d.A = p->shadow[st.a];
+            es[b].d.B = p->shadow[st.b];
+            es[b].d.a_plane = batch_slot_elems(p, st.a);
+            es[b].d.b_plane = batch_slot_elems(p, st.b);
+            es[b].d.lp_in = 1;
+          }
+          // one grouped conversion per operand side, over the systems whose
+          // slot was written since its last conversion (the others: no work)
+          for (int side = 0; side < 2; ++side) {
+            std::vector<ConvEntry> ce;
+            std::vector<int64_t> cu;
+            bool any = false;
+            for (size_t b = 0; b < B->plans.size(); ++b) {
+              cc_plan *p = B->plans[b];
+              const Step &st = p->iter[k];
+              const int sl = side ? st.b : st.a;
+              const bool need = !fresh[b][sl] && !p->slots[sl].constant;
+              ce.push_back(need ? make_conv_entry(static_cast<const double *>(ptr_of(p, sl)),
+                                                  batch_slot_elems(p, sl), p->shadow[sl])
+                                : make_conv_entry(nullptr, 0, nullptr));
+              cu.push_back(ce.back().units);
+              fresh[b][sl] = 1;
+              any = any || need;
+            }
+            if (!any) continue;
+            GStep::Conv c{};
+            c.entry_off = push_entries(B, ce);
+            c.off_off = push_offsets(B, cu, &c.blocks);
+            g.conv.push_back(c);
+          }
+        }
         g.entry_off = push_entries(B, es);
         g.off_off = push_offsets(B, units, &g.blocks);
         g.sk_entry_off = push_entries(B, sk);
@@ -229,6 +313,7 @@ void build_tables(cc_batch *B) {
         break;
       }
     }
+    written(k);
     B->gsteps.push_back(g);
   }
   const size_t bytes = std::max<size_t>(B->host_arena.size(), 256);
@@ -281,8 +366,13 @@ void run_gstep(cc_batch *B, size_t k, hipStream_t s) {
       launch_perm_grouped(dev_at<PermEntry>(B, g.entry_off), off, n, g.blocks, g.tiled, cplx, s);
       break;
     case Step::GEMM:
+      for (const GStep::Conv &c : g.conv)
+        convert_shadow_grouped(B->prec, dev_at<ConvEntry>(B, c.entry_off), dev_at<int64_t>(B, c.off_off), n,
+                               c.blocks, s);
       if (B->prec == PREC_F64)
         gemm_f64_grouped_launch(dev_at<GemmGroupEntry>(B, g.entry_off), off, n, g.blocks, g.akc, g.bkc, g.tile, s);
+      else if (g.lp)
+        gemm_lowp_grouped_launch_lp(dev_at<GemmGroupEntry>(B, g.entry_off), off, n, g.blocks, B->prec, g.tile, s);
       else
         gemm_lowp_grouped_launch(dev_at<GemmGroupEntry>(B, g.entry_off), off, n, g.blocks, g.akc, g.bkc, B->prec,
                                  g.tile, s);
@@ -607,7 +697,10 @@ const char *cc_batch_profile_table(const cc_batch *B) {
     std::string tag = g.tag.empty() ? "-" : g.tag;
     for (auto &c : tag)
       if (c == ' ') c = '_';
-    if (g.kind == ccmi::Step::GEMM) tag += std::string("@") + ccmi::gemm_f64_tile_name(g.tile);
+    if (g.kind == ccmi::Step::GEMM)
+      tag += std::string("@") + (B->prec == ccmi::PREC_F64 ? ccmi::gemm_f64_tile_name(g.tile)
+                                                           : ccmi::gemm_lowp_tile_name(B->prec, g.tile)) +
+             (g.lp ? "/copies" : "");
     const double avg = B->prof_calls ? B->step_ms[k] / double(B->prof_calls) : 0.0;
     s += std::to_string(k) + " " + kinds[g.kind] + " " + tag + " " + std::to_string(B->prof_calls) + " " +
          std::to_string(B->step_ms[k]) + " " + std::to_string(avg) + " " + std::to_string(g.flops) + "\n";

@@ -18,6 +18,7 @@
 // register set), and the 256x128 configurations with LDS-direct loads into
 // three stages for K-contiguous converted operands.
 #include "common.hpp"
+#include "kernels.hpp"
 
 #include <atomic>
 #include <cmath>
@@ -928,20 +929,21 @@ bool b3_dma_ok(const GemmDesc &d) {
          (reinterpret_cast<uintptr_t>(d.A) & 15) == 0 && (reinterpret_cast<uintptr_t>(d.B) & 15) == 0;
 }
 
-// Grouped launch over many systems (FP64 operands converted while staging):
-// system b owns logical tiles [off[b], off[b+1]).
-template <int MODE, int BM, int BN, int BK, int WM, int WN, bool AKC, bool BKC>
+// Grouped launch over many systems: system b owns logical tiles
+// [off[b], off[b+1]).  FP64 operands converted while staging, or (LPIN)
+// operand copies converted beforehand.
+template <int MODE, int BM, int BN, int BK, int WM, int WN, bool AKC, bool BKC, bool LPIN>
 __global__ __launch_bounds__(WM *WN *kWave) void gemm_lowp_grouped(const GemmGroupEntry *__restrict__ e,
                                                                     const int64_t *__restrict__ off, int n) {
   const int b = group_find(off, n, blockIdx.x);
   const GemmGroupEntry &g = e[b];
-  gemm_lowp_body<MODE, BM, BN, BK, WM, WN, AKC, BKC, false>(g.d, g.tilesM, g.tilesN,
-                                                            int64_t(blockIdx.x) - off[b]);
+  gemm_lowp_body<MODE, BM, BN, BK, WM, WN, AKC, BKC, LPIN>(g.d, g.tilesM, g.tilesN,
+                                                           int64_t(blockIdx.x) - off[b]);
 }
 
-template <int MODE, int BM, int BN, int BK, int WM, int WN, bool AKC, bool BKC>
+template <int MODE, int BM, int BN, int BK, int WM, int WN, bool AKC, bool BKC, bool LPIN = false>
 void launch_lg(const GemmGroupEntry *e, const int64_t *off, int n, int64_t blocks, hipStream_t s) {
-  hipLaunchKernelGGL((gemm_lowp_grouped<MODE, BM, BN, BK, WM, WN, AKC, BKC>), dim3(blocks),
+  hipLaunchKernelGGL((gemm_lowp_grouped<MODE, BM, BN, BK, WM, WN, AKC, BKC, LPIN>), dim3(blocks),
                      dim3(WM * WN * kWave), 0, s, e, off, n);
 }
 
@@ -967,6 +969,8 @@ struct LTile {
   void (*launch_grouped[4])(const GemmGroupEntry *, const int64_t *, int, int64_t, hipStream_t);
   int (*occupancy[8])();  // resident workgroups per CU, [lp_in*4 + akc*2 + bkc]
   bool blocked = false;   // its LDS-direct kernel also reads blocked copies (lp_in == 2)
+  // grouped launch on converted copies of K-contiguous operands (lp_in == 1)
+  void (*launch_grouped_lp)(const GemmGroupEntry *, const int64_t *, int, int64_t, hipStream_t) = nullptr;
 };
 
 // workgroups of one configuration resident on a CU (0 if unknown)
@@ -992,7 +996,8 @@ int occ_l() {
         &launch_l<MODE, BM, BN, BK, WM, WN, true, true, PF, 1>, &launch_l<MODE, BM, BN, BK, WM, WN, true, true, PF, 2>, \
         {&launch_lg<MODE, BM, BN, BK, WM, WN, false, false>, &launch_lg<MODE, BM, BN, BK, WM, WN, false, true>,     \
          &launch_lg<MODE, BM, BN, BK, WM, WN, true, false>, &launch_lg<MODE, BM, BN, BK, WM, WN, true, true>},      \
-        {CC_LOCC(MODE, BM, BN, BK, WM, WN, false, PF), CC_LOCC(MODE, BM, BN, BK, WM, WN, true, PF)}              \
+        {CC_LOCC(MODE, BM, BN, BK, WM, WN, false, PF), CC_LOCC(MODE, BM, BN, BK, WM, WN, true, PF)},             \
+        false, &launch_lg<MODE, BM, BN, BK, WM, WN, true, true, true>                                           \
   }
 template <int TAG>
 void launch_b3_dma(const GemmDesc &d, int64_t tm, int64_t tn, hipStream_t s) {
@@ -1077,7 +1082,9 @@ const LTile kF32Tiles[] = {
            &launch_lg<PREC_F32, 256, 128, 32, 4, 2, true, false>, &launch_lg<PREC_F32, 256, 128, 32, 4, 2, true, true>},
           {CC_LOCC(PREC_F32, 256, 128, 32, 4, 2, false, 1), &occ_l<PREC_F32, 256, 128, 32, 4, 2, false, false, true, 1>,
            &occ_l<PREC_F32, 256, 128, 32, 4, 2, false, true, true, 1>,
-           &occ_l<PREC_F32, 256, 128, 32, 4, 2, true, false, true, 1>, &occ_f32_dma}},
+           &occ_l<PREC_F32, 256, 128, 32, 4, 2, true, false, true, 1>, &occ_f32_dma},
+          false,
+          &launch_lg<PREC_F32, 256, 128, 32, 4, 2, true, true, true>},
 };
 const LTile kB3Tiles[] = {
     CC_LTILE(PREC_BF16X3, 128, 128, 32, 2, 2, 1), CC_LTILE(PREC_BF16X3, 64, 64, 32, 2, 2, 1),
@@ -1102,7 +1109,8 @@ const LTile kB3Tiles[] = {
           {CC_LOCC(PREC_BF16X3, 256, 128, 32, 4, 2, false, 1), &occ_l<PREC_BF16X3, 256, 128, 32, 4, 2, false, false, true, 1>,
            &occ_l<PREC_BF16X3, 256, 128, 32, 4, 2, false, true, true, 1>,
            &occ_l<PREC_BF16X3, 256, 128, 32, 4, 2, true, false, true, 1>, &occ_b3_dma},
-          true},
+          true,
+          &launch_lg<PREC_BF16X3, 256, 128, 32, 4, 2, true, true, true>},
     // the same with the next chunk's fragments read behind the current MFMAs
     LTile{"256x128x32_w4x2_ldsp",
           256,
@@ -1120,7 +1128,8 @@ const LTile kB3Tiles[] = {
           {CC_LOCC(PREC_BF16X3, 256, 128, 32, 4, 2, false, 1), &occ_l<PREC_BF16X3, 256, 128, 32, 4, 2, false, false, true, 1>,
            &occ_l<PREC_BF16X3, 256, 128, 32, 4, 2, false, true, true, 1>,
            &occ_l<PREC_BF16X3, 256, 128, 32, 4, 2, true, false, true, 1>, &occ_b3_dmap},
-          true},
+          true,
+          &launch_lg<PREC_BF16X3, 256, 128, 32, 4, 2, true, true, true>},
     // 256x256 with LDS-direct loads where the shape allows, else the staged
     // 256x128 kernel over its own tiles; no grouped launches (batches use
     // per-system tile tables of one tile shape)
@@ -1200,6 +1209,30 @@ __global__ __launch_bounds__(256) void to_bf16x2_kernel(const double *__restrict
     const unsigned short h = bf16_bits(x);
     hi[e] = h;
     lo[e] = bf16_bits(x - bf16_to_float(h));
+  }
+}
+
+// Grouped conversion: entry b's n values, kConvChunk per workgroup, rounded
+// and split exactly as to_f32_kernel / to_bf16x2_kernel do.
+constexpr int64_t kConvChunk = 2048;
+
+template <int MODE>
+__global__ __launch_bounds__(256) void g_convert_kernel(const ConvEntry *__restrict__ es,
+                                                        const int64_t *__restrict__ off, int n) {
+  const int b = group_find(off, n, blockIdx.x);
+  const double *__restrict__ src = es[b].src;
+  const int64_t m = es[b].n;
+  const int64_t base = (int64_t(blockIdx.x) - off[b]) * kConvChunk, end = std::min(m, base + kConvChunk);
+  for (int64_t e = base + threadIdx.x; e < end; e += 256) {
+    const float x = static_cast<float>(src[e]);
+    if (MODE == PREC_F32) {
+      static_cast<float *>(es[b].dst)[e] = x;
+    } else {
+      unsigned short *__restrict__ hi = static_cast<unsigned short *>(es[b].dst);
+      const unsigned short h = bf16_bits(x);
+      hi[e] = h;
+      hi[m + e] = bf16_bits(x - bf16_to_float(h));
+    }
   }
 }
 
@@ -1424,6 +1457,19 @@ void convert_shadow(int prec, const double *src, int64_t n, void *dst, hipStream
 
 int64_t blocked_plane(int64_t R, int64_t K) { return (R + 15) / 16 * 16 * K; }
 
+ConvEntry make_conv_entry(const double *src, int64_t n, void *dst) {
+  return ConvEntry{src, dst, n, n > 0 ? (n + kConvChunk - 1) / kConvChunk : 0};
+}
+
+void convert_shadow_grouped(int prec, const ConvEntry *e, const int64_t *off, int n, int64_t blocks,
+                            hipStream_t s) {
+  if (blocks <= 0) return;
+  CC_REQUIRE(blocks < (int64_t(1) << 31), -1, "grouped conversion: grid too large");
+  if (prec == PREC_F32) hipLaunchKernelGGL(g_convert_kernel<PREC_F32>, dim3(blocks), dim3(256), 0, s, e, off, n);
+  else hipLaunchKernelGGL(g_convert_kernel<PREC_BF16X3>, dim3(blocks), dim3(256), 0, s, e, off, n);
+  CC_HIP_CHECK(hipGetLastError());
+}
+
 void convert_blocked(const double *src, const double *ref, int64_t R, int64_t K, void *dst, hipStream_t s) {
   CC_REQUIRE(R > 0 && K > 0 && K % 32 == 0, -1, "blocked split-bf16 copy: K must be a multiple of 32");
   CC_REQUIRE((reinterpret_cast<uintptr_t>(dst) & 15) == 0, -1, "blocked split-bf16 copy: alignment");
@@ -1444,7 +1490,8 @@ int gemm_lowp_pick(int prec, int64_t M, int64_t N) { return pick_l(prec == PREC_
 
 bool gemm_lowp_tile_grouped(int prec, int tile_id) {
   return tile_id >= 0 && tile_id < num_l(prec) &&
-         (prec == PREC_F32 ? kF32Tiles : kB3Tiles)[tile_id].launch_grouped[0] != nullptr;
+         (prec == PREC_F32 ? kF32Tiles : kB3Tiles)[tile_id].launch_grouped[0] != nullptr &&
+         (prec == PREC_F32 ? kF32Tiles : kB3Tiles)[tile_id].launch_grouped_lp != nullptr;
 }
 
 void gemm_lowp_tile_shape(int prec, int tile_id, int *bm, int *bn) {
@@ -1464,6 +1511,16 @@ void gemm_lowp_grouped_launch(const GemmGroupEntry *dev_entries, const int64_t *
       dev_entries, dev_off, n, blocks, s);
   CC_HIP_CHECK(hipGetLastError());
 }
+void gemm_lowp_grouped_launch_lp(const GemmGroupEntry *dev_entries, const int64_t *dev_off, int n,
+                                 int64_t blocks, int prec, int tile_id, hipStream_t s) {
+  if (blocks <= 0) return;
+  CC_REQUIRE(prec == PREC_F32 || prec == PREC_BF16X3, -1, "grouped gemm: precision");
+  CC_REQUIRE(gemm_lowp_tile_grouped(prec, tile_id), -7, "grouped gemm: tile has no grouped launch");
+  CC_REQUIRE(blocks < (int64_t(1) << 31), -1, "grouped gemm: too many tiles");
+  (prec == PREC_F32 ? kF32Tiles : kB3Tiles)[tile_id].launch_grouped_lp(dev_entries, dev_off, n, blocks, s);
+  CC_HIP_CHECK(hipGetLastError());
+}
+
 const char *gemm_lowp_tile_name(int prec, int id) {
   if (id < 0 || id >= num_l(prec)) return "?";
   return prec == PREC_F32 ? kF32Tiles[id].name : kB3Tiles[id].name;

@@ -183,6 +183,23 @@ void launch_asm_grouped(const AsmEntry *e, const int64_t *off, int n, int64_t bl
 void launch_r1_grouped(const R1Entry *e, int n, bool cplx, hipStream_t s);
 void launch_fin_grouped(const FinEntry *e, int n, hipStream_t s);
 
+// One system's reduced-precision operand copy: n FP64 values to FP32, or to a
+// bf16 hi plane followed by the lo plane n elements further (the rounding and
+// split of the single-system copies).
+struct ConvEntry {
+  const double *src;
+  void *dst;
+  int64_t n;
+  int64_t units;  // workgroups
+};
+ConvEntry make_conv_entry(const double *src, int64_t n, void *dst);
+void convert_shadow_grouped(int prec, const ConvEntry *e, const int64_t *off, int n, int64_t blocks,
+                            hipStream_t s);
+// grouped reduced-precision GEMM reading such copies (lp_in = 1) of
+// K-contiguous operands
+void gemm_lowp_grouped_launch_lp(const GemmGroupEntry *dev_entries, const int64_t *dev_off, int n,
+                                 int64_t blocks, int prec, int tile_id, hipStream_t s);
+
 // ---- conveniences used by the single-system planner --------------------------
 void outer_acc(const OuterArgs &a, bool cplx, const void *A, const void *B, void *C, hipStream_t s);
 void fill_zero(void *p, int64_t n_elems, bool cplx, hipStream_t s);

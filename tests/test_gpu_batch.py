@@ -75,7 +75,8 @@ def test_batch_c4_shapes_run(E, ctx):
 
 @pytest.mark.parametrize("prec", ["f32", "bf16x3"])
 def test_batch_reduced_precision_equals_single_system(E, ctx, prec):
-    """Grouped reduced-precision GEMMs (operands converted while staging)
+    """Grouped reduced-precision GEMMs (K-contiguous operands read from
+    copies made by grouped conversions, the others converted while staging)
     against single-system plans (operands converted once into copies): the
     same products in the same order, so equal to FP64 rounding of the
     epilogues."""

@@ -88,14 +88,14 @@ def cpu_baseline(sysm, method, flops_per_step):
 
 def bench_batched(ctx, E, torch, steps, warmup):
     """64 uneven systems (o in [4,16], v in [20,60]), one grouped launch per
-    step of the contraction list, FP64 and FP32 contractions; then all 64
-    iterated to ||R|| < 1e-8 in FP64."""
+    step of the contraction list, FP64, FP32 and split-bf16 contractions;
+    then all 64 iterated to ||R|| < 1e-8 in FP64."""
     from ccinputs.synth import batch_shapes, make_system
     shapes = batch_shapes(64)
     ds = [E.DeviceSystem(make_system(o, v, seed), drop_host=True) for o, v, seed in shapes]
     out = {"systems": len(ds), "o_range": [min(s[0] for s in shapes), max(s[0] for s in shapes)],
            "v_range": [min(s[1] for s in shapes), max(s[1] for s in shapes)]}
-    for pname in ("f64", "f32"):
+    for pname in ("f64", "f32", "bf16x3"):
         with E.Batch(ctx, ds, E.CCSD, prec=E.PRECS[pname]) as B:
             B.step(0.0, True)
             torch.cuda.synchronize()

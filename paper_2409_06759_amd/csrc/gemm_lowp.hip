@@ -1268,6 +1268,44 @@ __global__ __launch_bounds__(256) void to_bf16x2_blocked_kernel(const double *__
   }
 }
 
+// The same copy with one wave per block (src and ref 16-byte aligned): load
+// i of lane L takes the two doubles k = 2 (L & 15), +1 of block row
+// 4 i + (L >> 4), so each load covers four whole 256-byte row segments; the
+// pair goes to slot row + 16 ((L & 15) >> 2), elements 2 (L & 3), +1.
+__global__ __launch_bounds__(256) void to_bf16x2_blocked_rows_kernel(const double *__restrict__ src,
+                                                                     const double *__restrict__ ref, int64_t R,
+                                                                     int64_t K, int64_t nblk, int64_t plane,
+                                                                     unsigned short *__restrict__ hi) {
+  const int64_t kblocks = K >> 5;
+  const int lane = threadIdx.x & 63, p = lane & 15;
+  for (int64_t blk = (blockIdx.x * int64_t(256) + threadIdx.x) >> 6; blk < nblk; blk += int64_t(gridDim.x) * 4) {
+    const int64_t r0 = (blk / kblocks) * 16, k = (blk % kblocks) * 32 + 2 * p;
+    unsigned short *__restrict__ hb = hi + blk * 512;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int rr = 4 * i + (lane >> 4);
+      const int64_t row = r0 + rr;
+      double x0 = 0.0, x1 = 0.0;
+      if (row < R) {
+        const double2 a = *reinterpret_cast<const double2 *>(src + row * K + k);
+        x0 = a.x;
+        x1 = a.y;
+        if (ref) {
+          const double2 b = *reinterpret_cast<const double2 *>(ref + row * K + k);
+          x0 = x0 - b.x;
+          x1 = x1 - b.y;
+        }
+      }
+      const float f0 = static_cast<float>(x0), f1 = static_cast<float>(x1);
+      const unsigned short h0 = bf16_bits(f0), h1 = bf16_bits(f1);
+      const unsigned short l0 = bf16_bits(f0 - bf16_to_float(h0)), l1 = bf16_bits(f1 - bf16_to_float(h1));
+      const int at = (rr + 16 * (p >> 2)) * 8 + 2 * (p & 3);
+      *reinterpret_cast<uint32_t *>(hb + at) = uint32_t(h0) | (uint32_t(h1) << 16);
+      *reinterpret_cast<uint32_t *>(hb + plane + at) = uint32_t(l0) | (uint32_t(l1) << 16);
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void delta_f32_kernel(const double *__restrict__ a, const double *__restrict__ ref,
                                                         int64_t n, float *__restrict__ dst) {
   for (int64_t e = blockIdx.x * int64_t(256) + threadIdx.x; e < n; e += int64_t(gridDim.x) * 256)
@@ -1474,9 +1512,15 @@ void convert_blocked(const double *src, const double *ref, int64_t R, int64_t K,
   CC_REQUIRE(R > 0 && K > 0 && K % 32 == 0, -1, "blocked split-bf16 copy: K must be a multiple of 32");
   CC_REQUIRE((reinterpret_cast<uintptr_t>(dst) & 15) == 0, -1, "blocked split-bf16 copy: alignment");
   const int64_t plane = blocked_plane(R, K), nslot = plane / 8;
-  const int64_t blocks = std::min<int64_t>((nslot + 255) / 256, 65536);
-  hipLaunchKernelGGL(to_bf16x2_blocked_kernel, dim3(blocks), dim3(256), 0, s, src, ref, R, K, nslot, plane,
-                     static_cast<unsigned short *>(dst));
+  if (((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(ref)) & 15) == 0) {
+    const int64_t nblk = plane / 512;
+    hipLaunchKernelGGL(to_bf16x2_blocked_rows_kernel, dim3(std::min<int64_t>((nblk + 3) / 4, 65536)), dim3(256), 0,
+                       s, src, ref, R, K, nblk, plane, static_cast<unsigned short *>(dst));
+  } else {
+    const int64_t blocks = std::min<int64_t>((nslot + 255) / 256, 65536);
+    hipLaunchKernelGGL(to_bf16x2_blocked_kernel, dim3(blocks), dim3(256), 0, s, src, ref, R, K, nslot, plane,
+                       static_cast<unsigned short *>(dst));
+  }
   CC_HIP_CHECK(hipGetLastError());
 }
 

@@ -128,15 +128,16 @@ __device__ __forceinline__ void perm_flat_body(const PermEntry &E, int64_t bid) 
   }
 }
 
-// Tiled path: 32x32 tile over (output unit-stride dim, input unit-stride dim),
-// read coalesced along the input's fast dim, written coalesced along the
-// output's fast dim through a padded LDS tile.
+// Tiled path: a TI x TO tile (TI TO = 1,024; TI = 32 unless the input's
+// unit-stride dim is shorter) over (input unit-stride dim, output
+// unit-stride dim), read coalesced along the input's fast dim, written
+// coalesced along the output's fast dim through a padded LDS tile.
 template <class T>
 __device__ __forceinline__ void perm_tiled_body(const PermEntry &E, int64_t bid) {
   const PermArgs &p = E.p;
   const T *__restrict__ in = static_cast<const T *>(E.in);
   T *__restrict__ out = static_cast<T *>(E.out);
-  __shared__ T tile[32][33];
+  __shared__ T tile[1280];  // TO rows of TI + 1 (TO <= 256)
   int64_t b = bid;
   const int64_t ti = b % p.tiles_i; b /= p.tiles_i;
   const int64_t to = b % p.tiles_o; b /= p.tiles_o;
@@ -147,20 +148,22 @@ __device__ __forceinline__ void perm_tiled_body(const PermEntry &E, int64_t bid)
     ib += x * p.rest_istr[d];
     ob += x * p.rest_ostr[d];
   }
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int lti = p.lti, lto = 10 - lti, TI = 1 << lti, TO = 1 << lto;
   const int64_t Do = p.dims[p.d_o], Di = p.dims[p.d_i];
-  const int64_t i0 = ti * 32, o0 = to * 32;
+  const int64_t i0 = ti * TI, o0 = to * TO;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    const int64_t xi = i0 + tx, xo = o0 + ty + 8 * k;
-    if (xi < Di && xo < Do) tile[ty + 8 * k][tx] = in[ib + xi * p.istr[p.d_i] + xo * p.istr[p.d_o]];
+    const int t = threadIdx.x + 256 * k, ri = t & (TI - 1), ro = t >> lti;
+    const int64_t xi = i0 + ri, xo = o0 + ro;
+    if (xi < Di && xo < Do) tile[ro * (TI + 1) + ri] = in[ib + xi * p.istr[p.d_i] + xo * p.istr[p.d_o]];
   }
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    const int64_t xo = o0 + tx, xi = i0 + ty + 8 * k;
+    const int t = threadIdx.x + 256 * k, ro = t & (TO - 1), ri = t >> lto;
+    const int64_t xo = o0 + ro, xi = i0 + ri;
     if (xi < Di && xo < Do) {
-      T v = tile[tx][ty + 8 * k];
+      T v = tile[ro * (TI + 1) + ri];
       if (p.conj) v = cj(v);
       v = sc(p.alpha, v);
       T *o = out + ob + xo * p.ostr[p.d_o] + xi * p.ostr[p.d_i];
@@ -567,20 +570,38 @@ int64_t chunks(int64_t n, int64_t ch) { return std::max<int64_t>(1, (n + ch - 1)
 PermEntry make_perm_entry(const PermDesc &d, const void *in, void *out) {
   PermEntry e{};
   PermArgs &p = e.p;
-  p.rank = d.rank;
+  // Drop dims of extent 1 and merge each dim into the one outside it when it
+  // continues that one in both tensors (outer stride = inner stride x inner
+  // extent): the same element map over fewer, longer dims.
   int64_t total = 1;
+  p.rank = 0;
   for (int i = 0; i < d.rank; ++i) {
-    p.dims[i] = d.out_dims[i];
-    p.istr[i] = d.in_strides[i];
-    p.ostr[i] = d.out_strides[i];
-    total *= d.out_dims[i];
+    const int64_t n = d.out_dims[i];
+    total *= n;
+    if (n == 1) continue;
+    const int r = p.rank;
+    if (r > 0 && p.istr[r - 1] == d.in_strides[i] * n && p.ostr[r - 1] == d.out_strides[i] * n) {
+      p.dims[r - 1] *= n;
+      p.istr[r - 1] = d.in_strides[i];
+      p.ostr[r - 1] = d.out_strides[i];
+    } else {
+      p.dims[r] = n;
+      p.istr[r] = d.in_strides[i];
+      p.ostr[r] = d.out_strides[i];
+      p.rank = r + 1;
+    }
+  }
+  if (p.rank == 0) {  // one element
+    p.rank = 1;
+    p.dims[0] = 1;
+    p.istr[0] = p.ostr[0] = 0;
   }
   p.total = total;
   p.alpha = d.alpha;
   p.beta = d.beta;
   p.conj = d.conj;
   int d_o = -1, d_i = -1;
-  for (int i = 0; i < d.rank; ++i) {
+  for (int i = 0; i < p.rank; ++i) {
     if (p.ostr[i] == 1 && p.dims[i] > 1) d_o = i;
     if (p.istr[i] == 1 && p.dims[i] > 1) d_i = i;
   }
@@ -599,7 +620,7 @@ PermEntry make_perm_entry(const PermDesc &d, const void *in, void *out) {
     p.d_i = d_i;
     p.nrest = 0;
     p.n_rest_total = 1;
-    for (int i = 0; i < d.rank; ++i) {
+    for (int i = 0; i < p.rank; ++i) {
       if (i == d_o || i == d_i) continue;
       p.rest_dims[p.nrest] = p.dims[i];
       p.rest_istr[p.nrest] = p.istr[i];
@@ -607,8 +628,12 @@ PermEntry make_perm_entry(const PermDesc &d, const void *in, void *out) {
       p.n_rest_total *= p.dims[i];
       ++p.nrest;
     }
-    p.tiles_o = (p.dims[d_o] + 31) / 32;
-    p.tiles_i = (p.dims[d_i] + 31) / 32;
+    // a short input fast dim (the occupied index of small systems) gets a
+    // narrow, long tile instead of a mostly empty 32 x 32 one
+    p.lti = 5;
+    while (p.lti > 2 && (int64_t(1) << (p.lti - 1)) >= p.dims[d_i]) --p.lti;
+    p.tiles_i = (p.dims[d_i] + (1 << p.lti) - 1) >> p.lti;
+    p.tiles_o = (p.dims[d_o] + (1 << (10 - p.lti)) - 1) >> (10 - p.lti);
     e.units = p.n_rest_total * p.tiles_o * p.tiles_i;
   }
   return e;

@@ -128,10 +128,10 @@ __device__ __forceinline__ void perm_flat_body(const PermEntry &E, int64_t bid) 
   }
 }
 
-// Tiled path: a TI x TO tile (TI TO = 1,024; TI = 32 unless the input's
-// unit-stride dim is shorter) over (input unit-stride dim, output
-// unit-stride dim), read coalesced along the input's fast dim, written
-// coalesced along the output's fast dim through a padded LDS tile.
+// Tiled path: a TI x TO tile (TI TO = 1,024; 32 x 32 unless one of the two
+// dims is shorter) over (input unit-stride dim, output unit-stride dim),
+// read coalesced along the input's fast dim, written coalesced along the
+// output's fast dim through a padded LDS tile.
 template <class T>
 __device__ __forceinline__ void perm_tiled_body(const PermEntry &E, int64_t bid) {
   const PermArgs &p = E.p;
@@ -628,10 +628,15 @@ PermEntry make_perm_entry(const PermDesc &d, const void *in, void *out) {
       p.n_rest_total *= p.dims[i];
       ++p.nrest;
     }
-    // a short input fast dim (the occupied index of small systems) gets a
-    // narrow, long tile instead of a mostly empty 32 x 32 one
-    p.lti = 5;
-    while (p.lti > 2 && (int64_t(1) << (p.lti - 1)) >= p.dims[d_i]) --p.lti;
+    // 32 x 32, or a narrow, long tile when one of the two fast dims is short
+    // (the occupied index of small systems) instead of a mostly empty one
+    auto lg = [](int64_t n) {  // log2 of the smallest power of two >= n, in [2, 8]
+      int l = 2;
+      while (l < 8 && (int64_t(1) << l) < n) ++l;
+      return l;
+    };
+    const int li = lg(p.dims[d_i]), lo = lg(p.dims[d_o]);
+    p.lti = li < 5 ? li : (lo < 5 ? 10 - lo : 5);
     p.tiles_i = (p.dims[d_i] + (1 << p.lti) - 1) >> p.lti;
     p.tiles_o = (p.dims[d_o] + (1 << (10 - p.lti)) - 1) >> (10 - p.lti);
     e.units = p.n_rest_total * p.tiles_o * p.tiles_i;

@@ -22,7 +22,7 @@ struct PermArgs {
   double alpha, beta;
   int conj;
   int d_o, d_i;  // tiled dims: output unit-stride dim and input unit-stride dim
-  int lti;       // tiled: log2 of the tile's extent along d_i (4..32; 1,024 elements per tile)
+  int lti;       // tiled: log2 of the tile's extent along d_i (4..256; 1,024 elements per tile)
   int64_t rest_dims[kMaxRank], rest_istr[kMaxRank], rest_ostr[kMaxRank];
   int nrest;
   int64_t n_rest_total, tiles_o, tiles_i;

@@ -54,7 +54,10 @@ def test_gemm_beta_zero_ignores_nan(ctx):
 @pytest.mark.parametrize("dims,perm", [((5, 7), (1, 0)), ((3, 40, 33, 5), (0, 2, 1, 3)),
                                        ((6, 6, 35, 35), (2, 0, 3, 1)), ((4, 5, 6, 7), (3, 2, 1, 0)),
                                        ((3, 4, 5, 6, 7), (4, 0, 3, 1, 2)),
-                                       ((2, 3, 4, 5, 6, 7), (5, 4, 3, 2, 1, 0))])
+                                       ((2, 3, 4, 5, 6, 7), (5, 4, 3, 2, 1, 0)),
+                                       # short fast dims (4..256-long tiles): output, input, both
+                                       ((4, 4, 20, 20), (0, 2, 3, 1)), ((7, 23, 23, 7), (0, 3, 1, 2)),
+                                       ((5, 300, 2, 3), (3, 1, 0, 2)), ((3, 5, 1, 6), (3, 2, 0, 1))])
 def test_permute_exact(ctx, dims, perm):
     from paper_2409_06759_amd import engine as E
     rng = np.random.default_rng(len(dims))

@@ -318,7 +318,11 @@ int cc_permute(cc_ctx *ctx, int scalar, int rank, const int64_t *in_dims, const 
  * HIP graph.  The amplitude buffers amps[b] are bound at creation (they are
  * updated in place by every step) and must stay valid until destruction.
  * The contraction precision is fixed at creation; batches of complex
- * systems take CC_PREC_F64 only (CC_EUNSUPPORTED otherwise). */
+ * systems take CC_PREC_F64 only (CC_EUNSUPPORTED otherwise).  Split-K
+ * factors follow the tiles of all systems together (fewer K-slices than a
+ * system alone would take); with the environment variable
+ * CC_BATCH_OWN_SPLITS set at creation each system keeps its own plan's
+ * factors, and its results then equal its single-system solve bit for bit. */
 int cc_batch_create(cc_ctx *ctx, int n, const cc_system *systems, int method, int prec, cc_amps *amps,
                     cc_batch **batch);
 int cc_batch_destroy(cc_batch *batch);

@@ -403,6 +403,28 @@ void run_gstep(cc_batch *B, size_t k, hipStream_t s) {
 
 }  // namespace
 
+// Split-K factors for the batch as a whole.  Each plan chose its factors to
+// fill the GPU with its own GEMMs alone (up to 16 K-slices for a small
+// system); in a batch the systems' tiles fill it together, so a step's
+// factor follows the tiles of all systems: slices only while they number
+// under 2,048 of 64 x 64, and never K-slices shorter than 256.  The plans'
+// workspaces were sized for their own, larger factors.
+void batch_group_splits(cc_batch *B) {
+  for (size_t k = 0; k < B->plans[0]->iter.size(); ++k) {
+    if (B->plans[0]->iter[k].kind != Step::GEMM) continue;
+    int64_t tiles = 0;
+    for (cc_plan *p : B->plans) {
+      const GemmDesc &d = p->iter[k].gemm;
+      tiles += ((d.M + 63) / 64) * ((d.N + 63) / 64);
+    }
+    const int64_t split = tiles >= 2048 ? 1 : (2048 + tiles - 1) / std::max<int64_t>(tiles, 1);
+    for (cc_plan *p : B->plans) {
+      GemmDesc &d = p->iter[k].gemm;
+      d.split = int(std::max<int64_t>(1, std::min<int64_t>({split, int64_t(d.split), std::max<int64_t>(1, d.K / 256)})));
+    }
+  }
+}
+
 void batch_run(cc_batch *B) {
   hipStream_t s = B->ctx->stream;
   if (!B->profiling) {
@@ -573,6 +595,7 @@ int cc_batch_create(cc_ctx *ctx, int n, const cc_system *systems, int method, in
         throw ccmi::CCError(CC_EUNSUPPORTED, "batches of complex systems run FP64 contractions only");
       for (cc_plan *p : B->plans)
         if (p->cplx != B->cplx) throw ccmi::CCError(CC_EINVAL, "batch mixes real and complex systems");
+      if (!std::getenv("CC_BATCH_OWN_SPLITS")) ccmi::batch_group_splits(B);
       CC_HIP_CHECK(hipMalloc(reinterpret_cast<void **>(&B->scalars), sizeof(double) * 4 * n));
       batch_prepare(B, 0.0, 0);
     } catch (...) {

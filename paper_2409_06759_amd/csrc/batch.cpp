@@ -246,6 +246,23 @@ void build_tables(cc_batch *B) {
             g.conv.push_back(c);
           }
         }
+        // systems in the launch in order of K per workgroup, longest first,
+        // so that the longest workgroups start in the first round instead of
+        // finishing last (the entries carry their own pointers: any order)
+        {
+          std::vector<size_t> ord(es.size());
+          for (size_t b = 0; b < ord.size(); ++b) ord[b] = b;
+          auto klen = [&](size_t b) { return (es[b].d.K + es[b].d.split - 1) / es[b].d.split; };
+          std::stable_sort(ord.begin(), ord.end(), [&](size_t x, size_t y) { return klen(x) > klen(y); });
+          std::vector<GemmGroupEntry> es2;
+          std::vector<int64_t> u2;
+          for (size_t b : ord) {
+            es2.push_back(es[b]);
+            u2.push_back(units[b]);
+          }
+          es.swap(es2);
+          units.swap(u2);
+        }
         g.entry_off = push_entries(B, es);
         g.off_off = push_offsets(B, units, &g.blocks);
         g.sk_entry_off = push_entries(B, sk);

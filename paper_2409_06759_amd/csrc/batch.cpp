@@ -70,6 +70,7 @@ struct cc_batch {
   std::vector<double> step_ms;
   int64_t prof_calls = 0;
   double flops = 0.0;
+  std::vector<std::vector<int>> own_split;  // per step and system: the plan's own split-K factor
 };
 
 namespace ccmi {
@@ -427,8 +428,10 @@ void run_gstep(cc_batch *B, size_t k, hipStream_t s) {
 // under 2,048 of 64 x 64, and never K-slices shorter than 256.  The plans'
 // workspaces were sized for their own, larger factors.
 void batch_group_splits(cc_batch *B) {
+  B->own_split.assign(B->plans[0]->iter.size(), {});
   for (size_t k = 0; k < B->plans[0]->iter.size(); ++k) {
     if (B->plans[0]->iter[k].kind != Step::GEMM) continue;
+    for (cc_plan *p : B->plans) B->own_split[k].push_back(p->iter[k].gemm.split);
     int64_t tiles = 0;
     for (cc_plan *p : B->plans) {
       const GemmDesc &d = p->iter[k].gemm;
@@ -469,8 +472,9 @@ void batch_run(cc_batch *B) {
   ++B->prof_calls;
 }
 
-// Time every FP64 tile configuration of each grouped GEMM (a contraction
-// class across the batch) and keep the fastest.
+// Time every tile configuration of each grouped GEMM (a contraction class
+// across the batch) and keep the fastest; then the plans' own split-K
+// factors against the batch's.
 void batch_autotune(cc_batch *B, int reps) {
   if (B->cplx) return;
   const int prec = B->prec;
@@ -502,6 +506,29 @@ void batch_autotune(cc_batch *B, int reps) {
         }
       }
       for (cc_plan *p : B->plans) tile_of(p->iter[k]) = best;
+      // then the plans' own split-K factors instead of the batch's, where
+      // faster (GEMMs with a tiny M x N and a long K want many K-slices)
+      if (B->own_split.size() == B->gsteps.size() && B->own_split[k].size() == B->plans.size()) {
+        std::vector<int> cur;
+        bool differs = false;
+        for (size_t b = 0; b < B->plans.size(); ++b) {
+          cur.push_back(B->plans[b]->iter[k].gemm.split);
+          differs = differs || cur[b] != B->own_split[k][b];
+        }
+        if (differs) {
+          for (size_t b = 0; b < B->plans.size(); ++b) B->plans[b]->iter[k].gemm.split = B->own_split[k][b];
+          build_tables(B);
+          run_gstep(B, k, s);
+          CC_HIP_CHECK(hipEventRecord(e0, s));
+          for (int r = 0; r < reps; ++r) run_gstep(B, k, s);
+          CC_HIP_CHECK(hipEventRecord(e1, s));
+          CC_HIP_CHECK(hipEventSynchronize(e1));
+          float ms = 0.f;
+          CC_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+          if (ms >= best_ms)
+            for (size_t b = 0; b < B->plans.size(); ++b) B->plans[b]->iter[k].gemm.split = cur[b];
+        }
+      }
     }
   } catch (...) {
     (void)hipEventDestroy(e0);

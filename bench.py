@@ -94,7 +94,8 @@ def bench_batched(ctx, E, torch, steps, warmup):
     shapes = batch_shapes(64)
     ds = [E.DeviceSystem(make_system(o, v, seed), drop_host=True) for o, v, seed in shapes]
     out = {"systems": len(ds), "o_range": [min(s[0] for s in shapes), max(s[0] for s in shapes)],
-           "v_range": [min(s[1] for s in shapes), max(s[1] for s in shapes)]}
+           "v_range": [min(s[1] for s in shapes), max(s[1] for s in shapes)],
+           "pairs": "packed (ladder, hole-hole ladder and Z over i<j, a<b, e<f); flops_per_step counts those"}
     for pname in ("f64", "f32", "bf16x3"):
         with E.Batch(ctx, ds, E.CCSD, prec=E.PRECS[pname]) as B:
             B.step(0.0, True)

@@ -322,7 +322,10 @@ int cc_permute(cc_ctx *ctx, int scalar, int rank, const int64_t *in_dims, const 
  * factors follow the tiles of all systems together (fewer K-slices than a
  * system alone would take); with the environment variable
  * CC_BATCH_OWN_SPLITS set at creation each system keeps its own plan's
- * factors, and its results then equal its single-system solve bit for bit. */
+ * factors, and its results then equal its single-system solve bit for bit.
+ * Real systems run the ladder, the hole-hole ladder and Z over packed pairs
+ * (i<j, a<b, e<f), as plans created with the packed flag of cc_plan_create2;
+ * CC_BATCH_DENSE set at creation keeps them dense. */
 int cc_batch_create(cc_ctx *ctx, int n, const cc_system *systems, int method, int prec, cc_amps *amps,
                     cc_batch **batch);
 int cc_batch_destroy(cc_batch *batch);

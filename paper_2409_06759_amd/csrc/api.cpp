@@ -237,8 +237,8 @@ cc_plan *make_plan(cc_ctx *ctx, const cc_system *sys, int method, int prec,
 
 namespace ccmi {
 cc_plan *make_plan_checked(cc_ctx *ctx, const cc_system *sys, int method, int prec, bool lowp_all,
-                           bool private_work) {
-  return make_plan(ctx, sys, method, prec, nullptr, false, lowp_all, private_work);
+                           bool private_work, bool packed) {
+  return make_plan(ctx, sys, method, prec, nullptr, packed, lowp_all, private_work);
 }
 void check_amps(const cc_amps *t, int method) { validate_amps(t, method, "t"); }
 }  // namespace ccmi

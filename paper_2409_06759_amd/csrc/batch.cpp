@@ -270,6 +270,19 @@ void build_tables(cc_batch *B) {
         g.sk_off_off = push_offsets(B, skunits, &g.sk_blocks);
         break;
       }
+      case Step::PAIR: {
+        std::vector<PairEntry> es;
+        for (cc_plan *p : B->plans) {
+          const Step &st = p->iter[k];
+          es.push_back(make_pair_entry(ptr_of(p, st.a), ptr_of(p, st.c), p->pair_tab[st.pair_rows],
+                                       p->pair_tab[st.pair_cols], st.pair_np, st.pair_nq, st.pair_ldq, st.pair_n[0],
+                                       st.pair_n[1], st.pair_n[2], st.pair_mode));
+          units.push_back(es.back().units);
+        }
+        g.entry_off = push_entries(B, es);
+        g.off_off = push_offsets(B, units, &g.blocks);
+        break;
+      }
       case Step::OUTER: {
         std::vector<OuterEntry> es;
         for (cc_plan *p : B->plans) {
@@ -400,6 +413,9 @@ void run_gstep(cc_batch *B, size_t k, hipStream_t s) {
       break;
     case Step::OUTER:
       launch_outer_grouped(dev_at<OuterEntry>(B, g.entry_off), off, n, g.blocks, cplx, s);
+      break;
+    case Step::PAIR:
+      launch_pair_grouped(dev_at<PairEntry>(B, g.entry_off), off, n, g.blocks, cplx, s);
       break;
     case Step::FILL:
       launch_fill_grouped(dev_at<FillEntry>(B, g.entry_off), off, n, g.blocks, cplx, s);
@@ -627,7 +643,10 @@ int cc_batch_create(cc_ctx *ctx, int n, const cc_system *systems, int method, in
     try {
       for (int b = 0; b < n; ++b) {
         // every contraction in the batch's precision: one grouped launch per step
-        cc_plan *p = ccmi::make_plan_checked(ctx, &systems[b], method, prec, true, true);
+        // real systems: the ladder, the hole-hole ladder and Z over packed
+        // pairs (i<j, a<b, e<f) unless CC_BATCH_DENSE is set
+        cc_plan *p = ccmi::make_plan_checked(ctx, &systems[b], method, prec, true, true,
+                                             !std::getenv("CC_BATCH_DENSE") && systems[b].scalar != CC_C128);
         ccmi::check_amps(&amps[b], method);
         p->t1 = amps[b].t1;
         p->t2 = amps[b].t2;

@@ -738,6 +738,9 @@ void launch_perm_grouped(const PermEntry *e, const int64_t *off, int n, int64_t 
 void launch_outer_grouped(const OuterEntry *e, const int64_t *off, int n, int64_t blocks, bool cplx, hipStream_t s) {
   CC_LAUNCHG(g_outer, e, off, n, blocks, cplx, s);
 }
+void launch_pair_grouped(const PairEntry *e, const int64_t *off, int n, int64_t blocks, bool cplx, hipStream_t s) {
+  CC_LAUNCHG(g_pair, e, off, n, blocks, cplx, s);
+}
 void launch_fill_grouped(const FillEntry *e, const int64_t *off, int n, int64_t blocks, bool cplx, hipStream_t s) {
   CC_LAUNCHG(g_fill, e, off, n, blocks, cplx, s);
 }

@@ -177,6 +177,7 @@ void launch_perm_grouped(const PermEntry *e, const int64_t *off, int n, int64_t 
                          hipStream_t s);
 void launch_outer_grouped(const OuterEntry *e, const int64_t *off, int n, int64_t blocks, bool cplx, hipStream_t s);
 void launch_fill_grouped(const FillEntry *e, const int64_t *off, int n, int64_t blocks, bool cplx, hipStream_t s);
+void launch_pair_grouped(const PairEntry *e, const int64_t *off, int n, int64_t blocks, bool cplx, hipStream_t s);
 void launch_splitk_grouped(const SplitkEntry *e, const int64_t *off, int n, int64_t blocks, bool cplx,
                            hipStream_t s);
 void launch_tau_grouped(const TauEntry *e, const int64_t *off, int n, int64_t blocks, bool cplx, hipStream_t s);

@@ -202,6 +202,6 @@ R1Entry r1_entry(cc_plan *p);
 FinEntry fin_entry(cc_plan *p);
 void *ptr_of(cc_plan *p, int slot);
 cc_plan *make_plan_checked(cc_ctx *ctx, const cc_system *sys, int method, int prec, bool lowp_all = false,
-                           bool private_work = false);
+                           bool private_work = false, bool packed = false);
 void check_amps(const cc_amps *t, int method);
 }  // namespace ccmi

@@ -27,11 +27,17 @@ def ctx(E):
 SHAPES = [(4, 20, 11), (7, 33, 12), (5, 26, 13), (9, 21, 14), (6, 41, 15)]
 
 
+@pytest.mark.parametrize("packed", [True, False])
 @pytest.mark.parametrize("method", ["ccd", "ccsd"])
-def test_batch_steps_equal_single_system_steps(E, ctx, method):
+def test_batch_steps_equal_single_system_steps(E, ctx, monkeypatch, method, packed):
+    """Batches of real systems run the ladder, the hole-hole ladder and Z over
+    packed pairs (CC_BATCH_DENSE keeps them dense): against single-system
+    plans of the same layout."""
     m = E.METHODS[method]
     systems = [make_system(o, v, seed) for o, v, seed in SHAPES]
     ds = [E.DeviceSystem(s) for s in systems]
+    if not packed:
+        monkeypatch.setenv("CC_BATCH_DENSE", "1")
     with E.Batch(ctx, ds, m) as B:
         for _ in range(4):
             B.step(0.0, True)
@@ -39,7 +45,7 @@ def test_batch_steps_equal_single_system_steps(E, ctx, method):
         amps_b = B.amps
         for b, d in enumerate(ds):
             t1, t2 = E.zeros_amps(d, m)
-            with E.Plan(ctx, d, m) as p:
+            with E.Plan(ctx, d, m, packed=packed) as p:
                 for _ in range(4):
                     p.step(t1, t2, 0.0, True)
                 rn, e, _ = p.scalars()
@@ -91,7 +97,7 @@ def test_batch_reduced_precision_equals_single_system(E, ctx, prec):
         amps_b = B.amps
         for b, d in enumerate(ds):
             t1, t2 = E.zeros_amps(d, E.CCSD)
-            with E.Plan(ctx, d, E.CCSD, prec=P, lowp_all=True) as p:  # as the batch: all in prec
+            with E.Plan(ctx, d, E.CCSD, prec=P, lowp_all=True, packed=True) as p:  # as the batch
                 for _ in range(3):
                     p.step(t1, t2, 0.0, True)
                 rn, e, _ = p.scalars()
@@ -104,7 +110,7 @@ def test_batch_c4_full_workload(E, ctx, monkeypatch):
     """All 64 systems of the batched workload iterated together to 1e-10.
     With the split-K factors each system's own plan chose
     (CC_BATCH_OWN_SPLITS=1) every system equals its own single-system solve
-    bitwise. With the batch's factors (the default; fewer K-slices, since
+    (over packed pairs, as the batch) bitwise. With the batch's factors (the default; fewer K-slices, since
     the systems fill the GPU together) the sums are ordered differently:
     the same iteration counts and energies within 1e-12 Eh. Three systems
     (the smallest, a middle and the largest) equal the oracle's converged
@@ -125,7 +131,7 @@ def test_batch_c4_full_workload(E, ctx, monkeypatch):
     worst = 0.0
     for b in range(64):
         t1, t2 = E.zeros_amps(ds[b], E.CCSD)
-        single = E.iterate(ctx, ds[b], E.CCSD, t1, t2, tol=1e-10, max_iter=200, dressed=True)
+        single = E.iterate(ctx, ds[b], E.CCSD, t1, t2, tol=1e-10, max_iter=200, dressed=True, packed=True)
         assert single["iters"] == own["systems"][b]["iters"] == out["systems"][b]["iters"]
         assert single["energy"] == own["systems"][b]["energy"]
         worst = max(worst, abs(single["energy"] - out["systems"][b]["energy"]))
